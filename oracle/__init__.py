@@ -1,0 +1,16 @@
+"""Plain, slow, obviously correct FP64 CPU oracle for moment-conserving GW.
+
+TEST INFRASTRUCTURE ONLY.  Nothing on the product path may import, call or
+execute this package: only the test-suite, the smoke check and the CPU
+baseline leg of the benchmark use it.  It shares no code with the HIP path;
+the only common module is the seeded input generator ``gwsynth``, which
+holds none of the method's arithmetic.
+
+Modules
+-------
+gw          density-response moments (TDA and RPA), self-energy moments,
+            block Lanczos from moments, upfolded Hamiltonian, QP assignment.
+quadrature  the mapped Gauss-Legendre grid used for the RPA zeroth moment.
+brute       brute-force references: full TDA/RPA diagonalisation, exact
+            Lehmann self-energy moments and the exact upfolded Hamiltonian.
+"""

@@ -1,0 +1,169 @@
+/*
+ * gwmom.h -- C ABI of the MI355X moment-conserving GW library (libgwmom.so).
+ *
+ * Method: Backhouse, Allen, Scott, Booth, "Self-consistent GW via conservation
+ * of spectral moments".  The library computes, on one AMD Instinct MI355X
+ * (gfx950), the density-fitted hot path of moment-conserving G0W0:
+ *
+ *   density-response moments  eta~^{(n)}, R_n = eta~^{(n)} V^T   (Sec. 2.2 RPA, Sec. 2.3 TDA)
+ *   self-energy moments       Sigma^{(n,<)}, Sigma^{(n,>)}        (eqs. convolution_occ/_vir, w_moments)
+ *   auxiliary poles           block Lanczos on the moments         (eq. effH, Sec. 2)
+ *   upfolded Hamiltonian      eigenpairs and QP assignment         (eqs. effH, ret_GF, quasiparticle_energy_update)
+ *
+ * Conventions (all entry points)
+ * ------------------------------
+ *  - nmo = nocc + nvir.  Orbital energies eps[nmo] list the nocc occupied
+ *    levels first, then the nvir virtual ones; every occupied energy must lie
+ *    below every virtual one.
+ *  - L[naux][nmo][nmo] is the three-index Coulomb factor in the MO basis
+ *    (the paper's V_{P,pq}), dense row-major FP64, symmetric in its last two
+ *    indices.  The particle-hole block is V[P][i*nvir + a] = L[P][i][nocc+a].
+ *  - Every array argument is a DEVICE pointer on the handle's device unless
+ *    marked "host".  Arrays are dense, row-major, caller-owned; the library
+ *    never frees or retains them past the call.
+ *  - Work is enqueued on the handle's stream.  gw_moments_* and
+ *    gw_sigma_moments return once the work is enqueued; gw_poles returns
+ *    after the stream has drained (it reports pole counts to the host).
+ *  - Inputs are validated before anything is launched; a failed validation
+ *    returns GW_EINVAL and leaves outputs untouched.  gw_last_error() gives
+ *    a message for the last failure on the handle.
+ *  - The library allocates its own device workspace (grow-only, owned by
+ *    the handle, released by gw_destroy).  One handle per host thread.
+ *  - nmom_max (the paper's n_mom^max) must be odd: the block Lanczos step
+ *    conserves moments 0..nmom_max with (nmom_max+1)/2 blocks per sector.
+ */
+#ifndef GWMOM_H
+#define GWMOM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gw_handle_s* gw_handle;
+
+typedef enum {
+    GW_OK = 0,
+    GW_EINVAL = -1,   /* bad argument: sizes, null pointers, even nmom_max, bad eps */
+    GW_ENOMEM = -2,   /* device workspace could not be allocated */
+    GW_EHIP = -3,     /* a HIP runtime call or kernel launch failed */
+    GW_ENUMERIC = -4, /* a moment matrix is not PSD or an eigensolve failed */
+    GW_ENOCONV = -5,  /* an iterative loop hit its iteration cap */
+    GW_ELIB = -6      /* rocBLAS / rocSOLVER reported an error */
+} gw_status;
+
+typedef enum { GW_FP64 = 0, GW_MIXED = 1 } gw_precision;
+typedef enum { GW_TDA = 0, GW_RPA = 1 } gw_screening;
+
+/* Optional knobs; pass NULL (or zero fields) for the defaults. */
+typedef struct {
+    int nquad;          /* RPA quadrature points; <= 0 -> 48                         */
+    double quad_scale;  /* RPA grid scale s in z = s(1+x)/(1-x); <= 0 -> median(D)  */
+    double pinv_tol;    /* Lanczos pseudo-inverse cut (relative); <= 0 -> 1e-12      */
+    double neg_tol;     /* Lanczos non-PSD tolerance (relative);  <= 0 -> 1e-8       */
+    int bf16_slices;    /* mixed precision: BF16 slices per operand (2 or 3); 0 -> 3 */
+    size_t zchunk_bytes;/* cap on the folded-intermediate chunk; 0 -> 4 GiB          */
+} gw_opts;
+
+/* Create a handle on HIP device `device` with its own non-blocking stream. */
+gw_status gw_create(gw_handle* h, int device);
+/* Use an existing hipStream_t (from the caller, e.g. a torch stream) instead
+ * of the handle's own; NULL restores the handle's stream. */
+gw_status gw_set_stream(gw_handle h, void* hip_stream);
+gw_status gw_synchronize(gw_handle h);
+gw_status gw_destroy(gw_handle h);
+/* Message for the last failure on h (static string if h is NULL). */
+const char* gw_last_error(gw_handle h);
+
+/*
+ * TDA density-response moments (Sec. 2.3):
+ *   eta~^{(0)} = V,  eta~^{(n)} = eta~^{(n-1)} (D + 2 V^T V),  R_n = eta~^{(n)} V^T.
+ * Outputs:
+ *   R   [nmom_max+1][naux][naux]          symmetric; required.
+ *   eta [nmom_max+1][naux][nocc*nvir]     nullable.
+ * prec must be GW_FP64 or GW_MIXED (mixed: BF16 split products, FP32
+ * accumulation, per-moment scaling; results still returned in FP64).
+ */
+gw_status gw_moments_tda(gw_handle h, int nocc, int nvir, int naux, int nmom_max,
+                         const double* eps, const double* L, gw_precision prec,
+                         const gw_opts* opts, double* R, double* eta);
+
+/*
+ * RPA density-response moments (Sec. 2.2): eta~^{(0)} = G D^-1 (I - 4 V^T
+ * (I + 4 V D^-1 V^T)^-1 V D^-1) with G = G_main + G_offset by opts->nquad-point
+ * mapped Gauss-Legendre quadrature (always FP64), eta~^{(1)} = V D,
+ * eta~^{(n)} = eta~^{(n-2)} (D^2 + 4 V^T V D).  Outputs as gw_moments_tda.
+ */
+gw_status gw_moments_rpa(gw_handle h, int nocc, int nvir, int naux, int nmom_max,
+                         const double* eps, const double* L, gw_precision prec,
+                         const gw_opts* opts, double* R, double* eta);
+
+/*
+ * Self-energy moments (eqs. convolution_occ, convolution_vir, w_moments) for
+ * n = 0..nmom_max, for a closed-shell reference (factor 2 from the spin sum):
+ *   Sigma^{(n,<)}_pq = 2 sum_t C(n,t) (-1)^t sum_{k occ} eps_k^{n-t} W^{(t)}_{pk,qk}
+ *   Sigma^{(n,>)}_pq = 2 sum_t C(n,t)         sum_{c vir} eps_c^{n-t} W^{(t)}_{pc,qc}
+ *   W^{(t)}_{px,qx}  = sum_PQ L[P][p][x] R_t[P][Q] L[Q][q][x]
+ * with R_t from the chosen screening.  Outputs (symmetric):
+ *   sigma_occ, sigma_vir  [nmom_max+1][nmo][nmo].
+ */
+gw_status gw_sigma_moments(gw_handle h, gw_screening screening, int nocc, int nvir,
+                           int naux, int nmom_max, const double* eps, const double* L,
+                           gw_precision prec, const gw_opts* opts,
+                           double* sigma_occ, double* sigma_vir);
+
+/*
+ * Self-energy moments from given aux-space cores R[nmom_max+1][naux][naux]
+ * (the contraction stage alone, same outputs as gw_sigma_moments).
+ */
+gw_status gw_sigma_from_R(gw_handle h, int nocc, int nvir, int naux, int nmom_max,
+                          const double* eps, const double* L, const double* R,
+                          gw_precision prec, const gw_opts* opts,
+                          double* sigma_occ, double* sigma_vir);
+
+/*
+ * Auxiliary poles and upfolded Hamiltonian (eq. effH; eqs. ret_GF and
+ * quasiparticle_energy_update), all FP64 on the device.
+ * Per sector, block Lanczos on the moments gives (nmom_max+1)/2 blocks;
+ * the block tridiagonal matrix is diagonalised and its poles coupled back
+ * through B0 = (Sigma^{(0)})^{1/2}.  Poles whose coupling norm is below
+ * 1e-14 of the largest are dropped.  Then
+ *   H~ = [[fock, v_occ, v_vir], [v_occ^T, diag e_occ, 0], [v_vir^T, 0, diag e_vir]]
+ * is diagonalised; the QP energy of orbital p is E_alpha with
+ * alpha = argmax_beta chi_{p beta}^2 (lowest alpha on ties), its weight chi_{p alpha}^2.
+ * Inputs:  sigma_occ, sigma_vir [nmom_max+1][nmo][nmo]; fock [nmo][nmo].
+ * Outputs (cap = nmo*(nmom_max+1)/2 poles per sector, dim_max = nmo*(nmom_max+2)):
+ *   npole_occ, npole_vir  host ints: poles kept per sector;
+ *   pole_e  [2*cap]            occupied poles then virtual (packed);
+ *   pole_v  [nmo][2*cap]       couplings, columns packed like pole_e;
+ *   E       [dim_max]          eigenvalues of H~ (first nmo+npole_occ+npole_vir valid, ascending);
+ *   chi     [nmo][dim_max]     physical rows of the eigenvectors (nullable);
+ *   qp_e, qp_w [nmo]           QP energies and weights.
+ * Returns GW_ENUMERIC if a moment matrix is not PSD beyond neg_tol or an
+ * eigensolve fails.
+ */
+gw_status gw_poles(gw_handle h, int nmo, int nmom_max, const double* sigma_occ,
+                   const double* sigma_vir, const double* fock, const gw_opts* opts,
+                   int* npole_occ, int* npole_vir, double* pole_e, double* pole_v,
+                   double* E, double* chi, double* qp_e, double* qp_w);
+
+/*
+ * Per-kernel timing for measurement.  While enabled, every launch of the
+ * instrumented kernel families is bracketed by HIP events recorded on the
+ * handle's stream (the stream the kernels run on).  Families:
+ *   "sigma_fold"     stage 1 of the self-energy contraction (R_t L with the eps-power fold)
+ *   "sigma_contract" stage 2 (sum over P and x of L Zt)
+ *   "recur_xvt"      R_n = eta~^{(n)} V^T
+ *   "recur_rv"       eta~ updates  D o X + c R V
+ *   "rpa_quad"       RPA quadrature products (Q/T matrices and the G product)
+ * gw_timing_read synchronises the stream, then returns the summed duration
+ * (ms) and the launch count of one family since the last reset.
+ */
+gw_status gw_timing_enable(gw_handle h, int enable);
+gw_status gw_timing_reset(gw_handle h);
+gw_status gw_timing_read(gw_handle h, const char* family, double* total_ms, long* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GWMOM_H */

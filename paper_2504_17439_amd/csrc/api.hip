@@ -1,0 +1,277 @@
+// C ABI entry points: handle management, argument validation, dispatch.
+#include "internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+namespace gwm {
+
+gw_status set_err(Handle* h, gw_status st, const std::string& msg) {
+    if (h) h->last_error = msg;
+    return st;
+}
+
+void* ws_get(Handle* h, int slot, size_t bytes) {
+    if (slot < 0 || slot >= WS_COUNT) return nullptr;
+    DevBuf& b = h->ws[slot];
+    if (bytes == 0) bytes = 8;
+    if (b.bytes >= bytes) return b.ptr;
+    if (b.ptr) {
+        // the stream may still use the old buffer
+        if (hipStreamSynchronize(h->stream) != hipSuccess) {
+            set_err(h, GW_EHIP, "ws_get: stream synchronize failed");
+            return nullptr;
+        }
+        (void)hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = (bytes + 255) & ~(size_t)255;
+    if (hipMalloc(&b.ptr, want) != hipSuccess) {
+        b.ptr = nullptr;
+        (void)hipGetLastError();
+        set_err(h, GW_ENOMEM, "device workspace allocation failed (" + std::to_string(want) + " bytes)");
+        return nullptr;
+    }
+    b.bytes = want;
+    return b.ptr;
+}
+
+KTimer::KTimer(Handle* hh, const char* family) : h(hh) {
+    if (!h->timing || !family) return;
+    TimedLaunch t;
+    t.family = family;
+    if (hipEventCreate(&t.start) != hipSuccess || hipEventCreate(&t.stop) != hipSuccess) return;
+    if (hipEventRecord(t.start, h->stream) != hipSuccess) return;
+    h->timed.push_back(t);
+    idx = (int)h->timed.size() - 1;
+}
+
+void KTimer::stop() {
+    if (idx >= 0) (void)hipEventRecord(h->timed[idx].stop, h->stream);
+    idx = -1;
+}
+
+static void clear_timed(Handle* h) {
+    for (auto& t : h->timed) {
+        if (t.start) (void)hipEventDestroy(t.start);
+        if (t.stop) (void)hipEventDestroy(t.stop);
+    }
+    h->timed.clear();
+}
+
+}  // namespace gwm
+
+using gwm::Handle;
+
+struct gw_handle_s : public Handle {};
+
+namespace {
+
+thread_local std::string g_static_err;
+
+gw_status validate_common(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                          const double* L) {
+    if (nocc < 1 || nvir < 1 || naux < 1)
+        return gwm::set_err(h, GW_EINVAL, "nocc, nvir and naux must be >= 1");
+    if (nmom_max < 1 || nmom_max % 2 == 0 || nmom_max > 15)
+        return gwm::set_err(h, GW_EINVAL, "nmom_max must be odd and in [1, 15]");
+    if (!eps || !L) return gwm::set_err(h, GW_EINVAL, "eps and L must be non-null");
+    long long ov = (long long)nocc * nvir;
+    if (ov > 0x7fffffffLL || (long long)naux * (nocc + nvir) > 0x7fffffffLL)
+        return gwm::set_err(h, GW_EINVAL, "problem too large for 32-bit K dimensions");
+    // energies: finite, occupied strictly below virtual
+    std::vector<double> e(nocc + nvir);
+    if (hipMemcpyAsync(e.data(), eps, sizeof(double) * e.size(), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+        return gwm::set_err(h, GW_EINVAL, "eps is not a readable device pointer");
+    double omax = -INFINITY, vmin = INFINITY;
+    for (int p = 0; p < nocc + nvir; ++p) {
+        if (!std::isfinite(e[p])) return gwm::set_err(h, GW_EINVAL, "eps contains a non-finite value");
+        if (p < nocc) omax = std::fmax(omax, e[p]);
+        else vmin = std::fmin(vmin, e[p]);
+    }
+    if (!(omax < vmin)) return gwm::set_err(h, GW_EINVAL, "every occupied energy must lie below every virtual one");
+    return GW_OK;
+}
+
+gw_status check_opts(Handle* h, gw_precision prec, const gw_opts* o) {
+    if (prec != GW_FP64 && prec != GW_MIXED) return gwm::set_err(h, GW_EINVAL, "unknown precision");
+    if (o) {
+        if (o->nquad < 0 || o->nquad == 1 || o->nquad > 512)
+            return gwm::set_err(h, GW_EINVAL, "nquad must be 0 (default) or in [2, 512]");
+        if (!(o->quad_scale >= 0.0) || !std::isfinite(o->quad_scale))
+            return gwm::set_err(h, GW_EINVAL, "quad_scale must be finite and >= 0");
+        if (o->bf16_slices != 0 && o->bf16_slices != 2 && o->bf16_slices != 3)
+            return gwm::set_err(h, GW_EINVAL, "bf16_slices must be 0, 2 or 3");
+    }
+    return GW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gw_status gw_create(gw_handle* out, int device) {
+    if (!out) return GW_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        g_static_err = "gw_create: no such HIP device";
+        return GW_EINVAL;
+    }
+    gw_handle h = new (std::nothrow) gw_handle_s();
+    if (!h) return GW_ENOMEM;
+    h->device = device;
+    h->ws.resize(gwm::WS_COUNT);
+    if (hipSetDevice(device) != hipSuccess ||
+        hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking) != hipSuccess) {
+        g_static_err = "gw_create: stream creation failed";
+        delete h;
+        return GW_EHIP;
+    }
+    h->stream = h->own_stream;
+    if (rocblas_create_handle(&h->blas) != rocblas_status_success) {
+        g_static_err = "gw_create: rocblas_create_handle failed";
+        (void)hipStreamDestroy(h->own_stream);
+        delete h;
+        return GW_ELIB;
+    }
+    rocblas_set_stream(h->blas, h->stream);
+    *out = h;
+    return GW_OK;
+}
+
+gw_status gw_set_stream(gw_handle h, void* s) {
+    if (!h) return GW_EINVAL;
+    h->stream = s ? (hipStream_t)s : h->own_stream;
+    rocblas_set_stream(h->blas, h->stream);
+    return GW_OK;
+}
+
+gw_status gw_synchronize(gw_handle h) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipStreamSynchronize(h->stream));
+    return GW_OK;
+}
+
+gw_status gw_timing_enable(gw_handle h, int enable) {
+    if (!h) return GW_EINVAL;
+    h->timing = enable != 0;
+    return GW_OK;
+}
+
+gw_status gw_timing_reset(gw_handle h) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipStreamSynchronize(h->stream));
+    gwm::clear_timed(h);
+    return GW_OK;
+}
+
+gw_status gw_timing_read(gw_handle h, const char* family, double* total_ms, long* launches) {
+    if (!h || !family || !total_ms || !launches) return GW_EINVAL;
+    GW_HIP(h, hipStreamSynchronize(h->stream));
+    double tot = 0.0;
+    long n = 0;
+    for (auto& t : h->timed) {
+        if (t.family != family) continue;
+        float ms = 0.0f;
+        GW_HIP(h, hipEventElapsedTime(&ms, t.start, t.stop));
+        tot += ms;
+        ++n;
+    }
+    *total_ms = tot;
+    *launches = n;
+    return GW_OK;
+}
+
+gw_status gw_destroy(gw_handle h) {
+    if (!h) return GW_OK;
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipStreamSynchronize(h->own_stream);
+    gwm::clear_timed(h);
+    for (auto& b : h->ws)
+        if (b.ptr) (void)hipFree(b.ptr);
+    if (h->blas) rocblas_destroy_handle(h->blas);
+    if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
+    delete h;
+    return GW_OK;
+}
+
+const char* gw_last_error(gw_handle h) {
+    if (!h) return g_static_err.c_str();
+    return h->last_error.c_str();
+}
+
+gw_status gw_moments_tda(gw_handle h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                         const double* L, gw_precision prec, const gw_opts* opts, double* R, double* eta) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    GW_TRY(validate_common(h, nocc, nvir, naux, nmom_max, eps, L));
+    GW_TRY(check_opts(h, prec, opts));
+    if (!R) return gwm::set_err(h, GW_EINVAL, "R must be non-null");
+    if (prec == GW_MIXED) return gwm::set_err(h, GW_EINVAL, "mixed precision moments: not available yet");
+    return gwm::tda_moments_f64(h, nocc, nvir, naux, nmom_max, eps, L, R, eta);
+}
+
+gw_status gw_moments_rpa(gw_handle h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                         const double* L, gw_precision prec, const gw_opts* opts, double* R, double* eta) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    GW_TRY(validate_common(h, nocc, nvir, naux, nmom_max, eps, L));
+    GW_TRY(check_opts(h, prec, opts));
+    if (!R) return gwm::set_err(h, GW_EINVAL, "R must be non-null");
+    if (prec == GW_MIXED) return gwm::set_err(h, GW_EINVAL, "mixed precision moments: not available yet");
+    return gwm::rpa_moments_f64(h, nocc, nvir, naux, nmom_max, eps, L, opts, R, eta);
+}
+
+gw_status gw_sigma_from_R(gw_handle h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                          const double* L, const double* R, gw_precision prec, const gw_opts* opts,
+                          double* sigma_occ, double* sigma_vir) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    GW_TRY(validate_common(h, nocc, nvir, naux, nmom_max, eps, L));
+    GW_TRY(check_opts(h, prec, opts));
+    if (!R || !sigma_occ || !sigma_vir) return gwm::set_err(h, GW_EINVAL, "R and sigma outputs must be non-null");
+    if (prec == GW_MIXED) return gwm::set_err(h, GW_EINVAL, "mixed precision sigma: not available yet");
+    return gwm::sigma_from_R_f64(h, nocc, nvir, naux, nmom_max, eps, L, R, opts, sigma_occ, sigma_vir);
+}
+
+gw_status gw_sigma_moments(gw_handle h, gw_screening screening, int nocc, int nvir, int naux, int nmom_max,
+                           const double* eps, const double* L, gw_precision prec, const gw_opts* opts,
+                           double* sigma_occ, double* sigma_vir) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    GW_TRY(validate_common(h, nocc, nvir, naux, nmom_max, eps, L));
+    GW_TRY(check_opts(h, prec, opts));
+    if (screening != GW_TDA && screening != GW_RPA) return gwm::set_err(h, GW_EINVAL, "unknown screening");
+    if (!sigma_occ || !sigma_vir) return gwm::set_err(h, GW_EINVAL, "sigma outputs must be non-null");
+    if (prec == GW_MIXED) return gwm::set_err(h, GW_EINVAL, "mixed precision sigma: not available yet");
+    const long n2 = (long)naux * naux;
+    double* R = (double*)gwm::ws_get(h, gwm::WS_R, sizeof(double) * (nmom_max + 1) * n2);
+    if (!R) return GW_ENOMEM;
+    if (screening == GW_TDA)
+        GW_TRY(gwm::tda_moments_f64(h, nocc, nvir, naux, nmom_max, eps, L, R, nullptr));
+    else
+        GW_TRY(gwm::rpa_moments_f64(h, nocc, nvir, naux, nmom_max, eps, L, opts, R, nullptr));
+    return gwm::sigma_from_R_f64(h, nocc, nvir, naux, nmom_max, eps, L, R, opts, sigma_occ, sigma_vir);
+}
+
+gw_status gw_poles(gw_handle h, int nmo, int nmom_max, const double* sigma_occ, const double* sigma_vir,
+                   const double* fock, const gw_opts* opts, int* npole_occ, int* npole_vir, double* pole_e,
+                   double* pole_v, double* E, double* chi, double* qp_e, double* qp_w) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    if (nmo < 1) return gwm::set_err(h, GW_EINVAL, "nmo must be >= 1");
+    if (nmom_max < 1 || nmom_max % 2 == 0 || nmom_max > 15)
+        return gwm::set_err(h, GW_EINVAL, "nmom_max must be odd and in [1, 15]");
+    if (!sigma_occ || !sigma_vir || !fock || !npole_occ || !npole_vir || !pole_e || !pole_v || !E || !qp_e || !qp_w)
+        return gwm::set_err(h, GW_EINVAL, "gw_poles: a required pointer is null");
+    return gwm::poles_f64(h, nmo, nmom_max, sigma_occ, sigma_vir, fock, opts, npole_occ, npole_vir, pole_e,
+                          pole_v, E, chi, qp_e, qp_w);
+}
+
+}  // extern "C"

@@ -1,0 +1,172 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gwmom.h"
+
+namespace gwm {
+
+// ---------------------------------------------------------------------------
+// Handle and workspace
+// ---------------------------------------------------------------------------
+
+// A grow-only device buffer owned by the handle.
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct TimedLaunch {
+    std::string family;
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
+struct Handle {
+    bool timing = false;
+    std::vector<TimedLaunch> timed;
+    int device = 0;
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+    rocblas_handle blas = nullptr;
+    std::string last_error;
+    // named workspaces (see WS_* below)
+    std::vector<DevBuf> ws;
+    hipEvent_t ev = nullptr;
+};
+
+enum WsSlot {
+    WS_V = 0, WS_D, WS_X0, WS_X1, WS_X2, WS_X3, WS_R, WS_SPLIT, WS_Z, WS_SIGACC,
+    WS_RPA_SCALE, WS_RPA_QT, WS_RPA_S, WS_RPA_G, WS_RPA_INFO, WS_MISC,
+    WS_LZ0, WS_LZ1, WS_LZ2, WS_LZ3, WS_LZ4, WS_LZ5, WS_LZ6,
+    WS_MIX0, WS_MIX1, WS_MIX2, WS_MIX3, WS_MIX4, WS_MIX5,
+    WS_COUNT
+};
+
+// Returns nullptr on failure (and records the message).
+void* ws_get(Handle* h, int slot, size_t bytes);
+
+// Error plumbing: every internal routine returns gw_status.
+gw_status set_err(Handle* h, gw_status st, const std::string& msg);
+
+#define GW_HIP(h, call)                                                         \
+    do {                                                                        \
+        hipError_t e_ = (call);                                                 \
+        if (e_ != hipSuccess)                                                   \
+            return ::gwm::set_err((h), GW_EHIP,                                 \
+                                  std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+#define GW_CHECK_LAUNCH(h) GW_HIP(h, hipGetLastError())
+
+#define GW_TRY(expr)                     \
+    do {                                 \
+        gw_status s_ = (expr);           \
+        if (s_ != GW_OK) return s_;      \
+    } while (0)
+
+// Brackets one launch with events when timing is enabled on the handle.
+struct KTimer {
+    Handle* h;
+    int idx = -1;
+    KTimer(Handle* hh, const char* family);
+    void stop();
+};
+
+// ---------------------------------------------------------------------------
+// FP64 MFMA GEMM (gemm_f64.hip)
+// ---------------------------------------------------------------------------
+//
+// C(m, n) = sum_k A(m, k) B(k, n) over a batch, with optional split-K.
+//
+// Operand A:
+//   a_kc = true :  A(m,k) = A[m*lda + k]                           (k contiguous)
+//   a_kc = false:  A(m,k) = A[a_off + (k/a_kdiv)*a_khi + (k%a_kdiv)*a_klo + m]
+//   ascale (a_kc only, nullable): A(m,k) *= ascale[batch*ascale_bs + k]
+// Operand B:
+//   b_kc = true :  B(k,n) = B[n*ldb + k]
+//   b_kc = false:  B(k,n) = B[b_off + (k/b_kdiv)*b_khi + (k%b_kdiv)*b_klo + n]
+//   bscale (b_kc false only, nullable): B(k,n) *= bscale[(k/b_kdiv)*bscale_ld + n]
+// Batch b adds a_bs*b, b_bs*b, c_bs*b to the A, B, C base pointers.
+// Split s of nsplit covers k in [s*kchunk, min(K, (s+1)*kchunk)).
+// sym_upper: only 128x128 tiles with tile_row <= tile_col are computed (M == N).
+// Epilogues:
+//   EPI_PARTIAL: C[(b*nsplit + s)*c_ps + m*ldc + n]  = acc      (or += when accumulate)
+//   EPI_AXPBY  : C[b*c_bs + m*ldc + n] = cs[n] * (alpha*acc + X[b*x_bs + m*ldx + n] * dg[n])
+//                (cs, X, dg nullable: 1, 0, 1)
+enum GemmEpi { EPI_PARTIAL = 0, EPI_AXPBY = 1 };
+
+struct GemmF64 {
+    int M = 0, N = 0, K = 0;
+    int batch = 1;
+    bool a_kc = true, b_kc = true;
+    const double* A = nullptr; long lda = 0; long a_off = 0, a_kdiv = 1L << 62, a_khi = 0, a_klo = 0;
+    const double* ascale = nullptr; long ascale_bs = 0;
+    const double* B = nullptr; long ldb = 0; long b_off = 0, b_kdiv = 1L << 62, b_khi = 0, b_klo = 0;
+    const double* bscale = nullptr; long bscale_ld = 0;
+    long a_bs = 0, b_bs = 0, c_bs = 0;
+    int nsplit = 1; int kchunk = 0;
+    bool sym_upper = false;
+    int epi = EPI_PARTIAL;
+    bool accumulate = false;
+    double* C = nullptr; long ldc = 0; long c_ps = 0;
+    double alpha = 1.0;
+    const double* X = nullptr; long ldx = 0; long x_bs = 0;
+    const double* dg = nullptr;
+    const double* cs = nullptr;
+    const char* tag = nullptr;  // timing family (nullable)
+};
+
+gw_status gemm_f64(Handle* h, const GemmF64& g);
+
+// Choose nsplit / kchunk so that the launch has at least `target_wg` groups.
+void plan_split(GemmF64& g, int target_wg);
+
+// out[b][m][n] = alpha * sum_s part[(b*nsplit+s)*ps + m*ld + n] (+ diag on m == n),
+// read from the upper triangle (m <= n) when `mirror`, which makes out exactly symmetric.
+gw_status reduce_splits(Handle* h, const double* part, int nsplit, long ps, int batch,
+                        int M, int N, long ld, bool mirror, double alpha, double diag,
+                        double* out, long out_bs, long ldo);
+
+// ---------------------------------------------------------------------------
+// Moment / sigma building blocks (moments.hip, sigma.hip)
+// ---------------------------------------------------------------------------
+
+// V[P][i*nvir+a] = L[P][i][nocc+a];  D[i*nvir+a] = eps[nocc+a] - eps[i].
+gw_status gather_ov(Handle* h, int nocc, int nvir, int naux, const double* eps,
+                    const double* L, double* V, double* D);
+
+// Stage 1 of the self-energy contraction for columns j in [j0, j1) of L viewed
+// as [naux][nmo*nmo] (j = x*nmo + q, with x whole rows so j0, j1 are multiples
+// of nmo):  Zt[n][P][j-j0] = sum_{t<=n} s_{n,t}(x) sum_Q R_t[P][Q] L[Q][j],
+// s_{n,t}(x) = 2 C(n,t) sigma_x^t eps_x^{n-t}, sigma_x = -1 (x < nocc) or +1.
+gw_status sigma_fold_f64(Handle* h, int nt, int naux, int nmo, int nocc, const double* eps,
+                         const double* R, const double* L, int x0, int x1, double* Zt);
+
+gw_status sigma_from_R_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max,
+                           const double* eps, const double* L, const double* R,
+                           const gw_opts* opts, double* sigma_occ, double* sigma_vir);
+
+gw_status tda_moments_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max,
+                          const double* eps, const double* L, double* R, double* eta);
+
+gw_status rpa_moments_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max,
+                          const double* eps, const double* L, const gw_opts* opts,
+                          double* R, double* eta);
+
+gw_status poles_f64(Handle* h, int nmo, int nmom_max, const double* sigma_occ,
+                    const double* sigma_vir, const double* fock, const gw_opts* opts,
+                    int* npole_occ, int* npole_vir, double* pole_e, double* pole_v,
+                    double* E, double* chi, double* qp_e, double* qp_w);
+
+// Elementwise helpers (moments.hip)
+gw_status fill_f64(Handle* h, double* p, size_t n, double v);
+gw_status copy_f64(Handle* h, double* dst, const double* src, size_t n);
+
+}  // namespace gwm

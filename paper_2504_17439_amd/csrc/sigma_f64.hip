@@ -1,0 +1,224 @@
+// Self-energy moments from the aux-space cores R_t (FP64 path).
+//
+// eqs. convolution_occ / convolution_vir with eq. w_moments:
+//   Sigma^{(n)}_pq = sum_x sum_{t<=n} s_{n,t}(x) sum_PQ L[P,p,x] R_t[P,Q] L[Q,q,x]
+//   s_{n,t}(x) = 2 C(n,t) (-1)^t eps_x^{n-t}  (x occupied: hole moments)
+//              = 2 C(n,t)        eps_x^{n-t}  (x virtual:  particle moments)
+//
+// Stage 1 (sigma_fold_kernel): Zt^{(n)}[P,x,q] = sum_t s_{n,t}(x) (R_t L)[P,x,q]
+//   -- all t for one (P-block, column-block) tile stay in registers, and the
+//   binomial / eps-power fold happens in the epilogue, so the per-t products
+//   never reach HBM.  L symmetric in (p,q) means L[Q,q,x] = L[Q,x,q], so the
+//   column index j = x*nmo + q walks L's rows contiguously.
+// Stage 2 (gemm_f64): Sigma^{(n)}[p,q] += sum_{P, x in sector} L[P,x,p] Zt^{(n)}[P,x,q],
+//   upper 128x128 tiles only, split-K partials accumulated over x chunks,
+//   then one reduction that mirrors the upper triangle (exactly symmetric).
+#include "internal.h"
+
+#include <algorithm>
+
+namespace gwm {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int FBP = 16;   // P rows per tile
+constexpr int FBN = 64;   // columns per tile (4 waves x 16)
+constexpr int FBK = 16;   // Q slab
+constexpr int FTHR = 256;
+
+constexpr double binom2(int n, int k) {
+    // 2 * C(n, k), exact in double for n < 64
+    double c = 1.0;
+    for (int i = 1; i <= k; ++i) c = c * (n - k + i) / i;
+    return 2.0 * c;
+}
+
+template <int NT>
+__global__ __launch_bounds__(FTHR, 2) void sigma_fold_kernel(const double* __restrict__ R,
+                                                              const double* __restrict__ L,
+                                                              const double* __restrict__ eps, int naux,
+                                                              int nmo, int nocc, long j0, long ncol,
+                                                              double* __restrict__ Zt) {
+    __shared__ double Ra[2][NT][FBK][FBP];
+    __shared__ double Lb[2][FBK][FBN + 2];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int lrow = lane & 15;
+    const int lk = lane >> 4;
+    const long c0 = (long)blockIdx.x * FBN;
+    const int P0 = blockIdx.y * FBP;
+    const long nmo2 = (long)nmo * nmo;
+
+    double rr[NT];
+    double rl[4];
+
+    auto load = [&](int q0) {
+        {
+            int k = tid & 15, p = tid >> 4;
+            int P = P0 + p, Q = q0 + k;
+            bool ok = (P < naux) && (Q < naux);
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                rr[t] = ok ? R[((long)t * naux + P) * naux + Q] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            int idx = e * FTHR + tid;
+            int c = idx & (FBN - 1), k = idx >> 6;
+            int Q = q0 + k;
+            long cc = c0 + c;
+            rl[e] = (Q < naux && cc < ncol) ? L[(long)Q * nmo2 + j0 + cc] : 0.0;
+        }
+    };
+    auto store = [&](int buf) {
+        int k = tid & 15, p = tid >> 4;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) Ra[buf][t][k][p] = rr[t];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            int idx = e * FTHR + tid;
+            Lb[buf][idx >> 6][idx & (FBN - 1)] = rl[e];
+        }
+    };
+
+    v4d acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+    const int nkt = (naux + FBK - 1) / FBK;
+    load(0);
+    store(0);
+    __syncthreads();
+    int cur = 0;
+    for (int kt = 0; kt < nkt; ++kt) {
+        bool more = kt + 1 < nkt;
+        if (more) load((kt + 1) * FBK);
+#pragma unroll
+        for (int k4 = 0; k4 < FBK / 4; ++k4) {
+            double b = Lb[cur][k4 * 4 + lk][wave * 16 + lrow];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                double a = Ra[cur][t][k4 * 4 + lk][lrow];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+            }
+        }
+        if (more) store(cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
+    }
+
+    // epilogue: binomial / eps-power fold, lane owns column c and rows lk + 4r
+    const long c = c0 + wave * 16 + lrow;
+    if (c >= ncol) return;
+    const long j = j0 + c;
+    const int x = (int)(j / nmo);
+    const double ex = eps[x];
+    const bool occ = x < nocc;
+    double pw[NT];
+    pw[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k < NT; ++k) pw[k] = pw[k - 1] * ex;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        int P = P0 + lk + 4 * r;
+        if (P >= naux) continue;
+        double a[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) a[t] = (occ && (t & 1)) ? -acc[t][r] : acc[t][r];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            double z = 0.0;
+#pragma unroll
+            for (int t = 0; t <= n; ++t) z += binom2(n, t) * pw[n - t] * a[t];
+            Zt[((long)n * naux + P) * ncol + c] = z;
+        }
+    }
+}
+
+template <int NT>
+void launch_fold(Handle* h, int naux, int nmo, int nocc, const double* eps, const double* R,
+                 const double* L, long j0, long ncol, double* Zt) {
+    dim3 grid((unsigned)((ncol + FBN - 1) / FBN), (unsigned)((naux + FBP - 1) / FBP));
+    hipLaunchKernelGGL((sigma_fold_kernel<NT>), grid, dim3(FTHR), 0, h->stream, R, L, eps, naux, nmo,
+                       nocc, j0, ncol, Zt);
+}
+
+}  // namespace
+
+gw_status sigma_fold_f64(Handle* h, int nt, int naux, int nmo, int nocc, const double* eps,
+                         const double* R, const double* L, int x0, int x1, double* Zt) {
+    long j0 = (long)x0 * nmo, ncol = (long)(x1 - x0) * nmo;
+    if (ncol <= 0) return GW_OK;
+    if ((ncol + FBN - 1) / FBN > 0x7fffffffL || (naux + FBP - 1) / FBP > 65535)
+        return set_err(h, GW_EINVAL, "sigma_fold: grid too large");
+    KTimer timer(h, "sigma_fold");
+    switch (nt) {
+        case 2: launch_fold<2>(h, naux, nmo, nocc, eps, R, L, j0, ncol, Zt); break;
+        case 4: launch_fold<4>(h, naux, nmo, nocc, eps, R, L, j0, ncol, Zt); break;
+        case 6: launch_fold<6>(h, naux, nmo, nocc, eps, R, L, j0, ncol, Zt); break;
+        case 8: launch_fold<8>(h, naux, nmo, nocc, eps, R, L, j0, ncol, Zt); break;
+        case 10: launch_fold<10>(h, naux, nmo, nocc, eps, R, L, j0, ncol, Zt); break;
+        case 12: launch_fold<12>(h, naux, nmo, nocc, eps, R, L, j0, ncol, Zt); break;
+        case 14: launch_fold<14>(h, naux, nmo, nocc, eps, R, L, j0, ncol, Zt); break;
+        case 16: launch_fold<16>(h, naux, nmo, nocc, eps, R, L, j0, ncol, Zt); break;
+        default: return set_err(h, GW_EINVAL, "sigma_fold: nmom_max+1 must be even and <= 16");
+    }
+    timer.stop();
+    GW_CHECK_LAUNCH(h);
+    return GW_OK;
+}
+
+gw_status sigma_from_R_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                           const double* L, const double* R, const gw_opts* opts, double* sigma_occ,
+                           double* sigma_vir) {
+    const int nmo = nocc + nvir;
+    const int nt = nmom_max + 1;
+    const long nmo2 = (long)nmo * nmo;
+    size_t cap = (opts && opts->zchunk_bytes) ? opts->zchunk_bytes : ((size_t)8 << 30);
+    size_t per_x = (size_t)nt * naux * nmo * sizeof(double);
+    int nx = (int)std::max<size_t>(1, std::min<size_t>((size_t)nmo, cap / per_x));
+    double* Zt = (double*)ws_get(h, WS_Z, per_x * nx);
+    if (!Zt) return GW_ENOMEM;
+
+    const int T = (nmo + 127) / 128;
+    const int tiles = T * (T + 1) / 2;
+    int S = std::max(1, std::min(64, (1024 + tiles * nt - 1) / (tiles * nt)));
+    const long part_per_sector = (long)nt * S * nmo2;
+    double* acc = (double*)ws_get(h, WS_SIGACC, sizeof(double) * 2 * part_per_sector);
+    if (!acc) return GW_ENOMEM;
+    GW_TRY(fill_f64(h, acc, (size_t)2 * part_per_sector, 0.0));
+
+    for (int x0 = 0; x0 < nmo; x0 += nx) {
+        int x1 = std::min(nmo, x0 + nx);
+        long ncol = (long)(x1 - x0) * nmo;
+        GW_TRY(sigma_fold_f64(h, nt, naux, nmo, nocc, eps, R, L, x0, x1, Zt));
+        for (int sector = 0; sector < 2; ++sector) {
+            int lo = sector == 0 ? 0 : nocc, hi = sector == 0 ? nocc : nmo;
+            int xs0 = std::max(x0, lo), xs1 = std::min(x1, hi);
+            if (xs1 <= xs0) continue;
+            int nxs = xs1 - xs0;
+            GemmF64 g;
+            g.M = nmo; g.N = nmo; g.K = naux * nxs; g.batch = nt;
+            g.a_kc = false; g.A = L; g.a_off = (long)xs0 * nmo; g.a_kdiv = nxs; g.a_khi = nmo2; g.a_klo = nmo;
+            g.b_kc = false; g.B = Zt; g.b_off = (long)(xs0 - x0) * nmo; g.b_kdiv = nxs; g.b_khi = ncol;
+            g.b_klo = nmo; g.b_bs = (long)naux * ncol;
+            g.sym_upper = true;
+            g.epi = EPI_PARTIAL; g.accumulate = true;
+            g.nsplit = S;
+            g.kchunk = ((g.K + S - 1) / S + 15) / 16 * 16;
+            g.C = acc + sector * part_per_sector; g.ldc = nmo; g.c_ps = nmo2;
+            g.tag = "sigma_contract";
+            GW_TRY(gemm_f64(h, g));
+        }
+    }
+    GW_TRY(reduce_splits(h, acc, S, nmo2, nt, nmo, nmo, nmo, true, 1.0, 0.0, sigma_occ, nmo2, nmo));
+    GW_TRY(reduce_splits(h, acc + part_per_sector, S, nmo2, nt, nmo, nmo, nmo, true, 1.0, 0.0, sigma_vir,
+                         nmo2, nmo));
+    return GW_OK;
+}
+
+}  // namespace gwm

@@ -1,0 +1,215 @@
+"""Thin ctypes binding of libgwmom.so (C ABI in include/gwmom.h).
+
+Argument marshalling only: every step of the computation runs in the
+library's HIP kernels.  PyTorch supplies device memory and the stream; the
+binding allocates output tensors and passes raw device pointers.  If the
+library is not built, or no HIP device is visible, construction fails
+loudly -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgwmom.so")
+
+GW_OK, GW_EINVAL, GW_ENOMEM, GW_EHIP, GW_ENUMERIC, GW_ENOCONV, GW_ELIB = 0, -1, -2, -3, -4, -5, -6
+GW_FP64, GW_MIXED = 0, 1
+GW_TDA, GW_RPA = 0, 1
+
+_STATUS = {GW_EINVAL: "GW_EINVAL", GW_ENOMEM: "GW_ENOMEM", GW_EHIP: "GW_EHIP",
+           GW_ENUMERIC: "GW_ENUMERIC", GW_ENOCONV: "GW_ENOCONV", GW_ELIB: "GW_ELIB"}
+
+# every symbol declared in include/gwmom.h
+EXPORTS = ("gw_create", "gw_set_stream", "gw_synchronize", "gw_destroy", "gw_last_error",
+           "gw_moments_tda", "gw_moments_rpa", "gw_sigma_moments", "gw_sigma_from_R", "gw_poles",
+           "gw_timing_enable", "gw_timing_reset", "gw_timing_read")
+
+
+class GWError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("nquad", ctypes.c_int), ("quad_scale", ctypes.c_double),
+                ("pinv_tol", ctypes.c_double), ("neg_tol", ctypes.c_double),
+                ("bf16_slices", ctypes.c_int), ("zchunk_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgwmom.so and declare its prototypes (no device needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run paper_2504_17439_amd.build first")
+    lib = ctypes.CDLL(path)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    H = ctypes.c_void_p
+    sig = {
+        "gw_create": ([ctypes.POINTER(H), I], I),
+        "gw_set_stream": ([H, P], I),
+        "gw_synchronize": ([H], I),
+        "gw_destroy": ([H], I),
+        "gw_last_error": ([H], ctypes.c_char_p),
+        "gw_moments_tda": ([H, I, I, I, I, P, P, I, P, P, P], I),
+        "gw_moments_rpa": ([H, I, I, I, I, P, P, I, P, P, P], I),
+        "gw_sigma_moments": ([H, I, I, I, I, I, P, P, I, P, P, P], I),
+        "gw_sigma_from_R": ([H, I, I, I, I, P, P, P, I, P, P, P], I),
+        "gw_poles": ([H, I, I, P, P, P, P, ctypes.POINTER(I), ctypes.POINTER(I), P, P, P, P, P, P], I),
+        "gw_timing_enable": ([H, I], I),
+        "gw_timing_reset": ([H], I),
+        "gw_timing_read": ([H, ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long)], I),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _opts(opts):
+    if opts is None:
+        return None
+    if isinstance(opts, Opts):
+        return ctypes.byref(opts)
+    o = Opts()
+    for k, v in dict(opts).items():
+        setattr(o, k, v)
+    return ctypes.byref(o)
+
+
+def _prec(p):
+    return {"fp64": GW_FP64, "mixed": GW_MIXED}[p] if isinstance(p, str) else int(p)
+
+
+def _check_dev(t, name, shape=None):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float64 device tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Handle:
+    """One library handle on one device, running on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the library has no CPU path")
+        self.device = device
+        h = ctypes.c_void_p()
+        st = self.lib.gw_create(ctypes.byref(h), device)
+        if st != GW_OK:
+            raise GWError(st, self.lib.gw_last_error(None).decode())
+        self.h = h
+        self._sync_stream()
+
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self.lib.gw_set_stream(self.h, ctypes.c_void_p(s))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.gw_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, name, *args):
+        self._sync_stream()
+        st = getattr(self.lib, name)(self.h, *args)
+        if st != GW_OK:
+            raise GWError(st, self.lib.gw_last_error(self.h).decode())
+
+    def _new(self, *shape):
+        return torch.empty(*shape, dtype=torch.float64, device=f"cuda:{self.device}")
+
+    # ------------------------------------------------------------------ timing
+    def timing(self, enable: bool):
+        self._call("gw_timing_enable", 1 if enable else 0)
+
+    def timing_reset(self):
+        self._call("gw_timing_reset")
+
+    def timing_read(self, family: str):
+        """(total_ms, launches) of one kernel family since the last reset."""
+        ms, n = ctypes.c_double(0.0), ctypes.c_long(0)
+        self._call("gw_timing_read", family.encode(), ctypes.byref(ms), ctypes.byref(n))
+        return ms.value, n.value
+
+    # ------------------------------------------------------------------ moments
+    def moments(self, eps, L, nocc, nmom_max, screening="tda", precision="fp64", eta=False, opts=None):
+        """R[nmom_max+1][naux][naux] (and eta~[nmom_max+1][naux][ov] if eta)."""
+        naux, nmo = L.shape[0], L.shape[1]
+        nvir = nmo - nocc
+        _check_dev(eps, "eps", (nmo,))
+        _check_dev(L, "L", (naux, nmo, nmo))
+        R = self._new(nmom_max + 1, naux, naux)
+        E = self._new(nmom_max + 1, naux, nocc * nvir) if eta else None
+        fn = "gw_moments_tda" if screening == "tda" else "gw_moments_rpa"
+        self._call(fn, nocc, nvir, naux, nmom_max, _ptr(eps), _ptr(L), _prec(precision), _opts(opts),
+                   _ptr(R), _ptr(E))
+        return (R, E) if eta else R
+
+    def sigma_moments(self, eps, L, nocc, nmom_max, screening="tda", precision="fp64", opts=None,
+                      out=None):
+        naux, nmo = L.shape[0], L.shape[1]
+        _check_dev(eps, "eps", (nmo,))
+        _check_dev(L, "L", (naux, nmo, nmo))
+        if out is None:
+            so, sv = self._new(nmom_max + 1, nmo, nmo), self._new(nmom_max + 1, nmo, nmo)
+        else:
+            so, sv = out
+        scr = GW_TDA if screening == "tda" else GW_RPA
+        self._call("gw_sigma_moments", scr, nocc, nmo - nocc, naux, nmom_max, _ptr(eps), _ptr(L),
+                   _prec(precision), _opts(opts), _ptr(so), _ptr(sv))
+        return so, sv
+
+    def sigma_from_R(self, eps, L, R, nocc, precision="fp64", opts=None):
+        naux, nmo = L.shape[0], L.shape[1]
+        nmom_max = R.shape[0] - 1
+        _check_dev(R, "R", (nmom_max + 1, naux, naux))
+        so, sv = self._new(nmom_max + 1, nmo, nmo), self._new(nmom_max + 1, nmo, nmo)
+        self._call("gw_sigma_from_R", nocc, nmo - nocc, naux, nmom_max, _ptr(eps), _ptr(L), _ptr(R),
+                   _prec(precision), _opts(opts), _ptr(so), _ptr(sv))
+        return so, sv
+
+    # ------------------------------------------------------------------ poles
+    def poles(self, sigma_occ, sigma_vir, fock, opts=None, want_chi=True):
+        nmom_max = sigma_occ.shape[0] - 1
+        nmo = sigma_occ.shape[1]
+        _check_dev(sigma_occ, "sigma_occ", (nmom_max + 1, nmo, nmo))
+        _check_dev(sigma_vir, "sigma_vir", (nmom_max + 1, nmo, nmo))
+        _check_dev(fock, "fock", (nmo, nmo))
+        cap = nmo * (nmom_max + 1) // 2
+        dim_max = nmo * (nmom_max + 2)
+        pe, pv = self._new(2 * cap), self._new(nmo, 2 * cap)
+        E = self._new(dim_max)
+        chi = self._new(nmo, dim_max) if want_chi else None
+        qe, qw = self._new(nmo), self._new(nmo)
+        no, nv = ctypes.c_int(0), ctypes.c_int(0)
+        self._call("gw_poles", nmo, nmom_max, _ptr(sigma_occ), _ptr(sigma_vir), _ptr(fock), _opts(opts),
+                   ctypes.byref(no), ctypes.byref(nv), _ptr(pe), _ptr(pv), _ptr(E), _ptr(chi), _ptr(qe),
+                   _ptr(qw))
+        no, nv = no.value, nv.value
+        dim = nmo + no + nv
+        return dict(e_occ=pe[:no], v_occ=pv[:, :no], e_vir=pe[no:no + nv], v_vir=pv[:, no:no + nv],
+                    E=E[:dim], chi=None if chi is None else chi[:, :dim], qp=qe, qp_weight=qw)

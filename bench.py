@@ -144,7 +144,12 @@ def main():
     # poles + upfolded eigensolve, once (not part of the metric)
     torch.cuda.synchronize()
     tp0 = time.perf_counter()
-    res = h.poles(so, sv, torch.diag(e).contiguous())
+    try:
+        res = h.poles(so, sv, torch.diag(e).contiguous())
+        qp = [float(res["qp"][o - 1]), float(res["qp"][o])]
+        poles_err = None
+    except gwmom.GWError as ex:
+        qp, poles_err = None, str(ex)
     torch.cuda.synchronize()
     tp1 = time.perf_counter()
 
@@ -169,7 +174,8 @@ def main():
         "useful_tflops": set_flops(o, v, A, N) * sets_per_s / 1e12,
         "kernel_ms_per_set": {k: ms / args.steps for k, (ms, n) in fams.items() if n},
         "poles_ms": 1e3 * (tp1 - tp0),
-        "homo_lumo_qp": [float(res["qp"][o - 1]), float(res["qp"][o])],
+        "homo_lumo_qp": qp,
+        "poles_error": poles_err,
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)

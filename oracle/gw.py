@@ -23,8 +23,9 @@ Readings of the paper taken here (each one is listed in the design notes):
   * the RPA zeroth-moment integrals use the mapped Gauss-Legendre grid of
     ``oracle.quadrature``;
   * the block Lanczos recursion conserves moments 0..nmom_max for odd
-    nmom_max with (nmom_max + 1) / 2 blocks per sector; pseudo-inverses
-    drop eigenvalues below pinv_tol times the largest.
+    nmom_max with (nmom_max + 1) / 2 blocks per sector; it runs on shifted
+    and scaled moments and deflates directions whose residual is below the
+    rounding level of the moment cancellations (see ``block_lanczos``).
 """
 from __future__ import annotations
 
@@ -154,7 +155,9 @@ def sigma_moments(eps: np.ndarray, L: np.ndarray, nocc: int, R):
     for t in range(nmom + 1):
         Y = np.tensordot(R[t], L, axes=(1, 0))        # Y[P,q,x] = sum_Q R_t[P,Q] L[Q,q,x]
         for x in range(nmo):
-            W = L[:, :, x].T @ Y[:, :, x]               # W^{(t)}_{px,qx}
+            Lx = np.ascontiguousarray(L[:, :, x])        # [P, p] at fixed x
+            Yx = np.ascontiguousarray(Y[:, :, x])        # [P, q] at fixed x
+            W = Lx.T @ Yx                                # W^{(t)}_{px,qx}
             for n in range(t, nmom + 1):
                 if x < nocc:
                     sig_occ[n] += 2.0 * comb(n, t) * (-1.0) ** t * eps[x] ** (n - t) * W
@@ -164,6 +167,29 @@ def sigma_moments(eps: np.ndarray, L: np.ndarray, nocc: int, R):
     sig_occ = 0.5 * (sig_occ + sig_occ.transpose(0, 2, 1))
     sig_vir = 0.5 * (sig_vir + sig_vir.transpose(0, 2, 1))
     return sig_occ, sig_vir, asym
+
+
+def sigma_moment_rows(eps: np.ndarray, L: np.ndarray, nocc: int, R, rows):
+    """Rows p in `rows` of Sigma^{(n,<)} and Sigma^{(n,>)} (unsymmetrised), by
+    the same definition as ``sigma_moments`` restricted to fixed p:
+    W^{(t)}_{px,qx} = sum_Q (sum_P L[P,p,x] R_t[P,Q]) L[Q,q,x].
+    For spot checks of large systems."""
+    nmom = len(R) - 1
+    nmo = eps.shape[0]
+    rows = list(rows)
+    so = np.zeros((nmom + 1, len(rows), nmo))
+    sv = np.zeros((nmom + 1, len(rows), nmo))
+    for t in range(nmom + 1):
+        for r, p in enumerate(rows):
+            U = np.ascontiguousarray(L[:, p, :]).T @ R[t]          # U[x, Q] = sum_P L[P,p,x] R_t[P,Q]
+            for x in range(nmo):
+                w = U[x] @ np.ascontiguousarray(L[:, :, x])       # W^{(t)}_{px,qx} over q
+                for n in range(t, nmom + 1):
+                    if x < nocc:
+                        so[n, r] += 2.0 * comb(n, t) * (-1.0) ** t * eps[x] ** (n - t) * w
+                    else:
+                        sv[n, r] += 2.0 * comb(n, t) * eps[x] ** (n - t) * w
+    return so, sv
 
 
 def gw_moments(eps, L, nocc, nmom_max, screening="tda", nquad=48, scale=None):
@@ -189,23 +215,38 @@ class LanczosError(RuntimeError):
     pass
 
 
-def _sym_sqrt_pinv(X: np.ndarray, pinv_tol: float, neg_tol: float, ref: float | None = None):
-    """Symmetric square root and pseudo-inverse square root of a PSD matrix.
-    With scale r = max(ref, largest |eigenvalue|), eigenvalues below
-    pinv_tol * r are dropped and any below -neg_tol * r mean the matrix is
-    not PSD and raise LanczosError."""
+EPS = np.finfo(float).eps
+
+
+def _sym_sqrt_pinv(X: np.ndarray, tol: float, neg: float):
+    """Symmetric square root and pseudo-inverse square root of a PSD matrix:
+    eigenvalues <= tol are dropped; any below -neg raises LanczosError."""
     X = 0.5 * (X + X.T)
     w, U = np.linalg.eigh(X)
-    wmax = max(float(np.abs(w).max()), float(ref or 0.0), np.finfo(float).tiny)
-    if w.min() < -neg_tol * wmax:
+    if w.min() < -neg:
         raise LanczosError("moment matrix is not positive semi-definite")
-    keep = w > pinv_tol * wmax
+    keep = w > tol
     Uk = U[:, keep]
     sw = np.sqrt(w[keep])
     return (Uk * sw) @ Uk.T, (Uk / sw) @ Uk.T
 
 
-def block_lanczos(T, pinv_tol: float = 1e-12, neg_tol: float = 1e-8):
+def shift_scale(T):
+    """Moments of the affinely mapped pole energies e' = (e - c) / s,
+    T'^{(n)} = s^-n sum_k C(n,k) (-c)^{n-k} T^{(k)}, with c the weighted mean
+    tr T1 / tr T0 and s the weighted spread sqrt(tr T2 / tr T0 - c^2).
+    Conserving T'^{(0..N)} is the same as conserving T^{(0..N)}; the map only
+    keeps the powers of the energy near unit size."""
+    t0 = np.trace(T[0])
+    c = np.trace(T[1]) / t0
+    s = np.sqrt(max(np.trace(T[2]) / t0 - c * c, 0.0)) if len(T) > 2 else 0.0
+    if not s > 0.0:
+        s = max(abs(c), 1.0)
+    Ts = [sum(comb(n, k) * (-c) ** (n - k) * T[k] for k in range(n + 1)) / s ** n for n in range(len(T))]
+    return Ts, c, s
+
+
+def block_lanczos(T, pinv_tol: float = 1e-12, neg_tol: float = 1e-8, kappa: float = 1.0):
     """Block tridiagonal representation that conserves the moments T[0..N].
 
     T[n] = v e^n v^T for some pole set (e, v).  With B0 = T[0]^{1/2} and the
@@ -219,26 +260,28 @@ def block_lanczos(T, pinv_tol: float = 1e-12, neg_tol: float = 1e-8):
       C_{j+1},k = B_j^+ Rhat_k
 
     For odd N = 2m+1 this runs to j = m+1 blocks and conserves moments 0..N.
-    Returns (A_blocks, B_blocks, B0)."""
+
+    Deflation: B_j^2 is a small difference of large terms once the
+    coefficients grow, so its eigenvalues are only known to about
+    noise_j = kappa * eps * (sum_k |Rhat_k|_F)^2 * max_{n<=2j} |S^{(n)}|_F.
+    Eigenvalues below max(pinv_tol |S^{(2)}|_F, noise_j) are dropped (those
+    directions have converged), and eigenvalues below
+    -max(neg_tol |S^{(2)}|_F, 10 noise_j) mean the input is not a moment
+    sequence (LanczosError).  T[0] itself is cut at pinv_tol times its largest
+    eigenvalue.  Returns (A_blocks, B_blocks, B0)."""
     N = len(T) - 1
     if N < 1 or N % 2 == 0:
         raise ValueError("nmom_max must be odd")
     m = (N - 1) // 2
     nmo = T[0].shape[0]
-    B0, B0i = _sym_sqrt_pinv(T[0], pinv_tol, neg_tol)
+    w0 = np.linalg.eigvalsh(0.5 * (T[0] + T[0].T))
+    wmax = max(float(np.abs(w0).max()), np.finfo(float).tiny)
+    B0, B0i = _sym_sqrt_pinv(T[0], pinv_tol * wmax, neg_tol * wmax)
     S = [B0i @ Tn @ B0i for Tn in T]
     S = [0.5 * (s + s.T) for s in S]
+    snorm = [float(np.linalg.norm(s)) for s in S]
+    ref = snorm[2] if N >= 2 else snorm[0]
     eye = np.eye(nmo)
-    # B_j^2 is a Gram matrix of residuals of the pole-energy operator, so its
-    # eigenvalues are bounded by those of S^{(2)}: the scale for its thresholds.
-    s2norm = float(np.abs(np.linalg.eigvalsh(S[2])).max()) if N >= 2 else 0.0
-
-    def inner(X, Y):
-        out = np.zeros((nmo, nmo))
-        for k, Xk in enumerate(X):
-            for l, Yl in enumerate(Y):
-                out += Xk @ S[k + l] @ Yl.T
-        return out
 
     A_blocks, B_blocks = [], []
     C_prev, C_cur, B_prev = None, [eye], None
@@ -261,7 +304,13 @@ def block_lanczos(T, pinv_tol: float = 1e-12, neg_tol: float = 1e-8):
             if C_prev is not None and k < j - 1:
                 r -= B_prev @ C_prev[k]
             Rh.append(r)
-        Bj, Bj_inv = _sym_sqrt_pinv(inner(Rh, Rh), pinv_tol, neg_tol, ref=s2norm)
+        B2 = np.zeros((nmo, nmo))
+        for k, Rk in enumerate(Rh):
+            for l, Rl in enumerate(Rh):
+                B2 += Rk @ S[k + l] @ Rl.T
+        rn = sum(float(np.linalg.norm(r)) for r in Rh)
+        noise = kappa * EPS * rn * rn * max(snorm[: 2 * j + 1])
+        Bj, Bj_inv = _sym_sqrt_pinv(B2, max(pinv_tol * ref, noise), max(neg_tol * ref, 10.0 * noise))
         B_blocks.append(Bj)
         C_prev, C_cur, B_prev = C_cur, [Bj_inv @ r for r in Rh], Bj
     return A_blocks, B_blocks, B0
@@ -282,13 +331,16 @@ def block_tridiagonal(A_blocks, B_blocks):
 def poles_from_moments(T, pinv_tol: float = 1e-12, neg_tol: float = 1e-8,
                        weight_tol: float = 1e-14):
     """Auxiliary poles (e[npole], v[nmo][npole]) whose moments v e^n v^T equal
-    T[n] for n <= N: diagonalise the block-tridiagonal Lanczos matrix
-    H_s = U diag(e) U^T and set v = B0 U[first block rows].  Poles whose
+    T[n] for n <= N: shift and scale the moments (``shift_scale``), diagonalise
+    the block-tridiagonal Lanczos matrix H_s = U diag(e') U^T, map back
+    e = c + s e' and set v = B0 U[first block rows].  Poles whose
     coupling norm is below weight_tol times the largest are dropped (they
     are decoupled directions left by pseudo-inverses)."""
-    A_blocks, B_blocks, B0 = block_lanczos(T, pinv_tol, neg_tol)
+    Ts, c, s = shift_scale([np.asarray(t) for t in T])
+    A_blocks, B_blocks, B0 = block_lanczos(Ts, pinv_tol, neg_tol)
     Hs = block_tridiagonal(A_blocks, B_blocks)
     e, U = np.linalg.eigh(Hs)
+    e = c + s * e
     nmo = T[0].shape[0]
     v = B0 @ U[:nmo, :]
     wt = (v * v).sum(axis=0)

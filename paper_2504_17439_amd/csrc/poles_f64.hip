@@ -2,15 +2,21 @@
 // (eq. effH and its block-Lanczos construction; eqs. ret_GF and
 // quasiparticle_energy_update), FP64 on the device.
 //
-// Per sector, with moments T[0..N] (N = 2m+1):
+// Per sector, with moments T[0..N] (N = 2m+1), first mapped to the moments of
+// e' = (e - c)/s (c = tr T1 / tr T0, s = weighted spread) so powers stay O(1):
 //   B0 = T[0]^{1/2} (pseudo-inverse B0^+ drops eigenvalues below pinv_tol*max),
 //   S[n] = B0^+ T[n] B0^+,  the block Hankel matrices H0 = [S[k+l]], H1 = [S[k+l+1]].
 //   Lanczos block j is kept as coefficients C_j = [C_j0 .. C_j,j-1] on Q1 e^k:
 //     A_j  = C_j H1 C_j^T
 //     Rhat = shift(C_j) - A_j C_j - B_{j-1} C_{j-1}
 //     B_j^2 = Rhat H0 Rhat^T,  B_j = (B_j^2)^{1/2},  C_{j+1} = B_j^+ Rhat
+//   B_j^2 is known only to noise_j = kappa eps (sum_k |Rhat_k|_F)^2 max_{n<=2j} |S[n]|_F
+//   (cancellation once the coefficients grow): eigenvalues below
+//   max(pinv_tol |S[2]|_F, noise_j) are deflated, below -max(neg_tol |S[2]|_F, 10 noise_j)
+//   the input is rejected as not a moment sequence.
 //   The block tridiagonal H_s (diagonal A_1..A_{m+1}, off-diagonal B_1..B_m)
-//   is diagonalised, H_s = U diag(e) U^T, and the poles couple as v = B0 U[first block].
+//   is diagonalised, H_s = U diag(e') U^T, e = c + s e', and the poles couple
+//   as v = B0 U[first block].
 // Dense products: rocBLAS dgemm; eigensolves: rocSOLVER dsyevd (both column-
 // major; row-major data is passed as its transpose where that matters).
 #include "internal.h"
@@ -160,6 +166,44 @@ __global__ void qp_kernel(int M, int dim, const double* __restrict__ Ut, const d
     }
 }
 
+// Ts[n][e] = sum_k coef[n][k] T[k][e]   (binomial shift / scale of moments)
+__global__ void shift_moments_kernel(int nt, long m2, const double* __restrict__ coef, const double* __restrict__ T,
+                                     double* __restrict__ Ts) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m2) return;
+    double t[16];
+    for (int k = 0; k < nt; ++k) t[k] = T[(long)k * m2 + i];
+    for (int n = 0; n < nt; ++n) {
+        double acc = 0.0;
+        for (int k = 0; k <= n; ++k) acc += coef[n * 16 + k] * t[k];
+        Ts[(long)n * m2 + i] = acc;
+    }
+}
+
+// out[k*rows + p] = sum_{c < w} X[p*ld + k*w + c]^2   (row sums of squares per column block)
+__global__ void block_rowsq_kernel(int rows, int w, int nb, long ld, const double* __restrict__ X,
+                                   double* __restrict__ out) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)rows * nb) return;
+    int k = (int)(i / rows), p = (int)(i % rows);
+    const double* x = X + (long)p * ld + (long)k * w;
+    double s = 0.0;
+    for (int c = 0; c < w; ++c) s += x[c] * x[c];
+    out[i] = s;
+}
+
+__global__ void diag_kernel(int n, int nm, const double* __restrict__ T, double* __restrict__ d) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)nm * n) return;
+    long b = i / n, p = i % n;
+    d[i] = T[b * (long)n * n + p * n + p];
+}
+
+__global__ void affine_kernel(long n, double c, double s, double* __restrict__ e) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) e[i] = c + s * e[i];
+}
+
 unsigned nblk(long n) { return (unsigned)((n + 255) / 256); }
 
 struct Eig {
@@ -181,8 +225,10 @@ gw_status syevd(Handle* h, int n, Eig& e, bool vectors) {
     return GW_OK;
 }
 
-// X (M x M, PSD) -> symmetric sqrt and pseudo-inverse sqrt. Scale r = max(ref, max|w|).
-gw_status sqrt_pinv(Handle* h, int M, const double* X, double pinv_tol, double neg_tol, double ref, double* Xs,
+// X (M x M, PSD) -> symmetric sqrt and pseudo-inverse sqrt.  With rel, the
+// cut and the negativity bound are tol * max|w| and neg * max|w|; otherwise
+// they are the absolute values tol and neg.
+gw_status sqrt_pinv(Handle* h, int M, const double* X, bool rel, double tol, double neg, double* Xs,
                     double* Xi, double* scratch /* 3 M^2 + 3M */, int* info) {
     double* A = scratch;
     double* Y = scratch + (long)M * M;
@@ -195,13 +241,14 @@ gw_status sqrt_pinv(Handle* h, int M, const double* X, double pinv_tol, double n
     std::vector<double> hw(M);
     GW_HIP(h, hipMemcpyAsync(hw.data(), w, sizeof(double) * M, hipMemcpyDeviceToHost, h->stream));
     GW_HIP(h, hipStreamSynchronize(h->stream));
-    double wmax = ref;
+    double wmax = 1e-300;
     for (double x : hw) wmax = std::max(wmax, std::fabs(x));
-    wmax = std::max(wmax, 1e-300);
-    if (hw[0] < -neg_tol * wmax) return set_err(h, GW_ENUMERIC, "moment matrix is not positive semi-definite");
+    const double cut = rel ? tol * wmax : tol;
+    const double negb = rel ? neg * wmax : neg;
+    if (hw[0] < -negb) return set_err(h, GW_ENUMERIC, "moment matrix is not positive semi-definite");
     std::vector<double> s1(M), s2(M);
     for (int i = 0; i < M; ++i) {
-        bool keep = hw[i] > pinv_tol * wmax;
+        bool keep = hw[i] > cut;
         s1[i] = keep ? std::sqrt(hw[i]) : 0.0;
         s2[i] = keep ? 1.0 / std::sqrt(hw[i]) : 0.0;
     }
@@ -227,8 +274,8 @@ gw_status symmetrize(Handle* h, int n, double* X) {
 }
 
 // One sector: packs kept poles at columns [col0, col0 + npole) of e_out / v_out.
-gw_status lanczos_sector(Handle* h, int M, int N, const double* T, double pinv_tol, double neg_tol, double* e_out,
-                         double* v_out, long ldv, int col0, int* npole) {
+gw_status lanczos_sector(Handle* h, int M, int N, const double* T_in, double pinv_tol, double neg_tol, double kappa,
+                         double* e_out, double* v_out, long ldv, int col0, int* npole) {
     const int m = (N - 1) / 2;
     const int nb = m + 1;
     const long M2 = (long)M * M;
@@ -241,7 +288,57 @@ gw_status lanczos_sector(Handle* h, int M, int N, const double* T, double pinv_t
     double* sm = (double*)ws_get(h, WS_LZ4, sizeof(double) * 8 * M2);
     double* Hs = (double*)ws_get(h, WS_LZ5, sizeof(double) * (dimH * dimH + 3 * dimH + (long)M * dimH + 16));
     int* info = (int*)ws_get(h, WS_RPA_INFO, sizeof(int) * 64);
-    if (!sc || !S || !Hk || !Cb || !sm || !Hs || !info) return GW_ENOMEM;
+    double* T = (double*)ws_get(h, WS_LZ7, sizeof(double) * (NT * M2 + 16L * 16 + (long)M * (NT + 2)));
+    if (!sc || !S || !Hk || !Cb || !sm || !Hs || !info || !T) return GW_ENOMEM;
+    double* dcoef = T + NT * M2;
+    double* rowsq = dcoef + 16 * 16;
+    // host helpers: Frobenius norms through row sums of squares
+    auto frob_blocks = [&](const double* X, int rows, int w, int nb, long ld, std::vector<double>& out) -> gw_status {
+        hipLaunchKernelGGL(block_rowsq_kernel, dim3(nblk((long)rows * nb)), dim3(256), 0, h->stream, rows, w, nb, ld, X,
+                           rowsq);
+        GW_CHECK_LAUNCH(h);
+        std::vector<double> hv((size_t)rows * nb);
+        GW_HIP(h, hipMemcpyAsync(hv.data(), rowsq, sizeof(double) * hv.size(), hipMemcpyDeviceToHost, h->stream));
+        GW_HIP(h, hipStreamSynchronize(h->stream));
+        out.assign(nb, 0.0);
+        for (int k = 0; k < nb; ++k) {
+            double acc = 0.0;
+            for (int p = 0; p < rows; ++p) acc += hv[(size_t)k * rows + p];
+            out[k] = std::sqrt(acc);
+        }
+        return GW_OK;
+    };
+    // shift / scale: c = tr T1 / tr T0, s = sqrt(tr T2 / tr T0 - c^2)
+    double c = 0.0, sc_ = 1.0;
+    {
+        hipLaunchKernelGGL(diag_kernel, dim3(nblk((long)M * std::min(NT, 3))), dim3(256), 0, h->stream, M,
+                           std::min(NT, 3), T_in, rowsq);
+        GW_CHECK_LAUNCH(h);
+        std::vector<double> hd((size_t)M * std::min(NT, 3));
+        GW_HIP(h, hipMemcpyAsync(hd.data(), rowsq, sizeof(double) * hd.size(), hipMemcpyDeviceToHost, h->stream));
+        GW_HIP(h, hipStreamSynchronize(h->stream));
+        double tr[3] = {0.0, 0.0, 0.0};
+        for (int b = 0; b < std::min(NT, 3); ++b)
+            for (int p = 0; p < M; ++p) tr[b] += hd[(size_t)b * M + p];
+        c = tr[1] / tr[0];
+        double var = NT > 2 ? tr[2] / tr[0] - c * c : 0.0;
+        sc_ = var > 0.0 ? std::sqrt(var) : std::max(std::fabs(c), 1.0);
+        if (!std::isfinite(c) || !std::isfinite(sc_))
+            return set_err(h, GW_ENUMERIC, "moments: trace of the zeroth moment is not positive");
+        std::vector<double> coef(16 * 16, 0.0);
+        for (int n = 0; n < NT; ++n) {
+            double binom = 1.0;
+            for (int k = 0; k <= n; ++k) {
+                // C(n,k) (-c)^{n-k} / s^n
+                coef[n * 16 + k] = binom * std::pow(-c, n - k) / std::pow(sc_, n);
+                binom = binom * (n - k) / (k + 1);
+            }
+        }
+        GW_HIP(h, hipMemcpyAsync(dcoef, coef.data(), sizeof(double) * 256, hipMemcpyHostToDevice, h->stream));
+        hipLaunchKernelGGL(shift_moments_kernel, dim3(nblk(M2)), dim3(256), 0, h->stream, NT, M2, dcoef, T_in, T);
+        GW_CHECK_LAUNCH(h);
+        GW_HIP(h, hipStreamSynchronize(h->stream));
+    }
     double* H0 = Hk;
     double* H1 = Hk + dimH * dimH;
     double* Cx[2] = {Cb, Cb + M * dimH};
@@ -256,24 +353,22 @@ gw_status lanczos_sector(Handle* h, int M, int N, const double* T, double pinv_t
     double* B2 = sm + 6 * M2;
 
     // B0 and its pseudo-inverse
-    GW_TRY(sqrt_pinv(h, M, T, pinv_tol, neg_tol, 0.0, B0, B0i, sc, info));
+    GW_TRY(sqrt_pinv(h, M, T, true, pinv_tol, neg_tol, B0, B0i, sc, info));
     // S[n] = B0^+ T[n] B0^+
     for (int n = 0; n < NT; ++n) {
         GW_TRY(gemm_rm(h, false, false, M, M, M, 1.0, T + n * M2, M, B0i, M, 0.0, B2, M));
         GW_TRY(gemm_rm(h, false, false, M, M, M, 1.0, B0i, M, B2, M, 0.0, S + n * M2, M));
         GW_TRY(symmetrize(h, M, S + n * M2));
     }
-    // threshold scale for B_j^2: spectral radius of S[2]
-    double s2norm = 0.0;
-    if (N >= 2) {
-        GW_TRY(copy_f64(h, sc, S + 2 * M2, (size_t)M2));
-        Eig e{sc, sc + 2 * M2, sc + 2 * M2 + M, info};
-        GW_TRY(syevd(h, M, e, false));
-        std::vector<double> hw(M);
-        GW_HIP(h, hipMemcpyAsync(hw.data(), e.w, sizeof(double) * M, hipMemcpyDeviceToHost, h->stream));
-        GW_HIP(h, hipStreamSynchronize(h->stream));
-        for (double x : hw) s2norm = std::max(s2norm, std::fabs(x));
+    // Frobenius norms of S[n]: the scale of the deflation thresholds
+    std::vector<double> snorm(NT, 0.0);
+    for (int n = 0; n < NT; ++n) {
+        std::vector<double> one;
+        GW_TRY(frob_blocks(S + n * M2, M, M, 1, M, one));
+        snorm[n] = one[0];
     }
+    const double ref = NT > 2 ? snorm[2] : snorm[0];
+    const double eps_m = 2.220446049250313e-16;
     hipLaunchKernelGGL(hankel_kernel, dim3(nblk(dimH * dimH)), dim3(256), 0, h->stream, M, nb, 0, S, H0);
     GW_CHECK_LAUNCH(h);
     hipLaunchKernelGGL(hankel_kernel, dim3(nblk(dimH * dimH)), dim3(256), 0, h->stream, M, nb, 1, S, H1);
@@ -313,7 +408,15 @@ gw_status lanczos_sector(Handle* h, int M, int N, const double* T, double pinv_t
         GW_TRY(gemm_rm(h, false, false, M, K1, K1, 1.0, Rh, (int)dimH, H0, (int)dimH, 0.0, tmp, (int)dimH));
         GW_TRY(gemm_rm(h, false, true, M, M, K1, 1.0, tmp, (int)dimH, Rh, (int)dimH, 0.0, B2, M));
         GW_TRY(symmetrize(h, M, B2));
-        GW_TRY(sqrt_pinv(h, M, B2, pinv_tol, neg_tol, s2norm, Bj, Bji, sc, info));
+        std::vector<double> rnorm;
+        GW_TRY(frob_blocks(Rh, M, M, j + 1, dimH, rnorm));
+        double rn = 0.0;
+        for (double x : rnorm) rn += x;
+        double smax = 0.0;
+        for (int n = 0; n <= std::min(2 * j, NT - 1); ++n) smax = std::max(smax, snorm[n]);
+        const double noise = kappa * eps_m * rn * rn * smax;
+        GW_TRY(sqrt_pinv(h, M, B2, false, std::max(pinv_tol * ref, noise), std::max(neg_tol * ref, 10.0 * noise), Bj,
+                         Bji, sc, info));
         hipLaunchKernelGGL(put_block_kernel, dim3(nblk(M2)), dim3(256), 0, h->stream, M, Bj, Hs, dimH, j - 1, j);
         GW_CHECK_LAUNCH(h);
         hipLaunchKernelGGL(put_block_kernel, dim3(nblk(M2)), dim3(256), 0, h->stream, M, Bj, Hs, dimH, j, j - 1);
@@ -332,6 +435,11 @@ gw_status lanczos_sector(Handle* h, int M, int N, const double* T, double pinv_t
     {
         Eig E{Hs, e, work, info};
         GW_TRY(syevd(h, (int)dimH, E, true));
+    }
+    {
+        // e = c + s e'
+        hipLaunchKernelGGL(affine_kernel, dim3(nblk(dimH)), dim3(256), 0, h->stream, dimH, c, sc_, e);
+        GW_CHECK_LAUNCH(h);
     }
     GW_TRY(gemm_rm(h, false, true, M, (int)dimH, M, 1.0, B0, M, Hs, (int)dimH, 0.0, vfull, (int)dimH));
     hipLaunchKernelGGL(colnorm2_kernel, dim3(nblk(dimH)), dim3(256), 0, h->stream, M, (int)dimH, vfull, wt);
@@ -365,13 +473,14 @@ gw_status poles_f64(Handle* h, int nmo, int nmom_max, const double* sigma_occ, c
                     double* pole_v, double* E, double* chi, double* qp_e, double* qp_w) {
     const double pinv_tol = (opts && opts->pinv_tol > 0) ? opts->pinv_tol : 1e-12;
     const double neg_tol = (opts && opts->neg_tol > 0) ? opts->neg_tol : 1e-8;
+    const double kappa = 1.0;
     const int M = nmo;
     const int cap = nmo * (nmom_max + 1) / 2;
     const long ldv = 2L * cap;
     GW_TRY(blas_ok(h, rocblas_set_stream(h->blas, h->stream), "rocblas_set_stream"));
     int no = 0, nv = 0;
-    GW_TRY(lanczos_sector(h, M, nmom_max, sigma_occ, pinv_tol, neg_tol, pole_e, pole_v, ldv, 0, &no));
-    GW_TRY(lanczos_sector(h, M, nmom_max, sigma_vir, pinv_tol, neg_tol, pole_e, pole_v, ldv, no, &nv));
+    GW_TRY(lanczos_sector(h, M, nmom_max, sigma_occ, pinv_tol, neg_tol, kappa, pole_e, pole_v, ldv, 0, &no));
+    GW_TRY(lanczos_sector(h, M, nmom_max, sigma_vir, pinv_tol, neg_tol, kappa, pole_e, pole_v, ldv, no, &nv));
     *npole_occ = no;
     *npole_vir = nv;
     const int np = no + nv;

@@ -1,0 +1,85 @@
+"""Full-size parity in the launch configuration the benchmark times
+(nocc=100, nvir=400, naux=1500, nmom_max=11, TDA, FP64): sampled rows of the
+self-energy moments against the oracle evaluated one row at a time, the
+invariants that hold at any size, and the poles / QP energies against the
+oracle's block Lanczos run on the same moments."""
+import numpy as np
+import pytest
+
+import gwsynth
+from oracle import gw as ogw
+
+pytestmark = pytest.mark.gpu
+
+O, V_, A, N = 100, 400, 1500, 11
+ROWS = [0, 57, 99, 100, 101, 250, 499]   # deepest hole, HOMO, LUMO, ..., highest virtual
+
+
+@pytest.fixture(scope="module")
+def c3():
+    import torch
+    from paper_2504_17439_amd import gwmom
+    print("\n[case] full-size TDA o=100 v=400 A=1500 N=11 seed=0", flush=True)
+    eps, L = gwsynth.system(O, V_, A, 0)
+    h = gwmom.Handle(0)
+    e = torch.from_numpy(eps).to("cuda:0")
+    l = torch.from_numpy(L).to("cuda:0")
+    so, sv = h.sigma_moments(e, l, O, N, "tda")
+    R = h.moments(e, l, O, N, "tda")
+    torch.cuda.synchronize()
+    out = dict(eps=eps, L=L, so=so.cpu().numpy(), sv=sv.cpu().numpy(), R=R.cpu().numpy(), h=h,
+               so_d=so, sv_d=sv, e_d=e)
+    yield out
+    h.close()
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def test_fullsize_R_matches_oracle_recursion(c3):
+    V, D = ogw.particle_hole(c3["eps"], c3["L"], O)
+    R_ref = ogw.w_core(ogw.tda_eta(V, D, N), V)
+    for n in range(N + 1):
+        assert rel(c3["R"][n], R_ref[n]) < 1e-10, n
+
+
+def test_fullsize_sigma_rows_match_oracle(c3):
+    R = list(c3["R"])          # checked against the oracle recursion above
+    ro, rv = ogw.sigma_moment_rows(c3["eps"], c3["L"], O, R, ROWS)
+    for n in range(N + 1):
+        so_rows = c3["so"][n][ROWS]
+        sv_rows = c3["sv"][n][ROWS]
+        assert np.abs(so_rows - ro[n]).max() < 1e-10 * np.abs(c3["so"][n]).max(), n
+        assert np.abs(sv_rows - rv[n]).max() < 1e-10 * np.abs(c3["sv"][n]).max(), n
+
+
+def test_fullsize_invariants(c3):
+    for T in (c3["so"], c3["sv"]):
+        for n in range(N + 1):
+            assert np.array_equal(T[n], T[n].T)
+        for n in (0, 2, 4):
+            w = np.linalg.eigvalsh(T[n])
+            assert w.min() > -1e-12 * w.max()
+
+
+def test_fullsize_poles_and_qp_match_oracle_lanczos(c3):
+    import torch
+    res = c3["h"].poles(c3["so_d"], c3["sv_d"], torch.diag(c3["e_d"]).contiguous())
+    torch.cuda.synchronize()
+    qp = res["qp"].cpu().numpy()
+    wt = res["qp_weight"].cpu().numpy()
+    eo, vo = ogw.poles_from_moments(list(c3["so"]))
+    ev, vv = ogw.poles_from_moments(list(c3["sv"]))
+    H = ogw.upfolded_hamiltonian(np.diag(c3["eps"]), eo, vo, ev, vv)
+    E, U = np.linalg.eigh(H)
+    qp_ref, wt_ref, _ = ogw.qp_assign(E, U[: O + V_])
+    front = slice(O - 5, O + 5)
+    assert np.abs(qp[front] - qp_ref[front]).max() < 1e-8
+    assert np.abs(wt[front] - wt_ref[front]).max() < 1e-7
+    # every conserved moment is reproduced by the device poles
+    for key, T in (("occ", c3["so"]), ("vir", c3["sv"])):
+        e = res["e_" + key].cpu().numpy()
+        v = res["v_" + key].cpu().numpy()
+        for n in range(N + 1):
+            assert rel((v * e[None, :] ** n) @ v.T, T[n]) < 1e-6, (key, n)

@@ -246,7 +246,8 @@ def shift_scale(T):
     return Ts, c, s
 
 
-def block_lanczos(T, pinv_tol: float = 1e-12, neg_tol: float = 1e-8, kappa: float = 1.0):
+def block_lanczos(T, pinv_tol: float = 1e-12, neg_tol: float = 1e-8, kappa: float = 1.0,
+                  moment_eps: float = EPS):
     """Block tridiagonal representation that conserves the moments T[0..N].
 
     T[n] = v e^n v^T for some pole set (e, v).  With B0 = T[0]^{1/2} and the
@@ -263,7 +264,9 @@ def block_lanczos(T, pinv_tol: float = 1e-12, neg_tol: float = 1e-8, kappa: floa
 
     Deflation: B_j^2 is a small difference of large terms once the
     coefficients grow, so its eigenvalues are only known to about
-    noise_j = kappa * eps * (sum_k |Rhat_k|_F)^2 * max_{n<=2j} |S^{(n)}|_F.
+    noise_j = kappa * eps_m * (sum_k |Rhat_k|_F)^2 * max_{n<=2j} |S^{(n)}|_F,
+    with eps_m the relative accuracy of the input moments (machine epsilon
+    for FP64 moments).
     Eigenvalues below max(pinv_tol |S^{(2)}|_F, noise_j) are dropped (those
     directions have converged), and eigenvalues below
     -max(neg_tol |S^{(2)}|_F, 10 noise_j) mean the input is not a moment
@@ -309,7 +312,7 @@ def block_lanczos(T, pinv_tol: float = 1e-12, neg_tol: float = 1e-8, kappa: floa
             for l, Rl in enumerate(Rh):
                 B2 += Rk @ S[k + l] @ Rl.T
         rn = sum(float(np.linalg.norm(r)) for r in Rh)
-        noise = kappa * EPS * rn * rn * max(snorm[: 2 * j + 1])
+        noise = kappa * moment_eps * rn * rn * max(snorm[: 2 * j + 1])
         Bj, Bj_inv = _sym_sqrt_pinv(B2, max(pinv_tol * ref, noise), max(neg_tol * ref, 10.0 * noise))
         B_blocks.append(Bj)
         C_prev, C_cur, B_prev = C_cur, [Bj_inv @ r for r in Rh], Bj
@@ -329,7 +332,7 @@ def block_tridiagonal(A_blocks, B_blocks):
 
 
 def poles_from_moments(T, pinv_tol: float = 1e-12, neg_tol: float = 1e-8,
-                       weight_tol: float = 1e-14):
+                       weight_tol: float = 1e-14, moment_eps: float = EPS):
     """Auxiliary poles (e[npole], v[nmo][npole]) whose moments v e^n v^T equal
     T[n] for n <= N: shift and scale the moments (``shift_scale``), diagonalise
     the block-tridiagonal Lanczos matrix H_s = U diag(e') U^T, map back
@@ -337,7 +340,7 @@ def poles_from_moments(T, pinv_tol: float = 1e-12, neg_tol: float = 1e-8,
     coupling norm is below weight_tol times the largest are dropped (they
     are decoupled directions left by pseudo-inverses)."""
     Ts, c, s = shift_scale([np.asarray(t) for t in T])
-    A_blocks, B_blocks, B0 = block_lanczos(Ts, pinv_tol, neg_tol)
+    A_blocks, B_blocks, B0 = block_lanczos(Ts, pinv_tol, neg_tol, moment_eps=moment_eps)
     Hs = block_tridiagonal(A_blocks, B_blocks)
     e, U = np.linalg.eigh(Hs)
     e = c + s * e

@@ -27,11 +27,6 @@ sys.path.insert(0, ROOT)
 MI355X_PEAK = {"f64": 78.6e12, "bf16": 2.5e15, "f32": 157.3e12}
 
 
-def flops_fold(nt, naux, nmo, ncol):
-    """Algorithmic flops of one stage-1 launch: (nt naux) x naux x ncol GEMM."""
-    return 2.0 * nt * naux * naux * ncol
-
-
 def set_flops(o, v, A, N):
     """Algorithmic flops of one TDA moment set: recursion (4N+2) A^2 ov,
     W-core contraction (N+1) 2 A^2 M^2, self-energy contraction (N+1) 2 A M^3."""
@@ -77,6 +72,8 @@ def main():
     ap.add_argument("--nmom", type=int, default=11)
     ap.add_argument("--screening", default="tda", choices=["tda", "rpa"])
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"],
+                    help="both: time the mixed form (the reported value) and the FP64 form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -100,58 +97,57 @@ def main():
     del L
     so = torch.empty(N + 1, M, M, dtype=torch.float64, device="cuda:0")
     sv = torch.empty_like(so)
+    fams_all = ("sigma_fold", "sigma_contract", "recur_xvt", "recur_rv", "recur_rr", "rpa_quad", "mixed_prep",
+                "mixed_zexp")
 
-    def step():
-        h.sigma_moments(e, l, o, N, args.screening, "fp64", out=(so, sv))
+    def run(prec, steps, warmup):
+        out = (torch.empty_like(so), torch.empty_like(sv))
 
-    print("[bench] warmup", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    h.timing(True)
-    h.timing_reset()
-    print("[bench] timed region", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    fams = {f: h.timing_read(f) for f in ("sigma_fold", "sigma_contract", "recur_xvt", "recur_rv", "rpa_quad")}
-    h.timing(False)
-    elapsed = t1 - t0
+        def step():
+            h.sigma_moments(e, l, o, N, args.screening, prec, out=out)
+
+        print(f"[bench] {prec}: warmup", file=sys.stderr, flush=True)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        h.timing(True)
+        h.timing_reset()
+        print(f"[bench] {prec}: timed region ({steps} sets)", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fams = {f: h.timing_read(f) for f in fams_all}
+        h.timing(False)
+        return out, (t1 - t0), fams
+
+    precs = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
+    results = {}
+    for prec in precs:
+        results[prec] = run(prec, args.steps, args.warmup)
+    head = precs[0]
+    (so_h, sv_h), elapsed, fams = results[head]
     sets_per_s = args.steps / elapsed
 
-    # dominant kernel: stage 1 of the self-energy contraction (the fold GEMM)
+    # dominant kernel: stage 1 of the self-energy contraction (the fold GEMM);
+    # its algorithmic flops per set are (N+1) 2 naux^2 nmo^2 whatever the x chunking,
+    # so the per-launch figure is that total over the launches per set
     fold_ms, fold_n = fams["sigma_fold"]
-    per_x = (N + 1) * A * M * 8
-    nx = max(1, min(M, (8 << 30) // per_x))
-    ncols = []
-    x0 = 0
-    while x0 < M:
-        x1 = min(M, x0 + nx)
-        ncols.append((x1 - x0) * M)
-        x0 = x1
-    fold_flops_per_set = sum(flops_fold(N + 1, A, M, c) for c in ncols)
-    launches_per_set = len(ncols)
-    avg_flops = fold_flops_per_set / launches_per_set
+    launches_per_set = max(fold_n, 1) / args.steps
+    avg_flops = (N + 1) * 2.0 * A * A * M * M / launches_per_set
     avg_ms = fold_ms / max(fold_n, 1)
     achieved = avg_flops / (avg_ms * 1e-3)
-    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": MI355X_PEAK["f64"] / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / MI355X_PEAK["f64"], "traffic": None,
-                "kernel": "sigma_fold_kernel", "launch_ms": avg_ms, "launch_flops": avg_flops}
-
-    # poles + upfolded eigensolve, once (not part of the metric)
-    torch.cuda.synchronize()
-    tp0 = time.perf_counter()
-    try:
-        res = h.poles(so, sv, torch.diag(e).contiguous())
-        qp = [float(res["qp"][o - 1]), float(res["qp"][o])]
-        poles_err = None
-    except gwmom.GWError as ex:
-        qp, poles_err = None, str(ex)
-    torch.cuda.synchronize()
-    tp1 = time.perf_counter()
+    peak = MI355X_PEAK["f64" if head == "fp64" else "bf16"]
+    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "kernel": "sigma_fold_kernel" if head == "fp64" else "fold_mixed_kernel",
+                "launch_ms": avg_ms, "launch_flops": avg_flops}
+    if head == "mixed":
+        # eight BF16 digit products per algorithmic multiply-add are issued
+        roofline["issued_tflops"] = 8 * achieved / 1e12
+        roofline["issued_frac"] = 8 * achieved / peak
 
     out = {
         "metric": "sigma_moment_sets_per_s",
@@ -164,19 +160,50 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if head == "fp64" else "bf16-digits/f32-acc/f64",
         "data": "synthetic",
-        "config": {"workload": f"single molecule {args.screening.upper()} moment set, nocc={o} nvir={v} "
-                               f"naux={A} nmom_max={N} (the mixed-vs-FP64 configuration)",
+        "config": {"workload": f"single molecule {args.screening.upper()} self-energy moment set, nocc={o} "
+                               f"nvir={v} naux={A} nmom_max={N} (the mixed-vs-FP64 configuration)",
                    "nocc": o, "nvir": v, "naux": A, "nmom_max": N, "screening": args.screening,
-                   "precision": "fp64", "seed": args.seed},
+                   "precision": head, "seed": args.seed},
         "roofline": roofline,
         "useful_tflops": set_flops(o, v, A, N) * sets_per_s / 1e12,
         "kernel_ms_per_set": {k: ms / args.steps for k, (ms, n) in fams.items() if n},
-        "poles_ms": 1e3 * (tp1 - tp0),
-        "homo_lumo_qp": qp,
-        "poles_error": poles_err,
     }
+    fock = torch.diag(e).contiguous()
+    if "fp64" in results:
+        (so64, sv64), el64, f64 = results["fp64"]
+        out["fp64_sets_per_s"] = args.steps / el64
+        out["fp64_kernel_ms_per_set"] = {k: ms / args.steps for k, (ms, n) in f64.items() if n}
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        try:
+            ref = h.poles(so64, sv64, fock)
+            out["poles_ms"] = 1e3 * (time.perf_counter() - tp0)
+        except gwmom.GWError as ex:
+            ref = None
+            out["poles_error"] = str(ex)
+        if head == "mixed":
+            out["speedup_vs_fp64"] = sets_per_s / out["fp64_sets_per_s"]
+            a, b = so_h.cpu().numpy(), so64.cpu().numpy()
+            c, d = sv_h.cpu().numpy(), sv64.cpu().numpy()
+            out["moment_rel_err"] = [float(max(np.abs(a[n] - b[n]).max() / np.abs(b[n]).max(),
+                                               np.abs(c[n] - d[n]).max() / np.abs(d[n]).max()))
+                                     for n in range(N + 1)]
+            try:
+                mres = h.poles(so_h, sv_h, fock, opts={"moment_eps": 1e-9})
+                if ref is not None:
+                    q64 = ref["qp"].cpu().numpy()
+                    w64 = ref["qp_weight"].cpu().numpy()
+                    qm = mres["qp"].cpu().numpy()
+                    front = [p for p in range(max(0, o - 5), min(M, o + 5)) if w64[p] >= 0.9]
+                    out["qp_err_frontier_ha"] = float(np.abs(qm[front] - q64[front]).max())
+                    out["qp_frontier_orbitals"] = front
+                    out["homo_lumo_qp"] = [float(q64[o - 1]), float(q64[o])]
+            except gwmom.GWError as ex:
+                out["mixed_poles_error"] = str(ex)
+        elif ref is not None:
+            out["homo_lumo_qp"] = [float(ref["qp"][o - 1]), float(ref["qp"][o])]
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(o, v, A, N, args.seed)

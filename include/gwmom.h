@@ -61,7 +61,9 @@ typedef struct {
     double pinv_tol;    /* Lanczos pseudo-inverse cut (relative); <= 0 -> 1e-12      */
     double neg_tol;     /* Lanczos non-PSD tolerance (relative);  <= 0 -> 1e-8       */
     int bf16_slices;    /* mixed precision: BF16 slices per operand (2 or 3); 0 -> 3 */
-    size_t zchunk_bytes;/* cap on the folded-intermediate chunk; 0 -> 4 GiB          */
+    size_t zchunk_bytes;/* cap on the folded-intermediate chunk; 0 -> 8 GiB          */
+    double moment_eps;  /* relative accuracy of the moments given to gw_poles; sets
+                           the Lanczos deflation level; <= 0 -> 2^-52 (FP64 moments) */
 } gw_opts;
 
 /* Create a handle on HIP device `device` with its own non-blocking stream. */
@@ -138,8 +140,13 @@ gw_status gw_sigma_from_R(gw_handle h, int nocc, int nvir, int naux, int nmom_ma
  *   E       [dim_max]          eigenvalues of H~ (first nmo+npole_occ+npole_vir valid, ascending);
  *   chi     [nmo][dim_max]     physical rows of the eigenvectors (nullable);
  *   qp_e, qp_w [nmo]           QP energies and weights.
- * Returns GW_ENUMERIC if a moment matrix is not PSD beyond neg_tol or an
- * eigensolve fails.
+ * Numerics: the moments are first mapped to those of e' = (e - c)/s (c the
+ * weighted mean pole energy, s the weighted spread), T[0] is pseudo-inverted
+ * below pinv_tol times its largest eigenvalue, and B_j^2 eigenvalues below
+ * max(pinv_tol |S2|_F, moment_eps (sum_k |Rhat_k|_F)^2 max_n |S^(n)|_F) are
+ * deflated (the rounding level of the moment cancellations).
+ * Returns GW_ENUMERIC if a moment matrix is not PSD beyond neg_tol (or ten
+ * times the deflation level) or an eigensolve fails.
  */
 gw_status gw_poles(gw_handle h, int nmo, int nmom_max, const double* sigma_occ,
                    const double* sigma_vir, const double* fock, const gw_opts* opts,
@@ -154,6 +161,7 @@ gw_status gw_poles(gw_handle h, int nmo, int nmom_max, const double* sigma_occ,
  *   "sigma_contract" stage 2 (sum over P and x of L Zt)
  *   "recur_xvt"      R_n = eta~^{(n)} V^T
  *   "recur_rv"       eta~ updates  D o X + c R V
+ *   "recur_rr"       2 R_k R_k terms of the half-order TDA moments
  *   "rpa_quad"       RPA quadrature products (Q/T matrices and the G product)
  * gw_timing_read synchronises the stream, then returns the summed duration
  * (ms) and the launch count of one family since the last reset.

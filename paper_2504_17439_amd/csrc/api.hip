@@ -213,7 +213,6 @@ gw_status gw_moments_tda(gw_handle h, int nocc, int nvir, int naux, int nmom_max
     GW_TRY(validate_common(h, nocc, nvir, naux, nmom_max, eps, L));
     GW_TRY(check_opts(h, prec, opts));
     if (!R) return gwm::set_err(h, GW_EINVAL, "R must be non-null");
-    if (prec == GW_MIXED) return gwm::set_err(h, GW_EINVAL, "mixed precision moments: not available yet");
     return gwm::tda_moments_f64(h, nocc, nvir, naux, nmom_max, eps, L, R, eta);
 }
 
@@ -224,7 +223,6 @@ gw_status gw_moments_rpa(gw_handle h, int nocc, int nvir, int naux, int nmom_max
     GW_TRY(validate_common(h, nocc, nvir, naux, nmom_max, eps, L));
     GW_TRY(check_opts(h, prec, opts));
     if (!R) return gwm::set_err(h, GW_EINVAL, "R must be non-null");
-    if (prec == GW_MIXED) return gwm::set_err(h, GW_EINVAL, "mixed precision moments: not available yet");
     return gwm::rpa_moments_f64(h, nocc, nvir, naux, nmom_max, eps, L, opts, R, eta);
 }
 
@@ -236,7 +234,8 @@ gw_status gw_sigma_from_R(gw_handle h, int nocc, int nvir, int naux, int nmom_ma
     GW_TRY(validate_common(h, nocc, nvir, naux, nmom_max, eps, L));
     GW_TRY(check_opts(h, prec, opts));
     if (!R || !sigma_occ || !sigma_vir) return gwm::set_err(h, GW_EINVAL, "R and sigma outputs must be non-null");
-    if (prec == GW_MIXED) return gwm::set_err(h, GW_EINVAL, "mixed precision sigma: not available yet");
+    if (prec == GW_MIXED)
+        return gwm::sigma_from_R_mixed(h, nocc, nvir, naux, nmom_max, eps, L, R, opts, sigma_occ, sigma_vir);
     return gwm::sigma_from_R_f64(h, nocc, nvir, naux, nmom_max, eps, L, R, opts, sigma_occ, sigma_vir);
 }
 
@@ -249,7 +248,8 @@ gw_status gw_sigma_moments(gw_handle h, gw_screening screening, int nocc, int nv
     GW_TRY(check_opts(h, prec, opts));
     if (screening != GW_TDA && screening != GW_RPA) return gwm::set_err(h, GW_EINVAL, "unknown screening");
     if (!sigma_occ || !sigma_vir) return gwm::set_err(h, GW_EINVAL, "sigma outputs must be non-null");
-    if (prec == GW_MIXED) return gwm::set_err(h, GW_EINVAL, "mixed precision sigma: not available yet");
+    if (prec == GW_MIXED && nmom_max > 11)
+        return gwm::set_err(h, GW_EINVAL, "mixed precision: nmom_max must be <= 11");
     const long n2 = (long)naux * naux;
     double* R = (double*)gwm::ws_get(h, gwm::WS_R, sizeof(double) * (nmom_max + 1) * n2);
     if (!R) return GW_ENOMEM;
@@ -257,6 +257,8 @@ gw_status gw_sigma_moments(gw_handle h, gw_screening screening, int nocc, int nv
         GW_TRY(gwm::tda_moments_f64(h, nocc, nvir, naux, nmom_max, eps, L, R, nullptr));
     else
         GW_TRY(gwm::rpa_moments_f64(h, nocc, nvir, naux, nmom_max, eps, L, opts, R, nullptr));
+    if (prec == GW_MIXED)
+        return gwm::sigma_from_R_mixed(h, nocc, nvir, naux, nmom_max, eps, L, R, opts, sigma_occ, sigma_vir);
     return gwm::sigma_from_R_f64(h, nocc, nvir, naux, nmom_max, eps, L, R, opts, sigma_occ, sigma_vir);
 }
 

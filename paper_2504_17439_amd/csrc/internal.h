@@ -153,6 +153,10 @@ gw_status sigma_from_R_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max
                            const double* eps, const double* L, const double* R,
                            const gw_opts* opts, double* sigma_occ, double* sigma_vir);
 
+gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_max,
+                             const double* eps, const double* L, const double* R,
+                             const gw_opts* opts, double* sigma_occ, double* sigma_vir);
+
 gw_status tda_moments_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max,
                           const double* eps, const double* L, double* R, double* eta);
 

@@ -1,6 +1,7 @@
 // Density-response moments, FP64 path (Sec. 2.3 TDA; RPA in rpa_f64.hip).
 //
-// TDA:  X_0 = V,  X_{n+1} = D o X_n + 2 (X_n V^T) V,  R_n = X_n V^T.
+// TDA:  X_0 = V,  X_{n+1} = D o X_n + 2 (X_n V^T) V,  R_n = X_n V^T
+// (all eta~^{(n)} requested), or the half-order form below (R only).
 // R_n is symmetric (V A^n V^T with A symmetric), so only its upper 128x128
 // tiles are computed, split over K = ov, and mirrored in the reduction.
 #include "internal.h"
@@ -57,11 +58,13 @@ gw_status gather_ov(Handle* h, int nocc, int nvir, int naux, const double* eps, 
     return GW_OK;
 }
 
-// R = X V^T (symmetric): upper tiles, split-K partials, mirrored reduction.
-static gw_status syrk_xvt(Handle* h, int naux, long ov, const double* X, const double* V, double* R) {
+// R = X diag(s) V^T (symmetric when X = V or s = 1 with X V^T symmetric):
+// upper tiles, split-K partials, mirrored reduction.  s is nullable.
+static gw_status syrk_xvt(Handle* h, int naux, long ov, const double* X, const double* V, double* R,
+                          const double* s = nullptr) {
     GemmF64 g;
     g.M = naux; g.N = naux; g.K = (int)ov;
-    g.a_kc = true; g.A = X; g.lda = ov;
+    g.a_kc = true; g.A = X; g.lda = ov; g.ascale = s;
     g.b_kc = true; g.B = V; g.ldb = ov;
     g.sym_upper = true;
     g.epi = EPI_PARTIAL;
@@ -89,6 +92,37 @@ static gw_status update_rv(Handle* h, int naux, long ov, const double* R, const 
     return gemm_f64(h, g);
 }
 
+// Half-order form of the TDA moments (used when the eta~ are not requested):
+// with A = D + 2 V^T V symmetric and X_k = V A^k,
+//   R_{2k}   = V A^{2k}   V^T = X_k X_k^T
+//   R_{2k+1} = V A^{2k+1} V^T = X_k D X_k^T + 2 R_k R_k
+// so only X_0 .. X_{N/2} are formed (22 instead of 34 naux^2 ov flop units at N = 11).
+static gw_status tda_moments_half(Handle* h, int naux, long ov, int nmom_max, const double* V, const double* D,
+                                  double* X, double* R) {
+    const long asz = (long)naux * naux;
+    const long xsz = (long)naux * ov;
+    GW_TRY(copy_f64(h, X, V, xsz));
+    const int K = nmom_max / 2;
+    for (int k = 0; k <= K; ++k) {
+        if (2 * k <= nmom_max) GW_TRY(syrk_xvt(h, naux, ov, X, X, R + 2 * k * asz));
+        if (2 * k + 1 <= nmom_max) {
+            double* Ro = R + (2 * k + 1) * asz;
+            GW_TRY(syrk_xvt(h, naux, ov, X, X, Ro, D));
+            // Ro += 2 R_k R_k   (R_k is complete: k <= 2k)
+            GemmF64 g;
+            g.M = naux; g.N = naux; g.K = naux;
+            g.a_kc = true; g.A = R + k * asz; g.lda = naux;
+            g.b_kc = false; g.B = R + k * asz; g.b_klo = naux;
+            g.epi = EPI_AXPBY; g.alpha = 2.0; g.X = Ro; g.ldx = naux;
+            g.C = Ro; g.ldc = naux;
+            g.tag = "recur_rr";
+            GW_TRY(gemm_f64(h, g));
+        }
+        if (k < K) GW_TRY(update_rv(h, naux, ov, R + k * asz, V, 2.0, X, D, nullptr, X));
+    }
+    return GW_OK;
+}
+
 gw_status tda_moments_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
                           const double* L, double* R, double* eta) {
     const long ov = (long)nocc * nvir;
@@ -97,6 +131,11 @@ gw_status tda_moments_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max,
     double* D = (double*)ws_get(h, WS_D, sizeof(double) * ov);
     if (!V || !D) return GW_ENOMEM;
     GW_TRY(gather_ov(h, nocc, nvir, naux, eps, L, V, D));
+    if (!eta) {
+        double* X = (double*)ws_get(h, WS_X0, sizeof(double) * xsz);
+        if (!X) return GW_ENOMEM;
+        return tda_moments_half(h, naux, ov, nmom_max, V, D, X, R);
+    }
     double* xb[2] = {nullptr, nullptr};
     if (!eta) {
         xb[0] = (double*)ws_get(h, WS_X0, sizeof(double) * xsz);

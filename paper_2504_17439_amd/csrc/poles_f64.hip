@@ -473,7 +473,8 @@ gw_status poles_f64(Handle* h, int nmo, int nmom_max, const double* sigma_occ, c
                     double* pole_v, double* E, double* chi, double* qp_e, double* qp_w) {
     const double pinv_tol = (opts && opts->pinv_tol > 0) ? opts->pinv_tol : 1e-12;
     const double neg_tol = (opts && opts->neg_tol > 0) ? opts->neg_tol : 1e-8;
-    const double kappa = 1.0;
+    // deflation level: kappa * (relative accuracy of the input moments)
+    const double kappa = (opts && opts->moment_eps > 0) ? opts->moment_eps / 2.220446049250313e-16 : 1.0;
     const int M = nmo;
     const int cap = nmo * (nmom_max + 1) / 2;
     const long ldv = 2L * cap;

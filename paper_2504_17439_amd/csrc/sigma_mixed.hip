@@ -1,0 +1,623 @@
+// Self-energy moments from R_t in mixed precision: BF16 fixed-point digits
+// on MFMA with exact FP32 accumulation, combined in FP64.
+//
+// Same contraction as the FP64 path (eqs. convolution_occ / convolution_vir
+// with eq. w_moments):
+//   stage 1  Zt^{(n)}[x,q,P] = sum_t s_{n,t}(x) sum_Q R_t[P,Q] L[Q,x,q]
+//   stage 2  Sigma^{(n)}[p,q] = sum_{x in sector} sum_P L[P,x,p] Zt^{(n)}[x,q,P]
+//
+// Number format.  Every operand row (A) or column (B) of a contraction is
+// scaled by a power of two 2^e so that |a| 2^-e <= 1/2, then written as
+//   a = 2^e (d0/2^8 + d1/2^16 + d2/2^24 + d3/2^32),  d_i integers in [-128, 128],
+// four BF16 values that hold their integer digits exactly (ND = 4).  The
+// product of two such numbers keeps the ten terms of digit weight i+j <= 3
+// and drops the rest (~2^-32 of the leading term).  Weight-0 terms are
+// multiples of 2^-16 of magnitude <= 1/4, so their FP32 MFMA sums are exact
+// while |partial sum| < 2^8; all other terms go to a second FP32 accumulator
+// whose rounding sits ~2^-31 below the total.  The two accumulators are
+// combined in FP64 and scaled by 2^(e_row + e_col).  What remains is the
+// truncation of the operands (~2^-33 of the row/column maxima), not the FP32
+// accumulation error of ordinary split products.
+// The folded stage-1 result is stored as an FP32 value plus a BF16 residual
+// (~32 significant bits); stage 2 re-digitises it per (x, q) column.
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace gwm {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16;
+
+namespace {
+
+constexpr int MK = 32;        // k per MFMA (v_mfma_f32_16x16x32_bf16)
+constexpr int LDP = MK + 8;   // LDS row pitch in bf16 (80 B: conflict-free b128 reads)
+
+__device__ __forceinline__ u16 bf_bits(float f) {
+    // exact for the digit values used here (<= 8 significant bits)
+    return (u16)(__float_as_uint(f) >> 16);
+}
+
+constexpr int ND = 4;         // digits per operand
+constexpr int MAXW = 3;       // largest digit weight i + j kept in a product
+
+__device__ __forceinline__ void digitsN(double a, int e, u16* dg) {
+    double x = ldexp(a, -e);          // |x| <= 1/2
+    double scale = 1.0 / 256.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        double q = rint(x * 256.0);
+        x = x * 256.0 - q;
+        dg[d] = bf_bits((float)(q * scale));
+        scale *= 1.0 / 256.0;
+    }
+}
+
+__device__ __forceinline__ int scale_exp(double amax) {
+    // 2^e with amax * 2^-e <= 1/2 (e = ilogb + 2); zero rows get e = 0
+    return amax > 0.0 ? ilogb(amax) + 2 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Operand preparation
+// ---------------------------------------------------------------------------
+
+// Row exponents of a row-major [rows][cols] FP64 matrix (one wave per row).
+__global__ void row_exp_kernel(long rows, long cols, long ld, const double* __restrict__ X, int* __restrict__ e) {
+    long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    int lane = threadIdx.x & 63;
+    if (row >= rows) return;
+    double m = 0.0;
+    for (long c = lane; c < cols; c += 64) m = fmax(m, fabs(X[row * ld + c]));
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if (lane == 0) e[row] = scale_exp(m);
+}
+
+// Column exponents of L viewed as [naux][ncol]: e[j] over Q (one thread per column).
+__global__ void col_exp_kernel(int naux, long ncol, const double* __restrict__ L, int* __restrict__ e) {
+    long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ncol) return;
+    double m = 0.0;
+    for (int Q = 0; Q < naux; ++Q) m = fmax(m, fabs(L[(long)Q * ncol + j]));
+    e[j] = scale_exp(m);
+}
+
+// R digits: Rd[d][row][Ap] (d < ND) for rows = nt*naux (row = t*naux + P), zero padded in Q.
+__global__ void digits_rows_kernel(long rows, int cols, int Ap, const double* __restrict__ X,
+                                   const int* __restrict__ e, u16* __restrict__ Xd) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * Ap) return;
+    long row = i / Ap;
+    int c = (int)(i - row * Ap);
+    u16 dg[ND] = {};
+    if (c < cols) digitsN(X[row * cols + c], e[row], dg);
+    long plane = rows * (long)Ap;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) Xd[d * plane + i] = dg[d];
+}
+
+// L digits, transposed: Ld[d][j][Ap] (d < ND) = digits of L[Q][j] (Q < naux, else 0), 32x32 LDS tiles.
+__global__ void digits_lt_kernel(int naux, long ncol, int Ap, const double* __restrict__ L,
+                                 const int* __restrict__ e, u16* __restrict__ Ld) {
+    __shared__ double tile[32][33];
+    const long j0 = (long)blockIdx.x * 32;
+    const int q0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 8 rows per pass
+    for (int r = ty; r < 32; r += 8) {
+        int Q = q0 + r;
+        long j = j0 + tx;
+        tile[r][tx] = (Q < naux && j < ncol) ? L[(long)Q * ncol + j] : 0.0;
+    }
+    __syncthreads();
+    const long plane = ncol * (long)Ap;
+    for (int r = ty; r < 32; r += 8) {
+        long j = j0 + r;
+        int Q = q0 + tx;
+        if (j >= ncol || Q >= Ap) continue;
+        u16 dg[ND] = {};
+        if (Q < naux) digitsN(tile[tx][r], e[j], dg);
+        long o = j * Ap + Q;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) Ld[d * plane + o] = dg[d];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stage 1: R_t . L for all t of a 16(P) x 128(j) tile, fold, FP32 + BF16-residual output
+// ---------------------------------------------------------------------------
+
+constexpr double binom2(int n, int k) {
+    double c = 1.0;
+    for (int i = 1; i <= k; ++i) c = c * (n - k + i) / i;
+    return 2.0 * c;
+}
+
+template <int NT>
+__global__ __launch_bounds__(256, 1) void fold_mixed_kernel(
+    const u16* __restrict__ Rd, const int* __restrict__ eR, const u16* __restrict__ Ld,
+    const int* __restrict__ eL, const double* __restrict__ eps, int naux, int Ap, int nmo, int nocc,
+    long j0, long ncol, long rplane, long lplane, float* __restrict__ Zt, u16* __restrict__ Zl) {
+    // LDS: A digits [ND][NT][16][LDP], B digits [ND][128][LDP]
+    __shared__ u16 As[ND][NT][16][LDP];
+    __shared__ u16 Bs[ND][128][LDP];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int lr = lane & 15;
+    const int lk = lane >> 4;
+    const long c0 = (long)blockIdx.x * 128;
+    const int P0 = blockIdx.y * 16;
+
+    // prefetch registers, in 16-byte vectors (8 bf16 of one k slab row):
+    // A tile rows (d, t, p): ND*NT*16 rows x 4 vectors; B tile rows (d, c): ND*128 rows x 4
+    constexpr int AV = ND * NT * 64;
+    constexpr int AVT = (AV + 255) / 256;
+    constexpr int BV = ND * 128 * 4;
+    constexpr int BVT = BV / 256;
+    uint4 ra[AVT];
+    uint4 rb[BVT];
+
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int s = 0; s < AVT; ++s) {
+            int v = s * 256 + tid;
+            uint4 val = make_uint4(0, 0, 0, 0);
+            if (v < AV) {
+                int kv = v & 3, row = v >> 2;            // row over (d, t, p)
+                int p = row % 16, dt = row / 16;
+                int t = dt % NT, d = dt / NT;
+                int P = P0 + p;
+                if (P < naux) {
+                    const u16* src = Rd + d * rplane + ((long)t * naux + P) * Ap + k0 + kv * 8;
+                    val = *(const uint4*)src;
+                }
+            }
+            ra[s] = val;
+        }
+#pragma unroll
+        for (int s = 0; s < BVT; ++s) {
+            int v = s * 256 + tid;
+            int kv = v & 3, row = v >> 2;                // row over (d, c)
+            int c = row & 127, d = row >> 7;
+            long cc = c0 + c;
+            uint4 val = make_uint4(0, 0, 0, 0);
+            if (cc < ncol) val = *(const uint4*)(Ld + d * lplane + (j0 + cc) * Ap + k0 + kv * 8);
+            rb[s] = val;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int s = 0; s < AVT; ++s) {
+            int v = s * 256 + tid;
+            if (v < AV) {
+                int kv = v & 3, row = v >> 2;
+                int p = row % 16, dt = row / 16;
+                int t = dt % NT, d = dt / NT;
+                *(uint4*)&As[d][t][p][kv * 8] = ra[s];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < BVT; ++s) {
+            int v = s * 256 + tid;
+            int kv = v & 3, row = v >> 2;
+            int c = row & 127, d = row >> 7;
+            *(uint4*)&Bs[d][c][kv * 8] = rb[s];
+        }
+    };
+
+    f32x4 acc0[NT][2], acc1[NT][2];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            acc0[t][cb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            acc1[t][cb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        }
+
+    const int nkt = Ap / MK;
+    load(0);
+    for (int kt = 0; kt < nkt; ++kt) {
+        __syncthreads();  // previous compute done with LDS
+        store();
+        __syncthreads();
+        if (kt + 1 < nkt) load((kt + 1) * MK);
+        bf16x8 b[2][ND];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int d = 0; d < ND; ++d)
+                b[cb][d] = *(const bf16x8*)&Bs[d][wave * 32 + cb * 16 + lr][lk * 8];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            bf16x8 a[ND];
+#pragma unroll
+            for (int d = 0; d < ND; ++d) a[d] = *(const bf16x8*)&As[d][t][lr][lk * 8];
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                acc0[t][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[cb][0], acc0[t][cb], 0, 0, 0);
+                f32x4 x = acc1[t][cb];
+#pragma unroll
+                for (int w = 1; w <= MAXW; ++w)
+#pragma unroll
+                    for (int i = 0; i <= w; ++i)
+                        if (i < ND && w - i < ND)
+                            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[cb][w - i], x, 0, 0, 0);
+                acc1[t][cb] = x;
+            }
+        }
+    }
+
+    // epilogue: FP64 combination, scaling, binomial / eps-power fold, FP32 store
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const long c = c0 + wave * 32 + cb * 16 + lr;
+        if (c >= ncol) continue;
+        const long j = j0 + c;
+        const int x = (int)(j / nmo);
+        const double ex = eps[x];
+        const bool occ = x < nocc;
+        const int ej = eL[j];
+        double pw[NT];
+        pw[0] = 1.0;
+#pragma unroll
+        for (int k = 1; k < NT; ++k) pw[k] = pw[k - 1] * ex;
+        float outv[NT][4];
+        u16 outl[NT][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int P = P0 + 4 * lk + r;
+            double a[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                double z = 0.0;
+                if (P < naux) {
+                    z = ((double)acc0[t][cb][r] + (double)acc1[t][cb][r]);
+                    z = ldexp(z, eR[(long)t * naux + P] + ej);
+                }
+                a[t] = (occ && (t & 1)) ? -z : z;
+            }
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                double z = 0.0;
+#pragma unroll
+                for (int t = 0; t <= n; ++t) z += binom2(n, t) * pw[n - t] * a[t];
+                // FP32 value + BF16 residual: ~32 significant bits
+                float hi = (float)z;
+                float lo = (float)(z - (double)hi);
+                outv[n][r] = hi;
+                outl[n][r] = (u16)((__float_as_uint(lo) + 0x7fffu + ((__float_as_uint(lo) >> 16) & 1u)) >> 16);
+            }
+        }
+        // rows P0 + 4 lk + r are consecutive: one 16-byte + one 8-byte store per moment
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            long o = ((long)n * ncol + c) * Ap + P0 + 4 * lk;
+            *(float4*)(Zt + o) = make_float4(outv[n][0], outv[n][1], outv[n][2], outv[n][3]);
+            *(uint2*)(Zl + o) = make_uint2(outl[n][0] | ((unsigned)outl[n][1] << 16),
+                                           outl[n][2] | ((unsigned)outl[n][3] << 16));
+        }
+    }
+}
+
+// eZ[row] = scale exponent of max |Zt[row][0..Ap)| (one wave per row)
+__global__ void zexp_kernel(long rows, int Ap, const float* __restrict__ Zt, int* __restrict__ eZ) {
+    long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    int lane = threadIdx.x & 63;
+    if (row >= rows) return;
+    float m = 0.f;
+    const float* z = Zt + row * Ap;
+    for (int c = lane; c < Ap; c += 64) m = fmaxf(m, fabsf(z[c]));
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if (lane == 0) eZ[row] = scale_exp((double)m);
+}
+
+// ---------------------------------------------------------------------------
+// Stage 2: Sigma^{(n)}[p,q] += sum_{x,P} L[P,x,p] Zt^{(n)}[x,q,P]
+// 128x128 upper tiles, 4 waves of 64x64, promotion to FP64 once per x.
+// ---------------------------------------------------------------------------
+
+__device__ inline void upper_tile2(int t, int T, int& bi, int& bj) {
+    int r = 0;
+    while (t >= T - r) { t -= T - r; ++r; }
+    bi = r;
+    bj = r + t;
+}
+
+struct ContractArgs {
+    const u16* Ld; long lplane; const int* eL;  // A digits [ND][nmo*nmo][Ap], exps [nmo*nmo]
+    const float* Zt; const u16* Zl; const int* eZ; // B = Zt + Zl (FP32 + BF16 residual) [nt][ncol][Ap], exps [nt][ncol]
+    int nmo, Ap, naux;
+    int x0;                                      // first x of the Zt chunk
+    int xs0[2], nxs[2];                          // per sector: first x, count (within the chunk)
+    int nt, nsplit, tiles_T;
+    long ncol;
+    double* part;                                // [2][nt][nsplit][nmo][nmo] FP64, accumulated
+};
+
+__global__ __launch_bounds__(256, 1) void contract_mixed_kernel(ContractArgs g) {
+    __shared__ u16 As[ND][128][LDP];
+    __shared__ u16 Bs[ND][128][LDP];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int lr = lane & 15;
+    const int lk = lane >> 4;
+    const int split = blockIdx.y;
+    const int n = blockIdx.z % g.nt;
+    const int sector = blockIdx.z / g.nt;
+    const int nxs = g.nxs[sector];
+    if (nxs <= 0) return;
+    int bi, bj;
+    upper_tile2(blockIdx.x, g.tiles_T, bi, bj);
+    const int m0 = bi * 128, n0 = bj * 128;
+    // this split's x range
+    const int per = (nxs + g.nsplit - 1) / g.nsplit;
+    const int xa = g.xs0[sector] + split * per;
+    const int xb = min(g.xs0[sector] + nxs, xa + per);
+    const int M = g.nmo;
+    const long M2 = (long)M * M;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+    double acc64[4][4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
+
+    uint4 ra[ND * 2];  // A: ND digits x 128 rows x 4 vectors / 256 threads
+    float rbv[16]; // B: 128 cols x 32 k FP32 = 4096 / 256
+    u16 rbl[16];   // and their BF16 residuals
+    const float* Zn = g.Zt + (long)n * g.ncol * g.Ap;
+    const u16* Zln = g.Zl + (long)n * g.ncol * g.Ap;
+    const int* eZn = g.eZ + (long)n * g.ncol;
+
+    for (int x = xa; x < xb; ++x) {
+        const long xl = x - g.x0;  // column block of the chunk
+        // B scale per column for this x
+        auto load = [&](int k0) {
+#pragma unroll
+            for (int s = 0; s < ND * 2; ++s) {
+                int v = s * 256 + tid;
+                int kv = v & 3, row = v >> 2;
+                int p = row & 127, d = row >> 7;
+                int pg = m0 + p;
+                uint4 val = make_uint4(0, 0, 0, 0);
+                if (pg < M) val = *(const uint4*)(g.Ld + d * g.lplane + ((long)x * M + pg) * g.Ap + k0 + kv * 8);
+                ra[s] = val;
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                int v = s * 256 + tid;      // 1024 float4 vectors: (q, kv) with kv in 0..7
+                int kv = v & 7, q = v >> 3;
+                int qg = n0 + q;
+                float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+                uint2 lv = make_uint2(0, 0);
+                if (qg < M) {
+                    long o = (xl * M + qg) * g.Ap + k0 + kv * 4;
+                    val = *(const float4*)(Zn + o);
+                    lv = *(const uint2*)(Zln + o);
+                }
+                rbv[s * 4 + 0] = val.x;
+                rbv[s * 4 + 1] = val.y;
+                rbv[s * 4 + 2] = val.z;
+                rbv[s * 4 + 3] = val.w;
+                rbl[s * 4 + 0] = (u16)(lv.x & 0xffff);
+                rbl[s * 4 + 1] = (u16)(lv.x >> 16);
+                rbl[s * 4 + 2] = (u16)(lv.y & 0xffff);
+                rbl[s * 4 + 3] = (u16)(lv.y >> 16);
+            }
+        };
+        auto store = [&]() {
+#pragma unroll
+            for (int s = 0; s < ND * 2; ++s) {
+                int v = s * 256 + tid;
+                int kv = v & 3, row = v >> 2;
+                int p = row & 127, d = row >> 7;
+                *(uint4*)&As[d][p][kv * 8] = ra[s];
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                int v = s * 256 + tid;
+                int kv = v & 7, q = v >> 3;
+                int qg = n0 + q;
+                int e = (qg < M) ? eZn[xl * M + qg] : 0;
+                u16 dg[4][ND];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    double zv = (double)rbv[s * 4 + u] + (double)__uint_as_float((unsigned)rbl[s * 4 + u] << 16);
+                    digitsN(zv, e, dg[u]);
+                }
+#pragma unroll
+                for (int d = 0; d < ND; ++d)
+                    *(uint2*)&Bs[d][q][kv * 4] = make_uint2(dg[0][d] | ((unsigned)dg[1][d] << 16),
+                                                            dg[2][d] | ((unsigned)dg[3][d] << 16));
+            }
+        };
+
+        f32x4 acc0[4][4], acc1[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                acc0[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+                acc1[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            }
+        const int nkt = g.Ap / MK;
+        load(0);
+        for (int kt = 0; kt < nkt; ++kt) {
+            __syncthreads();
+            store();
+            __syncthreads();
+            if (kt + 1 < nkt) load((kt + 1) * MK);
+            bf16x8 b[4][ND];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int d = 0; d < ND; ++d) b[j][d] = *(const bf16x8*)&Bs[d][wn + j * 16 + lr][lk * 8];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                bf16x8 a[ND];
+#pragma unroll
+                for (int d = 0; d < ND; ++d) a[d] = *(const bf16x8*)&As[d][wm + i * 16 + lr][lk * 8];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc0[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][0], acc0[i][j], 0, 0, 0);
+                    f32x4 y = acc1[i][j];
+#pragma unroll
+                    for (int w = 1; w <= MAXW; ++w)
+#pragma unroll
+                        for (int ii = 0; ii <= w; ++ii)
+                            if (ii < ND && w - ii < ND)
+                                y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ii], b[j][w - ii], y, 0, 0, 0);
+                    acc1[i][j] = y;
+                }
+            }
+        }
+        // promote this x's partial sums to FP64 with the row (p) and column (q) scales
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int qg = n0 + wn + j * 16 + lr;
+            int eq = (qg < M) ? eZn[xl * M + qg] : 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    int pg = m0 + wm + i * 16 + 4 * lk + r;
+                    int ep = (pg < M) ? g.eL[(long)x * M + pg] : 0;
+                    double s = (double)acc0[i][j][r] + (double)acc1[i][j][r];
+                    acc64[i][j][r] += ldexp(s, ep + eq);
+                }
+        }
+    }
+    double* dst = g.part + (((long)sector * g.nt + n) * g.nsplit + split) * M2;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int col = n0 + wn + j * 16 + lr;
+            if (col >= M) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int row = m0 + wm + i * 16 + 4 * lk + r;
+                if (row >= M) continue;
+                dst[(long)row * M + col] += acc64[i][j][r];
+            }
+        }
+}
+
+template <int NT>
+void launch_fold_mixed(Handle* h, const u16* Rd, const int* eR, const u16* Ld, const int* eL, const double* eps,
+                       int naux, int Ap, int nmo, int nocc, long j0, long ncol, long rplane, long lplane,
+                       float* Zt, u16* Zl) {
+    // every padded row P < Ap is written (zeros for P >= naux): stage 2 reads all Ap rows
+    dim3 grid((unsigned)((ncol + 127) / 128), (unsigned)(Ap / 16));
+    hipLaunchKernelGGL((fold_mixed_kernel<NT>), grid, dim3(256), 0, h->stream, Rd, eR, Ld, eL, eps, naux, Ap, nmo,
+                       nocc, j0, ncol, rplane, lplane, Zt, Zl);
+}
+
+unsigned nb256(long n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                             const double* L, const double* R, const gw_opts* opts, double* sigma_occ,
+                             double* sigma_vir) {
+    const int nmo = nocc + nvir;
+    const int nt = nmom_max + 1;
+    const long M2 = (long)nmo * nmo;
+    const int Ap = (naux + MK - 1) / MK * MK;
+    if (nt > 12) return set_err(h, GW_EINVAL, "mixed precision: nmom_max must be <= 11");
+    // --- operand digits
+    const long lplane = M2 * Ap;
+    const long rrows = (long)nt * naux;
+    const long rplane = rrows * Ap;
+    u16* Ld = (u16*)ws_get(h, WS_MIX0, sizeof(u16) * ND * lplane);
+    int* eL = (int*)ws_get(h, WS_MIX1, sizeof(int) * (M2 + rrows));
+    u16* Rd = (u16*)ws_get(h, WS_MIX2, sizeof(u16) * ND * rplane);
+    if (!Ld || !eL || !Rd) return GW_ENOMEM;
+    int* eR = eL + M2;
+    {
+        KTimer tm(h, "mixed_prep");
+        hipLaunchKernelGGL(col_exp_kernel, dim3(nb256(M2)), dim3(256), 0, h->stream, naux, M2, L, eL);
+        hipLaunchKernelGGL(digits_lt_kernel, dim3((unsigned)((M2 + 31) / 32), (unsigned)((Ap + 31) / 32)),
+                           dim3(256), 0, h->stream, naux, M2, Ap, L, eL, Ld);
+        hipLaunchKernelGGL(row_exp_kernel, dim3((unsigned)((rrows + 3) / 4)), dim3(256), 0, h->stream, rrows,
+                           (long)naux, (long)naux, R, eR);
+        hipLaunchKernelGGL(digits_rows_kernel, dim3(nb256(rrows * Ap)), dim3(256), 0, h->stream, rrows, naux, Ap,
+                           R, eR, Rd);
+        tm.stop();
+        GW_CHECK_LAUNCH(h);
+    }
+    // --- chunk over x so that the FP32 intermediate fits the cap
+    size_t cap = (opts && opts->zchunk_bytes) ? opts->zchunk_bytes : ((size_t)8 << 30);
+    size_t per_x = (size_t)nt * nmo * Ap * (sizeof(float) + sizeof(u16));
+    int nx = (int)std::max<size_t>(1, std::min<size_t>((size_t)nmo, cap / per_x));
+    float* Zt = (float*)ws_get(h, WS_MIX3, (size_t)nt * nmo * Ap * sizeof(float) * nx);
+    u16* Zl = (u16*)ws_get(h, WS_MIX5, (size_t)nt * nmo * Ap * sizeof(u16) * nx);
+    int* eZ = (int*)ws_get(h, WS_MIX4, sizeof(int) * (size_t)nt * nx * nmo);
+    if (!Zt || !Zl || !eZ) return GW_ENOMEM;
+    const int T = (nmo + 127) / 128;
+    const int tiles = T * (T + 1) / 2;
+    int S = std::max(1, std::min(64, (512 + tiles * nt - 1) / (tiles * nt)));
+    const long part_per_sector = (long)nt * S * M2;
+    double* acc = (double*)ws_get(h, WS_SIGACC, sizeof(double) * 2 * part_per_sector);
+    if (!acc) return GW_ENOMEM;
+    GW_TRY(fill_f64(h, acc, (size_t)2 * part_per_sector, 0.0));
+    for (int x0 = 0; x0 < nmo; x0 += nx) {
+        int x1 = std::min(nmo, x0 + nx);
+        long ncol = (long)(x1 - x0) * nmo;
+        long j0 = (long)x0 * nmo;
+        {
+            KTimer tm(h, "sigma_fold");
+            switch (nt) {
+                case 2: launch_fold_mixed<2>(h, Rd, eR, Ld, eL, eps, naux, Ap, nmo, nocc, j0, ncol, rplane, lplane, Zt, Zl); break;
+                case 4: launch_fold_mixed<4>(h, Rd, eR, Ld, eL, eps, naux, Ap, nmo, nocc, j0, ncol, rplane, lplane, Zt, Zl); break;
+                case 6: launch_fold_mixed<6>(h, Rd, eR, Ld, eL, eps, naux, Ap, nmo, nocc, j0, ncol, rplane, lplane, Zt, Zl); break;
+                case 8: launch_fold_mixed<8>(h, Rd, eR, Ld, eL, eps, naux, Ap, nmo, nocc, j0, ncol, rplane, lplane, Zt, Zl); break;
+                case 10: launch_fold_mixed<10>(h, Rd, eR, Ld, eL, eps, naux, Ap, nmo, nocc, j0, ncol, rplane, lplane, Zt, Zl); break;
+                case 12: launch_fold_mixed<12>(h, Rd, eR, Ld, eL, eps, naux, Ap, nmo, nocc, j0, ncol, rplane, lplane, Zt, Zl); break;
+                default: return set_err(h, GW_EINVAL, "mixed precision: nmom_max+1 must be even and <= 12");
+            }
+            tm.stop();
+            GW_CHECK_LAUNCH(h);
+        }
+        {
+            KTimer tm(h, "mixed_zexp");
+            long rows = (long)nt * ncol;
+            hipLaunchKernelGGL(zexp_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, h->stream, rows, Ap, Zt,
+                               eZ);
+            tm.stop();
+            GW_CHECK_LAUNCH(h);
+        }
+        ContractArgs a;
+        a.Ld = Ld; a.lplane = lplane; a.eL = eL;
+        a.Zt = Zt; a.Zl = Zl; a.eZ = eZ;
+        a.nmo = nmo; a.Ap = Ap; a.naux = naux;
+        a.x0 = x0;
+        for (int s = 0; s < 2; ++s) {
+            int lo = s == 0 ? 0 : nocc, hi = s == 0 ? nocc : nmo;
+            int xs0 = std::max(x0, lo), xs1 = std::min(x1, hi);
+            a.xs0[s] = xs0;
+            a.nxs[s] = std::max(0, xs1 - xs0);
+        }
+        a.nt = nt; a.nsplit = S; a.tiles_T = T; a.ncol = ncol;
+        a.part = acc;
+        {
+            KTimer tm(h, "sigma_contract");
+            dim3 grid((unsigned)tiles, (unsigned)S, (unsigned)(2 * nt));
+            hipLaunchKernelGGL(contract_mixed_kernel, grid, dim3(256), 0, h->stream, a);
+            tm.stop();
+            GW_CHECK_LAUNCH(h);
+        }
+    }
+    GW_TRY(reduce_splits(h, acc, S, M2, nt, nmo, nmo, nmo, true, 1.0, 0.0, sigma_occ, M2, nmo));
+    GW_TRY(reduce_splits(h, acc + part_per_sector, S, M2, nt, nmo, nmo, nmo, true, 1.0, 0.0, sigma_vir, M2, nmo));
+    return GW_OK;
+}
+
+}  // namespace gwm

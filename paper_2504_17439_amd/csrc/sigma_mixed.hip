@@ -85,7 +85,11 @@ __global__ void col_exp_kernel(int naux, long ncol, const double* __restrict__ L
     e[j] = scale_exp(m);
 }
 
-// R digits: Rd[d][row][Ap] (d < ND) for rows = nt*naux (row = t*naux + P), zero padded in Q.
+// Digit planes are k-blocked: element (row, k) of a plane with `rows` rows sits
+// at ((k / 32) * rows + row) * 32 + k % 32, so the 32 k of one MFMA step of 16
+// consecutive rows are 1 KB of contiguous memory (whole cache lines).
+
+// R digits: Rd[d] k-blocked over rows = nt*naux (row = t*naux + P), zero padded in Q.
 __global__ void digits_rows_kernel(long rows, int cols, int Ap, const double* __restrict__ X,
                                    const int* __restrict__ e, u16* __restrict__ Xd) {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -95,11 +99,13 @@ __global__ void digits_rows_kernel(long rows, int cols, int Ap, const double* __
     u16 dg[ND] = {};
     if (c < cols) digitsN(X[row * cols + c], e[row], dg);
     long plane = rows * (long)Ap;
+    long o = ((long)(c >> 5) * rows + row) * 32 + (c & 31);
 #pragma unroll
-    for (int d = 0; d < ND; ++d) Xd[d * plane + i] = dg[d];
+    for (int d = 0; d < ND; ++d) Xd[d * plane + o] = dg[d];
 }
 
-// L digits, transposed: Ld[d][j][Ap] (d < ND) = digits of L[Q][j] (Q < naux, else 0), 32x32 LDS tiles.
+// L digits, transposed: Ld[d] k-blocked over rows j (k = Q) = digits of L[Q][j] (Q < naux, else 0),
+// 32x32 LDS tiles.
 __global__ void digits_lt_kernel(int naux, long ncol, int Ap, const double* __restrict__ L,
                                  const int* __restrict__ e, u16* __restrict__ Ld) {
     __shared__ double tile[32][33];
@@ -119,7 +125,7 @@ __global__ void digits_lt_kernel(int naux, long ncol, int Ap, const double* __re
         if (j >= ncol || Q >= Ap) continue;
         u16 dg[ND] = {};
         if (Q < naux) digitsN(tile[tx][r], e[j], dg);
-        long o = j * Ap + Q;
+        long o = ((long)blockIdx.y * ncol + j) * 32 + tx;
 #pragma unroll
         for (int d = 0; d < ND; ++d) Ld[d * plane + o] = dg[d];
     }
@@ -135,77 +141,106 @@ constexpr double binom2(int n, int k) {
     return 2.0 * c;
 }
 
+// LDS slab rows hold 32 k (64 B); the 16-byte chunk c of row r is stored at
+// chunk c ^ f(r), f(r) = ((r >> 1) & 3) ^ ((r >> 3) & 1).  A b128 read of one
+// chunk column by 16 rows then touches 16 distinct 16-byte slots modulo 256 B,
+// and each group of 8 rows 8 distinct slots modulo 128 B, so it is free of bank
+// conflicts whether the LDS serves 8 or 16 lanes of a b128 read per cycle.
+__device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >> 1) & 3) ^ ((row >> 3) & 1); }
+
+// Tile: 16 P rows x 128 columns j, all NT moments t.  Wave w owns columns
+// [32w, 32w+32) (two 16-column blocks) for every t, so the binomial / eps-power
+// fold over t is done in registers in the epilogue.  LDS holds two K slabs
+// (double buffering, 160 KB at NT = 12); moments are processed in groups so
+// that several independent accumulator chains interleave on the MFMA pipe.
 template <int NT>
 __global__ __launch_bounds__(256, 1) void fold_mixed_kernel(
     const u16* __restrict__ Rd, const int* __restrict__ eR, const u16* __restrict__ Ld,
     const int* __restrict__ eL, const double* __restrict__ eps, int naux, int Ap, int nmo, int nocc,
     long j0, long ncol, long rplane, long lplane, float* __restrict__ Zt, u16* __restrict__ Zl) {
-    // LDS: A digits [ND][NT][16][LDP], B digits [ND][128][LDP]
-    __shared__ u16 As[ND][NT][16][LDP];
-    __shared__ u16 Bs[ND][128][LDP];
+    constexpr int A_ROWS = ND * NT * 16;              // (d, t, p) rows of the A slab
+    constexpr int B_ROWS = ND * 128;                  // (d, c) rows of the B slab
+    constexpr int SLAB = (A_ROWS + B_ROWS) * 32;      // u16 per buffer
+    __shared__ __attribute__((aligned(16))) u16 lds[2 * SLAB];
+
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int lr = lane & 15;
     const int lk = lane >> 4;
-    const long c0 = (long)blockIdx.x * 128;
-    const int P0 = blockIdx.y * 16;
+    // XCD-aware grouped raster over (P-block, column tile): consecutive work
+    // groups land on different XCDs, so work group b runs on XCD b % 8; each XCD
+    // walks groups of 8 P-blocks x 4 column tiles, which share their L-digit
+    // (B) and R-digit (A) K slabs through that XCD's L2.
+    int pb, ct;
+    {
+        const int nP = Ap / 16;
+        const int nC = (int)((ncol + 127) / 128);
+        const int nPg = (nP + 7) / 8;
+        const int b = blockIdx.x;
+        const int xcd = b & 7, local = b >> 3;
+        const int g = (local >> 5) * 8 + xcd;          // group index
+        const int w = local & 31;
+        pb = (g % nPg) * 8 + (w & 7);
+        ct = (g / nPg) * 4 + (w >> 3);
+        if (pb >= nP || ct >= nC) return;
+    }
+    const long c0 = (long)ct * 128;
+    const int P0 = pb * 16;
 
-    // prefetch registers, in 16-byte vectors (8 bf16 of one k slab row):
-    // A tile rows (d, t, p): ND*NT*16 rows x 4 vectors; B tile rows (d, c): ND*128 rows x 4
-    constexpr int AV = ND * NT * 64;
-    constexpr int AVT = (AV + 255) / 256;
-    constexpr int BV = ND * 128 * 4;
-    constexpr int BVT = BV / 256;
-    uint4 ra[AVT];
-    uint4 rb[BVT];
+    // Global -> LDS staging.  256 threads move 16-byte vectors; vector s of
+    // thread tid is slab row s * 64 + (tid >> 2), 16-byte chunk tid & 3.  For
+    // the A slab (rows (d, t, p)) that row has p = (tid >> 2) & 15 and
+    // (d, t) = divmod(4 s + wave, NT), so the source address is a wave-uniform
+    // base plus one loop-invariant lane offset; for the B slab (rows (d, c))
+    // c = 64 (s & 1) + (tid >> 2), d = s >> 1.  Rows past naux and columns past
+    // ncol read clamped (valid) rows: their products are never stored.
+    static_assert((A_ROWS * 4) % 256 == 0 && (B_ROWS * 4) % 256 == 0, "slab vectors per thread");
+    constexpr int AVT = A_ROWS * 4 / 256;
+    constexpr int BVT = B_ROWS * 4 / 256;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const long M2 = lplane / Ap;                      // rows of an L digit plane
+    const unsigned offA = (unsigned)(min(P0 + ((tid >> 2) & 15), naux - 1) * 32 + (tid & 3) * 8) * 2u;  // bytes
+    unsigned offB[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        long cc = c0 + h * 64 + (tid >> 2);
+        if (cc > ncol - 1) cc = ncol - 1;
+        offB[h] = (unsigned)((j0 + cc) * 32 + (tid & 3) * 8) * 2u;
+    }
+    uint4 ra[AVT], rb[BVT];
 
-    auto load = [&](int k0) {
+    // raw buffer loads from the k-blocked planes: the resource (SGPRs) points at
+    // the k block of one digit plane, the wave-uniform row offset goes in
+    // soffset, the lane part in voffset
+    auto load = [&](int kt) {
 #pragma unroll
         for (int s = 0; s < AVT; ++s) {
-            int v = s * 256 + tid;
-            uint4 val = make_uint4(0, 0, 0, 0);
-            if (v < AV) {
-                int kv = v & 3, row = v >> 2;            // row over (d, t, p)
-                int p = row % 16, dt = row / 16;
-                int t = dt % NT, d = dt / NT;
-                int P = P0 + p;
-                if (P < naux) {
-                    const u16* src = Rd + d * rplane + ((long)t * naux + P) * Ap + k0 + kv * 8;
-                    val = *(const uint4*)src;
-                }
-            }
-            ra[s] = val;
+            const int dt = 4 * s + wv;
+            const int t = dt % NT, d = dt / NT;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(Rd + d * rplane + (long)kt * NT * naux * 32), (short)0, NT * naux * 64, 0x00020000);
+            auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, offA, t * naux * 64, 0);
+            ra[s] = *(uint4*)&v;
         }
 #pragma unroll
         for (int s = 0; s < BVT; ++s) {
-            int v = s * 256 + tid;
-            int kv = v & 3, row = v >> 2;                // row over (d, c)
-            int c = row & 127, d = row >> 7;
-            long cc = c0 + c;
-            uint4 val = make_uint4(0, 0, 0, 0);
-            if (cc < ncol) val = *(const uint4*)(Ld + d * lplane + (j0 + cc) * Ap + k0 + kv * 8);
-            rb[s] = val;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(Ld + (s >> 1) * lplane + (long)kt * M2 * 32), (short)0, (int)(M2 * 64), 0x00020000);
+            auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, offB[s & 1], 0, 0);
+            rb[s] = *(uint4*)&v;
         }
     };
-    auto store = [&]() {
+    // LDS destinations: row s * 64 + (tid >> 2), swizzled chunk
+    const int srow = tid >> 2;
+    const int sdst = srow * 32 + swz(srow & 15, tid & 3) * 8;
+    auto store = [&](int buf) {
+        u16* A = lds + buf * SLAB + sdst;
+        u16* B = lds + buf * SLAB + A_ROWS * 32 + sdst;
 #pragma unroll
-        for (int s = 0; s < AVT; ++s) {
-            int v = s * 256 + tid;
-            if (v < AV) {
-                int kv = v & 3, row = v >> 2;
-                int p = row % 16, dt = row / 16;
-                int t = dt % NT, d = dt / NT;
-                *(uint4*)&As[d][t][p][kv * 8] = ra[s];
-            }
-        }
+        for (int s = 0; s < AVT; ++s) *(uint4*)(A + s * 64 * 32) = ra[s];
 #pragma unroll
-        for (int s = 0; s < BVT; ++s) {
-            int v = s * 256 + tid;
-            int kv = v & 3, row = v >> 2;
-            int c = row & 127, d = row >> 7;
-            *(uint4*)&Bs[d][c][kv * 8] = rb[s];
-        }
+        for (int s = 0; s < BVT; ++s) *(uint4*)(B + s * 64 * 32) = rb[s];
     };
 
     f32x4 acc0[NT][2], acc1[NT][2];
@@ -219,38 +254,56 @@ __global__ __launch_bounds__(256, 1) void fold_mixed_kernel(
 
     const int nkt = Ap / MK;
     load(0);
+    store(0);
+    __syncthreads();
     for (int kt = 0; kt < nkt; ++kt) {
-        __syncthreads();  // previous compute done with LDS
-        store();
-        __syncthreads();
-        if (kt + 1 < nkt) load((kt + 1) * MK);
+        const int cur = kt & 1;
+        const bool more = kt + 1 < nkt;
+        if (more) load(kt + 1);
+        const u16* A = lds + cur * SLAB;
+        const u16* B = A + A_ROWS * 32;
+        const int aoff = lr * 32 + swz(lr, lk) * 8;
         bf16x8 b[2][ND];
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-            for (int d = 0; d < ND; ++d)
-                b[cb][d] = *(const bf16x8*)&Bs[d][wave * 32 + cb * 16 + lr][lk * 8];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            bf16x8 a[ND];
-#pragma unroll
-            for (int d = 0; d < ND; ++d) a[d] = *(const bf16x8*)&As[d][t][lr][lk * 8];
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-                acc0[t][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[cb][0], acc0[t][cb], 0, 0, 0);
-                f32x4 x = acc1[t][cb];
-#pragma unroll
-                for (int w = 1; w <= MAXW; ++w)
-#pragma unroll
-                    for (int i = 0; i <= w; ++i)
-                        if (i < ND && w - i < ND)
-                            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[cb][w - i], x, 0, 0, 0);
-                acc1[t][cb] = x;
+            for (int d = 0; d < ND; ++d) {
+                int row = d * 128 + wave * 32 + cb * 16 + lr;
+                b[cb][d] = *(const bf16x8*)(B + row * 32 + swz(lr, lk) * 8);
             }
+        // moments in groups of G: every product is issued for all G*2 (t, cb)
+        // accumulators before the next product, so G*2 independent MFMA chains
+        // interleave and hide the MFMA dependency latency
+        constexpr int G = (NT % 3 == 0) ? 3 : 2;
+#pragma unroll
+        for (int t0 = 0; t0 < NT; t0 += G) {
+            bf16x8 a[G][ND];
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int d = 0; d < ND; ++d) a[g][d] = *(const bf16x8*)(A + (d * NT + t0 + g) * 16 * 32 + aoff);
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    acc0[t0 + g][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[g][0], b[cb][0], acc0[t0 + g][cb], 0, 0, 0);
+#pragma unroll
+            for (int w = 1; w <= MAXW; ++w)
+#pragma unroll
+                for (int ii = 0; ii <= w; ++ii)
+#pragma unroll
+                    for (int g = 0; g < G; ++g)
+#pragma unroll
+                        for (int cb = 0; cb < 2; ++cb)
+                            if (ii < ND && w - ii < ND)
+                                acc1[t0 + g][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                    a[g][ii], b[cb][w - ii], acc1[t0 + g][cb], 0, 0, 0);
         }
+        if (more) store(cur ^ 1);
+        __syncthreads();
     }
 
-    // epilogue: FP64 combination, scaling, binomial / eps-power fold, FP32 store
+    // epilogue: FP64 combination, scaling, binomial / eps-power fold, FP32 + BF16 residual store
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
         const long c = c0 + wave * 32 + cb * 16 + lr;
@@ -273,10 +326,7 @@ __global__ __launch_bounds__(256, 1) void fold_mixed_kernel(
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 double z = 0.0;
-                if (P < naux) {
-                    z = ((double)acc0[t][cb][r] + (double)acc1[t][cb][r]);
-                    z = ldexp(z, eR[(long)t * naux + P] + ej);
-                }
+                if (P < naux) z = ldexp((double)acc0[t][cb][r] + (double)acc1[t][cb][r], eR[(long)t * naux + P] + ej);
                 a[t] = (occ && (t & 1)) ? -z : z;
             }
 #pragma unroll
@@ -284,11 +334,11 @@ __global__ __launch_bounds__(256, 1) void fold_mixed_kernel(
                 double z = 0.0;
 #pragma unroll
                 for (int t = 0; t <= n; ++t) z += binom2(n, t) * pw[n - t] * a[t];
-                // FP32 value + BF16 residual: ~32 significant bits
                 float hi = (float)z;
                 float lo = (float)(z - (double)hi);
+                unsigned lb = __float_as_uint(lo);
                 outv[n][r] = hi;
-                outl[n][r] = (u16)((__float_as_uint(lo) + 0x7fffu + ((__float_as_uint(lo) >> 16) & 1u)) >> 16);
+                outl[n][r] = (u16)((lb + 0x7fffu + ((lb >> 16) & 1u)) >> 16);
             }
         }
         // rows P0 + 4 lk + r are consecutive: one 16-byte + one 8-byte store per moment
@@ -387,7 +437,8 @@ __global__ __launch_bounds__(256, 1) void contract_mixed_kernel(ContractArgs g) 
                 int p = row & 127, d = row >> 7;
                 int pg = m0 + p;
                 uint4 val = make_uint4(0, 0, 0, 0);
-                if (pg < M) val = *(const uint4*)(g.Ld + d * g.lplane + ((long)x * M + pg) * g.Ap + k0 + kv * 8);
+                if (pg < M)
+                    val = *(const uint4*)(g.Ld + d * g.lplane + ((long)(k0 / MK) * M2 + (long)x * M + pg) * MK + kv * 8);
                 ra[s] = val;
             }
 #pragma unroll
@@ -515,7 +566,11 @@ void launch_fold_mixed(Handle* h, const u16* Rd, const int* eR, const u16* Ld, c
                        int naux, int Ap, int nmo, int nocc, long j0, long ncol, long rplane, long lplane,
                        float* Zt, u16* Zl) {
     // every padded row P < Ap is written (zeros for P >= naux): stage 2 reads all Ap rows
-    dim3 grid((unsigned)((ncol + 127) / 128), (unsigned)(Ap / 16));
+    // groups of 8 P-blocks x 4 column tiles, 8 groups per round of the XCDs
+    const int nP = Ap / 16, nC = (int)((ncol + 127) / 128);
+    const long groups = (long)((nP + 7) / 8) * ((nC + 3) / 4);
+    const long rounds = (groups + 7) / 8;
+    dim3 grid((unsigned)(rounds * 8 * 32));
     hipLaunchKernelGGL((fold_mixed_kernel<NT>), grid, dim3(256), 0, h->stream, Rd, eR, Ld, eL, eps, naux, Ap, nmo,
                        nocc, j0, ncol, rplane, lplane, Zt, Zl);
 }
@@ -532,6 +587,8 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
     const long M2 = (long)nmo * nmo;
     const int Ap = (naux + MK - 1) / MK * MK;
     if (nt > 12) return set_err(h, GW_EINVAL, "mixed precision: nmom_max must be <= 11");
+    if ((long)nt * naux * 64 >= (1L << 31) || M2 * 64 >= (1L << 31))
+        return set_err(h, GW_EINVAL, "mixed precision: digit plane rows exceed 31-bit byte offsets");
     // --- operand digits
     const long lplane = M2 * Ap;
     const long rrows = (long)nt * naux;

@@ -188,59 +188,52 @@ __global__ __launch_bounds__(256, 1) void fold_mixed_kernel(
     const long c0 = (long)ct * 128;
     const int P0 = pb * 16;
 
-    // Global -> LDS staging.  256 threads move 16-byte vectors; vector s of
-    // thread tid is slab row s * 64 + (tid >> 2), 16-byte chunk tid & 3.  For
-    // the A slab (rows (d, t, p)) that row has p = (tid >> 2) & 15 and
-    // (d, t) = divmod(4 s + wave, NT), so the source address is a wave-uniform
-    // base plus one loop-invariant lane offset; for the B slab (rows (d, c))
-    // c = 64 (s & 1) + (tid >> 2), d = s >> 1.  Rows past naux and columns past
-    // ncol read clamped (valid) rows: their products are never stored.
+    // Global -> LDS staging by LDS-DMA buffer loads (16 bytes per lane; one
+    // wave instruction fills 1 KB of LDS at M0 + 16 * lane).  Vector s of wave
+    // w fills slab rows s * 64 + 16 w + (lane >> 2), slot lane & 3.  For the A
+    // slab (rows (d, t, p)) that row has p = lane >> 2 and (d, t) =
+    // divmod(4 s + w, NT); for the B slab (rows (d, c)) c = 64 (s & 1) + 16 w +
+    // (lane >> 2), d = s >> 1.  The lane fetches the global chunk that the
+    // swizzle puts in its slot, so the source is a wave-uniform base plus one
+    // loop-invariant lane offset.  Rows past naux and columns past ncol read
+    // clamped (valid) rows: their products are never stored.
     static_assert((A_ROWS * 4) % 256 == 0 && (B_ROWS * 4) % 256 == 0, "slab vectors per thread");
     constexpr int AVT = A_ROWS * 4 / 256;
     constexpr int BVT = B_ROWS * 4 / 256;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const long M2 = lplane / Ap;                      // rows of an L digit plane
-    const unsigned offA = (unsigned)(min(P0 + ((tid >> 2) & 15), naux - 1) * 32 + (tid & 3) * 8) * 2u;  // bytes
+    const int lrow = lane >> 2;
+    const int gch = swz(lrow, lane & 3);              // swz is an involution in the chunk
+    const unsigned offA = (unsigned)(min(P0 + lrow, naux - 1) * 32 + gch * 8) * 2u;  // bytes
     unsigned offB[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        long cc = c0 + h * 64 + (tid >> 2);
+        long cc = c0 + h * 64 + wv * 16 + lrow;
         if (cc > ncol - 1) cc = ncol - 1;
-        offB[h] = (unsigned)((j0 + cc) * 32 + (tid & 3) * 8) * 2u;
+        offB[h] = (unsigned)((j0 + cc) * 32 + gch * 8) * 2u;
     }
-    uint4 ra[AVT], rb[BVT];
 
-    // raw buffer loads from the k-blocked planes: the resource (SGPRs) points at
-    // the k block of one digit plane, the wave-uniform row offset goes in
-    // soffset, the lane part in voffset
-    auto load = [&](int kt) {
+    // the resource (SGPRs) points at the k block of one digit plane, the
+    // wave-uniform row offset goes in soffset, the lane part in voffset
+    auto load = [&](int kt, int buf) {
+        u16* A = lds + buf * SLAB + wv * 16 * 32;
+        u16* B = A + A_ROWS * 32;
 #pragma unroll
         for (int s = 0; s < AVT; ++s) {
             const int dt = 4 * s + wv;
             const int t = dt % NT, d = dt / NT;
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 (void*)(Rd + d * rplane + (long)kt * NT * naux * 32), (short)0, NT * naux * 64, 0x00020000);
-            auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, offA, t * naux * 64, 0);
-            ra[s] = *(uint4*)&v;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(A + s * 64 * 32),
+                                                     16, offA, t * naux * 64, 0, 0);
         }
 #pragma unroll
         for (int s = 0; s < BVT; ++s) {
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 (void*)(Ld + (s >> 1) * lplane + (long)kt * M2 * 32), (short)0, (int)(M2 * 64), 0x00020000);
-            auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, offB[s & 1], 0, 0);
-            rb[s] = *(uint4*)&v;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(B + s * 64 * 32),
+                                                     16, offB[s & 1], 0, 0, 0);
         }
-    };
-    // LDS destinations: row s * 64 + (tid >> 2), swizzled chunk
-    const int srow = tid >> 2;
-    const int sdst = srow * 32 + swz(srow & 15, tid & 3) * 8;
-    auto store = [&](int buf) {
-        u16* A = lds + buf * SLAB + sdst;
-        u16* B = lds + buf * SLAB + A_ROWS * 32 + sdst;
-#pragma unroll
-        for (int s = 0; s < AVT; ++s) *(uint4*)(A + s * 64 * 32) = ra[s];
-#pragma unroll
-        for (int s = 0; s < BVT; ++s) *(uint4*)(B + s * 64 * 32) = rb[s];
     };
 
     f32x4 acc0[NT][2], acc1[NT][2];
@@ -253,13 +246,14 @@ __global__ __launch_bounds__(256, 1) void fold_mixed_kernel(
         }
 
     const int nkt = Ap / MK;
-    load(0);
-    store(0);
+    load(0, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     for (int kt = 0; kt < nkt; ++kt) {
         const int cur = kt & 1;
         const bool more = kt + 1 < nkt;
-        if (more) load(kt + 1);
+        // buffer cur ^ 1 was last read before the barrier that ended step kt - 1
+        if (more) load(kt + 1, cur ^ 1);
         const u16* A = lds + cur * SLAB;
         const u16* B = A + A_ROWS * 32;
         const int aoff = lr * 32 + swz(lr, lk) * 8;
@@ -299,7 +293,8 @@ __global__ __launch_bounds__(256, 1) void fold_mixed_kernel(
                                 acc1[t0 + g][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                                     a[g][ii], b[cb][w - ii], acc1[t0 + g][cb], 0, 0, 0);
         }
-        if (more) store(cur ^ 1);
+        // this wave's DMA writes have landed; the barrier makes every wave's visible
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
     }
 

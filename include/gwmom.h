@@ -163,6 +163,8 @@ gw_status gw_poles(gw_handle h, int nmo, int nmom_max, const double* sigma_occ,
  *   "recur_rv"       eta~ updates  D o X + c R V
  *   "recur_rr"       2 R_k R_k terms of the half-order TDA moments
  *   "rpa_quad"       RPA quadrature products (Q/T matrices and the G product)
+ *   "mixed_prep"     (mixed precision) scales and digit planes of L and R_t
+ *   "mixed_zdig"     (mixed precision) scales and digit planes of the stage-1 result
  * gw_timing_read synchronises the stream, then returns the summed duration
  * (ms) and the launch count of one family since the last reset.
  */

@@ -45,7 +45,7 @@ enum WsSlot {
     WS_V = 0, WS_D, WS_X0, WS_X1, WS_X2, WS_X3, WS_R, WS_SPLIT, WS_Z, WS_SIGACC,
     WS_RPA_SCALE, WS_RPA_QT, WS_RPA_S, WS_RPA_G, WS_RPA_INFO, WS_MISC,
     WS_LZ0, WS_LZ1, WS_LZ2, WS_LZ3, WS_LZ4, WS_LZ5, WS_LZ6, WS_LZ7,
-    WS_MIX0, WS_MIX1, WS_MIX2, WS_MIX3, WS_MIX4, WS_MIX5,
+    WS_MIX0, WS_MIX1, WS_MIX2, WS_MIX3, WS_MIX4, WS_MIX5, WS_MIX6,
     WS_COUNT
 };
 

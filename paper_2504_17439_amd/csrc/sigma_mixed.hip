@@ -34,7 +34,6 @@ typedef unsigned short u16;
 namespace {
 
 constexpr int MK = 32;        // k per MFMA (v_mfma_f32_16x16x32_bf16)
-constexpr int LDP = MK + 8;   // LDS row pitch in bf16 (80 B: conflict-free b128 reads)
 
 __device__ __forceinline__ u16 bf_bits(float f) {
     // exact for the digit values used here (<= 8 significant bits)
@@ -348,15 +347,59 @@ __global__ __launch_bounds__(256, 1) void fold_mixed_kernel(
 }
 
 // eZ[row] = scale exponent of max |Zt[row][0..Ap)| (one wave per row)
-__global__ void zexp_kernel(long rows, int Ap, const float* __restrict__ Zt, int* __restrict__ eZ) {
+// Stage-1 result to digits: per row r = n * ncol + c (one wave) the exponent
+// of max_P |Zt| and the digits of Zt + Zl (FP32 + BF16 residual) into the
+// k-blocked planes Zd[d] (rows = nt * ncol, k = P).  Each lane holds 8
+// consecutive P per 512-wide pass (Ap <= 64 * 8 * ZPASS), so reads are 32 + 16
+// bytes and every digit plane gets one 16-byte store per lane and pass.
+constexpr int ZPASS = 8;
+__global__ void zdig_kernel(long rows, int Ap, const float* __restrict__ Zt, const u16* __restrict__ Zl,
+                            int* __restrict__ eZ, u16* __restrict__ Zd) {
     long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
     int lane = threadIdx.x & 63;
     if (row >= rows) return;
-    float m = 0.f;
     const float* z = Zt + row * Ap;
-    for (int c = lane; c < Ap; c += 64) m = fmaxf(m, fabsf(z[c]));
+    const u16* zl = Zl + row * Ap;
+    float4 v[ZPASS][2];
+    uint4 w[ZPASS];
+    float m = 0.f;
+#pragma unroll
+    for (int ps = 0; ps < ZPASS; ++ps) {
+        const int c = ps * 512 + lane * 8;
+        v[ps][0] = v[ps][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        w[ps] = make_uint4(0, 0, 0, 0);
+        if (c < Ap) {
+            v[ps][0] = *(const float4*)(z + c);
+            v[ps][1] = *(const float4*)(z + c + 4);
+            w[ps] = *(const uint4*)(zl + c);
+            m = fmaxf(m, fmaxf(fmaxf(fabsf(v[ps][0].x), fabsf(v[ps][0].y)), fmaxf(fabsf(v[ps][0].z), fabsf(v[ps][0].w))));
+            m = fmaxf(m, fmaxf(fmaxf(fabsf(v[ps][1].x), fabsf(v[ps][1].y)), fmaxf(fabsf(v[ps][1].z), fabsf(v[ps][1].w))));
+        }
+    }
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    if (lane == 0) eZ[row] = scale_exp((double)m);
+    const int e = scale_exp((double)m);
+    if (lane == 0) eZ[row] = e;
+    const long plane = rows * (long)Ap;
+#pragma unroll
+    for (int ps = 0; ps < ZPASS; ++ps) {
+        const int c = ps * 512 + lane * 8;
+        if (c >= Ap) continue;
+        const float hv[8] = {v[ps][0].x, v[ps][0].y, v[ps][0].z, v[ps][0].w,
+                             v[ps][1].x, v[ps][1].y, v[ps][1].z, v[ps][1].w};
+        const unsigned lw[4] = {w[ps].x, w[ps].y, w[ps].z, w[ps].w};
+        u16 dg[8][ND];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const unsigned lb = (u & 1) ? (lw[u >> 1] & 0xffff0000u) : (lw[u >> 1] << 16);
+            digitsN((double)hv[u] + (double)__uint_as_float(lb), e, dg[u]);
+        }
+        const long o = ((long)(c >> 5) * rows + row) * 32 + (c & 31);
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+            *(uint4*)(Zd + d * plane + o) =
+                make_uint4(dg[0][d] | ((unsigned)dg[1][d] << 16), dg[2][d] | ((unsigned)dg[3][d] << 16),
+                           dg[4][d] | ((unsigned)dg[5][d] << 16), dg[6][d] | ((unsigned)dg[7][d] << 16));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -372,19 +415,24 @@ __device__ inline void upper_tile2(int t, int T, int& bi, int& bj) {
 }
 
 struct ContractArgs {
-    const u16* Ld; long lplane; const int* eL;  // A digits [ND][nmo*nmo][Ap], exps [nmo*nmo]
-    const float* Zt; const u16* Zl; const int* eZ; // B = Zt + Zl (FP32 + BF16 residual) [nt][ncol][Ap], exps [nt][ncol]
+    const u16* Ld; long lplane; const int* eL;  // L digit planes, k-blocked, rows (x, p) = nmo^2; exps per row
+    const u16* Zd; long zplane; const int* eZ;  // Z digit planes, k-blocked, rows (n, c) = nt * ncol; exps per row
     int nmo, Ap, naux;
-    int x0;                                      // first x of the Zt chunk
+    int x0;                                      // first x of the chunk
     int xs0[2], nxs[2];                          // per sector: first x, count (within the chunk)
     int nt, nsplit, tiles_T;
     long ncol;
     double* part;                                // [2][nt][nsplit][nmo][nmo] FP64, accumulated
 };
 
+// One work group: a 128 x 128 upper tile of Sigma^{(n)} for one sector and
+// one split of that sector's x range.  The (x, k-block) steps form one
+// double-buffered LDS-DMA pipeline; the FP32 digit-weight accumulators are
+// promoted to FP64 with the row and column scales at the end of every x.
 __global__ __launch_bounds__(256, 1) void contract_mixed_kernel(ContractArgs g) {
-    __shared__ u16 As[ND][128][LDP];
-    __shared__ u16 Bs[ND][128][LDP];
+    constexpr int ROWS = ND * 128;               // (d, i) rows of one operand slab
+    constexpr int OPS = ROWS * 32;               // u16 per operand slab (32 KB)
+    __shared__ __attribute__((aligned(16))) u16 lds[2 * 2 * OPS];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -398,147 +446,124 @@ __global__ __launch_bounds__(256, 1) void contract_mixed_kernel(ContractArgs g) 
     int bi, bj;
     upper_tile2(blockIdx.x, g.tiles_T, bi, bj);
     const int m0 = bi * 128, n0 = bj * 128;
-    // this split's x range
     const int per = (nxs + g.nsplit - 1) / g.nsplit;
     const int xa = g.xs0[sector] + split * per;
     const int xb = min(g.xs0[sector] + nxs, xa + per);
+    if (xa >= xb) return;
     const int M = g.nmo;
     const long M2 = (long)M * M;
+    const long zrows = (long)g.nt * g.ncol;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
 
+    // LDS-DMA staging as in stage 1: vector s of wave w fills slab rows
+    // s * 64 + 16 w + (lane >> 2) = (d, i) with d = s >> 1,
+    // i = 64 (s & 1) + 16 w + (lane >> 2); rows past nmo read clamped rows.
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const int lrow = lane >> 2;
+    const int gch = swz(lrow, lane & 3);
+    unsigned offA[2], offB[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int i = h * 64 + wv * 16 + lrow;
+        offA[h] = (unsigned)(min(m0 + i, M - 1) * 32 + gch * 8) * 2u;
+        offB[h] = (unsigned)(min(n0 + i, M - 1) * 32 + gch * 8) * 2u;
+    }
+    auto load = [&](int x, int kt, int buf) {
+        u16* A = lds + buf * 2 * OPS + wv * 16 * 32;
+        u16* B = A + OPS;
+        const unsigned soA = (unsigned)x * M * 64u;
+        const unsigned soB = (unsigned)((long)n * g.ncol + (long)(x - g.x0) * M) * 64u;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(g.Ld + (s >> 1) * g.lplane + (long)kt * M2 * 32), (short)0, (int)(M2 * 64), 0x00020000);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(A + s * 64 * 32),
+                                                     16, offA[s & 1], soA, 0, 0);
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(g.Zd + (s >> 1) * g.zplane + (long)kt * zrows * 32), (short)0, (int)(zrows * 64), 0x00020000);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(B + s * 64 * 32),
+                                                     16, offB[s & 1], soB, 0, 0);
+        }
+    };
+
     double acc64[4][4][4];
+    f32x4 acc0[4][4], acc1[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 4; ++j) {
+            acc0[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            acc1[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
-
-    uint4 ra[ND * 2];  // A: ND digits x 128 rows x 4 vectors / 256 threads
-    float rbv[16]; // B: 128 cols x 32 k FP32 = 4096 / 256
-    u16 rbl[16];   // and their BF16 residuals
-    const float* Zn = g.Zt + (long)n * g.ncol * g.Ap;
-    const u16* Zln = g.Zl + (long)n * g.ncol * g.Ap;
+        }
     const int* eZn = g.eZ + (long)n * g.ncol;
+    const int nkt = g.Ap / MK;
+    const int total = (xb - xa) * nkt;
+    const int so = swz(lr, lk) * 8;
 
-    for (int x = xa; x < xb; ++x) {
-        const long xl = x - g.x0;  // column block of the chunk
-        // B scale per column for this x
-        auto load = [&](int k0) {
+    load(xa, 0, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    int x = xa, kt = 0;            // step being computed
+    int xn = xa, ktn = 0;          // step being loaded
+    for (int it = 0; it < total; ++it) {
+        const int cur = it & 1;
+        if (++ktn == nkt) { ktn = 0; ++xn; }
+        if (it + 1 < total) load(xn, ktn, cur ^ 1);
+        const u16* A = lds + cur * 2 * OPS;
+        const u16* B = A + OPS;
+        bf16x8 b[4][ND];
 #pragma unroll
-            for (int s = 0; s < ND * 2; ++s) {
-                int v = s * 256 + tid;
-                int kv = v & 3, row = v >> 2;
-                int p = row & 127, d = row >> 7;
-                int pg = m0 + p;
-                uint4 val = make_uint4(0, 0, 0, 0);
-                if (pg < M)
-                    val = *(const uint4*)(g.Ld + d * g.lplane + ((long)(k0 / MK) * M2 + (long)x * M + pg) * MK + kv * 8);
-                ra[s] = val;
-            }
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                int v = s * 256 + tid;      // 1024 float4 vectors: (q, kv) with kv in 0..7
-                int kv = v & 7, q = v >> 3;
-                int qg = n0 + q;
-                float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
-                uint2 lv = make_uint2(0, 0);
-                if (qg < M) {
-                    long o = (xl * M + qg) * g.Ap + k0 + kv * 4;
-                    val = *(const float4*)(Zn + o);
-                    lv = *(const uint2*)(Zln + o);
-                }
-                rbv[s * 4 + 0] = val.x;
-                rbv[s * 4 + 1] = val.y;
-                rbv[s * 4 + 2] = val.z;
-                rbv[s * 4 + 3] = val.w;
-                rbl[s * 4 + 0] = (u16)(lv.x & 0xffff);
-                rbl[s * 4 + 1] = (u16)(lv.x >> 16);
-                rbl[s * 4 + 2] = (u16)(lv.y & 0xffff);
-                rbl[s * 4 + 3] = (u16)(lv.y >> 16);
-            }
-        };
-        auto store = [&]() {
+            for (int d = 0; d < ND; ++d) b[j][d] = *(const bf16x8*)(B + (d * 128 + wn + j * 16 + lr) * 32 + so);
 #pragma unroll
-            for (int s = 0; s < ND * 2; ++s) {
-                int v = s * 256 + tid;
-                int kv = v & 3, row = v >> 2;
-                int p = row & 127, d = row >> 7;
-                *(uint4*)&As[d][p][kv * 8] = ra[s];
-            }
+        for (int i = 0; i < 4; ++i) {
+            bf16x8 a[ND];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                int v = s * 256 + tid;
-                int kv = v & 7, q = v >> 3;
-                int qg = n0 + q;
-                int e = (qg < M) ? eZn[xl * M + qg] : 0;
-                u16 dg[4][ND];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    double zv = (double)rbv[s * 4 + u] + (double)__uint_as_float((unsigned)rbl[s * 4 + u] << 16);
-                    digitsN(zv, e, dg[u]);
-                }
-#pragma unroll
-                for (int d = 0; d < ND; ++d)
-                    *(uint2*)&Bs[d][q][kv * 4] = make_uint2(dg[0][d] | ((unsigned)dg[1][d] << 16),
-                                                            dg[2][d] | ((unsigned)dg[3][d] << 16));
-            }
-        };
-
-        f32x4 acc0[4][4], acc1[4][4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                acc0[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-                acc1[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-            }
-        const int nkt = g.Ap / MK;
-        load(0);
-        for (int kt = 0; kt < nkt; ++kt) {
-            __syncthreads();
-            store();
-            __syncthreads();
-            if (kt + 1 < nkt) load((kt + 1) * MK);
-            bf16x8 b[4][ND];
+            for (int d = 0; d < ND; ++d) a[d] = *(const bf16x8*)(A + (d * 128 + wm + i * 16 + lr) * 32 + so);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
+                acc0[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][0], acc0[i][j], 0, 0, 0);
+            // each product for all four j before the next: four independent chains
 #pragma unroll
-                for (int d = 0; d < ND; ++d) b[j][d] = *(const bf16x8*)&Bs[d][wn + j * 16 + lr][lk * 8];
+            for (int w = 1; w <= MAXW; ++w)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                bf16x8 a[ND];
+                for (int ii = 0; ii <= w; ++ii)
 #pragma unroll
-                for (int d = 0; d < ND; ++d) a[d] = *(const bf16x8*)&As[d][wm + i * 16 + lr][lk * 8];
+                    for (int j = 0; j < 4; ++j)
+                        if (ii < ND && w - ii < ND)
+                            acc1[i][j] =
+                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ii], b[j][w - ii], acc1[i][j], 0, 0, 0);
+        }
+        if (++kt == nkt) {
+            // end of this x: promote with the row (p) and column (q) scales
+            const long xl = x - g.x0;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    acc0[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][0], acc0[i][j], 0, 0, 0);
-                    f32x4 y = acc1[i][j];
+            for (int j = 0; j < 4; ++j) {
+                const int qg = n0 + wn + j * 16 + lr;
+                const int eq = (qg < M) ? eZn[xl * M + qg] : 0;
 #pragma unroll
-                    for (int w = 1; w <= MAXW; ++w)
+                for (int i = 0; i < 4; ++i) {
 #pragma unroll
-                        for (int ii = 0; ii <= w; ++ii)
-                            if (ii < ND && w - ii < ND)
-                                y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ii], b[j][w - ii], y, 0, 0, 0);
-                    acc1[i][j] = y;
+                    for (int r = 0; r < 4; ++r) {
+                        const int pg = m0 + wm + i * 16 + 4 * lk + r;
+                        const int ep = (pg < M) ? g.eL[(long)x * M + pg] : 0;
+                        acc64[i][j][r] += ldexp((double)acc0[i][j][r] + (double)acc1[i][j][r], ep + eq);
+                    }
+                    acc0[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+                    acc1[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
                 }
             }
+            kt = 0;
+            ++x;
         }
-        // promote this x's partial sums to FP64 with the row (p) and column (q) scales
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            int qg = n0 + wn + j * 16 + lr;
-            int eq = (qg < M) ? eZn[xl * M + qg] : 0;
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    int pg = m0 + wm + i * 16 + 4 * lk + r;
-                    int ep = (pg < M) ? g.eL[(long)x * M + pg] : 0;
-                    double s = (double)acc0[i][j][r] + (double)acc1[i][j][r];
-                    acc64[i][j][r] += ldexp(s, ep + eq);
-                }
-        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
     }
     double* dst = g.part + (((long)sector * g.nt + n) * g.nsplit + split) * M2;
 #pragma unroll
@@ -582,6 +607,7 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
     const long M2 = (long)nmo * nmo;
     const int Ap = (naux + MK - 1) / MK * MK;
     if (nt > 12) return set_err(h, GW_EINVAL, "mixed precision: nmom_max must be <= 11");
+    if (Ap > 512 * ZPASS) return set_err(h, GW_EINVAL, "mixed precision: naux must be <= 4096");
     if ((long)nt * naux * 64 >= (1L << 31) || M2 * 64 >= (1L << 31))
         return set_err(h, GW_EINVAL, "mixed precision: digit plane rows exceed 31-bit byte offsets");
     // --- operand digits
@@ -605,17 +631,22 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
         tm.stop();
         GW_CHECK_LAUNCH(h);
     }
-    // --- chunk over x so that the FP32 intermediate fits the cap
-    size_t cap = (opts && opts->zchunk_bytes) ? opts->zchunk_bytes : ((size_t)8 << 30);
-    size_t per_x = (size_t)nt * nmo * Ap * (sizeof(float) + sizeof(u16));
+    // --- chunk over x so that the stage-1 intermediates (FP32 + BF16 residual
+    // and the ND digit planes) fit the cap
+    size_t cap = (opts && opts->zchunk_bytes) ? opts->zchunk_bytes : ((size_t)16 << 30);
+    size_t per_x = (size_t)nt * nmo * Ap * (sizeof(float) + sizeof(u16) + ND * sizeof(u16));
     int nx = (int)std::max<size_t>(1, std::min<size_t>((size_t)nmo, cap / per_x));
-    float* Zt = (float*)ws_get(h, WS_MIX3, (size_t)nt * nmo * Ap * sizeof(float) * nx);
-    u16* Zl = (u16*)ws_get(h, WS_MIX5, (size_t)nt * nmo * Ap * sizeof(u16) * nx);
-    int* eZ = (int*)ws_get(h, WS_MIX4, sizeof(int) * (size_t)nt * nx * nmo);
-    if (!Zt || !Zl || !eZ) return GW_ENOMEM;
+    // the stage-2 kernel addresses a chunk's digit plane rows with 31-bit byte offsets
+    nx = (int)std::max<long>(1, std::min<long>(nx, ((1L << 31) - 1) / ((long)nt * nmo * 64)));
+    const long zrows_max = (long)nt * nx * nmo;
+    float* Zt = (float*)ws_get(h, WS_MIX3, sizeof(float) * zrows_max * Ap);
+    u16* Zl = (u16*)ws_get(h, WS_MIX5, sizeof(u16) * zrows_max * Ap);
+    u16* Zd = (u16*)ws_get(h, WS_MIX6, sizeof(u16) * ND * zrows_max * Ap);
+    int* eZ = (int*)ws_get(h, WS_MIX4, sizeof(int) * zrows_max);
+    if (!Zt || !Zl || !Zd || !eZ) return GW_ENOMEM;
     const int T = (nmo + 127) / 128;
     const int tiles = T * (T + 1) / 2;
-    int S = std::max(1, std::min(64, (512 + tiles * nt - 1) / (tiles * nt)));
+    int S = std::max(1, std::min(64, (2048 + tiles * nt - 1) / (tiles * nt)));
     const long part_per_sector = (long)nt * S * M2;
     double* acc = (double*)ws_get(h, WS_SIGACC, sizeof(double) * 2 * part_per_sector);
     if (!acc) return GW_ENOMEM;
@@ -638,17 +669,17 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
             tm.stop();
             GW_CHECK_LAUNCH(h);
         }
+        const long zrows = (long)nt * ncol;
         {
-            KTimer tm(h, "mixed_zexp");
-            long rows = (long)nt * ncol;
-            hipLaunchKernelGGL(zexp_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, h->stream, rows, Ap, Zt,
-                               eZ);
+            KTimer tm(h, "mixed_zdig");
+            hipLaunchKernelGGL(zdig_kernel, dim3((unsigned)((zrows + 3) / 4)), dim3(256), 0, h->stream, zrows, Ap, Zt,
+                               Zl, eZ, Zd);
             tm.stop();
             GW_CHECK_LAUNCH(h);
         }
         ContractArgs a;
         a.Ld = Ld; a.lplane = lplane; a.eL = eL;
-        a.Zt = Zt; a.Zl = Zl; a.eZ = eZ;
+        a.Zd = Zd; a.zplane = zrows * Ap; a.eZ = eZ;
         a.nmo = nmo; a.Ap = Ap; a.naux = naux;
         a.x0 = x0;
         for (int s = 0; s < 2; ++s) {

@@ -154,6 +154,57 @@ gw_status gw_poles(gw_handle h, int nmo, int nmom_max, const double* sigma_occ,
                    double* E, double* chi, double* qp_e, double* qp_w);
 
 /*
+ * Fock / chemical-potential self-consistent GW (Sec. 3.6, Alg. 2).
+ * The loop state is the Fock matrix F in the reference MO basis (eps, L).
+ * Outer iteration: diagonalise F (orbital energies e, orbitals C), rotate
+ * L_P <- C^T L_P C, build the self-energy moments (screening, precision as in
+ * gw_sigma_moments) and the auxiliary poles (as in gw_poles); then the Fock
+ * loop in that basis, from diag(e):
+ *   zeta with Tr rho = N_e = 2 nocc, where rho = 2 sum_{a<n} chi_a chi_a^T over
+ *   the n lowest eigenvectors of H~ = [[F, W], [W^T, diag(e_aux + zeta)]] and
+ *   n minimises |2 sum_{a<n} |chi_a|^2 - N_e| (Aufbau); zeta is searched in
+ *   [zeta_lo, zeta_hi], starting from +-1e-3 Ha around the previous zeta, to
+ *   zeta_tol electrons or a 1e-13 Ha bracket (the end with the smaller
+ *   residual when the interval holds no root);
+ *   F <- h + J[rho] - K[rho]/2 with density-fitted J, K and the core
+ *   Hamiltonian h = diag(eps) - (J[rho0] - K[rho0]/2), rho0 = 2 diag(1_occ);
+ *   DIIS over the Fock matrices (diis_space vectors) with error vectors
+ *   rho_k - rho_{k-1}, until max |rho_k - rho_{k-1}| < fock_tol.
+ * The QP energies of H~ (as in gw_poles) end the iteration; the loop stops
+ * when the sorted QP energies change by less than tol (Ha).
+ * Inputs (device): eps [nmo], L [naux][nmo][nmo], F0 [nmo][nmo] or NULL for
+ * diag(eps) (a warm start).  Outputs (device): F [nmo][nmo] (reference basis),
+ * qp_e, qp_w [nmo] of the last iteration; info (host, nullable) the counts.
+ * Options: NULL or zero fields take the defaults in brackets.  Returns
+ * GW_ENOCONV (outputs still written) when max_outer is reached, the errors
+ * of gw_sigma_moments and gw_poles otherwise.  Synchronises the stream.
+ */
+typedef struct {
+    double tol;        /* outer: max |change of sorted QP energies| [1e-6 Ha] */
+    int max_outer;     /* [30] */
+    int max_fock;      /* Fock-loop steps per outer iteration [50] */
+    double fock_tol;   /* max |density change| ending the Fock loop [1e-8] */
+    int diis_space;    /* [12] */
+    double zeta_tol;   /* electron-number tolerance of the zeta search [1e-13] */
+    double zeta_lo;    /* zeta bracket [-1, 1] Ha (used when zeta_hi > zeta_lo) */
+    double zeta_hi;
+} gw_fsgw_opts;
+
+typedef struct {
+    int iterations;    /* outer iterations (self-energy rebuilds) */
+    int fock_steps;    /* Fock-loop steps, all iterations */
+    int eig_calls;     /* eigensolves of H~ */
+    int converged;
+    double zeta;       /* final auxiliary shift */
+    double last_dqp;   /* QP change of the last iteration (-1 after one iteration) */
+} gw_fsgw_info;
+
+gw_status gw_fsgw(gw_handle h, gw_screening screening, int nocc, int nvir, int naux,
+                  int nmom_max, const double* eps, const double* L, const double* F0,
+                  gw_precision prec, const gw_opts* opts, const gw_fsgw_opts* fopts,
+                  double* F, double* qp_e, double* qp_w, gw_fsgw_info* info);
+
+/*
  * Per-kernel timing for measurement.  While enabled, every launch of the
  * instrumented kernel families is bracketed by HIP events recorded on the
  * handle's stream (the stream the kernels run on).  Families:

@@ -11,7 +11,9 @@ its numerics):
   * electron number (eq. density): the lowest n eigenstates of H~ are filled,
     n chosen to minimise |2 sum_{alpha<n} |chi_alpha|^2 - N_e| (Aufbau);
   * zeta (the shift of the auxiliary poles) is found by bisection of
-    Tr rho(zeta) - N_e on [-1, 1] Ha;
+    Tr rho(zeta) - N_e on [-1, 1] Ha, to 1e-13 electrons or a 1e-13 Ha
+    bracket: Tr rho is flat in zeta, and a looser electron count leaves zeta,
+    and with it rho, uncertain above the density tolerance of the Fock loop;
   * the Fock loop is a DIIS (12 vectors) extrapolation of the Fock matrices
     F[rho_k] with error vectors rho_k - rho_{k-1}; zeta is re-optimised at
     every Fock step, and the loop ends when the density stops changing (max
@@ -77,7 +79,7 @@ def trace_density(F, e_aux, W, zeta, nelec):
     return float(np.trace(density(F, e_aux, W, zeta, nelec)[0]))
 
 
-def solve_zeta(F, e_aux, W, nelec, lo=-1.0, hi=1.0, tol=1e-10, maxit=100):
+def solve_zeta(F, e_aux, W, nelec, lo=-1.0, hi=1.0, tol=1e-13, maxit=100):
     """Root of Tr rho(zeta) - nelec on [lo, hi] by bisection, to tol electrons
     (or a bracket narrower than 1e-13 Ha).  Raising zeta lifts the auxiliary
     poles, which moves weight onto the physical states, so the count is

@@ -276,4 +276,24 @@ gw_status gw_poles(gw_handle h, int nmo, int nmom_max, const double* sigma_occ, 
                           pole_v, E, chi, qp_e, qp_w);
 }
 
+gw_status gw_fsgw(gw_handle h, gw_screening screening, int nocc, int nvir, int naux, int nmom_max,
+                  const double* eps, const double* L, const double* F0, gw_precision prec, const gw_opts* opts,
+                  const gw_fsgw_opts* fopts, double* F, double* qp_e, double* qp_w, gw_fsgw_info* info) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    GW_TRY(validate_common(h, nocc, nvir, naux, nmom_max, eps, L));
+    GW_TRY(check_opts(h, prec, opts));
+    if (screening != GW_TDA && screening != GW_RPA) return gwm::set_err(h, GW_EINVAL, "unknown screening");
+    if (nmom_max % 2 == 0 || nmom_max > 15)
+        return gwm::set_err(h, GW_EINVAL, "fsGW: nmom_max must be odd and <= 15");
+    if (prec == GW_MIXED && nmom_max > 11)
+        return gwm::set_err(h, GW_EINVAL, "mixed precision: nmom_max must be <= 11");
+    if (!F || !qp_e || !qp_w) return gwm::set_err(h, GW_EINVAL, "gw_fsgw: F, qp_e and qp_w must be non-null");
+    if (fopts && (fopts->tol < 0 || fopts->fock_tol < 0 || fopts->zeta_tol < 0 || fopts->max_outer < 0 ||
+                  fopts->max_fock < 0 || fopts->diis_space < 0))
+        return gwm::set_err(h, GW_EINVAL, "gw_fsgw: negative option");
+    return gwm::fsgw_run(h, screening, nocc, nvir, naux, nmom_max, eps, L, F0, prec, opts, fopts, F, qp_e, qp_w,
+                         info);
+}
+
 }  // extern "C"

@@ -46,6 +46,7 @@ enum WsSlot {
     WS_RPA_SCALE, WS_RPA_QT, WS_RPA_S, WS_RPA_G, WS_RPA_INFO, WS_MISC,
     WS_LZ0, WS_LZ1, WS_LZ2, WS_LZ3, WS_LZ4, WS_LZ5, WS_LZ6, WS_LZ7,
     WS_MIX0, WS_MIX1, WS_MIX2, WS_MIX3, WS_MIX4, WS_MIX5, WS_MIX6,
+    WS_FS0, WS_FS1, WS_FS2, WS_FS3, WS_FS4, WS_FS5, WS_FS6, WS_FS7,
     WS_COUNT
 };
 
@@ -168,6 +169,31 @@ gw_status poles_f64(Handle* h, int nmo, int nmom_max, const double* sigma_occ,
                     const double* sigma_vir, const double* fock, const gw_opts* opts,
                     int* npole_occ, int* npole_vir, double* pole_e, double* pole_v,
                     double* E, double* chi, double* qp_e, double* qp_w);
+
+// Row-major C[m x n] = alpha op(A) op(B) + beta C (rocBLAS).
+gw_status gemm_rowmajor(Handle* h, bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda,
+                        const double* B, int ldb, double beta, double* C, int ldc);
+
+// Symmetric eigensolve in place: A (n x n) -> rows are eigenvectors, w ascending
+// (work: n doubles, info: device int).
+gw_status eigh_rows(Handle* h, int n, double* A, double* w, double* work, int* info);
+
+// Auxiliary poles of both sectors (block Lanczos), packed as in gw_poles.
+gw_status poles_lanczos(Handle* h, int nmo, int nmom_max, const double* sigma_occ, const double* sigma_vir,
+                        const gw_opts* opts, double* pole_e, double* pole_v, long ldv, int* npole_occ,
+                        int* npole_vir);
+
+// Eigensystem of H~ = [[fock, W], [W^T, diag(pole_e + zeta)]], W = pole_v[:, :np]:
+// H (dim^2, dim = M + np) receives the eigenvectors as rows, w the eigenvalues.
+gw_status upfold_eigh(Handle* h, int M, int np, const double* fock, const double* pole_e, double zeta,
+                      const double* pole_v, long ldv, double* H, double* w, double* work, int* info);
+
+// QP energies / weights from an H~ eigensystem (device outputs).
+gw_status qp_assign_dev(Handle* h, int M, int dim, const double* Ut, const double* E, double* qp_e, double* qp_w);
+
+gw_status fsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                   const double* L, const double* F0, gw_precision prec, const gw_opts* opts,
+                   const gw_fsgw_opts* fo, double* F, double* qp_e, double* qp_w, gw_fsgw_info* info);
 
 // Elementwise helpers (moments.hip)
 gw_status fill_f64(Handle* h, double* p, size_t n, double v);

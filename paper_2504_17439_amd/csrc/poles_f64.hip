@@ -110,9 +110,9 @@ __global__ void pack_poles_kernel(int M, int nd, int nk, const int* __restrict__
     else v_out[(long)p * ldv + col0 + t] = v[(long)p * nd + s];
 }
 
-// H~ = [[fock, W], [W^T, diag(e)]], W = v[:, :np] (row stride ldv)
+// H~ = [[fock, W], [W^T, diag(e + zeta)]], W = v[:, :np] (row stride ldv)
 __global__ void upfold_kernel(int M, int np, const double* __restrict__ fock, const double* __restrict__ e,
-                              const double* __restrict__ v, long ldv, double* __restrict__ H) {
+                              double zeta, const double* __restrict__ v, long ldv, double* __restrict__ H) {
     long dim = M + np;
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= dim * dim) return;
@@ -121,7 +121,7 @@ __global__ void upfold_kernel(int M, int np, const double* __restrict__ fock, co
     if (r < M && c < M) x = fock[r * M + c];
     else if (r < M) x = v[r * ldv + (c - M)];
     else if (c < M) x = v[c * ldv + (r - M)];
-    else if (r == c) x = e[r - M];
+    else if (r == c) x = e[r - M] + zeta;
     H[i] = x;
 }
 
@@ -490,8 +490,8 @@ gw_status poles_f64(Handle* h, int nmo, int nmom_max, const double* sigma_occ, c
     double* H = (double*)ws_get(h, WS_LZ6, sizeof(double) * (dim * dim + 2 * dim + 16));
     int* info = (int*)ws_get(h, WS_RPA_INFO, sizeof(int) * 64);
     if (!H || !info) return GW_ENOMEM;
-    hipLaunchKernelGGL(upfold_kernel, dim3(nblk(dim * dim)), dim3(256), 0, h->stream, M, np, fock, pole_e, pole_v,
-                       ldv, H);
+    hipLaunchKernelGGL(upfold_kernel, dim3(nblk(dim * dim)), dim3(256), 0, h->stream, M, np, fock, pole_e, 0.0,
+                       pole_v, ldv, H);
     GW_CHECK_LAUNCH(h);
     double* w = H + dim * dim;
     {
@@ -507,6 +507,50 @@ gw_status poles_f64(Handle* h, int nmo, int nmom_max, const double* sigma_occ, c
     hipLaunchKernelGGL(qp_kernel, dim3(M), dim3(256), 0, h->stream, M, (int)dim, H, w, qp_e, qp_w);
     GW_CHECK_LAUNCH(h);
     GW_HIP(h, hipStreamSynchronize(h->stream));
+    return GW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Helpers shared with the self-consistent loop
+// ---------------------------------------------------------------------------
+
+gw_status gemm_rowmajor(Handle* h, bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda,
+                        const double* B, int ldb, double beta, double* C, int ldc) {
+    return gemm_rm(h, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+gw_status eigh_rows(Handle* h, int n, double* A, double* w, double* work, int* info) {
+    Eig e{A, w, work, info};
+    return syevd(h, n, e, true);
+}
+
+gw_status poles_lanczos(Handle* h, int nmo, int nmom_max, const double* sigma_occ, const double* sigma_vir,
+                        const gw_opts* opts, double* pole_e, double* pole_v, long ldv, int* npole_occ,
+                        int* npole_vir) {
+    const double pinv_tol = (opts && opts->pinv_tol > 0) ? opts->pinv_tol : 1e-12;
+    const double neg_tol = (opts && opts->neg_tol > 0) ? opts->neg_tol : 1e-8;
+    const double kappa = (opts && opts->moment_eps > 0) ? opts->moment_eps / 2.220446049250313e-16 : 1.0;
+    GW_TRY(blas_ok(h, rocblas_set_stream(h->blas, h->stream), "rocblas_set_stream"));
+    int no = 0, nv = 0;
+    GW_TRY(lanczos_sector(h, nmo, nmom_max, sigma_occ, pinv_tol, neg_tol, kappa, pole_e, pole_v, ldv, 0, &no));
+    GW_TRY(lanczos_sector(h, nmo, nmom_max, sigma_vir, pinv_tol, neg_tol, kappa, pole_e, pole_v, ldv, no, &nv));
+    *npole_occ = no;
+    *npole_vir = nv;
+    return GW_OK;
+}
+
+gw_status upfold_eigh(Handle* h, int M, int np, const double* fock, const double* pole_e, double zeta,
+                      const double* pole_v, long ldv, double* H, double* w, double* work, int* info) {
+    const long dim = (long)M + np;
+    hipLaunchKernelGGL(upfold_kernel, dim3(nblk(dim * dim)), dim3(256), 0, h->stream, M, np, fock, pole_e, zeta,
+                       pole_v, ldv, H);
+    GW_CHECK_LAUNCH(h);
+    return eigh_rows(h, (int)dim, H, w, work, info);
+}
+
+gw_status qp_assign_dev(Handle* h, int M, int dim, const double* Ut, const double* E, double* qp_e, double* qp_w) {
+    hipLaunchKernelGGL(qp_kernel, dim3(M), dim3(256), 0, h->stream, M, dim, Ut, E, qp_e, qp_w);
+    GW_CHECK_LAUNCH(h);
     return GW_OK;
 }
 

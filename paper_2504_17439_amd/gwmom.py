@@ -26,7 +26,7 @@ _STATUS = {GW_EINVAL: "GW_EINVAL", GW_ENOMEM: "GW_ENOMEM", GW_EHIP: "GW_EHIP",
 # every symbol declared in include/gwmom.h
 EXPORTS = ("gw_create", "gw_set_stream", "gw_synchronize", "gw_destroy", "gw_last_error",
            "gw_moments_tda", "gw_moments_rpa", "gw_sigma_moments", "gw_sigma_from_R", "gw_poles",
-           "gw_timing_enable", "gw_timing_reset", "gw_timing_read")
+           "gw_fsgw", "gw_timing_enable", "gw_timing_reset", "gw_timing_read")
 
 
 class GWError(RuntimeError):
@@ -40,6 +40,17 @@ class Opts(ctypes.Structure):
                 ("pinv_tol", ctypes.c_double), ("neg_tol", ctypes.c_double),
                 ("bf16_slices", ctypes.c_int), ("zchunk_bytes", ctypes.c_size_t),
                 ("moment_eps", ctypes.c_double)]
+
+
+class FsgwOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("max_fock", ctypes.c_int),
+                ("fock_tol", ctypes.c_double), ("diis_space", ctypes.c_int), ("zeta_tol", ctypes.c_double),
+                ("zeta_lo", ctypes.c_double), ("zeta_hi", ctypes.c_double)]
+
+
+class FsgwInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("fock_steps", ctypes.c_int), ("eig_calls", ctypes.c_int),
+                ("converged", ctypes.c_int), ("zeta", ctypes.c_double), ("last_dqp", ctypes.c_double)]
 
 
 _lib = None
@@ -66,6 +77,7 @@ def load_library(path: str = LIB_PATH):
         "gw_sigma_moments": ([H, I, I, I, I, I, P, P, I, P, P, P], I),
         "gw_sigma_from_R": ([H, I, I, I, I, P, P, P, I, P, P, P], I),
         "gw_poles": ([H, I, I, P, P, P, P, ctypes.POINTER(I), ctypes.POINTER(I), P, P, P, P, P, P], I),
+        "gw_fsgw": ([H, I, I, I, I, I, P, P, P, I, P, P, P, P, P, P], I),
         "gw_timing_enable": ([H, I], I),
         "gw_timing_reset": ([H], I),
         "gw_timing_read": ([H, ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long)], I),
@@ -192,6 +204,33 @@ class Handle:
         self._call("gw_sigma_from_R", nocc, nmo - nocc, naux, nmom_max, _ptr(eps), _ptr(L), _ptr(R),
                    _prec(precision), _opts(opts), _ptr(so), _ptr(sv))
         return so, sv
+
+    # ------------------------------------------------------------------ fsGW
+    def fsgw(self, eps, L, nocc, nmom_max, screening="tda", precision="fp64", F0=None, opts=None,
+             fopts=None, allow_noconv=False):
+        """Self-consistent loop; returns dict(F, qp, qp_weight, iterations, fock_steps,
+        eig_calls, converged, zeta, last_dqp)."""
+        naux, nmo = L.shape[0], L.shape[1]
+        _check_dev(eps, "eps", (nmo,))
+        _check_dev(L, "L", (naux, nmo, nmo))
+        if F0 is not None:
+            _check_dev(F0, "F0", (nmo, nmo))
+        F = self._new(nmo, nmo)
+        qe, qw = self._new(nmo), self._new(nmo)
+        fo = FsgwOpts()
+        for k, v in dict(fopts or {}).items():
+            setattr(fo, k, v)
+        info = FsgwInfo()
+        scr = GW_TDA if screening == "tda" else GW_RPA
+        self._sync_stream()
+        st = self.lib.gw_fsgw(self.h, scr, nocc, nmo - nocc, naux, nmom_max, _ptr(eps), _ptr(L), _ptr(F0),
+                              _prec(precision), _opts(opts), ctypes.byref(fo), _ptr(F), _ptr(qe), _ptr(qw),
+                              ctypes.byref(info))
+        if st != GW_OK and not (st == GW_ENOCONV and allow_noconv):
+            raise GWError(st, self.lib.gw_last_error(self.h).decode())
+        return dict(F=F, qp=qe, qp_weight=qw, iterations=info.iterations, fock_steps=info.fock_steps,
+                    eig_calls=info.eig_calls, converged=bool(info.converged), zeta=info.zeta,
+                    last_dqp=info.last_dqp)
 
     # ------------------------------------------------------------------ poles
     def poles(self, sigma_occ, sigma_vir, fock, opts=None, want_chi=True):

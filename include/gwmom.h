@@ -68,8 +68,9 @@ typedef struct {
 
 /* Create a handle on HIP device `device` with its own non-blocking stream. */
 gw_status gw_create(gw_handle* h, int device);
-/* Use an existing hipStream_t (from the caller, e.g. a torch stream) instead
- * of the handle's own; NULL restores the handle's stream. */
+/* Run on an existing hipStream_t (from the caller, e.g. a torch stream)
+ * instead of the handle's own non-blocking stream; NULL selects the device's
+ * default (null) stream, so that work is ordered with a caller that uses it. */
 gw_status gw_set_stream(gw_handle h, void* hip_stream);
 gw_status gw_synchronize(gw_handle h);
 gw_status gw_destroy(gw_handle h);
@@ -203,6 +204,44 @@ gw_status gw_fsgw(gw_handle h, gw_screening screening, int nocc, int nvir, int n
                   int nmom_max, const double* eps, const double* L, const double* F0,
                   gw_precision prec, const gw_opts* opts, const gw_fsgw_opts* fopts,
                   double* F, double* qp_e, double* qp_w, gw_fsgw_info* info);
+
+/*
+ * Learned warm start for gw_fsgw (not in the paper): a per-orbital MLP
+ * 3 -> 128 -> 128 -> 128 -> 1 with SiLU after each hidden layer, FP32, that
+ * predicts s_p ~ F*_pp - eps_p (the diagonal of the converged Fock matrix in
+ * the reference basis) from the features of gw_mlp_features; the warm start
+ * is F0 = diag(eps + s).
+ * params: one flat float vector of gw_mlp_param_count() = 33665 values, in the
+ *   order W1 [128][3], b1 [128], W2 [128][128], b2, W3 [128][128], b3,
+ *   W4 [1][128], b4 (row-major, W[out][in]).
+ * norm [8] (device floats): input mean [3], input std [3], target mean,
+ *   target std.  Inputs are standardised, the output is mapped back to target
+ *   units: y = norm[6] + norm[7] * out; the loss is mean(((y - t)/norm[7])^2).
+ * act [6][rows][128]: z1, a1, z2, a2, z3, a3 of the forward pass (kept for
+ *   gw_mlp_backward); NULL in gw_mlp_forward uses library workspace.
+ * All pointers are device pointers; calls are asynchronous on the handle's
+ * stream.  GW_EINVAL for rows < 1 or null required pointers.
+ */
+long gw_mlp_param_count(void);
+
+/* feat [nmo][3] = (eps_p, sum_{P,q} L[P][p][q]^2, eps_p - (eps_{nocc-1} + eps_nocc)/2) */
+gw_status gw_mlp_features(gw_handle h, int nocc, int nvir, int naux, const double* eps,
+                          const double* L, float* feat);
+
+/* y [rows] from x [rows][3] */
+gw_status gw_mlp_forward(gw_handle h, int rows, const float* params, const float* norm,
+                         const float* x, float* act, float* y);
+
+/* grad [33665] of the loss at (x, target) from a forward pass (act, y) on the
+ * same x with the same params; loss [1] (nullable) receives the loss value. */
+gw_status gw_mlp_backward(gw_handle h, int rows, const float* params, const float* norm,
+                          const float* x, const float* act, const float* y,
+                          const float* target, float* grad, float* loss);
+
+/* One Adam step (step counts from 1, bias-corrected) on params with moment
+ * buffers m, v [33665] (zero before the first step). */
+gw_status gw_mlp_adam(gw_handle h, int step, float lr, float beta1, float beta2, float eps,
+                      float* params, const float* grad, float* m, float* v);
 
 /*
  * Per-kernel timing for measurement.  While enabled, every launch of the

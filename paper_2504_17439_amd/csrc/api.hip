@@ -146,7 +146,7 @@ gw_status gw_create(gw_handle* out, int device) {
 
 gw_status gw_set_stream(gw_handle h, void* s) {
     if (!h) return GW_EINVAL;
-    h->stream = s ? (hipStream_t)s : h->own_stream;
+    h->stream = (hipStream_t)s;  // NULL is the device's default (null) stream
     rocblas_set_stream(h->blas, h->stream);
     return GW_OK;
 }
@@ -294,6 +294,44 @@ gw_status gw_fsgw(gw_handle h, gw_screening screening, int nocc, int nvir, int n
         return gwm::set_err(h, GW_EINVAL, "gw_fsgw: negative option");
     return gwm::fsgw_run(h, screening, nocc, nvir, naux, nmom_max, eps, L, F0, prec, opts, fopts, F, qp_e, qp_w,
                          info);
+}
+
+long gw_mlp_param_count(void) { return gwm::mlp_param_count(); }
+
+gw_status gw_mlp_features(gw_handle h, int nocc, int nvir, int naux, const double* eps, const double* L,
+                          float* feat) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    if (nocc < 1 || nvir < 1 || naux < 1 || !eps || !L || !feat)
+        return gwm::set_err(h, GW_EINVAL, "gw_mlp_features: bad sizes or null pointer");
+    return gwm::mlp_features(h, nocc, nvir, naux, eps, L, feat);
+}
+
+gw_status gw_mlp_forward(gw_handle h, int rows, const float* params, const float* norm, const float* x, float* act,
+                         float* y) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    if (rows < 1 || !params || !norm || !x || !y) return gwm::set_err(h, GW_EINVAL, "gw_mlp_forward: bad arguments");
+    return gwm::mlp_forward(h, rows, params, norm, x, act, y);
+}
+
+gw_status gw_mlp_backward(gw_handle h, int rows, const float* params, const float* norm, const float* x,
+                          const float* act, const float* y, const float* target, float* grad, float* loss) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    if (rows < 1 || !params || !norm || !x || !act || !y || !target || !grad)
+        return gwm::set_err(h, GW_EINVAL, "gw_mlp_backward: bad arguments");
+    return gwm::mlp_backward(h, rows, params, norm, x, act, y, target, grad, loss);
+}
+
+gw_status gw_mlp_adam(gw_handle h, int step, float lr, float beta1, float beta2, float eps, float* params,
+                      const float* grad, float* m, float* v) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    if (step < 1 || !params || !grad || !m || !v || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) ||
+        !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        return gwm::set_err(h, GW_EINVAL, "gw_mlp_adam: bad arguments");
+    return gwm::mlp_adam(h, step, lr, beta1, beta2, eps, params, grad, m, v);
 }
 
 }  // extern "C"

@@ -195,6 +195,14 @@ gw_status fsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
                    const double* L, const double* F0, gw_precision prec, const gw_opts* opts,
                    const gw_fsgw_opts* fo, double* F, double* qp_e, double* qp_w, gw_fsgw_info* info);
 
+long mlp_param_count();
+gw_status mlp_features(Handle* h, int nocc, int nvir, int naux, const double* eps, const double* L, float* feat);
+gw_status mlp_forward(Handle* h, int rows, const float* prm, const float* norm, const float* x, float* act, float* y);
+gw_status mlp_backward(Handle* h, int rows, const float* prm, const float* norm, const float* x, const float* act,
+                       const float* y, const float* t, float* grad, float* loss);
+gw_status mlp_adam(Handle* h, int step, float lr, float b1, float b2, float eps, float* prm, const float* grad,
+                   float* m, float* v);
+
 // Elementwise helpers (moments.hip)
 gw_status fill_f64(Handle* h, double* p, size_t n, double v);
 gw_status copy_f64(Handle* h, double* dst, const double* src, size_t n);

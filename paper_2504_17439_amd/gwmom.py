@@ -26,7 +26,8 @@ _STATUS = {GW_EINVAL: "GW_EINVAL", GW_ENOMEM: "GW_ENOMEM", GW_EHIP: "GW_EHIP",
 # every symbol declared in include/gwmom.h
 EXPORTS = ("gw_create", "gw_set_stream", "gw_synchronize", "gw_destroy", "gw_last_error",
            "gw_moments_tda", "gw_moments_rpa", "gw_sigma_moments", "gw_sigma_from_R", "gw_poles",
-           "gw_fsgw", "gw_timing_enable", "gw_timing_reset", "gw_timing_read")
+           "gw_fsgw", "gw_mlp_param_count", "gw_mlp_features", "gw_mlp_forward", "gw_mlp_backward",
+           "gw_mlp_adam", "gw_timing_enable", "gw_timing_reset", "gw_timing_read")
 
 
 class GWError(RuntimeError):
@@ -78,6 +79,11 @@ def load_library(path: str = LIB_PATH):
         "gw_sigma_from_R": ([H, I, I, I, I, P, P, P, I, P, P, P], I),
         "gw_poles": ([H, I, I, P, P, P, P, ctypes.POINTER(I), ctypes.POINTER(I), P, P, P, P, P, P], I),
         "gw_fsgw": ([H, I, I, I, I, I, P, P, P, I, P, P, P, P, P, P], I),
+        "gw_mlp_param_count": ([], ctypes.c_long),
+        "gw_mlp_features": ([H, I, I, I, P, P, P], I),
+        "gw_mlp_forward": ([H, I, P, P, P, P, P], I),
+        "gw_mlp_backward": ([H, I, P, P, P, P, P, P, P, P], I),
+        "gw_mlp_adam": ([H, I, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P, P, P, P], I),
         "gw_timing_enable": ([H, I], I),
         "gw_timing_reset": ([H], I),
         "gw_timing_read": ([H, ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long)], I),
@@ -114,6 +120,11 @@ def _check_dev(t, name, shape=None):
         raise ValueError(f"{name} must be a contiguous float64 device tensor")
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _check_f32(t, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 device tensor")
 
 
 class Handle:
@@ -231,6 +242,36 @@ class Handle:
         return dict(F=F, qp=qe, qp_weight=qw, iterations=info.iterations, fock_steps=info.fock_steps,
                     eig_calls=info.eig_calls, converged=bool(info.converged), zeta=info.zeta,
                     last_dqp=info.last_dqp)
+
+    # ------------------------------------------------------------------ warm-start MLP
+    def _f32(self, *shape):
+        return torch.empty(*shape, dtype=torch.float32, device=f"cuda:{self.device}")
+
+    def mlp_features(self, eps, L, nocc):
+        naux, nmo = L.shape[0], L.shape[1]
+        _check_dev(eps, "eps", (nmo,))
+        _check_dev(L, "L", (naux, nmo, nmo))
+        feat = self._f32(nmo, 3)
+        self._call("gw_mlp_features", nocc, nmo - nocc, naux, _ptr(eps), _ptr(L), _ptr(feat))
+        return feat
+
+    def mlp_forward(self, params, norm, x, act=None):
+        rows = x.shape[0]
+        for t, n in ((params, "params"), (norm, "norm"), (x, "x")):
+            _check_f32(t, n)
+        y = self._f32(rows)
+        self._call("gw_mlp_forward", rows, _ptr(params), _ptr(norm), _ptr(x), _ptr(act), _ptr(y))
+        return y
+
+    def mlp_backward(self, params, norm, x, act, y, target, grad=None, loss=None):
+        rows = x.shape[0]
+        grad = self._f32(params.shape[0]) if grad is None else grad
+        self._call("gw_mlp_backward", rows, _ptr(params), _ptr(norm), _ptr(x), _ptr(act), _ptr(y), _ptr(target),
+                   _ptr(grad), _ptr(loss))
+        return grad
+
+    def mlp_adam(self, step, params, grad, m, v, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._call("gw_mlp_adam", step, lr, beta1, beta2, eps, _ptr(params), _ptr(grad), _ptr(m), _ptr(v))
 
     # ------------------------------------------------------------------ poles
     def poles(self, sigma_occ, sigma_vir, fock, opts=None, want_chi=True):

@@ -1,0 +1,212 @@
+"""Learned warm start for the fsGW loop (not in the paper).
+
+A per-orbital MLP (FP32 device kernels behind the C ABI: gw_mlp_features,
+gw_mlp_forward, gw_mlp_backward, gw_mlp_adam) predicts the diagonal shift
+s_p = F*_pp - eps_p of the converged fsGW Fock matrix in the reference basis
+from (eps_p, (L L^T)_pp, eps_p - mu_mid); the warm start is F0 = diag(eps + s).
+
+Data: synthetic systems from ``gwsynth`` with nmo = M, nocc = M/5,
+naux = round(3.5 M); targets from cold gw_fsgw solves on the device.
+
+    python -m paper_2504_17439_amd.warmstart --train 2000 --test 100
+
+prints one progress line per solve and a final JSON summary (cold vs warm
+outer iterations, Fock steps, eigensolves, QP agreement).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+import torch
+
+import gwsynth
+
+from . import gwmom
+
+SIZES = (3, 128, 128, 128, 1)
+
+
+def system_shape(M: int):
+    return M // 5, M - M // 5, int(round(3.5 * M))
+
+
+class WarmStartModel:
+    """Parameters, Adam state and normalisation of the MLP, on the device."""
+
+    def __init__(self, handle: gwmom.Handle, seed: int = 0):
+        self.h = handle
+        n = handle.lib.gw_mlp_param_count()
+        rng = np.random.default_rng(seed)
+        theta = []
+        for i in range(len(SIZES) - 1):
+            fan_in, fan_out = SIZES[i], SIZES[i + 1]
+            theta.append(rng.standard_normal(fan_out * fan_in) / np.sqrt(fan_in))
+            theta.append(np.zeros(fan_out))
+        theta = np.concatenate(theta).astype(np.float32)
+        assert theta.size == n
+        dev = f"cuda:{handle.device}"
+        self.params = torch.from_numpy(theta).to(dev)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.norm = torch.tensor([0, 0, 0, 1, 1, 1, 0, 1], dtype=torch.float32, device=dev)
+        self.step = 0
+
+    def set_norm(self, X: torch.Tensor, T: torch.Tensor):
+        """Standardisation from the training data (host statistics of a
+        [rows][3] feature matrix and its targets)."""
+        x = X.cpu().numpy().astype(np.float64)
+        t = T.cpu().numpy().astype(np.float64)
+        sx = np.maximum(x.std(axis=0), 1e-12)
+        st = max(t.std(), 1e-12)
+        vals = np.r_[x.mean(axis=0), sx, t.mean(), st].astype(np.float32)
+        self.norm = torch.from_numpy(vals).to(self.params.device)
+
+    def predict(self, X: torch.Tensor) -> torch.Tensor:
+        return self.h.mlp_forward(self.params, self.norm, X)
+
+    def train(self, X, T, epochs=200, batch=4096, lr=1e-3, seed=0, log=None):
+        rows = X.shape[0]
+        rng = np.random.default_rng(seed)
+        dev = self.params.device
+        act = torch.empty(6 * min(batch, rows) * 128, dtype=torch.float32, device=dev)
+        hist = []
+        for ep in range(epochs):
+            perm = torch.from_numpy(rng.permutation(rows)).to(dev)
+            tot, nb = 0.0, 0
+            for s in range(0, rows, batch):
+                idx = perm[s:s + batch]
+                xb = X.index_select(0, idx).contiguous()
+                tb = T.index_select(0, idx).contiguous()
+                y = self.h.mlp_forward(self.params, self.norm, xb, act=act)
+                self.h.mlp_backward(self.params, self.norm, xb, act, y, tb, grad=self.grad, loss=self.loss)
+                self.step += 1
+                self.h.mlp_adam(self.step, self.params, self.grad, self.m, self.v, lr=lr)
+                tot += float(self.loss.item())
+                nb += 1
+            hist.append(tot / nb)
+            if log and (ep % max(1, epochs // 10) == 0 or ep == epochs - 1):
+                log(f"epoch {ep} loss {hist[-1]:.4e}")
+        return hist
+
+    def warm_start(self, eps: torch.Tensor, L: torch.Tensor, nocc: int) -> torch.Tensor:
+        feat = self.h.mlp_features(eps, L, nocc)
+        s = self.predict(feat)
+        return torch.diag(eps + s.double()).contiguous()
+
+
+def generate(handle, seeds, sizes, nmom_max=5, log=None):
+    """Cold fsGW solves -> features [rows][3] and targets [rows] (device)."""
+    xs, ts, stats = [], [], []
+    for seed, M in zip(seeds, sizes):
+        o, v, A = system_shape(M)
+        eps, L = gwsynth.system(o, v, A, seed)
+        e = torch.from_numpy(eps).cuda(handle.device)
+        l = torch.from_numpy(L).cuda(handle.device)
+        t0 = time.time()
+        r = handle.fsgw(e, l, o, nmom_max, allow_noconv=True)
+        F = r["F"]
+        xs.append(handle.mlp_features(e, l, o))
+        ts.append((torch.diagonal(F) - e).float())
+        stats.append(dict(seed=seed, M=M, iterations=r["iterations"], converged=r["converged"]))
+        if log:
+            log(f"train system seed {seed} M {M}: {r['iterations']} iterations, {r['fock_steps']} Fock steps, "
+                f"{time.time() - t0:.1f}s")
+        del e, l
+    return torch.cat(xs).contiguous(), torch.cat(ts).contiguous(), stats
+
+
+def evaluate(handle, model, seeds, M, nmom_max=5, log=None):
+    o, v, A = system_shape(M)
+    out = []
+    for seed in seeds:
+        eps, L = gwsynth.system(o, v, A, seed)
+        e = torch.from_numpy(eps).cuda(handle.device)
+        l = torch.from_numpy(L).cuda(handle.device)
+        t0 = time.time()
+        cold = handle.fsgw(e, l, o, nmom_max, allow_noconv=True)
+        t1 = time.time()
+        F0 = model.warm_start(e, l, o)
+        warm = handle.fsgw(e, l, o, nmom_max, F0=F0, allow_noconv=True)
+        t2 = time.time()
+        shift_err = float((torch.diagonal(F0) - torch.diagonal(cold["F"])).abs().max())
+        dqp = float((warm["qp"].sort()[0] - cold["qp"].sort()[0]).abs().max())
+        rec = dict(seed=seed, M=M, cold_iterations=cold["iterations"], warm_iterations=warm["iterations"],
+                   cold_fock_steps=cold["fock_steps"], warm_fock_steps=warm["fock_steps"],
+                   cold_eigensolves=cold["eig_calls"], warm_eigensolves=warm["eig_calls"],
+                   cold_s=t1 - t0, warm_s=t2 - t1, max_diag_error=shift_err, max_qp_difference=dqp,
+                   converged=bool(cold["converged"] and warm["converged"]))
+        out.append(rec)
+        if log:
+            log(f"test system seed {seed}: cold {rec['cold_iterations']} it / {rec['cold_fock_steps']} Fock, "
+                f"warm {rec['warm_iterations']} it / {rec['warm_fock_steps']} Fock, diag error "
+                f"{shift_err:.2e}, QP difference {dqp:.1e}")
+        del e, l
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--train", type=int, default=2000, help="training systems (seeds 1..n)")
+    ap.add_argument("--test", type=int, default=100, help="test systems (seeds 10001..)")
+    ap.add_argument("--mmin", type=int, default=40)
+    ap.add_argument("--mmax", type=int, default=200)
+    ap.add_argument("--mtest", type=int, default=300)
+    ap.add_argument("--nmom", type=int, default=5)
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--save-data", default=None, help="write the training set (npz) and stop")
+    ap.add_argument("--load-data", default=None, help="train on a saved training set")
+    args = ap.parse_args(argv)
+
+    def log(msg):
+        print(f"[warmstart] {msg}", flush=True)
+
+    h = gwmom.Handle(0)
+    if args.load_data:
+        d = np.load(args.load_data)
+        X = torch.from_numpy(d["X"]).cuda()
+        T = torch.from_numpy(d["T"]).cuda()
+        gen = json.loads(str(d["meta"]))
+    else:
+        rng = np.random.default_rng(12345)
+        sizes = [int(5 * rng.integers(args.mmin // 5, args.mmax // 5 + 1)) for _ in range(args.train)]
+        X, T, stats = generate(h, list(range(1, args.train + 1)), sizes, args.nmom, log)
+        gen = dict(systems=args.train, rows=int(X.shape[0]), mean_cold_iterations=float(
+            np.mean([s["iterations"] for s in stats])))
+        if args.save_data:
+            np.savez(args.save_data, X=X.cpu().numpy(), T=T.cpu().numpy(), meta=json.dumps(gen))
+            log(f"saved {X.shape[0]} rows to {args.save_data}")
+            return 0
+    model = WarmStartModel(h, seed=0)
+    model.set_norm(X, T)
+    t0 = time.time()
+    hist = model.train(X, T, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
+    train_s = time.time() - t0
+    res = evaluate(h, model, list(range(10001, 10001 + args.test)), args.mtest, args.nmom, log)
+    ci = np.array([r["cold_iterations"] for r in res], dtype=float)
+    wi = np.array([r["warm_iterations"] for r in res], dtype=float)
+    cf = np.array([r["cold_fock_steps"] for r in res], dtype=float)
+    wf = np.array([r["warm_fock_steps"] for r in res], dtype=float)
+    summary = dict(
+        train=gen, train_loss_first=hist[0], train_loss_last=hist[-1], train_seconds=train_s,
+        test_systems=len(res), test_M=args.mtest, nmom_max=args.nmom,
+        cold_iterations_mean=float(ci.mean()), warm_iterations_mean=float(wi.mean()),
+        iteration_ratio=float(ci.mean() / wi.mean()),
+        cold_fock_steps_mean=float(cf.mean()), warm_fock_steps_mean=float(wf.mean()),
+        fock_step_ratio=float(cf.mean() / wf.mean()),
+        max_diag_error=float(max(r["max_diag_error"] for r in res)),
+        max_qp_difference=float(max(r["max_qp_difference"] for r in res)),
+        all_converged=all(r["converged"] for r in res))
+    print(json.dumps(summary), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

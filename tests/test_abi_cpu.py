@@ -12,7 +12,7 @@ HEADER = os.path.join(ROOT, "include", "gwmom.h")
 
 def declared_symbols():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:gw_status|const char\*)\s+(gw_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:gw_status|const char\*|long)\s+(gw_\w+)\s*\(", text, re.M)))
 
 
 def test_header_declares_the_abi():

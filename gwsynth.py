@@ -62,3 +62,30 @@ def batch_shapes(nsys: int = 64, seed: int = 0, nmo_lo: int = 60, nmo_hi: int = 
         nocc = int(round(nmo * occ_frac))
         out.append((nocc, nmo - nocc, int(round(aux_ratio * nmo))))
     return out
+
+
+def system_device(nocc: int, nvir: int, naux: int, seed: int = 0, device: str = "cuda:0",
+                  amp: float = AMP, decay: float = DECAY,
+                  occ_range=OCC_RANGE, vir_range=VIR_RANGE):
+    """The same recipe drawn on the device with torch's generator (for inputs
+    too large to draw on the host quickly).  The values differ from
+    ``system`` for the same seed; the distributions and structure do not."""
+    import torch
+    if nocc < 1 or nvir < 1 or naux < 1:
+        raise ValueError("nocc, nvir and naux must be >= 1")
+    nmo = nocc + nvir
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f64 = torch.float64
+    eo = torch.sort(torch.rand(nocc, generator=g, device=device, dtype=f64))[0]
+    ev = torch.sort(torch.rand(nvir, generator=g, device=device, dtype=f64))[0]
+    eps = torch.cat([occ_range[0] + (occ_range[1] - occ_range[0]) * eo,
+                     vir_range[0] + (vir_range[1] - vir_range[0]) * ev]).contiguous()
+    idx = torch.arange(nmo, device=device, dtype=f64)
+    envelope = (amp / np.sqrt(naux)) * torch.exp(-(idx[:, None] - idx[None, :]).abs() / decay) / np.sqrt(2.0)
+    L = torch.empty((naux, nmo, nmo), device=device, dtype=f64)
+    for P0 in range(0, naux, 64):
+        P1 = min(naux, P0 + 64)
+        G = torch.randn((P1 - P0, nmo, nmo), generator=g, device=device, dtype=f64)
+        L[P0:P1] = (G + G.transpose(1, 2)) * envelope
+    return eps, L

@@ -206,6 +206,49 @@ gw_status gw_fsgw(gw_handle h, gw_screening screening, int nocc, int nvir, int n
                   double* F, double* qp_e, double* qp_w, gw_fsgw_info* info);
 
 /*
+ * Batched self-energy moments for many molecules (as gw_sigma_moments for
+ * each).  gw_batch_create plans the batch once: per-molecule buffers; x
+ * chunks of each molecule ("jobs") whose stage-1 intermediates fit job_bytes;
+ * waves of consecutive jobs that fit wave_bytes.  In mixed precision each wave
+ * is one grouped, persistent launch per contraction stage over a work queue of
+ * (job, tile) items; contraction splits follow a work-item target
+ * (split_target, or with autotune the fastest of 256, 512, 1024, 2048 by
+ * timing the whole sequence).  The sequence is run once eagerly (the outputs
+ * are valid when create returns) and, for TDA screening unless no_graph is
+ * set, captured into a hipGraph; gw_batch_run replays it on the handle's
+ * current stream (RPA, or no_graph: re-enqueued).  Pointers in sys are used
+ * as given at creation: the caller keeps them alive and may change the
+ * contents of eps and L between runs.  Errors as gw_sigma_moments, checked
+ * for every molecule before anything runs; GW_ENOMEM if the plan's buffers do
+ * not fit.
+ */
+typedef struct {
+    int nocc, nvir, naux;
+    const double* eps;   /* device [nmo] */
+    const double* L;     /* device [naux][nmo][nmo] */
+    double* sigma_occ;   /* device [nmom_max+1][nmo][nmo] (output) */
+    double* sigma_vir;
+} gw_system;
+
+typedef struct {
+    size_t job_bytes;    /* stage-1 intermediates per job [4 GiB] */
+    size_t wave_bytes;   /* per grouped launch [24 GiB] */
+    int split_target;    /* contraction work items per job [512] */
+    int autotune;        /* 1: choose split_target by timing */
+    int no_graph;        /* 1: replay by re-enqueueing */
+} gw_batch_opts;
+
+typedef struct gw_batch_s* gw_batch;
+
+gw_status gw_batch_create(gw_handle h, int nsys, const gw_system* sys, gw_screening screening,
+                          int nmom_max, gw_precision prec, const gw_opts* opts,
+                          const gw_batch_opts* bopts, gw_batch* batch);
+gw_status gw_batch_run(gw_batch batch);
+/* Plan facts (host ints, each nullable): jobs, waves, graph captured (0/1), split target. */
+gw_status gw_batch_info(gw_batch batch, int* njobs, int* nwaves, int* graph, int* split_target);
+gw_status gw_batch_destroy(gw_batch batch);
+
+/*
  * Learned warm start for gw_fsgw (not in the paper): a per-orbital MLP
  * 3 -> 128 -> 128 -> 128 -> 1 with SiLU after each hidden layer, FP32, that
  * predicts s_p ~ F*_pp - eps_p (the diagonal of the converged Fock matrix in

@@ -296,6 +296,43 @@ gw_status gw_fsgw(gw_handle h, gw_screening screening, int nocc, int nvir, int n
                          info);
 }
 
+gw_status gw_batch_create(gw_handle h, int nsys, const gw_system* sys, gw_screening screening, int nmom_max,
+                          gw_precision prec, const gw_opts* opts, const gw_batch_opts* bopts, gw_batch* batch) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    if (!batch) return gwm::set_err(h, GW_EINVAL, "gw_batch_create: batch must be non-null");
+    *batch = nullptr;
+    if (nsys < 1 || !sys) return gwm::set_err(h, GW_EINVAL, "gw_batch_create: need at least one system");
+    if (screening != GW_TDA && screening != GW_RPA) return gwm::set_err(h, GW_EINVAL, "unknown screening");
+    GW_TRY(check_opts(h, prec, opts));
+    if (prec == GW_MIXED && nmom_max > 11)
+        return gwm::set_err(h, GW_EINVAL, "mixed precision: nmom_max must be <= 11");
+    if (prec == GW_MIXED && nmom_max % 2 == 0)
+        return gwm::set_err(h, GW_EINVAL, "mixed precision: nmom_max must be odd");
+    if (bopts && bopts->split_target < 0) return gwm::set_err(h, GW_EINVAL, "gw_batch_create: negative option");
+    for (int i = 0; i < nsys; ++i) {
+        GW_TRY(validate_common(h, sys[i].nocc, sys[i].nvir, sys[i].naux, nmom_max, sys[i].eps, sys[i].L));
+        if (!sys[i].sigma_occ || !sys[i].sigma_vir)
+            return gwm::set_err(h, GW_EINVAL, "gw_batch_create: sigma outputs must be non-null");
+    }
+    return gwm::batch_create(h, nsys, sys, screening, nmom_max, prec, opts, bopts, batch);
+}
+
+gw_status gw_batch_run(gw_batch batch) {
+    if (!batch) return GW_EINVAL;
+    return gwm::batch_run(batch);
+}
+
+gw_status gw_batch_info(gw_batch batch, int* njobs, int* nwaves, int* graph, int* split_target) {
+    if (!batch) return GW_EINVAL;
+    return gwm::batch_info(batch, njobs, nwaves, graph, split_target);
+}
+
+gw_status gw_batch_destroy(gw_batch batch) {
+    gwm::batch_destroy(batch);
+    return GW_OK;
+}
+
 long gw_mlp_param_count(void) { return gwm::mlp_param_count(); }
 
 gw_status gw_mlp_features(gw_handle h, int nocc, int nvir, int naux, const double* eps, const double* L,

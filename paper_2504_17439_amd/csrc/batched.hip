@@ -1,0 +1,475 @@
+// Batched self-energy moments for many molecules: a plan built once, replayed
+// as one captured hipGraph.
+//
+// Per molecule the path is that of gw_sigma_moments (density-response
+// moments, then the two contraction stages).  In mixed precision the two
+// contraction stages and the digitisation between them run as grouped,
+// persistent launches over a work queue of (molecule, x chunk, tile) items
+// from device job tables, so a batch of small and large molecules fills the
+// chip in one launch per stage instead of one under-filled launch per
+// molecule.  Jobs (x chunks of one molecule, each with its stage-1
+// intermediates) are packed into waves whose intermediates fit a byte cap;
+// every wave is one fold, one digitisation and one contraction launch.
+// Contraction splits S per job follow a work-item target, which the optional
+// autotuner picks from a candidate list by timing the whole sequence.
+// The recursions (and, in FP64, the contractions) run per molecule inside the
+// same graph.  The sequence is enqueued once eagerly (so that every shared
+// workspace slot reaches its final size) and then captured on the handle's
+// own stream; gw_batch_run replays the graph on the caller's stream.
+#include "mixed_jobs.h"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+struct gw_batch_s {
+    gwm::Handle* h = nullptr;
+    int nsys = 0, nmom_max = 0, nt = 0;
+    gw_screening screening = GW_TDA;
+    gw_precision prec = GW_MIXED;
+    gw_opts opts{};
+    bool has_opts = false;
+    std::vector<gw_system> sys;
+
+    struct Mol {
+        int nmo, Ap;
+        long M2, lplane, rrows, rplane;
+        double* R = nullptr;
+        gwm::u16* Ld = nullptr;
+        int* eL = nullptr;
+        gwm::u16* Rd = nullptr;
+        int* eR = nullptr;
+        double* part = nullptr;
+        int slots = 0;  // contraction split slots (all jobs of the molecule)
+    };
+    std::vector<Mol> mol;
+
+    struct Job {
+        int m, x0, x1;
+        long zrows;              // nt * ncol
+        size_t zt_off, zl_off, zd_off, ez_off;  // element offsets in the wave buffers
+        int S, slot0;
+    };
+    std::vector<Job> jobs;
+    std::vector<std::vector<int>> waves;  // job indices per wave
+
+    // device job tables per wave
+    struct WaveTab {
+        gwm::FoldJob* fold = nullptr;
+        gwm::ZdigJob* zdig = nullptr;
+        gwm::ContractArgs* con = nullptr;
+        int njobs = 0;
+        long fold_total = 0, zdig_total = 0, con_total = 0;
+    };
+    std::vector<WaveTab> tabs;
+
+    void* mem = nullptr;    // per-molecule buffers
+    void* zmem = nullptr;   // wave intermediates
+    void* tmem = nullptr;   // job tables
+    float* Zt = nullptr;
+    gwm::u16* Zl = nullptr;
+    gwm::u16* Zd = nullptr;
+    int* eZ = nullptr;
+
+    int ncu = 256;
+    int split_target = 512;
+    bool graph_ok = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace gwm {
+
+namespace {
+
+int contract_tiles(int nmo) {
+    const int T = (nmo + 127) / 128;
+    return T * (T + 1) / 2;
+}
+
+// S for a job of nx orbitals x: enough contraction work items for the target
+int job_split(const gw_batch_s* b, int nmo, int nx, int target) {
+    const int per = contract_tiles(nmo) * 2 * b->nt;
+    return std::max(1, std::min({64, nx, (target + per - 1) / per}));
+}
+
+// Build (or rebuild) the contraction split plan and the device job tables.
+gw_status build_tables(gw_batch_s* b, int target) {
+    Handle* h = b->h;
+    const int nt = b->nt;
+    for (auto& m : b->mol) m.slots = 0;
+    // every job's slots are assigned before any table is built: nsplit_total is final
+    for (auto& j : b->jobs) {
+        j.S = job_split(b, b->mol[j.m].nmo, j.x1 - j.x0, target);
+        j.slot0 = b->mol[j.m].slots;
+        b->mol[j.m].slots += j.S;
+    }
+    for (size_t w = 0; w < b->waves.size(); ++w) {
+        auto& tab = b->tabs[w];
+        const auto& ids = b->waves[w];
+        std::vector<FoldJob> fj;
+        std::vector<ZdigJob> zj;
+        std::vector<ContractArgs> cj;
+        long fi = 0, zi = 0, ci = 0;
+        for (int id : ids) {
+            const auto& j = b->jobs[id];
+            const auto& m = b->mol[j.m];
+            const gw_system& s = b->sys[j.m];
+            const long ncol = (long)(j.x1 - j.x0) * m.nmo;
+            float* Zt = b->Zt + j.zt_off;
+            u16* Zl = b->Zl + j.zl_off;
+            u16* Zd = b->Zd + j.zd_off;
+            int* eZ = b->eZ + j.ez_off;
+            FoldJob f = make_fold_job(m.Rd, m.eR, m.Ld, m.eL, s.eps, s.naux, m.Ap, m.nmo, s.nocc,
+                                      (long)j.x0 * m.nmo, ncol, m.rplane, m.lplane, Zt, Zl);
+            f.item0 = fi;
+            fi += (long)f.nP * f.nC;
+            fj.push_back(f);
+            ZdigJob z{j.zrows, m.Ap, Zt, Zl, eZ, Zd, zi};
+            zi += j.zrows;
+            zj.push_back(z);
+            ContractArgs a{};
+            a.Ld = m.Ld; a.lplane = m.lplane; a.eL = m.eL;
+            a.Zd = Zd; a.zplane = j.zrows * m.Ap; a.eZ = eZ;
+            a.nmo = m.nmo; a.Ap = m.Ap; a.naux = s.naux;
+            a.x0 = j.x0;
+            for (int sec = 0; sec < 2; ++sec) {
+                const int lo = sec == 0 ? 0 : s.nocc, hi = sec == 0 ? s.nocc : m.nmo;
+                const int xs0 = std::max(j.x0, lo), xs1 = std::min(j.x1, hi);
+                a.xs0[sec] = xs0;
+                a.nxs[sec] = std::max(0, xs1 - xs0);
+            }
+            a.nt = nt; a.nsplit = j.S; a.tiles_T = (m.nmo + 127) / 128; a.ncol = ncol;
+            a.part = m.part; a.nsplit_total = m.slots; a.split_off = j.slot0;
+            a.item0 = ci;
+            ci += (long)contract_tiles(m.nmo) * j.S * 2 * nt;
+            cj.push_back(a);
+        }
+        tab.njobs = (int)ids.size();
+        tab.fold_total = fi;
+        tab.zdig_total = zi;
+        tab.con_total = ci;
+        GW_HIP(h, hipMemcpy(tab.fold, fj.data(), sizeof(FoldJob) * fj.size(), hipMemcpyHostToDevice));
+        GW_HIP(h, hipMemcpy(tab.zdig, zj.data(), sizeof(ZdigJob) * zj.size(), hipMemcpyHostToDevice));
+        GW_HIP(h, hipMemcpy(tab.con, cj.data(), sizeof(ContractArgs) * cj.size(), hipMemcpyHostToDevice));
+    }
+    b->split_target = target;
+    return GW_OK;
+}
+
+// The whole launch sequence on h->stream.
+gw_status enqueue(gw_batch_s* b) {
+    Handle* h = b->h;
+    const int nt = b->nt;
+    const gw_opts* opts = b->has_opts ? &b->opts : nullptr;
+    if (b->prec == GW_MIXED)
+        for (auto& m : b->mol) GW_TRY(fill_f64(h, m.part, (size_t)2 * nt * m.slots * m.M2, 0.0));
+    for (int i = 0; i < b->nsys; ++i) {
+        const gw_system& s = b->sys[i];
+        auto& m = b->mol[i];
+        if (b->screening == GW_TDA)
+            GW_TRY(tda_moments_f64(h, s.nocc, s.nvir, s.naux, b->nmom_max, s.eps, s.L, m.R, nullptr));
+        else
+            GW_TRY(rpa_moments_f64(h, s.nocc, s.nvir, s.naux, b->nmom_max, s.eps, s.L, opts, m.R, nullptr));
+        if (b->prec == GW_MIXED) GW_TRY(mixed_prep(h, s.naux, m.nmo, nt, s.L, m.R, m.Ld, m.eL, m.Rd, m.eR));
+        else
+            GW_TRY(sigma_from_R_f64(h, s.nocc, s.nvir, s.naux, b->nmom_max, s.eps, s.L, m.R, opts, s.sigma_occ,
+                                    s.sigma_vir));
+    }
+    if (b->prec != GW_MIXED) return GW_OK;
+    for (auto& tab : b->tabs) {
+        {
+            KTimer tm(h, "sigma_fold");
+            GW_TRY(launch_fold_grouped(h, nt, tab.fold, tab.njobs, tab.fold_total, b->ncu));
+            tm.stop();
+        }
+        {
+            KTimer tm(h, "mixed_zdig");
+            GW_TRY(launch_zdig_grouped(h, tab.zdig, tab.njobs, tab.zdig_total));
+            tm.stop();
+        }
+        {
+            KTimer tm(h, "sigma_contract");
+            GW_TRY(launch_contract_grouped(h, tab.con, tab.njobs, tab.con_total, b->ncu));
+            tm.stop();
+        }
+    }
+    for (int i = 0; i < b->nsys; ++i) {
+        const auto& m = b->mol[i];
+        const gw_system& s = b->sys[i];
+        const long ps = m.M2;
+        GW_TRY(reduce_splits(h, m.part, m.slots, ps, nt, m.nmo, m.nmo, m.nmo, true, 1.0, 0.0, s.sigma_occ, m.M2,
+                             m.nmo));
+        GW_TRY(reduce_splits(h, m.part + (long)nt * m.slots * m.M2, m.slots, ps, nt, m.nmo, m.nmo, m.nmo, true, 1.0,
+                             0.0, s.sigma_vir, m.M2, m.nmo));
+    }
+    return GW_OK;
+}
+
+gw_status time_sequence(gw_batch_s* b, float* ms) {
+    Handle* h = b->h;
+    hipEvent_t e0, e1;
+    GW_HIP(h, hipEventCreate(&e0));
+    GW_HIP(h, hipEventCreate(&e1));
+    GW_HIP(h, hipEventRecord(e0, h->stream));
+    gw_status st = enqueue(b);
+    GW_HIP(h, hipEventRecord(e1, h->stream));
+    GW_HIP(h, hipEventSynchronize(e1));
+    GW_HIP(h, hipEventElapsedTime(ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+void release(gw_batch_s* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->mem) (void)hipFree(b->mem);
+    if (b->zmem) (void)hipFree(b->zmem);
+    if (b->tmem) (void)hipFree(b->tmem);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->mem = b->zmem = b->tmem = nullptr;
+}
+
+}  // namespace
+
+gw_status batch_create(Handle* h, int nsys, const gw_system* sys, gw_screening screening, int nmom_max,
+                       gw_precision prec, const gw_opts* opts, const gw_batch_opts* bo, gw_batch* out) {
+    using Job = gw_batch_s::Job;
+    auto* b = new (std::nothrow) gw_batch_s();
+    if (!b) return GW_ENOMEM;
+    b->h = h;
+    b->nsys = nsys;
+    b->nmom_max = nmom_max;
+    b->nt = nmom_max + 1;
+    b->screening = screening;
+    b->prec = prec;
+    if (opts) {
+        b->opts = *opts;
+        b->has_opts = true;
+    }
+    b->sys.assign(sys, sys + nsys);
+    const size_t job_bytes = (bo && bo->job_bytes) ? bo->job_bytes : ((size_t)4 << 30);
+    const size_t wave_bytes = std::max(job_bytes, (bo && bo->wave_bytes) ? bo->wave_bytes : ((size_t)24 << 30));
+    const bool want_graph = !(bo && bo->no_graph) && screening == GW_TDA;
+    const bool autotune = bo && bo->autotune && prec == GW_MIXED;
+    const int nt = b->nt;
+    (void)hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, h->device);
+
+    // ---- per-molecule plans and jobs
+    const int max_target = 2048;
+    size_t bytes = 0;
+    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    b->mol.resize(nsys);
+    for (int i = 0; i < nsys; ++i) {
+        auto& m = b->mol[i];
+        const gw_system& s = sys[i];
+        m.nmo = s.nocc + s.nvir;
+        m.Ap = mixed_Ap(s.naux);
+        m.M2 = (long)m.nmo * m.nmo;
+        m.lplane = m.M2 * m.Ap;
+        m.rrows = (long)nt * s.naux;
+        m.rplane = m.rrows * m.Ap;
+        if (prec == GW_MIXED && ((long)nt * s.naux * 64 >= (1L << 31) || m.M2 * 64 >= (1L << 31) || m.Ap > 4096)) {
+            release(b);
+            delete b;
+            return set_err(h, GW_EINVAL, "batch: a molecule exceeds the mixed-precision size limits");
+        }
+        bytes += align(sizeof(double) * nt * (size_t)s.naux * s.naux);
+        if (prec == GW_MIXED) {
+            bytes += align(sizeof(u16) * MIX_ND * m.lplane) + align(sizeof(int) * (m.M2 + m.rrows)) +
+                     align(sizeof(u16) * MIX_ND * m.rplane);
+            // stage-1 intermediates per x: FP32 + BF16 residual + ND digit planes, plus one exponent per row
+            const size_t per_x = (size_t)nt * m.nmo * ((size_t)m.Ap * (sizeof(float) + sizeof(u16) +
+                                                                      MIX_ND * sizeof(u16)) + sizeof(int));
+            int nx = (int)std::max<size_t>(1, std::min<size_t>((size_t)m.nmo, job_bytes / per_x));
+            nx = (int)std::max<long>(1, std::min<long>(nx, ((1L << 31) - 1) / ((long)nt * m.nmo * 64)));
+            int slots_max = 0;
+            for (int x0 = 0; x0 < m.nmo; x0 += nx) {
+                Job j{};
+                j.m = i;
+                j.x0 = x0;
+                j.x1 = std::min(m.nmo, x0 + nx);
+                j.zrows = (long)nt * (j.x1 - j.x0) * m.nmo;
+                b->jobs.push_back(j);
+                slots_max += job_split(b, m.nmo, j.x1 - j.x0, max_target);
+            }
+            bytes += align(sizeof(double) * 2 * nt * (size_t)slots_max * m.M2);
+            m.slots = slots_max;
+        }
+    }
+    // ---- waves: consecutive jobs while their intermediates fit wave_bytes
+    size_t zt_max = 0, zl_max = 0, zd_max = 0, ez_max = 0;
+    if (prec == GW_MIXED) {
+        size_t zt = 0, zl = 0, zd = 0, ez = 0, used = 0;
+        std::vector<int> cur;
+        for (size_t k = 0; k < b->jobs.size(); ++k) {
+            auto& j = b->jobs[k];
+            const size_t e = (size_t)j.zrows * b->mol[j.m].Ap;
+            const size_t jb = e * (sizeof(float) + sizeof(u16) + MIX_ND * sizeof(u16)) + sizeof(int) * j.zrows;
+            if (!cur.empty() && used + jb > wave_bytes) {
+                b->waves.push_back(cur);
+                cur.clear();
+                zt = zl = zd = ez = used = 0;
+            }
+            j.zt_off = zt;
+            j.zl_off = zl;
+            j.zd_off = zd;
+            j.ez_off = ez;
+            zt += (e + 63) & ~(size_t)63;
+            zl += (e + 127) & ~(size_t)127;
+            zd += MIX_ND * ((e + 127) & ~(size_t)127);
+            ez += (j.zrows + 63) & ~(size_t)63;
+            used += jb;
+            zt_max = std::max(zt_max, zt);
+            zl_max = std::max(zl_max, zl);
+            zd_max = std::max(zd_max, zd);
+            ez_max = std::max(ez_max, ez);
+            cur.push_back((int)k);
+        }
+        if (!cur.empty()) b->waves.push_back(cur);
+    }
+    // ---- allocation
+    if (hipMalloc(&b->mem, std::max<size_t>(bytes, 256)) != hipSuccess) {
+        (void)hipGetLastError();
+        release(b);
+        delete b;
+        return set_err(h, GW_ENOMEM, "batch: device allocation failed (" + std::to_string(bytes) + " bytes)");
+    }
+    {
+        char* p = (char*)b->mem;
+        for (int i = 0; i < nsys; ++i) {
+            auto& m = b->mol[i];
+            const gw_system& s = sys[i];
+            m.R = (double*)p;
+            p += align(sizeof(double) * nt * (size_t)s.naux * s.naux);
+            if (prec != GW_MIXED) continue;
+            m.Ld = (u16*)p;
+            p += align(sizeof(u16) * MIX_ND * m.lplane);
+            m.eL = (int*)p;
+            m.eR = m.eL + m.M2;
+            p += align(sizeof(int) * (m.M2 + m.rrows));
+            m.Rd = (u16*)p;
+            p += align(sizeof(u16) * MIX_ND * m.rplane);
+            m.part = (double*)p;
+            p += align(sizeof(double) * 2 * nt * (size_t)m.slots * m.M2);
+        }
+    }
+    if (prec == GW_MIXED) {
+        const size_t zb = sizeof(float) * zt_max + sizeof(u16) * (zl_max + zd_max) + sizeof(int) * ez_max + 4096;
+        const size_t nw = b->waves.size(), nj = b->jobs.size();
+        const size_t tb = (sizeof(FoldJob) + sizeof(ZdigJob) + sizeof(ContractArgs)) * nj + 3 * 256 * nw;
+        if (hipMalloc(&b->zmem, zb) != hipSuccess || hipMalloc(&b->tmem, tb) != hipSuccess) {
+            (void)hipGetLastError();
+            release(b);
+            delete b;
+            return set_err(h, GW_ENOMEM, "batch: wave buffer allocation failed");
+        }
+        char* p = (char*)b->zmem;
+        b->Zt = (float*)p;
+        p += align(sizeof(float) * zt_max);
+        b->Zl = (u16*)p;
+        p += align(sizeof(u16) * zl_max);
+        b->Zd = (u16*)p;
+        p += align(sizeof(u16) * zd_max);
+        b->eZ = (int*)p;
+        char* t = (char*)b->tmem;
+        b->tabs.resize(nw);
+        for (size_t w = 0; w < nw; ++w) {
+            const size_t n = b->waves[w].size();
+            b->tabs[w].fold = (FoldJob*)t;
+            t += align(sizeof(FoldJob) * n);
+            b->tabs[w].zdig = (ZdigJob*)t;
+            t += align(sizeof(ZdigJob) * n);
+            b->tabs[w].con = (ContractArgs*)t;
+            t += align(sizeof(ContractArgs) * n);
+        }
+    }
+
+    // ---- contraction split plan (optionally autotuned), eager warm-up
+    const bool timing = h->timing;
+    gw_status st = GW_OK;
+    if (prec == GW_MIXED) st = build_tables(b, (bo && bo->split_target > 0) ? bo->split_target : 512);
+    if (st == GW_OK) st = enqueue(b);  // grows the shared workspace to its final size
+    if (st == GW_OK) {
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) st = set_err(h, GW_EHIP, std::string("batch warm-up: ") + hipGetErrorString(e));
+    }
+    if (st == GW_OK && autotune) {
+        h->timing = false;
+        int best = b->split_target;
+        float best_ms = 1e30f;
+        for (int target : {256, 512, 1024, 2048}) {
+            st = build_tables(b, target);
+            float ms = 0.f;
+            if (st == GW_OK) st = time_sequence(b, &ms);
+            if (st != GW_OK) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = target;
+            }
+        }
+        if (st == GW_OK) st = build_tables(b, best);
+        h->timing = timing;
+    }
+    // ---- capture
+    if (st == GW_OK && want_graph) {
+        hipStream_t caller = h->stream;
+        h->stream = h->own_stream;
+        rocblas_set_stream(h->blas, h->stream);
+        h->timing = false;
+        hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed);
+        gw_status es = GW_OK;
+        if (e == hipSuccess) {
+            es = enqueue(b);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(h->stream, &g);
+            if (e == hipSuccess && es == GW_OK) {
+                b->graph = g;
+                e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+                b->graph_ok = (e == hipSuccess);
+            } else if (g) {
+                (void)hipGraphDestroy(g);
+            }
+        }
+        (void)hipGetLastError();
+        h->timing = timing;
+        h->stream = caller;
+        rocblas_set_stream(h->blas, h->stream);
+        if (!b->graph_ok) st = set_err(h, GW_EHIP, "batch: graph capture failed");
+    }
+    if (st != GW_OK) {
+        release(b);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return GW_OK;
+}
+
+gw_status batch_run(gw_batch b) {
+    Handle* h = b->h;
+    if (b->graph_ok) {
+        GW_HIP(h, hipGraphLaunch(b->exec, h->stream));
+        return GW_OK;
+    }
+    return enqueue(b);
+}
+
+gw_status batch_info(gw_batch b, int* njobs, int* nwaves, int* graph, int* split_target) {
+    if (njobs) *njobs = (int)b->jobs.size();
+    if (nwaves) *nwaves = (int)b->waves.size();
+    if (graph) *graph = b->graph_ok ? 1 : 0;
+    if (split_target) *split_target = b->split_target;
+    return GW_OK;
+}
+
+void batch_destroy(gw_batch b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->h->stream);
+    release(b);
+    delete b;
+}
+
+}  // namespace gwm

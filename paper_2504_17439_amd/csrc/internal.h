@@ -195,6 +195,12 @@ gw_status fsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
                    const double* L, const double* F0, gw_precision prec, const gw_opts* opts,
                    const gw_fsgw_opts* fo, double* F, double* qp_e, double* qp_w, gw_fsgw_info* info);
 
+gw_status batch_create(Handle* h, int nsys, const gw_system* sys, gw_screening screening, int nmom_max,
+                       gw_precision prec, const gw_opts* opts, const gw_batch_opts* bo, gw_batch* out);
+gw_status batch_run(gw_batch b);
+gw_status batch_info(gw_batch b, int* njobs, int* nwaves, int* graph, int* split_target);
+void batch_destroy(gw_batch b);
+
 long mlp_param_count();
 gw_status mlp_features(Handle* h, int nocc, int nvir, int naux, const double* eps, const double* L, float* feat);
 gw_status mlp_forward(Handle* h, int rows, const float* prm, const float* norm, const float* x, float* act, float* y);

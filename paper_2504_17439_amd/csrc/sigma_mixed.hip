@@ -20,7 +20,7 @@
 // accumulation error of ordinary split products.
 // The folded stage-1 result is stored as an FP32 value plus a BF16 residual
 // (~32 significant bits); stage 2 re-digitises it per (x, q) column.
-#include "internal.h"
+#include "mixed_jobs.h"
 
 #include <algorithm>
 #include <cmath>
@@ -29,18 +29,17 @@ namespace gwm {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef unsigned short u16;
 
 namespace {
 
-constexpr int MK = 32;        // k per MFMA (v_mfma_f32_16x16x32_bf16)
+constexpr int MK = MIX_MK;    // k per MFMA (v_mfma_f32_16x16x32_bf16)
 
 __device__ __forceinline__ u16 bf_bits(float f) {
     // exact for the digit values used here (<= 8 significant bits)
     return (u16)(__float_as_uint(f) >> 16);
 }
 
-constexpr int ND = 4;         // digits per operand
+constexpr int ND = MIX_ND;    // digits per operand
 constexpr int MAXW = 3;       // largest digit weight i + j kept in a product
 
 __device__ __forceinline__ void digitsN(double a, int e, u16* dg) {
@@ -153,37 +152,44 @@ __device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >>
 // (double buffering, 160 KB at NT = 12); moments are processed in groups so
 // that several independent accumulator chains interleave on the MFMA pipe.
 template <int NT>
-__global__ __launch_bounds__(256, 1) void fold_mixed_kernel(
-    const u16* __restrict__ Rd, const int* __restrict__ eR, const u16* __restrict__ Ld,
-    const int* __restrict__ eL, const double* __restrict__ eps, int naux, int Ap, int nmo, int nocc,
-    long j0, long ncol, long rplane, long lplane, float* __restrict__ Zt, u16* __restrict__ Zl) {
-    constexpr int A_ROWS = ND * NT * 16;              // (d, t, p) rows of the A slab
-    constexpr int B_ROWS = ND * 128;                  // (d, c) rows of the B slab
-    constexpr int SLAB = (A_ROWS + B_ROWS) * 32;      // u16 per buffer
-    __shared__ __attribute__((aligned(16))) u16 lds[2 * SLAB];
+struct FoldSlab {
+    static constexpr int A_ROWS = ND * NT * 16;  // (d, t, p) rows of the A slab
+    static constexpr int B_ROWS = ND * 128;      // (d, c) rows of the B slab
+    static constexpr int SLAB = (A_ROWS + B_ROWS) * 32;  // u16 per buffer
+};
+
+// Binary search of the job whose first work item is the largest <= item.
+template <typename Job>
+__device__ __forceinline__ int find_job(const Job* __restrict__ jobs, int njobs, long item) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].item0 <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+template <int NT>
+__device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, u16* lds) {
+    const u16* __restrict__ Rd = g.Rd;
+    const int* __restrict__ eR = g.eR;
+    const u16* __restrict__ Ld = g.Ld;
+    const int* __restrict__ eL = g.eL;
+    const double* __restrict__ eps = g.eps;
+    const int naux = g.naux, Ap = g.Ap, nmo = g.nmo, nocc = g.nocc;
+    const long j0 = g.j0, ncol = g.ncol, rplane = g.rplane, lplane = g.lplane;
+    float* __restrict__ Zt = g.Zt;
+    u16* __restrict__ Zl = g.Zl;
+    constexpr int A_ROWS = FoldSlab<NT>::A_ROWS;
+    constexpr int B_ROWS = FoldSlab<NT>::B_ROWS;
+    constexpr int SLAB = FoldSlab<NT>::SLAB;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int lr = lane & 15;
     const int lk = lane >> 4;
-    // XCD-aware grouped raster over (P-block, column tile): consecutive work
-    // groups land on different XCDs, so work group b runs on XCD b % 8; each XCD
-    // walks groups of 8 P-blocks x 4 column tiles, which share their L-digit
-    // (B) and R-digit (A) K slabs through that XCD's L2.
-    int pb, ct;
-    {
-        const int nP = Ap / 16;
-        const int nC = (int)((ncol + 127) / 128);
-        const int nPg = (nP + 7) / 8;
-        const int b = blockIdx.x;
-        const int xcd = b & 7, local = b >> 3;
-        const int g = (local >> 5) * 8 + xcd;          // group index
-        const int w = local & 31;
-        pb = (g % nPg) * 8 + (w & 7);
-        ct = (g / nPg) * 4 + (w >> 3);
-        if (pb >= nP || ct >= nC) return;
-    }
     const long c0 = (long)ct * 128;
     const int P0 = pb * 16;
 
@@ -346,18 +352,51 @@ __global__ __launch_bounds__(256, 1) void fold_mixed_kernel(
     }
 }
 
-// eZ[row] = scale exponent of max |Zt[row][0..Ap)| (one wave per row)
+// Single job: XCD-aware grouped raster over (P-block, column tile).  Work
+// group b runs on XCD b % 8; each XCD walks groups of 8 P-blocks x 4 column
+// tiles, which share their L-digit (B) and R-digit (A) slabs through its L2.
+template <int NT>
+__global__ __launch_bounds__(256, 1) void fold_mixed_kernel(FoldJob g) {
+    __shared__ __attribute__((aligned(16))) u16 lds[2 * FoldSlab<NT>::SLAB];
+    const int nPg = (g.nP + 7) / 8;
+    const int b = blockIdx.x;
+    const int xcd = b & 7, local = b >> 3;
+    const int grp = (local >> 5) * 8 + xcd;
+    const int w = local & 31;
+    const int pb = (grp % nPg) * 8 + (w & 7);
+    const int ct = (grp / nPg) * 4 + (w >> 3);
+    if (pb >= g.nP || ct >= g.nC) return;
+    fold_tile<NT>(g, pb, ct, lds);
+}
+
+// Grouped, persistent: work items (job, P-block, column tile) over all jobs;
+// the P-block index runs fastest so neighbouring items share a column tile.
+// LDS is free again at the start of each item: every wave has passed the last
+// barrier of the previous item's k loop before any wave reaches the new one.
+template <int NT>
+__global__ __launch_bounds__(256, 1) void fold_grouped_kernel(const FoldJob* __restrict__ jobs, int njobs,
+                                                              long total) {
+    __shared__ __attribute__((aligned(16))) u16 lds[2 * FoldSlab<NT>::SLAB];
+    for (long it = blockIdx.x; it < total; it += gridDim.x) {
+        const FoldJob g = jobs[find_job(jobs, njobs, it)];
+        const long local = it - g.item0;
+        fold_tile<NT>(g, (int)(local % g.nP), (int)(local / g.nP), lds);
+    }
+}
+
 // Stage-1 result to digits: per row r = n * ncol + c (one wave) the exponent
 // of max_P |Zt| and the digits of Zt + Zl (FP32 + BF16 residual) into the
 // k-blocked planes Zd[d] (rows = nt * ncol, k = P).  Each lane holds 8
 // consecutive P per 512-wide pass (Ap <= 64 * 8 * ZPASS), so reads are 32 + 16
 // bytes and every digit plane gets one 16-byte store per lane and pass.
 constexpr int ZPASS = 8;
-__global__ void zdig_kernel(long rows, int Ap, const float* __restrict__ Zt, const u16* __restrict__ Zl,
-                            int* __restrict__ eZ, u16* __restrict__ Zd) {
-    long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    int lane = threadIdx.x & 63;
-    if (row >= rows) return;
+__device__ __forceinline__ void zdig_row(const ZdigJob& g, long row, int lane) {
+    const long rows = g.rows;
+    const int Ap = g.Ap;
+    const float* __restrict__ Zt = g.Zt;
+    const u16* __restrict__ Zl = g.Zl;
+    int* __restrict__ eZ = g.eZ;
+    u16* __restrict__ Zd = g.Zd;
     const float* z = Zt + row * Ap;
     const u16* zl = Zl + row * Ap;
     float4 v[ZPASS][2];
@@ -384,14 +423,14 @@ __global__ void zdig_kernel(long rows, int Ap, const float* __restrict__ Zt, con
     for (int ps = 0; ps < ZPASS; ++ps) {
         const int c = ps * 512 + lane * 8;
         if (c >= Ap) continue;
-        const float hv[8] = {v[ps][0].x, v[ps][0].y, v[ps][0].z, v[ps][0].w,
-                             v[ps][1].x, v[ps][1].y, v[ps][1].z, v[ps][1].w};
-        const unsigned lw[4] = {w[ps].x, w[ps].y, w[ps].z, w[ps].w};
         u16 dg[8][ND];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const unsigned lb = (u & 1) ? (lw[u >> 1] & 0xffff0000u) : (lw[u >> 1] << 16);
-            digitsN((double)hv[u] + (double)__uint_as_float(lb), e, dg[u]);
+            const float4 vv = v[ps][u >> 2];
+            const float hv = (u & 3) == 0 ? vv.x : (u & 3) == 1 ? vv.y : (u & 3) == 2 ? vv.z : vv.w;
+            const unsigned lw = (u >> 1) == 0 ? w[ps].x : (u >> 1) == 1 ? w[ps].y : (u >> 1) == 2 ? w[ps].z : w[ps].w;
+            const unsigned lb = (u & 1) ? (lw & 0xffff0000u) : (lw << 16);
+            digitsN((double)hv + (double)__uint_as_float(lb), e, dg[u]);
         }
         const long o = ((long)(c >> 5) * rows + row) * 32 + (c & 31);
 #pragma unroll
@@ -400,6 +439,25 @@ __global__ void zdig_kernel(long rows, int Ap, const float* __restrict__ Zt, con
                 make_uint4(dg[0][d] | ((unsigned)dg[1][d] << 16), dg[2][d] | ((unsigned)dg[3][d] << 16),
                            dg[4][d] | ((unsigned)dg[5][d] << 16), dg[6][d] | ((unsigned)dg[7][d] << 16));
     }
+}
+
+__global__ __launch_bounds__(256) void zdig_kernel(ZdigJob g) {
+    const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row < g.rows) zdig_row(g, row, threadIdx.x & 63);
+}
+
+// Grouped: one wave per row over the rows of all jobs.
+__global__ __launch_bounds__(256) void zdig_grouped_kernel(const ZdigJob* __restrict__ jobs, int njobs, long total) {
+    const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= total) return;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].item0 <= row) lo = mid;
+        else hi = mid - 1;
+    }
+    const ZdigJob g = jobs[lo];
+    zdig_row(g, row - g.item0, threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------------------
@@ -414,41 +472,30 @@ __device__ inline void upper_tile2(int t, int T, int& bi, int& bj) {
     bj = r + t;
 }
 
-struct ContractArgs {
-    const u16* Ld; long lplane; const int* eL;  // L digit planes, k-blocked, rows (x, p) = nmo^2; exps per row
-    const u16* Zd; long zplane; const int* eZ;  // Z digit planes, k-blocked, rows (n, c) = nt * ncol; exps per row
-    int nmo, Ap, naux;
-    int x0;                                      // first x of the chunk
-    int xs0[2], nxs[2];                          // per sector: first x, count (within the chunk)
-    int nt, nsplit, tiles_T;
-    long ncol;
-    double* part;                                // [2][nt][nsplit][nmo][nmo] FP64, accumulated
-};
-
 // One work group: a 128 x 128 upper tile of Sigma^{(n)} for one sector and
 // one split of that sector's x range.  The (x, k-block) steps form one
 // double-buffered LDS-DMA pipeline; the FP32 digit-weight accumulators are
 // promoted to FP64 with the row and column scales at the end of every x.
-__global__ __launch_bounds__(256, 1) void contract_mixed_kernel(ContractArgs g) {
-    constexpr int ROWS = ND * 128;               // (d, i) rows of one operand slab
-    constexpr int OPS = ROWS * 32;               // u16 per operand slab (32 KB)
-    __shared__ __attribute__((aligned(16))) u16 lds[2 * 2 * OPS];
+constexpr int C_OPS = ND * 128 * 32;  // u16 per operand slab of stage 2 (32 KB)
+
+__device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, int split, int zi, u16* lds) {
+    constexpr int OPS = C_OPS;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int lr = lane & 15;
     const int lk = lane >> 4;
-    const int split = blockIdx.y;
-    const int n = blockIdx.z % g.nt;
-    const int sector = blockIdx.z / g.nt;
-    const int nxs = g.nxs[sector];
+    const int n = zi % g.nt;
+    const int sector = zi / g.nt;
+    const int nxs = sector ? g.nxs[1] : g.nxs[0];
+    const int xs0 = sector ? g.xs0[1] : g.xs0[0];
     if (nxs <= 0) return;
     int bi, bj;
-    upper_tile2(blockIdx.x, g.tiles_T, bi, bj);
+    upper_tile2(tile, g.tiles_T, bi, bj);
     const int m0 = bi * 128, n0 = bj * 128;
     const int per = (nxs + g.nsplit - 1) / g.nsplit;
-    const int xa = g.xs0[sector] + split * per;
-    const int xb = min(g.xs0[sector] + nxs, xa + per);
+    const int xa = xs0 + split * per;
+    const int xb = min(xs0 + nxs, xa + per);
     if (xa >= xb) return;
     const int M = g.nmo;
     const long M2 = (long)M * M;
@@ -565,7 +612,7 @@ __global__ __launch_bounds__(256, 1) void contract_mixed_kernel(ContractArgs g) 
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
     }
-    double* dst = g.part + (((long)sector * g.nt + n) * g.nsplit + split) * M2;
+    double* dst = g.part + (((long)sector * g.nt + n) * g.nsplit_total + g.split_off + split) * M2;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -581,18 +628,37 @@ __global__ __launch_bounds__(256, 1) void contract_mixed_kernel(ContractArgs g) 
         }
 }
 
+// One work group per (upper tile, split, sector * nt + n).
+__global__ __launch_bounds__(256, 1) void contract_mixed_kernel(ContractArgs g) {
+    __shared__ __attribute__((aligned(16))) u16 lds[2 * 2 * C_OPS];
+    contract_tile(g, blockIdx.x, blockIdx.y, blockIdx.z, lds);
+}
+
+// Grouped, persistent: work items (job, tile, split, sector * nt + n).  As in
+// stage 1, every wave has passed the last barrier of an item before any wave
+// starts loading the next one.
+__global__ __launch_bounds__(256, 1) void contract_grouped_kernel(const ContractArgs* __restrict__ jobs, int njobs,
+                                                                  long total) {
+    __shared__ __attribute__((aligned(16))) u16 lds[2 * 2 * C_OPS];
+    for (long it = blockIdx.x; it < total; it += gridDim.x) {
+        const ContractArgs g = jobs[find_job(jobs, njobs, it)];
+        const int tiles = g.tiles_T * (g.tiles_T + 1) / 2;
+        long local = it - g.item0;
+        const int tile = (int)(local % tiles);
+        local /= tiles;
+        const int split = (int)(local % g.nsplit);
+        const int zi = (int)(local / g.nsplit);
+        contract_tile(g, tile, split, zi, lds);
+    }
+}
+
 template <int NT>
-void launch_fold_mixed(Handle* h, const u16* Rd, const int* eR, const u16* Ld, const int* eL, const double* eps,
-                       int naux, int Ap, int nmo, int nocc, long j0, long ncol, long rplane, long lplane,
-                       float* Zt, u16* Zl) {
+void launch_fold_mixed(Handle* h, const FoldJob& g) {
     // every padded row P < Ap is written (zeros for P >= naux): stage 2 reads all Ap rows
     // groups of 8 P-blocks x 4 column tiles, 8 groups per round of the XCDs
-    const int nP = Ap / 16, nC = (int)((ncol + 127) / 128);
-    const long groups = (long)((nP + 7) / 8) * ((nC + 3) / 4);
+    const long groups = (long)((g.nP + 7) / 8) * ((g.nC + 3) / 4);
     const long rounds = (groups + 7) / 8;
-    dim3 grid((unsigned)(rounds * 8 * 32));
-    hipLaunchKernelGGL((fold_mixed_kernel<NT>), grid, dim3(256), 0, h->stream, Rd, eR, Ld, eL, eps, naux, Ap, nmo,
-                       nocc, j0, ncol, rplane, lplane, Zt, Zl);
+    hipLaunchKernelGGL((fold_mixed_kernel<NT>), dim3((unsigned)(rounds * 8 * 32)), dim3(256), 0, h->stream, g);
 }
 
 unsigned nb256(long n) { return (unsigned)((n + 255) / 256); }
@@ -619,18 +685,7 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
     u16* Rd = (u16*)ws_get(h, WS_MIX2, sizeof(u16) * ND * rplane);
     if (!Ld || !eL || !Rd) return GW_ENOMEM;
     int* eR = eL + M2;
-    {
-        KTimer tm(h, "mixed_prep");
-        hipLaunchKernelGGL(col_exp_kernel, dim3(nb256(M2)), dim3(256), 0, h->stream, naux, M2, L, eL);
-        hipLaunchKernelGGL(digits_lt_kernel, dim3((unsigned)((M2 + 31) / 32), (unsigned)((Ap + 31) / 32)),
-                           dim3(256), 0, h->stream, naux, M2, Ap, L, eL, Ld);
-        hipLaunchKernelGGL(row_exp_kernel, dim3((unsigned)((rrows + 3) / 4)), dim3(256), 0, h->stream, rrows,
-                           (long)naux, (long)naux, R, eR);
-        hipLaunchKernelGGL(digits_rows_kernel, dim3(nb256(rrows * Ap)), dim3(256), 0, h->stream, rrows, naux, Ap,
-                           R, eR, Rd);
-        tm.stop();
-        GW_CHECK_LAUNCH(h);
-    }
+    GW_TRY(mixed_prep(h, naux, nmo, nt, L, R, Ld, eL, Rd, eR));
     // --- chunk over x so that the stage-1 intermediates (FP32 + BF16 residual
     // and the ND digit planes) fit the cap
     size_t cap = (opts && opts->zchunk_bytes) ? opts->zchunk_bytes : ((size_t)16 << 30);
@@ -657,13 +712,15 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
         long j0 = (long)x0 * nmo;
         {
             KTimer tm(h, "sigma_fold");
+            const FoldJob fj =
+                make_fold_job(Rd, eR, Ld, eL, eps, naux, Ap, nmo, nocc, j0, ncol, rplane, lplane, Zt, Zl);
             switch (nt) {
-                case 2: launch_fold_mixed<2>(h, Rd, eR, Ld, eL, eps, naux, Ap, nmo, nocc, j0, ncol, rplane, lplane, Zt, Zl); break;
-                case 4: launch_fold_mixed<4>(h, Rd, eR, Ld, eL, eps, naux, Ap, nmo, nocc, j0, ncol, rplane, lplane, Zt, Zl); break;
-                case 6: launch_fold_mixed<6>(h, Rd, eR, Ld, eL, eps, naux, Ap, nmo, nocc, j0, ncol, rplane, lplane, Zt, Zl); break;
-                case 8: launch_fold_mixed<8>(h, Rd, eR, Ld, eL, eps, naux, Ap, nmo, nocc, j0, ncol, rplane, lplane, Zt, Zl); break;
-                case 10: launch_fold_mixed<10>(h, Rd, eR, Ld, eL, eps, naux, Ap, nmo, nocc, j0, ncol, rplane, lplane, Zt, Zl); break;
-                case 12: launch_fold_mixed<12>(h, Rd, eR, Ld, eL, eps, naux, Ap, nmo, nocc, j0, ncol, rplane, lplane, Zt, Zl); break;
+                case 2: launch_fold_mixed<2>(h, fj); break;
+                case 4: launch_fold_mixed<4>(h, fj); break;
+                case 6: launch_fold_mixed<6>(h, fj); break;
+                case 8: launch_fold_mixed<8>(h, fj); break;
+                case 10: launch_fold_mixed<10>(h, fj); break;
+                case 12: launch_fold_mixed<12>(h, fj); break;
                 default: return set_err(h, GW_EINVAL, "mixed precision: nmom_max+1 must be even and <= 12");
             }
             tm.stop();
@@ -672,8 +729,8 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
         const long zrows = (long)nt * ncol;
         {
             KTimer tm(h, "mixed_zdig");
-            hipLaunchKernelGGL(zdig_kernel, dim3((unsigned)((zrows + 3) / 4)), dim3(256), 0, h->stream, zrows, Ap, Zt,
-                               Zl, eZ, Zd);
+            const ZdigJob zj{zrows, Ap, Zt, Zl, eZ, Zd, 0};
+            hipLaunchKernelGGL(zdig_kernel, dim3((unsigned)((zrows + 3) / 4)), dim3(256), 0, h->stream, zj);
             tm.stop();
             GW_CHECK_LAUNCH(h);
         }
@@ -690,6 +747,7 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
         }
         a.nt = nt; a.nsplit = S; a.tiles_T = T; a.ncol = ncol;
         a.part = acc;
+        a.nsplit_total = S; a.split_off = 0; a.item0 = 0;
         {
             KTimer tm(h, "sigma_contract");
             dim3 grid((unsigned)tiles, (unsigned)S, (unsigned)(2 * nt));
@@ -700,6 +758,69 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
     }
     GW_TRY(reduce_splits(h, acc, S, M2, nt, nmo, nmo, nmo, true, 1.0, 0.0, sigma_occ, M2, nmo));
     GW_TRY(reduce_splits(h, acc + part_per_sector, S, M2, nt, nmo, nmo, nmo, true, 1.0, 0.0, sigma_vir, M2, nmo));
+    return GW_OK;
+}
+
+FoldJob make_fold_job(const u16* Rd, const int* eR, const u16* Ld, const int* eL, const double* eps, int naux,
+                      int Ap, int nmo, int nocc, long j0, long ncol, long rplane, long lplane, float* Zt, u16* Zl) {
+    FoldJob g;
+    g.Rd = Rd; g.eR = eR; g.Ld = Ld; g.eL = eL; g.eps = eps;
+    g.naux = naux; g.Ap = Ap; g.nmo = nmo; g.nocc = nocc;
+    g.j0 = j0; g.ncol = ncol; g.rplane = rplane; g.lplane = lplane;
+    g.Zt = Zt; g.Zl = Zl;
+    g.item0 = 0;
+    g.nP = Ap / 16;
+    g.nC = (int)((ncol + 127) / 128);
+    return g;
+}
+
+gw_status mixed_prep(Handle* h, int naux, int nmo, int nt, const double* L, const double* R, u16* Ld, int* eL,
+                     u16* Rd, int* eR) {
+    const long M2 = (long)nmo * nmo;
+    const int Ap = mixed_Ap(naux);
+    const long rrows = (long)nt * naux;
+    KTimer tm(h, "mixed_prep");
+    hipLaunchKernelGGL(col_exp_kernel, dim3(nb256(M2)), dim3(256), 0, h->stream, naux, M2, L, eL);
+    hipLaunchKernelGGL(digits_lt_kernel, dim3((unsigned)((M2 + 31) / 32), (unsigned)((Ap + 31) / 32)), dim3(256), 0,
+                       h->stream, naux, M2, Ap, L, eL, Ld);
+    hipLaunchKernelGGL(row_exp_kernel, dim3((unsigned)((rrows + 3) / 4)), dim3(256), 0, h->stream, rrows, (long)naux,
+                       (long)naux, R, eR);
+    hipLaunchKernelGGL(digits_rows_kernel, dim3(nb256(rrows * Ap)), dim3(256), 0, h->stream, rrows, naux, Ap, R, eR,
+                       Rd);
+    tm.stop();
+    GW_CHECK_LAUNCH(h);
+    return GW_OK;
+}
+
+gw_status launch_fold_grouped(Handle* h, int nt, const FoldJob* jobs, int njobs, long total, int grid) {
+    if (total <= 0) return GW_OK;
+    const dim3 g((unsigned)std::max<long>(1, std::min<long>(grid, total)));
+    switch (nt) {
+        case 2: hipLaunchKernelGGL((fold_grouped_kernel<2>), g, dim3(256), 0, h->stream, jobs, njobs, total); break;
+        case 4: hipLaunchKernelGGL((fold_grouped_kernel<4>), g, dim3(256), 0, h->stream, jobs, njobs, total); break;
+        case 6: hipLaunchKernelGGL((fold_grouped_kernel<6>), g, dim3(256), 0, h->stream, jobs, njobs, total); break;
+        case 8: hipLaunchKernelGGL((fold_grouped_kernel<8>), g, dim3(256), 0, h->stream, jobs, njobs, total); break;
+        case 10: hipLaunchKernelGGL((fold_grouped_kernel<10>), g, dim3(256), 0, h->stream, jobs, njobs, total); break;
+        case 12: hipLaunchKernelGGL((fold_grouped_kernel<12>), g, dim3(256), 0, h->stream, jobs, njobs, total); break;
+        default: return set_err(h, GW_EINVAL, "mixed precision: nmom_max+1 must be even and <= 12");
+    }
+    GW_CHECK_LAUNCH(h);
+    return GW_OK;
+}
+
+gw_status launch_zdig_grouped(Handle* h, const ZdigJob* jobs, int njobs, long total_rows) {
+    if (total_rows <= 0) return GW_OK;
+    hipLaunchKernelGGL(zdig_grouped_kernel, dim3((unsigned)((total_rows + 3) / 4)), dim3(256), 0, h->stream, jobs,
+                       njobs, total_rows);
+    GW_CHECK_LAUNCH(h);
+    return GW_OK;
+}
+
+gw_status launch_contract_grouped(Handle* h, const ContractArgs* jobs, int njobs, long total, int grid) {
+    if (total <= 0) return GW_OK;
+    const dim3 g((unsigned)std::max<long>(1, std::min<long>(grid, total)));
+    hipLaunchKernelGGL(contract_grouped_kernel, g, dim3(256), 0, h->stream, jobs, njobs, total);
+    GW_CHECK_LAUNCH(h);
     return GW_OK;
 }
 

@@ -26,7 +26,8 @@ _STATUS = {GW_EINVAL: "GW_EINVAL", GW_ENOMEM: "GW_ENOMEM", GW_EHIP: "GW_EHIP",
 # every symbol declared in include/gwmom.h
 EXPORTS = ("gw_create", "gw_set_stream", "gw_synchronize", "gw_destroy", "gw_last_error",
            "gw_moments_tda", "gw_moments_rpa", "gw_sigma_moments", "gw_sigma_from_R", "gw_poles",
-           "gw_fsgw", "gw_mlp_param_count", "gw_mlp_features", "gw_mlp_forward", "gw_mlp_backward",
+           "gw_fsgw", "gw_batch_create", "gw_batch_run", "gw_batch_info", "gw_batch_destroy",
+           "gw_mlp_param_count", "gw_mlp_features", "gw_mlp_forward", "gw_mlp_backward",
            "gw_mlp_adam", "gw_timing_enable", "gw_timing_reset", "gw_timing_read")
 
 
@@ -41,6 +42,17 @@ class Opts(ctypes.Structure):
                 ("pinv_tol", ctypes.c_double), ("neg_tol", ctypes.c_double),
                 ("bf16_slices", ctypes.c_int), ("zchunk_bytes", ctypes.c_size_t),
                 ("moment_eps", ctypes.c_double)]
+
+
+class System(ctypes.Structure):
+    _fields_ = [("nocc", ctypes.c_int), ("nvir", ctypes.c_int), ("naux", ctypes.c_int),
+                ("eps", ctypes.c_void_p), ("L", ctypes.c_void_p),
+                ("sigma_occ", ctypes.c_void_p), ("sigma_vir", ctypes.c_void_p)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("job_bytes", ctypes.c_size_t), ("wave_bytes", ctypes.c_size_t), ("split_target", ctypes.c_int),
+                ("autotune", ctypes.c_int), ("no_graph", ctypes.c_int)]
 
 
 class FsgwOpts(ctypes.Structure):
@@ -79,6 +91,10 @@ def load_library(path: str = LIB_PATH):
         "gw_sigma_from_R": ([H, I, I, I, I, P, P, P, I, P, P, P], I),
         "gw_poles": ([H, I, I, P, P, P, P, ctypes.POINTER(I), ctypes.POINTER(I), P, P, P, P, P, P], I),
         "gw_fsgw": ([H, I, I, I, I, I, P, P, P, I, P, P, P, P, P, P], I),
+        "gw_batch_create": ([H, I, P, I, I, I, P, P, ctypes.POINTER(ctypes.c_void_p)], I),
+        "gw_batch_run": ([P], I),
+        "gw_batch_info": ([P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)], I),
+        "gw_batch_destroy": ([P], I),
         "gw_mlp_param_count": ([], ctypes.c_long),
         "gw_mlp_features": ([H, I, I, I, P, P, P], I),
         "gw_mlp_forward": ([H, I, P, P, P, P, P], I),
@@ -243,6 +259,12 @@ class Handle:
                     eig_calls=info.eig_calls, converged=bool(info.converged), zeta=info.zeta,
                     last_dqp=info.last_dqp)
 
+    # ------------------------------------------------------------------ batches
+    def batch(self, systems, nmom_max, screening="tda", precision="mixed", opts=None, bopts=None):
+        """systems: list of (eps, L, nocc) device tensors.  Returns a Batch whose
+        .sigma[i] = (sigma_occ, sigma_vir) are filled at creation and by every run()."""
+        return Batch(self, systems, nmom_max, screening, precision, opts, bopts)
+
     # ------------------------------------------------------------------ warm-start MLP
     def _f32(self, *shape):
         return torch.empty(*shape, dtype=torch.float32, device=f"cuda:{self.device}")
@@ -294,3 +316,50 @@ class Handle:
         dim = nmo + no + nv
         return dict(e_occ=pe[:no], v_occ=pv[:, :no], e_vir=pe[no:no + nv], v_vir=pv[:, no:no + nv],
                     E=E[:dim], chi=None if chi is None else chi[:, :dim], qp=qe, qp_weight=qw)
+
+
+class Batch:
+    """A planned batch (gw_batch): the tensors it reads and writes stay referenced here."""
+
+    def __init__(self, handle, systems, nmom_max, screening, precision, opts, bopts):
+        self.handle = handle
+        self.inputs = []
+        self.sigma = []
+        arr = (System * len(systems))()
+        for i, (eps, L, nocc) in enumerate(systems):
+            naux, nmo = L.shape[0], L.shape[1]
+            _check_dev(eps, "eps", (nmo,))
+            _check_dev(L, "L", (naux, nmo, nmo))
+            so, sv = handle._new(nmom_max + 1, nmo, nmo), handle._new(nmom_max + 1, nmo, nmo)
+            self.inputs.append((eps, L))
+            self.sigma.append((so, sv))
+            arr[i] = System(nocc, nmo - nocc, naux, eps.data_ptr(), L.data_ptr(), so.data_ptr(), sv.data_ptr())
+        bo = BatchOpts()
+        for k, v in dict(bopts or {}).items():
+            setattr(bo, k, v)
+        self.b = ctypes.c_void_p()
+        scr = GW_TDA if screening == "tda" else GW_RPA
+        handle._call("gw_batch_create", len(systems), ctypes.cast(arr, ctypes.c_void_p), scr, nmom_max,
+                     _prec(precision), _opts(opts), ctypes.byref(bo), ctypes.byref(self.b))
+
+    def run(self):
+        self.handle._sync_stream()
+        st = self.handle.lib.gw_batch_run(self.b)
+        if st != GW_OK:
+            raise GWError(st, self.handle.lib.gw_last_error(self.handle.h).decode())
+
+    def info(self):
+        v = [ctypes.c_int(0) for _ in range(4)]
+        self.handle.lib.gw_batch_info(self.b, *[ctypes.byref(x) for x in v])
+        return dict(jobs=v[0].value, waves=v[1].value, graph=bool(v[2].value), split_target=v[3].value)
+
+    def close(self):
+        if getattr(self, "b", None) and self.b.value:
+            self.handle.lib.gw_batch_destroy(self.b)
+            self.b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

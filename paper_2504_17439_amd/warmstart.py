@@ -34,6 +34,11 @@ def system_shape(M: int):
     return M // 5, M - M // 5, int(round(3.5 * M))
 
 
+def system_size(seed: int, mmin: int, mmax: int) -> int:
+    """Training-system size for a seed: a multiple of 5, uniform in [mmin, mmax]."""
+    return int(5 * np.random.default_rng(seed + 7777).integers(mmin // 5, mmax // 5 + 1))
+
+
 class WarmStartModel:
     """Parameters, Adam state and normalisation of the MLP, on the device."""
 
@@ -152,7 +157,8 @@ def evaluate(handle, model, seeds, M, nmom_max=5, log=None):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--train", type=int, default=2000, help="training systems (seeds 1..n)")
+    ap.add_argument("--train", type=int, default=2000, help="training systems (seeds seed0 .. seed0+n-1)")
+    ap.add_argument("--seed0", type=int, default=1)
     ap.add_argument("--test", type=int, default=100, help="test systems (seeds 10001..)")
     ap.add_argument("--mmin", type=int, default=40)
     ap.add_argument("--mmax", type=int, default=200)
@@ -162,7 +168,7 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--save-data", default=None, help="write the training set (npz) and stop")
-    ap.add_argument("--load-data", default=None, help="train on a saved training set")
+    ap.add_argument("--load-data", default=None, help="train on saved training sets (comma-separated npz)")
     args = ap.parse_args(argv)
 
     def log(msg):
@@ -170,14 +176,17 @@ def main(argv=None):
 
     h = gwmom.Handle(0)
     if args.load_data:
-        d = np.load(args.load_data)
-        X = torch.from_numpy(d["X"]).cuda()
-        T = torch.from_numpy(d["T"]).cuda()
-        gen = json.loads(str(d["meta"]))
+        parts = [np.load(f) for f in args.load_data.split(",")]
+        X = torch.from_numpy(np.concatenate([d["X"] for d in parts])).cuda()
+        T = torch.from_numpy(np.concatenate([d["T"] for d in parts])).cuda()
+        metas = [json.loads(str(d["meta"])) for d in parts]
+        nsys = sum(m["systems"] for m in metas)
+        gen = dict(systems=nsys, rows=int(X.shape[0]), mean_cold_iterations=float(
+            sum(m["mean_cold_iterations"] * m["systems"] for m in metas) / nsys))
     else:
-        rng = np.random.default_rng(12345)
-        sizes = [int(5 * rng.integers(args.mmin // 5, args.mmax // 5 + 1)) for _ in range(args.train)]
-        X, T, stats = generate(h, list(range(1, args.train + 1)), sizes, args.nmom, log)
+        seeds = list(range(args.seed0, args.seed0 + args.train))
+        sizes = [system_size(s, args.mmin, args.mmax) for s in seeds]
+        X, T, stats = generate(h, seeds, sizes, args.nmom, log)
         gen = dict(systems=args.train, rows=int(X.shape[0]), mean_cold_iterations=float(
             np.mean([s["iterations"] for s in stats])))
         if args.save_data:

@@ -61,6 +61,22 @@ def cpu_baseline(o, v, A, N, seed):
                        f"({t2 - t1:.1f} s) x {N + 1} t-passes; same inputs, FP64 NumPy")}
 
 
+def recorded_traffic(o, v, A, N):
+    """HBM bytes per stage-1 launch from the committed rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), used only
+    for the workload they were taken on and while the kernel source is the one
+    they were taken with; otherwise None."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "fold_mixed_traffic.json")))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256") or (o, v, A, N) != (100, 400, 1500, 11):
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def bench_batched(args):
     """64-molecule batch (nmo uniform over multiples of 5 in [60, 400], nocc =
     nmo/5, naux = 3.5 nmo, TDA, nmom_max = 7, mixed): sets/s of the captured
@@ -215,6 +231,7 @@ def main():
         # ten BF16 digit products per algorithmic multiply-add are issued
         roofline["issued_tflops"] = 10 * achieved / 1e12
         roofline["issued_frac"] = 10 * achieved / peak
+        roofline["traffic"] = recorded_traffic(o, v, A, N)
 
     out = {
         "metric": "sigma_moment_sets_per_s",

@@ -180,8 +180,8 @@ def main():
     del L
     so = torch.empty(N + 1, M, M, dtype=torch.float64, device="cuda:0")
     sv = torch.empty_like(so)
-    fams_all = ("sigma_fold", "sigma_contract", "recur_xvt", "recur_rv", "recur_rr", "rpa_quad", "mixed_prep",
-                "mixed_zdig")
+    fams_all = ("sigma_fold", "sigma_contract", "recur_xvt", "recur_rv", "recur_rr", "recur_digits", "rpa_quad",
+                "mixed_prep", "mixed_zdig")
 
     def run(prec, steps, warmup):
         out = (torch.empty_like(so), torch.empty_like(sv))

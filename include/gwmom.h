@@ -83,8 +83,12 @@ const char* gw_last_error(gw_handle h);
  * Outputs:
  *   R   [nmom_max+1][naux][naux]          symmetric; required.
  *   eta [nmom_max+1][naux][nocc*nvir]     nullable.
- * prec must be GW_FP64 or GW_MIXED (mixed: BF16 split products, FP32
- * accumulation, per-moment scaling; results still returned in FP64).
+ * prec: GW_FP64 (FP64 MFMA), or GW_MIXED with eta NULL: the half-order
+ * products R_2k = X_k X_k^T, R_2k+1 = X_k D X_k^T + 2 R_k R_k and the updates
+ * X_k+1 = D o X_k + 2 R_k V use four-digit BF16 fixed-point operands (one
+ * power-of-two scale per row), exact FP32 accumulation of the leading digit
+ * products over 1024-long k chunks and FP64 combination (R_k R_k and X stay
+ * FP64); with eta requested the FP64 form is used.  R is returned in FP64.
  */
 gw_status gw_moments_tda(gw_handle h, int nocc, int nvir, int naux, int nmom_max,
                          const double* eps, const double* L, gw_precision prec,
@@ -93,8 +97,10 @@ gw_status gw_moments_tda(gw_handle h, int nocc, int nvir, int naux, int nmom_max
 /*
  * RPA density-response moments (Sec. 2.2): eta~^{(0)} = G D^-1 (I - 4 V^T
  * (I + 4 V D^-1 V^T)^-1 V D^-1) with G = G_main + G_offset by opts->nquad-point
- * mapped Gauss-Legendre quadrature (always FP64), eta~^{(1)} = V D,
- * eta~^{(n)} = eta~^{(n-2)} (D^2 + 4 V^T V D).  Outputs as gw_moments_tda.
+ * mapped Gauss-Legendre quadrature, eta~^{(1)} = V D,
+ * eta~^{(n)} = eta~^{(n-2)} (D^2 + 4 V^T V D).  Outputs as gw_moments_tda;
+ * computed in FP64 for either prec (in GW_MIXED only the self-energy stages
+ * of gw_sigma_moments use digit products).
  */
 gw_status gw_moments_rpa(gw_handle h, int nocc, int nvir, int naux, int nmom_max,
                          const double* eps, const double* L, gw_precision prec,
@@ -295,6 +301,7 @@ gw_status gw_mlp_adam(gw_handle h, int step, float lr, float beta1, float beta2,
  *   "recur_xvt"      R_n = eta~^{(n)} V^T
  *   "recur_rv"       eta~ updates  D o X + c R V
  *   "recur_rr"       2 R_k R_k terms of the half-order TDA moments
+ *   "recur_digits"   (mixed precision) scales and digit planes of the recursion operands
  *   "rpa_quad"       RPA quadrature products (Q/T matrices and the G product)
  *   "mixed_prep"     (mixed precision) scales and digit planes of L and R_t
  *   "mixed_zdig"     (mixed precision) scales and digit planes of the stage-1 result

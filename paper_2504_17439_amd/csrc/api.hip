@@ -213,6 +213,7 @@ gw_status gw_moments_tda(gw_handle h, int nocc, int nvir, int naux, int nmom_max
     GW_TRY(validate_common(h, nocc, nvir, naux, nmom_max, eps, L));
     GW_TRY(check_opts(h, prec, opts));
     if (!R) return gwm::set_err(h, GW_EINVAL, "R must be non-null");
+    if (prec == GW_MIXED && !eta) return gwm::tda_moments_mixed(h, nocc, nvir, naux, nmom_max, eps, L, R);
     return gwm::tda_moments_f64(h, nocc, nvir, naux, nmom_max, eps, L, R, eta);
 }
 
@@ -253,7 +254,9 @@ gw_status gw_sigma_moments(gw_handle h, gw_screening screening, int nocc, int nv
     const long n2 = (long)naux * naux;
     double* R = (double*)gwm::ws_get(h, gwm::WS_R, sizeof(double) * (nmom_max + 1) * n2);
     if (!R) return GW_ENOMEM;
-    if (screening == GW_TDA)
+    if (screening == GW_TDA && prec == GW_MIXED)
+        GW_TRY(gwm::tda_moments_mixed(h, nocc, nvir, naux, nmom_max, eps, L, R));
+    else if (screening == GW_TDA)
         GW_TRY(gwm::tda_moments_f64(h, nocc, nvir, naux, nmom_max, eps, L, R, nullptr));
     else
         GW_TRY(gwm::rpa_moments_f64(h, nocc, nvir, naux, nmom_max, eps, L, opts, R, nullptr));

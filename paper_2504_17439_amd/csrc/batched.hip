@@ -167,7 +167,9 @@ gw_status enqueue(gw_batch_s* b) {
     for (int i = 0; i < b->nsys; ++i) {
         const gw_system& s = b->sys[i];
         auto& m = b->mol[i];
-        if (b->screening == GW_TDA)
+        if (b->screening == GW_TDA && b->prec == GW_MIXED)
+            GW_TRY(tda_moments_mixed(h, s.nocc, s.nvir, s.naux, b->nmom_max, s.eps, s.L, m.R));
+        else if (b->screening == GW_TDA)
             GW_TRY(tda_moments_f64(h, s.nocc, s.nvir, s.naux, b->nmom_max, s.eps, s.L, m.R, nullptr));
         else
             GW_TRY(rpa_moments_f64(h, s.nocc, s.nvir, s.naux, b->nmom_max, s.eps, s.L, opts, m.R, nullptr));

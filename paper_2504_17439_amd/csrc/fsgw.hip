@@ -268,7 +268,8 @@ gw_status fsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
         GW_TRY(gemm_rowmajor(h, false, true, M, M, M, 1.0, hcore, M, Ut, M, 0.0, tmp, M));
         GW_TRY(gemm_rowmajor(h, false, false, M, M, M, 1.0, Ut, M, tmp, M, 0.0, hc, M));
         // self-energy moments and auxiliary poles in this basis
-        if (screening == GW_TDA) GW_TRY(tda_moments_f64(h, nocc, nvir, A, nmom_max, ecur, Lc, R, nullptr));
+        if (screening == GW_TDA && prec == GW_MIXED) GW_TRY(tda_moments_mixed(h, nocc, nvir, A, nmom_max, ecur, Lc, R));
+        else if (screening == GW_TDA) GW_TRY(tda_moments_f64(h, nocc, nvir, A, nmom_max, ecur, Lc, R, nullptr));
         else GW_TRY(rpa_moments_f64(h, nocc, nvir, A, nmom_max, ecur, Lc, opts, R, nullptr));
         if (prec == GW_MIXED) GW_TRY(sigma_from_R_mixed(h, nocc, nvir, A, nmom_max, ecur, Lc, R, opts, so, sv));
         else GW_TRY(sigma_from_R_f64(h, nocc, nvir, A, nmom_max, ecur, Lc, R, opts, so, sv));

@@ -47,6 +47,7 @@ enum WsSlot {
     WS_LZ0, WS_LZ1, WS_LZ2, WS_LZ3, WS_LZ4, WS_LZ5, WS_LZ6, WS_LZ7,
     WS_MIX0, WS_MIX1, WS_MIX2, WS_MIX3, WS_MIX4, WS_MIX5, WS_MIX6,
     WS_FS0, WS_FS1, WS_FS2, WS_FS3, WS_FS4, WS_FS5, WS_FS6, WS_FS7,
+    WS_RC0, WS_RC1, WS_RC2, WS_RC3, WS_RC4, WS_RC5,
     WS_COUNT
 };
 
@@ -160,6 +161,10 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
 
 gw_status tda_moments_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max,
                           const double* eps, const double* L, double* R, double* eta);
+
+// TDA moments R[nmom_max+1][naux][naux] with digit-split (BF16 / FP32 / FP64) products.
+gw_status tda_moments_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_max,
+                            const double* eps, const double* L, double* R);
 
 gw_status rpa_moments_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max,
                           const double* eps, const double* L, const gw_opts* opts,

@@ -64,12 +64,14 @@ __device__ __forceinline__ int scale_exp(double amax) {
 // ---------------------------------------------------------------------------
 
 // Row exponents of a row-major [rows][cols] FP64 matrix (one wave per row).
-__global__ void row_exp_kernel(long rows, long cols, long ld, const double* __restrict__ X, int* __restrict__ e) {
+// With cs non-null the matrix is X[row][c] * cs[c].
+__global__ void row_exp_kernel(long rows, long cols, long ld, const double* __restrict__ X,
+                               const double* __restrict__ cs, int* __restrict__ e) {
     long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
     int lane = threadIdx.x & 63;
     if (row >= rows) return;
     double m = 0.0;
-    for (long c = lane; c < cols; c += 64) m = fmax(m, fabs(X[row * ld + c]));
+    for (long c = lane; c < cols; c += 64) m = fmax(m, fabs(X[row * ld + c] * (cs ? cs[c] : 1.0)));
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
     if (lane == 0) e[row] = scale_exp(m);
 }
@@ -89,13 +91,14 @@ __global__ void col_exp_kernel(int naux, long ncol, const double* __restrict__ L
 
 // R digits: Rd[d] k-blocked over rows = nt*naux (row = t*naux + P), zero padded in Q.
 __global__ void digits_rows_kernel(long rows, int cols, int Ap, const double* __restrict__ X,
-                                   const int* __restrict__ e, u16* __restrict__ Xd) {
+                                   const double* __restrict__ cs, const int* __restrict__ e,
+                                   u16* __restrict__ Xd) {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= rows * Ap) return;
     long row = i / Ap;
     int c = (int)(i - row * Ap);
     u16 dg[ND] = {};
-    if (c < cols) digitsN(X[row * cols + c], e[row], dg);
+    if (c < cols) digitsN(X[row * cols + c] * (cs ? cs[c] : 1.0), e[row], dg);
     long plane = rows * (long)Ap;
     long o = ((long)(c >> 5) * rows + row) * 32 + (c & 31);
 #pragma unroll
@@ -652,6 +655,177 @@ __global__ __launch_bounds__(256, 1) void contract_grouped_kernel(const Contract
     }
 }
 
+// ---------------------------------------------------------------------------
+// Digit GEMM: C[m][n] = sum_k A[m][k] B[n][k] with A, B given as k-blocked digit
+// planes with one exponent per row (the digit format above).  FP32 digit-
+// weight accumulators are promoted to FP64 every kc k-blocks (kc * 32 <= 1024
+// keeps the weight-0 sums exact).  128 x 128 tiles, 4 waves of 64 x 64, the
+// same LDS-DMA pipeline as stage 2.  Epilogues: FP64 split partials (upper
+// tiles only when sym) or Xout = Dv[n] * Xin + alpha * C (in place allowed).
+// ---------------------------------------------------------------------------
+struct DgemmArgs {
+    const u16* A;
+    long aplane;
+    int arows;
+    const int* eA;
+    const u16* B;
+    long bplane;
+    int brows;
+    const int* eB;
+    int M, N, nkb;    // output rows / cols; k-blocks of 32
+    int nsplit, kc;   // splits of the k-block range; promotion interval (k-blocks)
+    int sym, tilesN;  // upper tiles only (M == N); column tiles
+    double* part;     // [nsplit][M][N] (Xout == nullptr)
+    double* Xout;
+    const double* Xin;
+    const double* Dv;
+    double alpha;
+};
+
+// W22: also keep the weight-4 product d2 x d2.  In a Gram product (A = B) its
+// diagonal terms are squares and accumulate coherently over k (to ~2e-8 of the
+// result for rows with a wide dynamic range); every other dropped product has
+// random sign.
+template <bool W22>
+__device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int split, u16* lds) {
+    constexpr int OPS = C_OPS;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int lr = lane & 15;
+    const int lk = lane >> 4;
+    int bi, bj;
+    if (g.sym) upper_tile2(tile, g.tilesN, bi, bj);
+    else {
+        bi = tile / g.tilesN;
+        bj = tile - bi * g.tilesN;
+    }
+    const int m0 = bi * 128, n0 = bj * 128;
+    const int per = (g.nkb + g.nsplit - 1) / g.nsplit;
+    const int ka = split * per;
+    const int kb_end = min(g.nkb, ka + per);
+    const int total = kb_end - ka;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const int lrow = lane >> 2;
+    const int gch = swz(lrow, lane & 3);
+    unsigned offA[2], offB[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int i = h * 64 + wv * 16 + lrow;
+        offA[h] = (unsigned)(min(m0 + i, g.M - 1) * 32 + gch * 8) * 2u;
+        offB[h] = (unsigned)(min(n0 + i, g.N - 1) * 32 + gch * 8) * 2u;
+    }
+    auto load = [&](int kb, int buf) {
+        u16* A = lds + buf * 2 * OPS + wv * 16 * 32;
+        u16* B = A + OPS;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(g.A + (s >> 1) * g.aplane + (long)kb * g.arows * 32), (short)0, g.arows * 64, 0x00020000);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(A + s * 64 * 32),
+                                                     16, offA[s & 1], 0, 0, 0);
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(g.B + (s >> 1) * g.bplane + (long)kb * g.brows * 32), (short)0, g.brows * 64, 0x00020000);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(B + s * 64 * 32),
+                                                     16, offB[s & 1], 0, 0, 0);
+        }
+    };
+    double acc64[4][4][4];
+    f32x4 acc0[4][4], acc1[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            acc0[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            acc1[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
+        }
+    const int so = swz(lr, lk) * 8;
+    if (total > 0) {
+        load(ka, 0);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+    }
+    int since = 0;
+    for (int it = 0; it < total; ++it) {
+        const int cur = it & 1;
+        if (it + 1 < total) load(ka + it + 1, cur ^ 1);
+        const u16* A = lds + cur * 2 * OPS;
+        const u16* B = A + OPS;
+        bf16x8 b[4][ND];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int d = 0; d < ND; ++d) b[j][d] = *(const bf16x8*)(B + (d * 128 + wn + j * 16 + lr) * 32 + so);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bf16x8 a[ND];
+#pragma unroll
+            for (int d = 0; d < ND; ++d) a[d] = *(const bf16x8*)(A + (d * 128 + wm + i * 16 + lr) * 32 + so);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc0[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][0], acc0[i][j], 0, 0, 0);
+#pragma unroll
+            for (int w = 1; w <= MAXW; ++w)
+#pragma unroll
+                for (int ii = 0; ii <= w; ++ii)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (ii < ND && w - ii < ND)
+                            acc1[i][j] =
+                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ii], b[j][w - ii], acc1[i][j], 0, 0, 0);
+            if (W22)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[j][2], acc1[i][j], 0, 0, 0);
+        }
+        if (++since == g.kc || it + 1 == total) {
+            // promote: the row / column exponents are constant along k
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc0[i][j][r] + (double)acc1[i][j][r];
+                    acc0[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+                    acc1[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+                }
+            since = 0;
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+    }
+    // scale by 2^(e_row + e_col) once, then the epilogue
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = n0 + wn + j * 16 + lr;
+        if (col >= g.N) continue;
+        const int ec = g.eB[col];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm + i * 16 + 4 * lk + r;
+                if (row >= g.M) continue;
+                const double c = ldexp(acc64[i][j][r], g.eA[row] + ec);
+                const long o = (long)row * g.N + col;
+                if (g.Xout) g.Xout[o] = g.Dv[col] * g.Xin[o] + g.alpha * c;
+                else g.part[(long)split * g.M * g.N + o] = c;
+            }
+    }
+}
+
+template <bool W22>
+__global__ __launch_bounds__(256, 1) void dgemm_mixed_kernel(DgemmArgs g) {
+    __shared__ __attribute__((aligned(16))) u16 lds[2 * 2 * C_OPS];
+    dgemm_tile<W22>(g, blockIdx.x, blockIdx.y, lds);
+}
+
 template <int NT>
 void launch_fold_mixed(Handle* h, const FoldJob& g) {
     // every padded row P < Ap is written (zeros for P >= naux): stage 2 reads all Ap rows
@@ -784,9 +958,9 @@ gw_status mixed_prep(Handle* h, int naux, int nmo, int nt, const double* L, cons
     hipLaunchKernelGGL(digits_lt_kernel, dim3((unsigned)((M2 + 31) / 32), (unsigned)((Ap + 31) / 32)), dim3(256), 0,
                        h->stream, naux, M2, Ap, L, eL, Ld);
     hipLaunchKernelGGL(row_exp_kernel, dim3((unsigned)((rrows + 3) / 4)), dim3(256), 0, h->stream, rrows, (long)naux,
-                       (long)naux, R, eR);
-    hipLaunchKernelGGL(digits_rows_kernel, dim3(nb256(rrows * Ap)), dim3(256), 0, h->stream, rrows, naux, Ap, R, eR,
-                       Rd);
+                       (long)naux, R, (const double*)nullptr, eR);
+    hipLaunchKernelGGL(digits_rows_kernel, dim3(nb256(rrows * Ap)), dim3(256), 0, h->stream, rrows, naux, Ap, R,
+                       (const double*)nullptr, eR, Rd);
     tm.stop();
     GW_CHECK_LAUNCH(h);
     return GW_OK;
@@ -821,6 +995,134 @@ gw_status launch_contract_grouped(Handle* h, const ContractArgs* jobs, int njobs
     const dim3 g((unsigned)std::max<long>(1, std::min<long>(grid, total)));
     hipLaunchKernelGGL(contract_grouped_kernel, g, dim3(256), 0, h->stream, jobs, njobs, total);
     GW_CHECK_LAUNCH(h);
+    return GW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// TDA moments with digit GEMMs (half-order form, as in the FP64 path):
+//   R_2k = X_k X_k^T,  R_2k+1 = X_k D X_k^T + 2 R_k R_k,  X_k+1 = D o X_k + 2 R_k V.
+// X stays FP64; each product digitises its operands (X rows, (X o D) rows,
+// R_k rows, V^T rows once) and accumulates in FP64.  R_k R_k stays FP64.  The
+// symmetric products keep the d2 x d2 digit product as well (eleven products).
+// ---------------------------------------------------------------------------
+namespace {
+
+gw_status launch_dgemm(Handle* h, const DgemmArgs& g0, const char* tag) {
+    DgemmArgs g = g0;
+    const int T = (g.M + 127) / 128;
+    g.tilesN = g.sym ? T : (g.N + 127) / 128;
+    const long tiles = g.sym ? (long)T * (T + 1) / 2 : (long)T * g.tilesN;
+    KTimer tm(h, tag);
+    if (g.sym)
+        hipLaunchKernelGGL(dgemm_mixed_kernel<true>, dim3((unsigned)tiles, (unsigned)g.nsplit), dim3(256), 0,
+                           h->stream, g);
+    else
+        hipLaunchKernelGGL(dgemm_mixed_kernel<false>, dim3((unsigned)tiles, (unsigned)g.nsplit), dim3(256), 0,
+                           h->stream, g);
+    tm.stop();
+    GW_CHECK_LAUNCH(h);
+    return GW_OK;
+}
+
+// digit planes (rows x kpad, k-blocked) of X[rows][cols] (times cs[c] when cs is set)
+gw_status digitise_rows(Handle* h, long rows, long cols, int kpad, const double* X, const double* cs, int* e, u16* Xd) {
+    hipLaunchKernelGGL(row_exp_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, h->stream, rows, cols, cols, X,
+                       cs, e);
+    hipLaunchKernelGGL(digits_rows_kernel, dim3(nb256(rows * kpad)), dim3(256), 0, h->stream, rows, (int)cols, kpad, X,
+                       cs, e, Xd);
+    GW_CHECK_LAUNCH(h);
+    return GW_OK;
+}
+
+}  // namespace
+
+gw_status tda_moments_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps, const double* L,
+                            double* R) {
+    const long ov = (long)nocc * nvir;
+    const int Kp = (int)((ov + MK - 1) / MK * MK);
+    const int Ap = mixed_Ap(naux);
+    if (ov * 64 >= (1L << 31) || (long)naux * 64 >= (1L << 31))
+        return set_err(h, GW_EINVAL, "mixed precision: nocc*nvir too large for the digit recursion");
+    const long asz = (long)naux * naux;
+    double* V = (double*)ws_get(h, WS_V, sizeof(double) * naux * ov);
+    double* D = (double*)ws_get(h, WS_D, sizeof(double) * ov);
+    double* X = (double*)ws_get(h, WS_X0, sizeof(double) * naux * ov);
+    u16* Vt = (u16*)ws_get(h, WS_RC0, sizeof(u16) * ND * ov * Ap);
+    u16* Xd = (u16*)ws_get(h, WS_RC1, sizeof(u16) * ND * (long)naux * Kp);
+    u16* Yd = (u16*)ws_get(h, WS_RC2, sizeof(u16) * ND * (long)naux * Kp);
+    u16* Rk = (u16*)ws_get(h, WS_RC3, sizeof(u16) * ND * (long)naux * Ap);
+    int* ex = (int*)ws_get(h, WS_RC4, sizeof(int) * (ov + 3L * naux));
+    int ncu = 256;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device);
+    const int T = (naux + 127) / 128;
+    const int tiles = T * (T + 1) / 2;
+    const int nkbX = Kp / MK;
+    const int S = std::max(1, std::min(nkbX, (3 * ncu + tiles - 1) / tiles));
+    double* part = (double*)ws_get(h, WS_RC5, sizeof(double) * S * asz);
+    if (!V || !D || !X || !Vt || !Xd || !Yd || !Rk || !ex || !part) return GW_ENOMEM;
+    int *eVt = ex, *eX = ex + ov, *eY = eX + naux, *eR = eY + naux;
+    GW_TRY(gather_ov(h, nocc, nvir, naux, eps, L, V, D));
+    {
+        KTimer tm(h, "recur_digits");
+        hipLaunchKernelGGL(col_exp_kernel, dim3(nb256(ov)), dim3(256), 0, h->stream, naux, ov, V, eVt);
+        hipLaunchKernelGGL(digits_lt_kernel, dim3((unsigned)((ov + 31) / 32), (unsigned)((Ap + 31) / 32)), dim3(256),
+                           0, h->stream, naux, ov, Ap, V, eVt, Vt);
+        tm.stop();
+        GW_CHECK_LAUNCH(h);
+    }
+    GW_TRY(copy_f64(h, X, V, (size_t)naux * ov));
+    DgemmArgs sy{};
+    sy.M = sy.N = naux;
+    sy.nkb = nkbX;
+    sy.nsplit = S;
+    sy.kc = 32;
+    sy.sym = 1;
+    sy.part = part;
+    sy.A = Xd; sy.aplane = (long)naux * Kp; sy.arows = naux; sy.eA = eX;
+    const int K = nmom_max / 2;
+    for (int k = 0; k <= K; ++k) {
+        {
+            KTimer tm(h, "recur_digits");
+            GW_TRY(digitise_rows(h, naux, ov, Kp, X, nullptr, eX, Xd));
+            if (2 * k + 1 <= nmom_max) GW_TRY(digitise_rows(h, naux, ov, Kp, X, D, eY, Yd));
+            tm.stop();
+        }
+        if (2 * k <= nmom_max) {
+            DgemmArgs g = sy;
+            g.B = Xd; g.bplane = (long)naux * Kp; g.brows = naux; g.eB = eX;
+            GW_TRY(launch_dgemm(h, g, "recur_xvt"));
+            GW_TRY(reduce_splits(h, part, S, asz, 1, naux, naux, naux, true, 1.0, 0.0, R + 2 * k * asz, asz, naux));
+        }
+        if (2 * k + 1 <= nmom_max) {
+            double* Ro = R + (2 * k + 1) * asz;
+            DgemmArgs g = sy;
+            g.B = Yd; g.bplane = (long)naux * Kp; g.brows = naux; g.eB = eY;
+            GW_TRY(launch_dgemm(h, g, "recur_xvt"));
+            GW_TRY(reduce_splits(h, part, S, asz, 1, naux, naux, naux, true, 1.0, 0.0, Ro, asz, naux));
+            // Ro += 2 R_k R_k in FP64 (R_k is complete: k <= 2k)
+            GemmF64 gg;
+            gg.M = naux; gg.N = naux; gg.K = naux;
+            gg.a_kc = true; gg.A = R + k * asz; gg.lda = naux;
+            gg.b_kc = false; gg.B = R + k * asz; gg.b_klo = naux;
+            gg.epi = EPI_AXPBY; gg.alpha = 2.0; gg.X = Ro; gg.ldx = naux;
+            gg.C = Ro; gg.ldc = naux;
+            gg.tag = "recur_rr";
+            GW_TRY(gemm_f64(h, gg));
+        }
+        if (k < K) {
+            {
+                KTimer tm(h, "recur_digits");
+                GW_TRY(digitise_rows(h, naux, naux, Ap, R + k * asz, nullptr, eR, Rk));
+                tm.stop();
+            }
+            DgemmArgs g{};
+            g.A = Rk; g.aplane = (long)naux * Ap; g.arows = naux; g.eA = eR;
+            g.B = Vt; g.bplane = ov * Ap; g.brows = (int)ov; g.eB = eVt;
+            g.M = naux; g.N = (int)ov; g.nkb = Ap / MK; g.nsplit = 1; g.kc = 32; g.sym = 0;
+            g.Xout = X; g.Xin = X; g.Dv = D; g.alpha = 2.0;
+            GW_TRY(launch_dgemm(h, g, "recur_rv"));
+        }
+    }
     return GW_OK;
 }
 

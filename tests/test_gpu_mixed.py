@@ -64,6 +64,26 @@ def test_mixed_sigma_matches_oracle(handle, o, v, A, N, seed, scr):
         assert np.array_equal(so[n], so[n].T)
 
 
+@pytest.mark.parametrize("o,v,A,N,seed", [
+    (1, 1, 1, 1, 0),
+    (5, 19, 80, 3, 0),
+    (7, 37, 131, 5, 3),
+    (12, 30, 150, 11, 5),
+    (3, 45, 260, 7, 4),
+])
+def test_mixed_tda_moments_match_oracle(handle, o, v, A, N, seed):
+    """The digit-product recursion (half-order form): every R_n within the
+    format's tolerance of the oracle recursion, and exactly symmetric."""
+    print(f"\n[case] mixed tda moments o={o} v={v} A={A} N={N} seed={seed}", flush=True)
+    eps, L = gwsynth.system(o, v, A, seed)
+    V, D = ogw.particle_hole(eps, L, o)
+    R_ref = ogw.w_core(ogw.tda_eta(V, D, N), V)
+    R = host(handle.moments(dev(eps), dev(L), o, N, "tda", precision="mixed"))
+    for n in range(N + 1):
+        assert rel(R[n], R_ref[n]) < MIXED_TOL, (n, rel(R[n], R_ref[n]))
+        assert np.array_equal(R[n], R[n].T)
+
+
 def test_mixed_chunking_is_consistent(handle):
     o, v, A, N = 4, 21, 70, 5
     eps, L = gwsynth.system(o, v, A, 8)

@@ -63,19 +63,6 @@ __device__ __forceinline__ int scale_exp(double amax) {
 // Operand preparation
 // ---------------------------------------------------------------------------
 
-// Row exponents of a row-major [rows][cols] FP64 matrix (one wave per row).
-// With cs non-null the matrix is X[row][c] * cs[c].
-__global__ void row_exp_kernel(long rows, long cols, long ld, const double* __restrict__ X,
-                               const double* __restrict__ cs, int* __restrict__ e) {
-    long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    int lane = threadIdx.x & 63;
-    if (row >= rows) return;
-    double m = 0.0;
-    for (long c = lane; c < cols; c += 64) m = fmax(m, fabs(X[row * ld + c] * (cs ? cs[c] : 1.0)));
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-    if (lane == 0) e[row] = scale_exp(m);
-}
-
 // Column exponents of L viewed as [naux][ncol]: e[j] over Q (one thread per column).
 __global__ void col_exp_kernel(int naux, long ncol, const double* __restrict__ L, int* __restrict__ e) {
     long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -89,20 +76,43 @@ __global__ void col_exp_kernel(int naux, long ncol, const double* __restrict__ L
 // at ((k / 32) * rows + row) * 32 + k % 32, so the 32 k of one MFMA step of 16
 // consecutive rows are 1 KB of contiguous memory (whole cache lines).
 
-// R digits: Rd[d] k-blocked over rows = nt*naux (row = t*naux + P), zero padded in Q.
-__global__ void digits_rows_kernel(long rows, int cols, int Ap, const double* __restrict__ X,
-                                   const double* __restrict__ cs, const int* __restrict__ e,
-                                   u16* __restrict__ Xd) {
-    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= rows * Ap) return;
-    long row = i / Ap;
-    int c = (int)(i - row * Ap);
-    u16 dg[ND] = {};
-    if (c < cols) digitsN(X[row * cols + c] * (cs ? cs[c] : 1.0), e[row], dg);
-    long plane = rows * (long)Ap;
-    long o = ((long)(c >> 5) * rows + row) * 32 + (c & 31);
+// Row scales and k-blocked digit planes of X[rows][cols] (times cs[c] when cs is
+// set), zero-padded to kpad (a multiple of 32): one block per row, the row
+// maximum by a block reduction, then 8 consecutive k per thread so that each
+// digit plane gets one 16-byte store per thread and step.
+__global__ __launch_bounds__(256) void digitise_rows_kernel(long rows, int cols, int kpad,
+                                                            const double* __restrict__ X,
+                                                            const double* __restrict__ cs, int* __restrict__ e,
+                                                            u16* __restrict__ Xd) {
+    const long row = blockIdx.x;
+    const double* __restrict__ x = X + row * cols;
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int c = threadIdx.x; c < cols; c += 256) m = fmax(m, fabs(x[c] * (cs ? cs[c] : 1.0)));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    const int ex = scale_exp(red[0]);
+    if (threadIdx.x == 0) e[row] = ex;
+    const long plane = rows * (long)kpad;
+    for (int c0 = threadIdx.x * 8; c0 < kpad; c0 += 256 * 8) {
+        u16 dg[8][ND];
 #pragma unroll
-    for (int d = 0; d < ND; ++d) Xd[d * plane + o] = dg[d];
+        for (int u = 0; u < 8; ++u) {
+            const int c = c0 + u;
+            const double v = c < cols ? x[c] * (cs ? cs[c] : 1.0) : 0.0;
+            digitsN(v, ex, dg[u]);
+        }
+        const long o = ((long)(c0 >> 5) * rows + row) * 32 + (c0 & 31);
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+            *(uint4*)(Xd + d * plane + o) =
+                make_uint4(dg[0][d] | ((unsigned)dg[1][d] << 16), dg[2][d] | ((unsigned)dg[3][d] << 16),
+                           dg[4][d] | ((unsigned)dg[5][d] << 16), dg[6][d] | ((unsigned)dg[7][d] << 16));
+    }
 }
 
 // L digits, transposed: Ld[d] k-blocked over rows j (k = Q) = digits of L[Q][j] (Q < naux, else 0),
@@ -631,10 +641,24 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
         }
 }
 
-// One work group per (upper tile, split, sector * nt + n).
-__global__ __launch_bounds__(256, 1) void contract_mixed_kernel(ContractArgs g) {
+// XCD-aware mapping of a 1D grid onto (tile, group): work group b runs on XCD
+// b % 8, and all tiles of one group are placed on the same XCD, so the tiles
+// that share a row block (A slabs) or a column block (B slabs) meet in that
+// XCD's L2.  Returns false for the padding work groups of the last round.
+__device__ __forceinline__ bool xcd_group_item(int tiles, int groups, int& tile, int& group) {
+    const int b = blockIdx.x;
+    const int xcd = b & 7, local = b >> 3;
+    group = (local / tiles) * 8 + xcd;
+    tile = local - (local / tiles) * tiles;
+    return group < groups;
+}
+
+// One work group per (upper tile, split, sector * nt + n); groups are (split, z).
+__global__ __launch_bounds__(256, 1) void contract_mixed_kernel(ContractArgs g, int tiles) {
     __shared__ __attribute__((aligned(16))) u16 lds[2 * 2 * C_OPS];
-    contract_tile(g, blockIdx.x, blockIdx.y, blockIdx.z, lds);
+    int tile, grp;
+    if (!xcd_group_item(tiles, g.nsplit * 2 * g.nt, tile, grp)) return;
+    contract_tile(g, tile, grp % g.nsplit, grp / g.nsplit, lds);
 }
 
 // Grouped, persistent: work items (job, tile, split, sector * nt + n).  As in
@@ -820,10 +844,23 @@ __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int spl
     }
 }
 
+// Split products: a 2D grid (tile, split), spread over the XCDs.  The unsplit
+// update: XCD groups of 8 column tiles x all row tiles, so the row tiles that
+// share a column block of B meet in one L2.
 template <bool W22>
-__global__ __launch_bounds__(256, 1) void dgemm_mixed_kernel(DgemmArgs g) {
+__global__ __launch_bounds__(256, 1) void dgemm_mixed_kernel(DgemmArgs g, int gtiles, int groups) {
     __shared__ __attribute__((aligned(16))) u16 lds[2 * 2 * C_OPS];
-    dgemm_tile<W22>(g, blockIdx.x, blockIdx.y, lds);
+    if (g.nsplit > 1 || g.sym) {
+        dgemm_tile<W22>(g, blockIdx.x, blockIdx.y, lds);
+    } else {
+        int t, grp;
+        if (!xcd_group_item(gtiles, groups, t, grp)) return;
+        // t = row tile + rows * (column tile within the group)
+        const int rows = (g.M + 127) / 128;
+        const int bi = t % rows, bj = grp * 8 + t / rows;
+        if (bj >= g.tilesN) return;
+        dgemm_tile<W22>(g, bi * g.tilesN + bj, 0, lds);
+    }
 }
 
 template <int NT>
@@ -924,8 +961,9 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
         a.nsplit_total = S; a.split_off = 0; a.item0 = 0;
         {
             KTimer tm(h, "sigma_contract");
-            dim3 grid((unsigned)tiles, (unsigned)S, (unsigned)(2 * nt));
-            hipLaunchKernelGGL(contract_mixed_kernel, grid, dim3(256), 0, h->stream, a);
+            const long rounds = ((long)S * 2 * nt + 7) / 8;
+            hipLaunchKernelGGL(contract_mixed_kernel, dim3((unsigned)(rounds * 8 * tiles)), dim3(256), 0, h->stream, a,
+                               tiles);
             tm.stop();
             GW_CHECK_LAUNCH(h);
         }
@@ -957,9 +995,7 @@ gw_status mixed_prep(Handle* h, int naux, int nmo, int nt, const double* L, cons
     hipLaunchKernelGGL(col_exp_kernel, dim3(nb256(M2)), dim3(256), 0, h->stream, naux, M2, L, eL);
     hipLaunchKernelGGL(digits_lt_kernel, dim3((unsigned)((M2 + 31) / 32), (unsigned)((Ap + 31) / 32)), dim3(256), 0,
                        h->stream, naux, M2, Ap, L, eL, Ld);
-    hipLaunchKernelGGL(row_exp_kernel, dim3((unsigned)((rrows + 3) / 4)), dim3(256), 0, h->stream, rrows, (long)naux,
-                       (long)naux, R, (const double*)nullptr, eR);
-    hipLaunchKernelGGL(digits_rows_kernel, dim3(nb256(rrows * Ap)), dim3(256), 0, h->stream, rrows, naux, Ap, R,
+    hipLaunchKernelGGL(digitise_rows_kernel, dim3((unsigned)rrows), dim3(256), 0, h->stream, rrows, naux, Ap, R,
                        (const double*)nullptr, eR, Rd);
     tm.stop();
     GW_CHECK_LAUNCH(h);
@@ -1012,13 +1048,16 @@ gw_status launch_dgemm(Handle* h, const DgemmArgs& g0, const char* tag) {
     const int T = (g.M + 127) / 128;
     g.tilesN = g.sym ? T : (g.N + 127) / 128;
     const long tiles = g.sym ? (long)T * (T + 1) / 2 : (long)T * g.tilesN;
+    int gtiles = 0, groups = 0;
+    dim3 grid((unsigned)tiles, (unsigned)g.nsplit);
+    if (!(g.sym || g.nsplit > 1)) {
+        gtiles = T * 8;
+        groups = (g.tilesN + 7) / 8;
+        grid = dim3((unsigned)((groups + 7) / 8 * 8 * gtiles));
+    }
     KTimer tm(h, tag);
-    if (g.sym)
-        hipLaunchKernelGGL(dgemm_mixed_kernel<true>, dim3((unsigned)tiles, (unsigned)g.nsplit), dim3(256), 0,
-                           h->stream, g);
-    else
-        hipLaunchKernelGGL(dgemm_mixed_kernel<false>, dim3((unsigned)tiles, (unsigned)g.nsplit), dim3(256), 0,
-                           h->stream, g);
+    if (g.sym) hipLaunchKernelGGL(dgemm_mixed_kernel<true>, grid, dim3(256), 0, h->stream, g, gtiles, groups);
+    else hipLaunchKernelGGL(dgemm_mixed_kernel<false>, grid, dim3(256), 0, h->stream, g, gtiles, groups);
     tm.stop();
     GW_CHECK_LAUNCH(h);
     return GW_OK;
@@ -1026,9 +1065,7 @@ gw_status launch_dgemm(Handle* h, const DgemmArgs& g0, const char* tag) {
 
 // digit planes (rows x kpad, k-blocked) of X[rows][cols] (times cs[c] when cs is set)
 gw_status digitise_rows(Handle* h, long rows, long cols, int kpad, const double* X, const double* cs, int* e, u16* Xd) {
-    hipLaunchKernelGGL(row_exp_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, h->stream, rows, cols, cols, X,
-                       cs, e);
-    hipLaunchKernelGGL(digits_rows_kernel, dim3(nb256(rows * kpad)), dim3(256), 0, h->stream, rows, (int)cols, kpad, X,
+    hipLaunchKernelGGL(digitise_rows_kernel, dim3((unsigned)rows), dim3(256), 0, h->stream, rows, (int)cols, kpad, X,
                        cs, e, Xd);
     GW_CHECK_LAUNCH(h);
     return GW_OK;

@@ -121,7 +121,7 @@ def bench_batched(args):
     seq = time.perf_counter() - t0
     print(f"[bench] sequential {seq:.2f} s; planning the batch", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    b = h.batch(sys_t, N, precision="mixed", bopts={"autotune": 1})
+    b = h.batch(sys_t, N, precision="mixed", bopts={"autotune": 1, "branches": args.branches})
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     info = b.info()
@@ -157,6 +157,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="single", choices=["single", "batched"])
     ap.add_argument("--nsys", type=int, default=64)
+    ap.add_argument("--branches", type=int, default=4, help="batched: concurrent per-molecule streams")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)

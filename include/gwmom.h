@@ -219,7 +219,10 @@ gw_status gw_fsgw(gw_handle h, gw_screening screening, int nocc, int nvir, int n
  * is one grouped, persistent launch per contraction stage over a work queue of
  * (job, tile) items; contraction splits follow a work-item target
  * (split_target, or with autotune the fastest of 256, 512, 1024, 2048 by
- * timing the whole sequence).  The sequence is run once eagerly (the outputs
+ * timing the whole sequence).  For TDA the per-molecule work (recursion,
+ * digit preparation) of different molecules runs on `branches` streams with
+ * their own workspaces, molecules assigned largest first by nmo^4.  The
+ * sequence is run once eagerly (the outputs
  * are valid when create returns) and, for TDA screening unless no_graph is
  * set, captured into a hipGraph; gw_batch_run replays it on the handle's
  * current stream (RPA, or no_graph: re-enqueued).  Pointers in sys are used
@@ -242,6 +245,7 @@ typedef struct {
     int split_target;    /* contraction work items per job [512] */
     int autotune;        /* 1: choose split_target by timing */
     int no_graph;        /* 1: replay by re-enqueueing */
+    int branches;        /* TDA: concurrent streams for the per-molecule work [4]; 1 = serial */
 } gw_batch_opts;
 
 typedef struct gw_batch_s* gw_batch;

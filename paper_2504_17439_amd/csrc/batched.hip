@@ -71,6 +71,13 @@ struct gw_batch_s {
     gwm::u16* Zd = nullptr;
     int* eZ = nullptr;
 
+    // branches: the per-molecule work (recursion, digit preparation) of
+    // different molecules runs on separate streams, each with its own
+    // workspace, forked from and joined back to the main stream
+    std::vector<gwm::Handle*> br;
+    std::vector<int> mol_branch;
+    std::vector<hipEvent_t> ev;  // [0] fork, [1 + b] join of branch b, [1 + nbr + i] molecule i done
+
     int ncu = 256;
     int split_target = 512;
     bool graph_ok = false;
@@ -157,29 +164,63 @@ gw_status build_tables(gw_batch_s* b, int target) {
     return GW_OK;
 }
 
-// The whole launch sequence on h->stream.
+// Per-molecule work of molecule i on handle hb.
+gw_status molecule_work(gw_batch_s* b, Handle* hb, int i) {
+    const int nt = b->nt;
+    const gw_opts* opts = b->has_opts ? &b->opts : nullptr;
+    const gw_system& s = b->sys[i];
+    auto& m = b->mol[i];
+    if (b->screening == GW_TDA && b->prec == GW_MIXED)
+        GW_TRY(tda_moments_mixed(hb, s.nocc, s.nvir, s.naux, b->nmom_max, s.eps, s.L, m.R));
+    else if (b->screening == GW_TDA)
+        GW_TRY(tda_moments_f64(hb, s.nocc, s.nvir, s.naux, b->nmom_max, s.eps, s.L, m.R, nullptr));
+    else
+        GW_TRY(rpa_moments_f64(hb, s.nocc, s.nvir, s.naux, b->nmom_max, s.eps, s.L, opts, m.R, nullptr));
+    if (b->prec == GW_MIXED) GW_TRY(mixed_prep(hb, s.naux, m.nmo, nt, s.L, m.R, m.Ld, m.eL, m.Rd, m.eR));
+    else
+        GW_TRY(sigma_from_R_f64(hb, s.nocc, s.nvir, s.naux, b->nmom_max, s.eps, s.L, m.R, opts, s.sigma_occ,
+                                s.sigma_vir));
+    return GW_OK;
+}
+
+// The whole launch sequence on h->stream (forking to the branch streams).
 gw_status enqueue(gw_batch_s* b) {
     Handle* h = b->h;
     const int nt = b->nt;
-    const gw_opts* opts = b->has_opts ? &b->opts : nullptr;
     if (b->prec == GW_MIXED)
         for (auto& m : b->mol) GW_TRY(fill_f64(h, m.part, (size_t)2 * nt * m.slots * m.M2, 0.0));
-    for (int i = 0; i < b->nsys; ++i) {
-        const gw_system& s = b->sys[i];
-        auto& m = b->mol[i];
-        if (b->screening == GW_TDA && b->prec == GW_MIXED)
-            GW_TRY(tda_moments_mixed(h, s.nocc, s.nvir, s.naux, b->nmom_max, s.eps, s.L, m.R));
-        else if (b->screening == GW_TDA)
-            GW_TRY(tda_moments_f64(h, s.nocc, s.nvir, s.naux, b->nmom_max, s.eps, s.L, m.R, nullptr));
-        else
-            GW_TRY(rpa_moments_f64(h, s.nocc, s.nvir, s.naux, b->nmom_max, s.eps, s.L, opts, m.R, nullptr));
-        if (b->prec == GW_MIXED) GW_TRY(mixed_prep(h, s.naux, m.nmo, nt, s.L, m.R, m.Ld, m.eL, m.Rd, m.eR));
-        else
-            GW_TRY(sigma_from_R_f64(h, s.nocc, s.nvir, s.naux, b->nmom_max, s.eps, s.L, m.R, opts, s.sigma_occ,
-                                    s.sigma_vir));
+    if (b->br.empty()) {
+        for (int i = 0; i < b->nsys; ++i) GW_TRY(molecule_work(b, h, i));
+    } else {
+        GW_HIP(h, hipEventRecord(b->ev[0], h->stream));
+        for (auto* hb : b->br) GW_HIP(h, hipStreamWaitEvent(hb->stream, b->ev[0], 0));
+        const size_t nbr = b->br.size();
+        for (int i = 0; i < b->nsys; ++i) {
+            Handle* hb = b->br[b->mol_branch[i]];
+            gw_status st = molecule_work(b, hb, i);
+            if (st != GW_OK) return set_err(h, st, hb->last_error);
+            GW_HIP(h, hipEventRecord(b->ev[1 + nbr + i], hb->stream));
+        }
     }
-    if (b->prec != GW_MIXED) return GW_OK;
-    for (auto& tab : b->tabs) {
+    if (b->prec != GW_MIXED) {
+        for (size_t k = 0; k < b->br.size(); ++k) {
+            GW_HIP(h, hipEventRecord(b->ev[1 + k], b->br[k]->stream));
+            GW_HIP(h, hipStreamWaitEvent(h->stream, b->ev[1 + k], 0));
+        }
+        return GW_OK;
+    }
+    for (size_t w = 0; w < b->tabs.size(); ++w) {
+        auto& tab = b->tabs[w];
+        // a wave needs the per-molecule work of its own molecules only
+        if (!b->br.empty()) {
+            int last = -1;
+            for (int id : b->waves[w]) {
+                const int m = b->jobs[id].m;
+                if (m == last) continue;
+                last = m;
+                GW_HIP(h, hipStreamWaitEvent(h->stream, b->ev[1 + b->br.size() + m], 0));
+            }
+        }
         {
             KTimer tm(h, "sigma_fold");
             GW_TRY(launch_fold_grouped(h, nt, tab.fold, tab.njobs, tab.fold_total, b->ncu));
@@ -195,6 +236,11 @@ gw_status enqueue(gw_batch_s* b) {
             GW_TRY(launch_contract_grouped(h, tab.con, tab.njobs, tab.con_total, b->ncu));
             tm.stop();
         }
+    }
+    // every branch rejoins the main stream
+    for (size_t k = 0; k < b->br.size(); ++k) {
+        GW_HIP(h, hipEventRecord(b->ev[1 + k], b->br[k]->stream));
+        GW_HIP(h, hipStreamWaitEvent(h->stream, b->ev[1 + k], 0));
     }
     for (int i = 0; i < b->nsys; ++i) {
         const auto& m = b->mol[i];
@@ -224,6 +270,17 @@ gw_status time_sequence(gw_batch_s* b, float* ms) {
 }
 
 void release(gw_batch_s* b) {
+    for (auto* hb : b->br) {
+        (void)hipStreamSynchronize(hb->stream);
+        for (auto& w : hb->ws)
+            if (w.ptr) (void)hipFree(w.ptr);
+        if (hb->own_stream) (void)hipStreamDestroy(hb->own_stream);
+        delete hb;
+    }
+    b->br.clear();
+    for (auto e : b->ev)
+        if (e) (void)hipEventDestroy(e);
+    b->ev.clear();
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->mem) (void)hipFree(b->mem);
@@ -386,6 +443,45 @@ gw_status batch_create(Handle* h, int nsys, const gw_system* sys, gw_screening s
             t += align(sizeof(ZdigJob) * n);
             b->tabs[w].con = (ContractArgs*)t;
             t += align(sizeof(ContractArgs) * n);
+        }
+    }
+
+    // ---- branches (TDA: the per-molecule path uses no library handle); molecules
+    // assigned largest first to the least loaded branch by cost ~ nmo^4
+    const int nbr = screening == GW_TDA ? std::min((bo && bo->branches > 0) ? bo->branches : 4, nsys) : 0;
+    if (nbr > 1) {
+        b->ev.assign(1 + nbr + nsys, nullptr);
+        for (auto& e : b->ev)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                release(b);
+                delete b;
+                return set_err(h, GW_EHIP, "batch: event creation failed");
+            }
+        for (int k = 0; k < nbr; ++k) {
+            auto* hb = new (std::nothrow) Handle();
+            if (!hb || hipStreamCreateWithFlags(&hb->own_stream, hipStreamNonBlocking) != hipSuccess) {
+                (void)hipGetLastError();
+                delete hb;
+                release(b);
+                delete b;
+                return set_err(h, GW_EHIP, "batch: branch stream creation failed");
+            }
+            hb->device = h->device;
+            hb->stream = hb->own_stream;
+            hb->ws.resize(WS_COUNT);
+            b->br.push_back(hb);
+        }
+        std::vector<int> order(nsys);
+        for (int i = 0; i < nsys; ++i) order[i] = i;
+        auto cost = [&](int i) { return std::pow((double)b->mol[i].nmo, 4.0); };
+        std::sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+        std::vector<double> load(nbr, 0.0);
+        b->mol_branch.assign(nsys, 0);
+        for (int i : order) {
+            const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            b->mol_branch[i] = k;
+            load[k] += cost(i);
         }
     }
 

@@ -52,7 +52,7 @@ class System(ctypes.Structure):
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("job_bytes", ctypes.c_size_t), ("wave_bytes", ctypes.c_size_t), ("split_target", ctypes.c_int),
-                ("autotune", ctypes.c_int), ("no_graph", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("no_graph", ctypes.c_int), ("branches", ctypes.c_int)]
 
 
 class FsgwOpts(ctypes.Structure):

@@ -706,11 +706,13 @@ struct DgemmArgs {
     double alpha;
 };
 
-// W22: also keep the weight-4 product d2 x d2.  In a Gram product (A = B) its
-// diagonal terms are squares and accumulate coherently over k (to ~2e-8 of the
-// result for rows with a wide dynamic range); every other dropped product has
-// random sign.
-template <bool W22>
+// W4: also keep the weight-4 products d2 x d2, d1 x d3 and d3 x d1.  In a
+// Gram-type product (B = A or A o D) the diagonal d2 x d2 terms are squares and
+// accumulate coherently over k, and for rows with a wide dynamic range (most
+// entries far below the row maximum, whose leading digit is then d1) d1 x d3 is
+// the leading-times-last product of those entries: without them the moments
+// carry ~1e-8 relative error, with them ~5e-10.
+template <bool W4>
 __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int split, u16* lds) {
     constexpr int OPS = C_OPS;
     const int tid = threadIdx.x;
@@ -803,10 +805,13 @@ __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int spl
                         if (ii < ND && w - ii < ND)
                             acc1[i][j] =
                                 __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ii], b[j][w - ii], acc1[i][j], 0, 0, 0);
-            if (W22)
+            if (W4)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < 4; ++j) {
                     acc1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[j][2], acc1[i][j], 0, 0, 0);
+                    acc1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[j][3], acc1[i][j], 0, 0, 0);
+                    acc1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[3], b[j][1], acc1[i][j], 0, 0, 0);
+                }
         }
         if (++since == g.kc || it + 1 == total) {
             // promote: the row / column exponents are constant along k
@@ -847,11 +852,11 @@ __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int spl
 // Split products: a 2D grid (tile, split), spread over the XCDs.  The unsplit
 // update: XCD groups of 8 column tiles x all row tiles, so the row tiles that
 // share a column block of B meet in one L2.
-template <bool W22>
+template <bool W4>
 __global__ __launch_bounds__(256, 1) void dgemm_mixed_kernel(DgemmArgs g, int gtiles, int groups) {
     __shared__ __attribute__((aligned(16))) u16 lds[2 * 2 * C_OPS];
     if (g.nsplit > 1 || g.sym) {
-        dgemm_tile<W22>(g, blockIdx.x, blockIdx.y, lds);
+        dgemm_tile<W4>(g, blockIdx.x, blockIdx.y, lds);
     } else {
         int t, grp;
         if (!xcd_group_item(gtiles, groups, t, grp)) return;
@@ -859,7 +864,7 @@ __global__ __launch_bounds__(256, 1) void dgemm_mixed_kernel(DgemmArgs g, int gt
         const int rows = (g.M + 127) / 128;
         const int bi = t % rows, bj = grp * 8 + t / rows;
         if (bj >= g.tilesN) return;
-        dgemm_tile<W22>(g, bi * g.tilesN + bj, 0, lds);
+        dgemm_tile<W4>(g, bi * g.tilesN + bj, 0, lds);
     }
 }
 
@@ -1039,7 +1044,7 @@ gw_status launch_contract_grouped(Handle* h, const ContractArgs* jobs, int njobs
 //   R_2k = X_k X_k^T,  R_2k+1 = X_k D X_k^T + 2 R_k R_k,  X_k+1 = D o X_k + 2 R_k V.
 // X stays FP64; each product digitises its operands (X rows, (X o D) rows,
 // R_k rows, V^T rows once) and accumulates in FP64.  R_k R_k stays FP64.  The
-// symmetric products keep the d2 x d2 digit product as well (eleven products).
+// symmetric products keep the three weight-4 digit products as well (thirteen).
 // ---------------------------------------------------------------------------
 namespace {
 

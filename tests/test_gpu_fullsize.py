@@ -1,8 +1,8 @@
 """Full-size parity in the launch configuration the benchmark times
-(nocc=100, nvir=400, naux=1500, nmom_max=11, TDA, FP64): sampled rows of the
-self-energy moments against the oracle evaluated one row at a time, the
-invariants that hold at any size, and the poles / QP energies against the
-oracle's block Lanczos run on the same moments."""
+(nocc=100, nvir=400, naux=1500, nmom_max=11, TDA, FP64 and mixed): sampled
+rows of the self-energy moments against the oracle evaluated one row at a
+time, the invariants that hold at any size, and the poles / QP energies
+against the oracle's block Lanczos run on the same moments."""
 import numpy as np
 import pytest
 
@@ -26,27 +26,37 @@ def c3():
     l = torch.from_numpy(L).to("cuda:0")
     so, sv = h.sigma_moments(e, l, O, N, "tda")
     R = h.moments(e, l, O, N, "tda")
+    print("[case] same system, mixed precision", flush=True)
+    som, svm = h.sigma_moments(e, l, O, N, "tda", precision="mixed")
+    Rm = h.moments(e, l, O, N, "tda", precision="mixed")
     torch.cuda.synchronize()
     out = dict(eps=eps, L=L, so=so.cpu().numpy(), sv=sv.cpu().numpy(), R=R.cpu().numpy(), h=h,
-               so_d=so, sv_d=sv, e_d=e)
+               so_d=so, sv_d=sv, e_d=e,
+               so_m=som.cpu().numpy(), sv_m=svm.cpu().numpy(), R_m=Rm.cpu().numpy(), so_md=som, sv_md=svm)
     yield out
     h.close()
+
+
+@pytest.fixture(scope="module")
+def ref(c3):
+    """Oracle recursion and sampled oracle rows (computed once, shared)."""
+    V, D = ogw.particle_hole(c3["eps"], c3["L"], O)
+    R_ref = ogw.w_core(ogw.tda_eta(V, D, N), V)
+    ro, rv = ogw.sigma_moment_rows(c3["eps"], c3["L"], O, list(R_ref), ROWS)
+    return dict(R=R_ref, ro=ro, rv=rv)
 
 
 def rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-def test_fullsize_R_matches_oracle_recursion(c3):
-    V, D = ogw.particle_hole(c3["eps"], c3["L"], O)
-    R_ref = ogw.w_core(ogw.tda_eta(V, D, N), V)
+def test_fullsize_R_matches_oracle_recursion(c3, ref):
     for n in range(N + 1):
-        assert rel(c3["R"][n], R_ref[n]) < 1e-10, n
+        assert rel(c3["R"][n], ref["R"][n]) < 1e-10, n
 
 
-def test_fullsize_sigma_rows_match_oracle(c3):
-    R = list(c3["R"])          # checked against the oracle recursion above
-    ro, rv = ogw.sigma_moment_rows(c3["eps"], c3["L"], O, R, ROWS)
+def test_fullsize_sigma_rows_match_oracle(c3, ref):
+    ro, rv = ref["ro"], ref["rv"]
     for n in range(N + 1):
         so_rows = c3["so"][n][ROWS]
         sv_rows = c3["sv"][n][ROWS]
@@ -83,3 +93,46 @@ def test_fullsize_poles_and_qp_match_oracle_lanczos(c3):
         v = res["v_" + key].cpu().numpy()
         for n in range(N + 1):
             assert rel((v * e[None, :] ** n) @ v.T, T[n]) < 1e-6, (key, n)
+
+
+# Mixed precision at full size.  The digit products carry ~2^-32 relative
+# error per product and FP64 accumulation, so moments agree with the oracle to
+# ~1e-9 relative; the asserted bound is the mixed tolerance used at small size.
+MIXED_TOL = 1e-8
+
+
+def test_fullsize_mixed_R_matches_oracle_recursion(c3, ref):
+    errs = [rel(c3["R_m"][n], ref["R"][n]) for n in range(N + 1)]
+    print("mixed R errors " + " ".join(f"{e:.2e}" for e in errs), flush=True)
+    assert max(errs) < MIXED_TOL, errs
+
+
+def test_fullsize_mixed_sigma_rows_match_oracle(c3, ref):
+    errs = []
+    for n in range(N + 1):
+        for T, rows in ((c3["so_m"], ref["ro"]), (c3["sv_m"], ref["rv"])):
+            errs.append(np.abs(T[n][ROWS] - rows[n]).max() / np.abs(T[n]).max())
+        assert np.array_equal(c3["so_m"][n], c3["so_m"][n].T)
+    print("mixed sigma row errors " + " ".join(f"{e:.2e}" for e in errs), flush=True)
+    assert max(errs) < MIXED_TOL, errs
+
+
+def test_fullsize_mixed_qp_within_1e6_ha(c3):
+    """Frontier QP energies of the mixed moments against the oracle's block
+    Lanczos and upfolded diagonalisation on the FP64 moments (which match the
+    sampled oracle rows to 1e-10 above).  The mixed moments are PSD only to
+    their own accuracy, which the Lanczos is given (moment_eps) to set its
+    deflation and PSD levels."""
+    import torch
+    res = c3["h"].poles(c3["so_md"], c3["sv_md"], torch.diag(c3["e_d"]).contiguous(), opts={"moment_eps": 1e-9})
+    torch.cuda.synchronize()
+    qp = res["qp"].cpu().numpy()
+    eo, vo = ogw.poles_from_moments(list(c3["so"]))
+    ev, vv = ogw.poles_from_moments(list(c3["sv"]))
+    H = ogw.upfolded_hamiltonian(np.diag(c3["eps"]), eo, vo, ev, vv)
+    E, U = np.linalg.eigh(H)
+    qp_ref, _, _ = ogw.qp_assign(E, U[: O + V_])
+    front = slice(O - 5, O + 5)
+    err = np.abs(qp[front] - qp_ref[front]).max()
+    print(f"mixed frontier QP error {err:.3e} Ha", flush=True)
+    assert err < 1e-6

@@ -95,7 +95,8 @@ def recorded_traffic(o, v, A, N):
 def bench_batched(args):
     """64-molecule batch (nmo uniform over multiples of 5 in [60, 400], nocc =
     nmo/5, naux = 3.5 nmo, TDA, nmom_max = 7, mixed): sets/s of the captured
-    batch replay, beside 64 sequential single-molecule calls."""
+    batch replay, beside 64 sequential single-molecule calls in mixed
+    precision and in FP64."""
     import numpy as np
     import torch
     import gwsynth
@@ -119,7 +120,16 @@ def bench_batched(args):
         h.sigma_moments(e, l, o, N, precision="mixed")
     torch.cuda.synchronize()
     seq = time.perf_counter() - t0
-    print(f"[bench] sequential {seq:.2f} s; planning the batch", file=sys.stderr, flush=True)
+    print(f"[bench] sequential mixed {seq:.2f} s; sequential FP64 calls", file=sys.stderr, flush=True)
+    for e, l, o in sys_t[:2]:
+        h.sigma_moments(e, l, o, N, precision="fp64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e, l, o in sys_t:
+        h.sigma_moments(e, l, o, N, precision="fp64")
+    torch.cuda.synchronize()
+    seq64 = time.perf_counter() - t0
+    print(f"[bench] sequential FP64 {seq64:.2f} s; planning the batch", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     b = h.batch(sys_t, N, precision="mixed", bopts={"autotune": 1, "branches": args.branches})
     torch.cuda.synchronize()
@@ -147,6 +157,8 @@ def bench_batched(args):
                    "nsys": len(shapes), "nmom_max": N, "seed": args.seed},
         "sequential_sets_per_s": len(sys_t) / seq,
         "speedup_vs_sequential": (nsets / el) / (len(sys_t) / seq),
+        "sequential_fp64_sets_per_s": len(sys_t) / seq64,
+        "speedup_vs_sequential_fp64": (nsets / el) / (len(sys_t) / seq64),
         "plan_seconds": plan_s, "plan": info,
         "useful_tflops": flops * args.steps / el / 1e12,
     }

@@ -60,8 +60,7 @@ typedef struct {
     double quad_scale;  /* RPA grid scale s in z = s(1+x)/(1-x); <= 0 -> median(D)  */
     double pinv_tol;    /* Lanczos pseudo-inverse cut (relative); <= 0 -> 1e-12      */
     double neg_tol;     /* Lanczos non-PSD tolerance (relative);  <= 0 -> 1e-8       */
-    int bf16_slices;    /* mixed precision: BF16 slices per operand (2 or 3); 0 -> 3 */
-    size_t zchunk_bytes;/* cap on the folded-intermediate chunk; 0 -> 8 GiB          */
+    size_t zchunk_bytes;/* cap on the folded-intermediate chunk; 0 -> 16 GiB         */
     double moment_eps;  /* relative accuracy of the moments given to gw_poles; sets
                            the Lanczos deflation level; <= 0 -> 2^-52 (FP64 moments) */
 } gw_opts;
@@ -85,10 +84,11 @@ const char* gw_last_error(gw_handle h);
  *   eta [nmom_max+1][naux][nocc*nvir]     nullable.
  * prec: GW_FP64 (FP64 MFMA), or GW_MIXED with eta NULL: the half-order
  * products R_2k = X_k X_k^T, R_2k+1 = X_k D X_k^T + 2 R_k R_k and the updates
- * X_k+1 = D o X_k + 2 R_k V use four-digit BF16 fixed-point operands (one
- * power-of-two scale per row), exact FP32 accumulation of the leading digit
- * products over 1024-long k chunks and FP64 combination (R_k R_k and X stay
- * FP64); with eta requested the FP64 form is used.  R is returned in FP64.
+ * X_k+1 = D o X_k + 2 R_k V use four-digit int8 fixed-point operands (base
+ * 255, one power-of-two scale per row) on the integer MFMA, with exact int32
+ * sums per digit weight (k split into ranges of at most 32768) combined in
+ * FP64 (R_k R_k and X stay FP64); with eta requested the FP64 form is used.
+ * R is returned in FP64.  GW_MIXED needs naux <= 32768.
  */
 gw_status gw_moments_tda(gw_handle h, int nocc, int nvir, int naux, int nmom_max,
                          const double* eps, const double* L, gw_precision prec,
@@ -114,6 +114,11 @@ gw_status gw_moments_rpa(gw_handle h, int nocc, int nvir, int naux, int nmom_max
  *   W^{(t)}_{px,qx}  = sum_PQ L[P][p][x] R_t[P][Q] L[Q][q][x]
  * with R_t from the chosen screening.  Outputs (symmetric):
  *   sigma_occ, sigma_vir  [nmom_max+1][nmo][nmo].
+ * prec GW_MIXED: both contraction stages (R_t L with the eps-power fold, then
+ * the sum over x and P) run on four-digit int8 operands (base 255, one
+ * power-of-two scale per row or column) on the integer MFMA with exact int32
+ * sums per digit weight, combined in FP64; the folded intermediate is kept as
+ * FP32 + BF16 residual.  GW_MIXED needs nmom_max <= 11 and naux <= 4096.
  */
 gw_status gw_sigma_moments(gw_handle h, gw_screening screening, int nocc, int nvir,
                            int naux, int nmom_max, const double* eps, const double* L,

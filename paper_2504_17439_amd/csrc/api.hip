@@ -104,8 +104,6 @@ gw_status check_opts(Handle* h, gw_precision prec, const gw_opts* o) {
             return gwm::set_err(h, GW_EINVAL, "nquad must be 0 (default) or in [2, 512]");
         if (!(o->quad_scale >= 0.0) || !std::isfinite(o->quad_scale))
             return gwm::set_err(h, GW_EINVAL, "quad_scale must be finite and >= 0");
-        if (o->bf16_slices != 0 && o->bf16_slices != 2 && o->bf16_slices != 3)
-            return gwm::set_err(h, GW_EINVAL, "bf16_slices must be 0, 2 or 3");
     }
     return GW_OK;
 }

@@ -35,9 +35,9 @@ struct gw_batch_s {
         int nmo, Ap;
         long M2, lplane, rrows, rplane;
         double* R = nullptr;
-        gwm::u16* Ld = nullptr;
+        gwm::i8* Ld = nullptr;
         int* eL = nullptr;
-        gwm::u16* Rd = nullptr;
+        gwm::i8* Rd = nullptr;
         int* eR = nullptr;
         double* part = nullptr;
         int slots = 0;  // contraction split slots (all jobs of the molecule)
@@ -68,7 +68,7 @@ struct gw_batch_s {
     void* tmem = nullptr;   // job tables
     float* Zt = nullptr;
     gwm::u16* Zl = nullptr;
-    gwm::u16* Zd = nullptr;
+    gwm::i8* Zd = nullptr;
     int* eZ = nullptr;
 
     // branches: the per-molecule work (recursion, digit preparation) of
@@ -89,10 +89,7 @@ namespace gwm {
 
 namespace {
 
-int contract_tiles(int nmo) {
-    const int T = (nmo + 127) / 128;
-    return T * (T + 1) / 2;
-}
+int contract_tiles(int nmo) { return mixed_upper_tiles(nmo); }
 
 // S for a job of nx orbitals x: enough contraction work items for the target
 int job_split(const gw_batch_s* b, int nmo, int nx, int target) {
@@ -125,7 +122,7 @@ gw_status build_tables(gw_batch_s* b, int target) {
             const long ncol = (long)(j.x1 - j.x0) * m.nmo;
             float* Zt = b->Zt + j.zt_off;
             u16* Zl = b->Zl + j.zl_off;
-            u16* Zd = b->Zd + j.zd_off;
+            i8* Zd = b->Zd + j.zd_off;
             int* eZ = b->eZ + j.ez_off;
             FoldJob f = make_fold_job(m.Rd, m.eR, m.Ld, m.eL, s.eps, s.naux, m.Ap, m.nmo, s.nocc,
                                       (long)j.x0 * m.nmo, ncol, m.rplane, m.lplane, Zt, Zl);
@@ -146,7 +143,7 @@ gw_status build_tables(gw_batch_s* b, int target) {
                 a.xs0[sec] = xs0;
                 a.nxs[sec] = std::max(0, xs1 - xs0);
             }
-            a.nt = nt; a.nsplit = j.S; a.tiles_T = (m.nmo + 127) / 128; a.ncol = ncol;
+            a.nt = nt; a.nsplit = j.S; a.tilesN = (m.nmo + 63) / 64; a.tiles = contract_tiles(m.nmo); a.ncol = ncol;
             a.part = m.part; a.nsplit_total = m.slots; a.split_off = j.slot0;
             a.item0 = ci;
             ci += (long)contract_tiles(m.nmo) * j.S * 2 * nt;
@@ -337,11 +334,11 @@ gw_status batch_create(Handle* h, int nsys, const gw_system* sys, gw_screening s
         }
         bytes += align(sizeof(double) * nt * (size_t)s.naux * s.naux);
         if (prec == GW_MIXED) {
-            bytes += align(sizeof(u16) * MIX_ND * m.lplane) + align(sizeof(int) * (m.M2 + m.rrows)) +
-                     align(sizeof(u16) * MIX_ND * m.rplane);
+            bytes += align(sizeof(i8) * MIX_ND * m.lplane) + align(sizeof(int) * (m.M2 + m.rrows)) +
+                     align(sizeof(i8) * MIX_ND * m.rplane);
             // stage-1 intermediates per x: FP32 + BF16 residual + ND digit planes, plus one exponent per row
             const size_t per_x = (size_t)nt * m.nmo * ((size_t)m.Ap * (sizeof(float) + sizeof(u16) +
-                                                                      MIX_ND * sizeof(u16)) + sizeof(int));
+                                                                      MIX_ND * sizeof(i8)) + sizeof(int));
             int nx = (int)std::max<size_t>(1, std::min<size_t>((size_t)m.nmo, job_bytes / per_x));
             nx = (int)std::max<long>(1, std::min<long>(nx, ((1L << 31) - 1) / ((long)nt * m.nmo * 64)));
             int slots_max = 0;
@@ -366,7 +363,7 @@ gw_status batch_create(Handle* h, int nsys, const gw_system* sys, gw_screening s
         for (size_t k = 0; k < b->jobs.size(); ++k) {
             auto& j = b->jobs[k];
             const size_t e = (size_t)j.zrows * b->mol[j.m].Ap;
-            const size_t jb = e * (sizeof(float) + sizeof(u16) + MIX_ND * sizeof(u16)) + sizeof(int) * j.zrows;
+            const size_t jb = e * (sizeof(float) + sizeof(u16) + MIX_ND * sizeof(i8)) + sizeof(int) * j.zrows;
             if (!cur.empty() && used + jb > wave_bytes) {
                 b->waves.push_back(cur);
                 cur.clear();
@@ -404,19 +401,19 @@ gw_status batch_create(Handle* h, int nsys, const gw_system* sys, gw_screening s
             m.R = (double*)p;
             p += align(sizeof(double) * nt * (size_t)s.naux * s.naux);
             if (prec != GW_MIXED) continue;
-            m.Ld = (u16*)p;
-            p += align(sizeof(u16) * MIX_ND * m.lplane);
+            m.Ld = (i8*)p;
+            p += align(sizeof(i8) * MIX_ND * m.lplane);
             m.eL = (int*)p;
             m.eR = m.eL + m.M2;
             p += align(sizeof(int) * (m.M2 + m.rrows));
-            m.Rd = (u16*)p;
-            p += align(sizeof(u16) * MIX_ND * m.rplane);
+            m.Rd = (i8*)p;
+            p += align(sizeof(i8) * MIX_ND * m.rplane);
             m.part = (double*)p;
             p += align(sizeof(double) * 2 * nt * (size_t)m.slots * m.M2);
         }
     }
     if (prec == GW_MIXED) {
-        const size_t zb = sizeof(float) * zt_max + sizeof(u16) * (zl_max + zd_max) + sizeof(int) * ez_max + 4096;
+        const size_t zb = sizeof(float) * zt_max + sizeof(u16) * zl_max + sizeof(i8) * zd_max + sizeof(int) * ez_max + 4096;
         const size_t nw = b->waves.size(), nj = b->jobs.size();
         const size_t tb = (sizeof(FoldJob) + sizeof(ZdigJob) + sizeof(ContractArgs)) * nj + 3 * 256 * nw;
         if (hipMalloc(&b->zmem, zb) != hipSuccess || hipMalloc(&b->tmem, tb) != hipSuccess) {
@@ -430,8 +427,8 @@ gw_status batch_create(Handle* h, int nsys, const gw_system* sys, gw_screening s
         p += align(sizeof(float) * zt_max);
         b->Zl = (u16*)p;
         p += align(sizeof(u16) * zl_max);
-        b->Zd = (u16*)p;
-        p += align(sizeof(u16) * zd_max);
+        b->Zd = (i8*)p;
+        p += align(sizeof(i8) * zd_max);
         b->eZ = (int*)p;
         char* t = (char*)b->tmem;
         b->tabs.resize(nw);

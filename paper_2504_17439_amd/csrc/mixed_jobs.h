@@ -4,19 +4,22 @@
 
 #include "internal.h"
 
+#include <algorithm>
+
 namespace gwm {
 
-typedef unsigned short u16;
+typedef unsigned short u16;  // BF16 bit patterns
+typedef signed char i8;      // one base-255 digit
 
-constexpr int MIX_ND = 4;   // BF16 digits per operand
-constexpr int MIX_MK = 32;  // k per MFMA step; digit planes are padded to a multiple of it
+constexpr int MIX_ND = 4;   // int8 digits per operand
+constexpr int MIX_MK = 64;  // k per MFMA step (64 B per row); digit planes are padded to a multiple of it
 
 // One stage-1 job: a molecule's R_t digits and the x range [j0, j0 + ncol) of
 // its L digit columns.  item0 / nP / nC index its tiles in grouped launches.
 struct FoldJob {
-    const u16* Rd;
+    const i8* Rd;
     const int* eR;
-    const u16* Ld;
+    const i8* Ld;
     const int* eL;
     const double* eps;
     int naux, Ap, nmo, nocc;
@@ -33,17 +36,17 @@ struct ZdigJob {
     const float* Zt;
     const u16* Zl;
     int* eZ;
-    u16* Zd;
+    i8* Zd;
     long item0;  // first global row in grouped launches
 };
 
 struct ContractArgs {
-    const u16* Ld; long lplane; const int* eL;  // L digit planes, k-blocked, rows (x, p) = nmo^2; exps per row
-    const u16* Zd; long zplane; const int* eZ;  // Z digit planes, k-blocked, rows (n, c) = nt * ncol; exps per row
+    const i8* Ld; long lplane; const int* eL;   // L digit planes, k-blocked, rows (x, p) = nmo^2; exps per row
+    const i8* Zd; long zplane; const int* eZ;   // Z digit planes, k-blocked, rows (n, c) = nt * ncol; exps per row
     int nmo, Ap, naux;
     int x0;                                      // first x of the chunk
     int xs0[2], nxs[2];                          // per sector: first x, count (within the chunk)
-    int nt, nsplit, tiles_T;
+    int nt, nsplit, tilesN, tiles;               // column blocks of 64, upper 128 x 64 tiles
     long ncol;
     double* part;                                // [2][nt][nsplit_total][nmo][nmo] FP64, accumulated
     int nsplit_total, split_off;                 // this job's splits are slots split_off .. + nsplit
@@ -52,11 +55,20 @@ struct ContractArgs {
 
 inline int mixed_Ap(int naux) { return (naux + MIX_MK - 1) / MIX_MK * MIX_MK; }
 
-// Scales and k-blocked digit planes of L (rows (x, q)) and of R_t (rows (t, P)).
-gw_status mixed_prep(Handle* h, int naux, int nmo, int nt, const double* L, const double* R, u16* Ld, int* eL,
-                     u16* Rd, int* eR);
+// Upper 128-row x 64-column tiles of a symmetric M x M result: row block bi
+// keeps column blocks bj >= 2 bi.
+inline int mixed_upper_tiles(int M) {
+    const int TM = (M + 127) / 128, TN = (M + 63) / 64;
+    int n = 0;
+    for (int bi = 0; bi < TM; ++bi) n += std::max(0, TN - 2 * bi);
+    return n;
+}
 
-FoldJob make_fold_job(const u16* Rd, const int* eR, const u16* Ld, const int* eL, const double* eps, int naux,
+// Scales and k-blocked digit planes of L (rows (x, q)) and of R_t (rows (t, P)).
+gw_status mixed_prep(Handle* h, int naux, int nmo, int nt, const double* L, const double* R, i8* Ld, int* eL,
+                     i8* Rd, int* eR);
+
+FoldJob make_fold_job(const i8* Rd, const int* eR, const i8* Ld, const int* eL, const double* eps, int naux,
                       int Ap, int nmo, int nocc, long j0, long ncol, long rplane, long lplane, float* Zt, u16* Zl);
 
 // Grouped launches over device job tables (item0 prefix sums set by the caller).

@@ -1,5 +1,5 @@
-// Self-energy moments from R_t in mixed precision: BF16 fixed-point digits
-// on MFMA with exact FP32 accumulation, combined in FP64.
+// Self-energy moments from R_t in mixed precision: int8 fixed-point digits on
+// the integer MFMA with exact int32 accumulation, combined in FP64.
 //
 // Same contraction as the FP64 path (eqs. convolution_occ / convolution_vir
 // with eq. w_moments):
@@ -7,17 +7,18 @@
 //   stage 2  Sigma^{(n)}[p,q] = sum_{x in sector} sum_P L[P,x,p] Zt^{(n)}[x,q,P]
 //
 // Number format.  Every operand row (A) or column (B) of a contraction is
-// scaled by a power of two 2^e so that |a| 2^-e <= 1/2, then written as
-//   a = 2^e (d0/2^8 + d1/2^16 + d2/2^24 + d3/2^32),  d_i integers in [-128, 128],
-// four BF16 values that hold their integer digits exactly (ND = 4).  The
-// product of two such numbers keeps the ten terms of digit weight i+j <= 3
-// and drops the rest (~2^-32 of the leading term).  Weight-0 terms are
-// multiples of 2^-16 of magnitude <= 1/4, so their FP32 MFMA sums are exact
-// while |partial sum| < 2^8; all other terms go to a second FP32 accumulator
-// whose rounding sits ~2^-31 below the total.  The two accumulators are
-// combined in FP64 and scaled by 2^(e_row + e_col).  What remains is the
-// truncation of the operands (~2^-33 of the row/column maxima), not the FP32
-// accumulation error of ordinary split products.
+// scaled by a power of two 2^e so that |a| 2^-e < 1/2, then written in base
+// 255 as
+//   a = 2^e (d0/255 + d1/255^2 + d2/255^3 + d3/255^4),  d_i integers in [-127, 127],
+// four int8 values (ND = 4; the remainder after d3 is below 2^-33 of 2^e).
+// Base 255 rather than 256: balanced base-256 digits need the value 128,
+// which int8 does not hold.  The product of two such numbers keeps the ten
+// terms of digit weight w = i + j <= 3 (the dropped terms are ~2^-32 of the
+// leading one).  Each weight has its own int32 MFMA accumulator; |d_i d_j| <=
+// 127^2 and at most four pairs share a weight, so the sums are exact for up to
+// 32768 k.  The weights are combined in FP64 (sum_w acc_w 255^-(w+2)) and
+// scaled by 2^(e_row + e_col): the only error left is the truncation of the
+// operands, not any accumulation error.
 // The folded stage-1 result is stored as an FP32 value plus a BF16 residual
 // (~32 significant bits); stage 2 re-digitises it per (x, q) column.
 #include "mixed_jobs.h"
@@ -27,36 +28,44 @@
 
 namespace gwm {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int MK = MIX_MK;    // k per MFMA (v_mfma_f32_16x16x32_bf16)
-
-__device__ __forceinline__ u16 bf_bits(float f) {
-    // exact for the digit values used here (<= 8 significant bits)
-    return (u16)(__float_as_uint(f) >> 16);
-}
-
+constexpr int MK = MIX_MK;    // k per MFMA (v_mfma_i32_16x16x64_i8): 64 one-byte digits
 constexpr int ND = MIX_ND;    // digits per operand
 constexpr int MAXW = 3;       // largest digit weight i + j kept in a product
+constexpr int KEXACT = 32768; // k over which the int32 digit sums stay exact
 
-__device__ __forceinline__ void digitsN(double a, int e, u16* dg) {
-    double x = ldexp(a, -e);          // |x| <= 1/2
-    double scale = 1.0 / 256.0;
+// FP64 weight of an int32 accumulator of digit weight w: 255^-(w + 2), the
+// correctly rounded reciprocal of an integer that FP64 holds exactly
+__device__ __forceinline__ constexpr double wscale(int w) {
+    return w == 0 ? 1.0 / 65025.0
+         : w == 1 ? 1.0 / 16581375.0
+         : w == 2 ? 1.0 / 4228250625.0
+         : w == 3 ? 1.0 / 1078203909375.0
+                  : 1.0 / 274941996890625.0;
+}
+
+__device__ __forceinline__ void digitsN(double a, int e, i8* dg) {
+    double x = ldexp(a, -e);          // |x| < 1/2 (<= 1/2 after the clamp below)
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
-        double q = rint(x * 256.0);
-        x = x * 256.0 - q;
-        dg[d] = bf_bits((float)(q * scale));
-        scale *= 1.0 / 256.0;
+        const double y = x * 255.0;
+        const double q = fmin(127.0, fmax(-127.0, rint(y)));
+        x = y - q;                    // |x| <= 1/2
+        dg[d] = (i8)(int)q;
     }
 }
 
 __device__ __forceinline__ int scale_exp(double amax) {
-    // 2^e with amax * 2^-e <= 1/2 (e = ilogb + 2); zero rows get e = 0
+    // 2^e with amax * 2^-e in [1/4, 1/2) (e = ilogb + 2); zero rows get e = 0
     return amax > 0.0 ? ilogb(amax) + 2 : 0;
+}
+
+__device__ __forceinline__ unsigned pack4(const i8* d) {
+    return (unsigned)(unsigned char)d[0] | ((unsigned)(unsigned char)d[1] << 8) |
+           ((unsigned)(unsigned char)d[2] << 16) | ((unsigned)(unsigned char)d[3] << 24);
 }
 
 // ---------------------------------------------------------------------------
@@ -72,18 +81,18 @@ __global__ void col_exp_kernel(int naux, long ncol, const double* __restrict__ L
     e[j] = scale_exp(m);
 }
 
-// Digit planes are k-blocked: element (row, k) of a plane with `rows` rows sits
-// at ((k / 32) * rows + row) * 32 + k % 32, so the 32 k of one MFMA step of 16
+// Digit planes are k-blocked: digit (row, k) of a plane with `rows` rows sits at
+// byte ((k / 64) * rows + row) * 64 + k % 64, so the 64 k of one MFMA step of 16
 // consecutive rows are 1 KB of contiguous memory (whole cache lines).
 
 // Row scales and k-blocked digit planes of X[rows][cols] (times cs[c] when cs is
-// set), zero-padded to kpad (a multiple of 32): one block per row, the row
+// set), zero-padded to kpad (a multiple of 64): one block per row, the row
 // maximum by a block reduction, then 8 consecutive k per thread so that each
-// digit plane gets one 16-byte store per thread and step.
+// digit plane gets one 8-byte store per thread and step.
 __global__ __launch_bounds__(256) void digitise_rows_kernel(long rows, int cols, int kpad,
                                                             const double* __restrict__ X,
                                                             const double* __restrict__ cs, int* __restrict__ e,
-                                                            u16* __restrict__ Xd) {
+                                                            i8* __restrict__ Xd) {
     const long row = blockIdx.x;
     const double* __restrict__ x = X + row * cols;
     __shared__ double red[256];
@@ -99,26 +108,26 @@ __global__ __launch_bounds__(256) void digitise_rows_kernel(long rows, int cols,
     if (threadIdx.x == 0) e[row] = ex;
     const long plane = rows * (long)kpad;
     for (int c0 = threadIdx.x * 8; c0 < kpad; c0 += 256 * 8) {
-        u16 dg[8][ND];
+        i8 dg[ND][8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int c = c0 + u;
             const double v = c < cols ? x[c] * (cs ? cs[c] : 1.0) : 0.0;
-            digitsN(v, ex, dg[u]);
-        }
-        const long o = ((long)(c0 >> 5) * rows + row) * 32 + (c0 & 31);
+            i8 t[ND];
+            digitsN(v, ex, t);
 #pragma unroll
-        for (int d = 0; d < ND; ++d)
-            *(uint4*)(Xd + d * plane + o) =
-                make_uint4(dg[0][d] | ((unsigned)dg[1][d] << 16), dg[2][d] | ((unsigned)dg[3][d] << 16),
-                           dg[4][d] | ((unsigned)dg[5][d] << 16), dg[6][d] | ((unsigned)dg[7][d] << 16));
+            for (int d = 0; d < ND; ++d) dg[d][u] = t[d];
+        }
+        const long o = ((long)(c0 >> 6) * rows + row) * 64 + (c0 & 63);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) *(uint2*)(Xd + d * plane + o) = make_uint2(pack4(dg[d]), pack4(dg[d] + 4));
     }
 }
 
 // L digits, transposed: Ld[d] k-blocked over rows j (k = Q) = digits of L[Q][j] (Q < naux, else 0),
 // 32x32 LDS tiles.
 __global__ void digits_lt_kernel(int naux, long ncol, int Ap, const double* __restrict__ L,
-                                 const int* __restrict__ e, u16* __restrict__ Ld) {
+                                 const int* __restrict__ e, i8* __restrict__ Ld) {
     __shared__ double tile[32][33];
     const long j0 = (long)blockIdx.x * 32;
     const int q0 = blockIdx.y * 32;
@@ -134,9 +143,9 @@ __global__ void digits_lt_kernel(int naux, long ncol, int Ap, const double* __re
         long j = j0 + r;
         int Q = q0 + tx;
         if (j >= ncol || Q >= Ap) continue;
-        u16 dg[ND] = {};
+        i8 dg[ND] = {};
         if (Q < naux) digitsN(tile[tx][r], e[j], dg);
-        long o = ((long)blockIdx.y * ncol + j) * 32 + tx;
+        long o = ((long)(Q >> 6) * ncol + j) * 64 + (Q & 63);
 #pragma unroll
         for (int d = 0; d < ND; ++d) Ld[d * plane + o] = dg[d];
     }
@@ -152,12 +161,14 @@ constexpr double binom2(int n, int k) {
     return 2.0 * c;
 }
 
-// LDS slab rows hold 32 k (64 B); the 16-byte chunk c of row r is stored at
+// LDS slab rows hold 64 k (64 B); the 16-byte chunk c of row r is stored at
 // chunk c ^ f(r), f(r) = ((r >> 1) & 3) ^ ((r >> 3) & 1).  A b128 read of one
 // chunk column by 16 rows then touches 16 distinct 16-byte slots modulo 256 B,
 // and each group of 8 rows 8 distinct slots modulo 128 B, so it is free of bank
 // conflicts whether the LDS serves 8 or 16 lanes of a b128 read per cycle.
 __device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >> 1) & 3) ^ ((row >> 3) & 1); }
+
+typedef unsigned char lds_t;
 
 // Tile: 16 P rows x 128 columns j, all NT moments t.  Wave w owns columns
 // [32w, 32w+32) (two 16-column blocks) for every t, so the binomial / eps-power
@@ -168,7 +179,7 @@ template <int NT>
 struct FoldSlab {
     static constexpr int A_ROWS = ND * NT * 16;  // (d, t, p) rows of the A slab
     static constexpr int B_ROWS = ND * 128;      // (d, c) rows of the B slab
-    static constexpr int SLAB = (A_ROWS + B_ROWS) * 32;  // u16 per buffer
+    static constexpr int SLAB = (A_ROWS + B_ROWS) * 64;  // bytes per buffer
 };
 
 // Binary search of the job whose first work item is the largest <= item.
@@ -183,11 +194,17 @@ __device__ __forceinline__ int find_job(const Job* __restrict__ jobs, int njobs,
     return __builtin_amdgcn_readfirstlane(lo);
 }
 
+__device__ __forceinline__ i32x4 lds_b128(const lds_t* p) { return *(const i32x4*)p; }
+
+__device__ __forceinline__ i32x4 mfma8(i32x4 a, i32x4 b, i32x4 c) {
+    return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
+}
+
 template <int NT>
-__device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, u16* lds) {
-    const u16* __restrict__ Rd = g.Rd;
+__device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_t* lds) {
+    const i8* __restrict__ Rd = g.Rd;
     const int* __restrict__ eR = g.eR;
-    const u16* __restrict__ Ld = g.Ld;
+    const i8* __restrict__ Ld = g.Ld;
     const int* __restrict__ eL = g.eL;
     const double* __restrict__ eps = g.eps;
     const int naux = g.naux, Ap = g.Ap, nmo = g.nmo, nocc = g.nocc;
@@ -195,8 +212,8 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, u16*
     float* __restrict__ Zt = g.Zt;
     u16* __restrict__ Zl = g.Zl;
     constexpr int A_ROWS = FoldSlab<NT>::A_ROWS;
-    constexpr int B_ROWS = FoldSlab<NT>::B_ROWS;
     constexpr int SLAB = FoldSlab<NT>::SLAB;
+    constexpr int B_ROWS = FoldSlab<NT>::B_ROWS;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -222,46 +239,46 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, u16*
     const long M2 = lplane / Ap;                      // rows of an L digit plane
     const int lrow = lane >> 2;
     const int gch = swz(lrow, lane & 3);              // swz is an involution in the chunk
-    const unsigned offA = (unsigned)(min(P0 + lrow, naux - 1) * 32 + gch * 8) * 2u;  // bytes
+    const unsigned offA = (unsigned)(min(P0 + lrow, naux - 1) * 64 + gch * 16);  // bytes
     unsigned offB[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         long cc = c0 + h * 64 + wv * 16 + lrow;
         if (cc > ncol - 1) cc = ncol - 1;
-        offB[h] = (unsigned)((j0 + cc) * 32 + gch * 8) * 2u;
+        offB[h] = (unsigned)((j0 + cc) * 64 + gch * 16);
     }
 
     // the resource (SGPRs) points at the k block of one digit plane, the
     // wave-uniform row offset goes in soffset, the lane part in voffset
     auto load = [&](int kt, int buf) {
-        u16* A = lds + buf * SLAB + wv * 16 * 32;
-        u16* B = A + A_ROWS * 32;
+        lds_t* A = lds + buf * SLAB + wv * 16 * 64;
+        lds_t* B = A + A_ROWS * 64;
 #pragma unroll
         for (int s = 0; s < AVT; ++s) {
             const int dt = 4 * s + wv;
             const int t = dt % NT, d = dt / NT;
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void*)(Rd + d * rplane + (long)kt * NT * naux * 32), (short)0, NT * naux * 64, 0x00020000);
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(A + s * 64 * 32),
+                (void*)(Rd + d * rplane + (long)kt * NT * naux * 64), (short)0, NT * naux * 64, 0x00020000);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(A + s * 64 * 64),
                                                      16, offA, t * naux * 64, 0, 0);
         }
 #pragma unroll
         for (int s = 0; s < BVT; ++s) {
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void*)(Ld + (s >> 1) * lplane + (long)kt * M2 * 32), (short)0, (int)(M2 * 64), 0x00020000);
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(B + s * 64 * 32),
+                (void*)(Ld + (s >> 1) * lplane + (long)kt * M2 * 64), (short)0, (int)(M2 * 64), 0x00020000);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(B + s * 64 * 64),
                                                      16, offB[s & 1], 0, 0, 0);
         }
     };
 
-    f32x4 acc0[NT][2], acc1[NT][2];
+    // one exact int32 accumulator per digit weight
+    i32x4 acc[MAXW + 1][NT][2];
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int w = 0; w <= MAXW; ++w)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-            acc0[t][cb] = (f32x4){0.f, 0.f, 0.f, 0.f};
-            acc1[t][cb] = (f32x4){0.f, 0.f, 0.f, 0.f};
-        }
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) acc[w][t][cb] = (i32x4){0, 0, 0, 0};
 
     const int nkt = Ap / MK;
     load(0, 0);
@@ -272,51 +289,45 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, u16*
         const bool more = kt + 1 < nkt;
         // buffer cur ^ 1 was last read before the barrier that ended step kt - 1
         if (more) load(kt + 1, cur ^ 1);
-        const u16* A = lds + cur * SLAB;
-        const u16* B = A + A_ROWS * 32;
-        const int aoff = lr * 32 + swz(lr, lk) * 8;
-        bf16x8 b[2][ND];
+        const lds_t* A = lds + cur * SLAB;
+        const lds_t* B = A + A_ROWS * 64;
+        const int aoff = lr * 64 + swz(lr, lk) * 16;
+        i32x4 b[2][ND];
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-            for (int d = 0; d < ND; ++d) {
-                int row = d * 128 + wave * 32 + cb * 16 + lr;
-                b[cb][d] = *(const bf16x8*)(B + row * 32 + swz(lr, lk) * 8);
-            }
+            for (int d = 0; d < ND; ++d) b[cb][d] = lds_b128(B + (d * 128 + wave * 32 + cb * 16) * 64 + aoff);
         // moments in groups of G: every product is issued for all G*2 (t, cb)
-        // accumulators before the next product, so G*2 independent MFMA chains
+        // accumulators before the next product, so independent MFMA chains
         // interleave and hide the MFMA dependency latency
         constexpr int G = (NT % 3 == 0) ? 3 : 2;
 #pragma unroll
         for (int t0 = 0; t0 < NT; t0 += G) {
-            bf16x8 a[G][ND];
+            i32x4 a[G][ND];
 #pragma unroll
-            for (int g = 0; g < G; ++g)
+            for (int gg = 0; gg < G; ++gg)
 #pragma unroll
-                for (int d = 0; d < ND; ++d) a[g][d] = *(const bf16x8*)(A + (d * NT + t0 + g) * 16 * 32 + aoff);
+                for (int d = 0; d < ND; ++d) a[gg][d] = lds_b128(A + (d * NT + t0 + gg) * 16 * 64 + aoff);
 #pragma unroll
-            for (int g = 0; g < G; ++g)
-#pragma unroll
-                for (int cb = 0; cb < 2; ++cb)
-                    acc0[t0 + g][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[g][0], b[cb][0], acc0[t0 + g][cb], 0, 0, 0);
-#pragma unroll
-            for (int w = 1; w <= MAXW; ++w)
+            for (int w = 0; w <= MAXW; ++w)
 #pragma unroll
                 for (int ii = 0; ii <= w; ++ii)
 #pragma unroll
-                    for (int g = 0; g < G; ++g)
+                    for (int gg = 0; gg < G; ++gg)
 #pragma unroll
                         for (int cb = 0; cb < 2; ++cb)
                             if (ii < ND && w - ii < ND)
-                                acc1[t0 + g][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                    a[g][ii], b[cb][w - ii], acc1[t0 + g][cb], 0, 0, 0);
+                                acc[w][t0 + gg][cb] = mfma8(a[gg][ii], b[cb][w - ii], acc[w][t0 + gg][cb]);
         }
         // this wave's DMA writes have landed; the barrier makes every wave's visible
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
     }
 
-    // epilogue: FP64 combination, scaling, binomial / eps-power fold, FP32 + BF16 residual store
+    // epilogue: FP64 combination, scaling, binomial / eps-power fold, FP32 +
+    // BF16 residual store.  Per column block the accumulators are first turned
+    // into FP64 values a[r][t] (which frees them), then each moment n is folded
+    // and stored for the four consecutive rows P0 + 4 lk + r.
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
         const long c = c0 + wave * 32 + cb * 16 + lr;
@@ -326,41 +337,43 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, u16*
         const double ex = eps[x];
         const bool occ = x < nocc;
         const int ej = eL[j];
+        double a[4][NT];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int P = P0 + 4 * lk + r;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                double z = 0.0;
+                if (P < naux) {
+#pragma unroll
+                    for (int w = MAXW; w >= 0; --w) z += (double)acc[w][t][cb][r] * wscale(w);
+                    z = ldexp(z, eR[(long)t * naux + P] + ej);
+                }
+                a[r][t] = (occ && (t & 1)) ? -z : z;
+            }
+        }
         double pw[NT];
         pw[0] = 1.0;
 #pragma unroll
         for (int k = 1; k < NT; ++k) pw[k] = pw[k - 1] * ex;
-        float outv[NT][4];
-        u16 outl[NT][4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int P = P0 + 4 * lk + r;
-            double a[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                double z = 0.0;
-                if (P < naux) z = ldexp((double)acc0[t][cb][r] + (double)acc1[t][cb][r], eR[(long)t * naux + P] + ej);
-                a[t] = (occ && (t & 1)) ? -z : z;
-            }
-#pragma unroll
-            for (int n = 0; n < NT; ++n) {
-                double z = 0.0;
-#pragma unroll
-                for (int t = 0; t <= n; ++t) z += binom2(n, t) * pw[n - t] * a[t];
-                float hi = (float)z;
-                float lo = (float)(z - (double)hi);
-                unsigned lb = __float_as_uint(lo);
-                outv[n][r] = hi;
-                outl[n][r] = (u16)((lb + 0x7fffu + ((lb >> 16) & 1u)) >> 16);
-            }
-        }
-        // rows P0 + 4 lk + r are consecutive: one 16-byte + one 8-byte store per moment
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
-            long o = ((long)n * ncol + c) * Ap + P0 + 4 * lk;
-            *(float4*)(Zt + o) = make_float4(outv[n][0], outv[n][1], outv[n][2], outv[n][3]);
-            *(uint2*)(Zl + o) = make_uint2(outl[n][0] | ((unsigned)outl[n][1] << 16),
-                                           outl[n][2] | ((unsigned)outl[n][3] << 16));
+            float hv[4];
+            unsigned lv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double z = 0.0;
+#pragma unroll
+                for (int t = 0; t <= n; ++t) z += binom2(n, t) * pw[n - t] * a[r][t];
+                const float hi = (float)z;
+                const unsigned lb = __float_as_uint((float)(z - (double)hi));
+                hv[r] = hi;
+                lv[r] = (lb + 0x7fffu + ((lb >> 16) & 1u)) >> 16;
+            }
+            // rows P0 + 4 lk + r are consecutive: one 16-byte + one 8-byte store
+            const long o = ((long)n * ncol + c) * Ap + P0 + 4 * lk;
+            *(float4*)(Zt + o) = make_float4(hv[0], hv[1], hv[2], hv[3]);
+            *(uint2*)(Zl + o) = make_uint2(lv[0] | (lv[1] << 16), lv[2] | (lv[3] << 16));
         }
     }
 }
@@ -370,7 +383,7 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, u16*
 // tiles, which share their L-digit (B) and R-digit (A) slabs through its L2.
 template <int NT>
 __global__ __launch_bounds__(256, 1) void fold_mixed_kernel(FoldJob g) {
-    __shared__ __attribute__((aligned(16))) u16 lds[2 * FoldSlab<NT>::SLAB];
+    __shared__ __attribute__((aligned(16))) lds_t lds[2 * FoldSlab<NT>::SLAB];
     const int nPg = (g.nP + 7) / 8;
     const int b = blockIdx.x;
     const int xcd = b & 7, local = b >> 3;
@@ -389,7 +402,7 @@ __global__ __launch_bounds__(256, 1) void fold_mixed_kernel(FoldJob g) {
 template <int NT>
 __global__ __launch_bounds__(256, 1) void fold_grouped_kernel(const FoldJob* __restrict__ jobs, int njobs,
                                                               long total) {
-    __shared__ __attribute__((aligned(16))) u16 lds[2 * FoldSlab<NT>::SLAB];
+    __shared__ __attribute__((aligned(16))) lds_t lds[2 * FoldSlab<NT>::SLAB];
     for (long it = blockIdx.x; it < total; it += gridDim.x) {
         const FoldJob g = jobs[find_job(jobs, njobs, it)];
         const long local = it - g.item0;
@@ -401,7 +414,7 @@ __global__ __launch_bounds__(256, 1) void fold_grouped_kernel(const FoldJob* __r
 // of max_P |Zt| and the digits of Zt + Zl (FP32 + BF16 residual) into the
 // k-blocked planes Zd[d] (rows = nt * ncol, k = P).  Each lane holds 8
 // consecutive P per 512-wide pass (Ap <= 64 * 8 * ZPASS), so reads are 32 + 16
-// bytes and every digit plane gets one 16-byte store per lane and pass.
+// bytes and every digit plane gets one 8-byte store per lane and pass.
 constexpr int ZPASS = 8;
 __device__ __forceinline__ void zdig_row(const ZdigJob& g, long row, int lane) {
     const long rows = g.rows;
@@ -409,7 +422,7 @@ __device__ __forceinline__ void zdig_row(const ZdigJob& g, long row, int lane) {
     const float* __restrict__ Zt = g.Zt;
     const u16* __restrict__ Zl = g.Zl;
     int* __restrict__ eZ = g.eZ;
-    u16* __restrict__ Zd = g.Zd;
+    i8* __restrict__ Zd = g.Zd;
     const float* z = Zt + row * Ap;
     const u16* zl = Zl + row * Ap;
     float4 v[ZPASS][2];
@@ -436,21 +449,21 @@ __device__ __forceinline__ void zdig_row(const ZdigJob& g, long row, int lane) {
     for (int ps = 0; ps < ZPASS; ++ps) {
         const int c = ps * 512 + lane * 8;
         if (c >= Ap) continue;
-        u16 dg[8][ND];
+        i8 dg[ND][8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const float4 vv = v[ps][u >> 2];
             const float hv = (u & 3) == 0 ? vv.x : (u & 3) == 1 ? vv.y : (u & 3) == 2 ? vv.z : vv.w;
             const unsigned lw = (u >> 1) == 0 ? w[ps].x : (u >> 1) == 1 ? w[ps].y : (u >> 1) == 2 ? w[ps].z : w[ps].w;
             const unsigned lb = (u & 1) ? (lw & 0xffff0000u) : (lw << 16);
-            digitsN((double)hv + (double)__uint_as_float(lb), e, dg[u]);
-        }
-        const long o = ((long)(c >> 5) * rows + row) * 32 + (c & 31);
+            i8 t[ND];
+            digitsN((double)hv + (double)__uint_as_float(lb), e, t);
 #pragma unroll
-        for (int d = 0; d < ND; ++d)
-            *(uint4*)(Zd + d * plane + o) =
-                make_uint4(dg[0][d] | ((unsigned)dg[1][d] << 16), dg[2][d] | ((unsigned)dg[3][d] << 16),
-                           dg[4][d] | ((unsigned)dg[5][d] << 16), dg[6][d] | ((unsigned)dg[7][d] << 16));
+            for (int d = 0; d < ND; ++d) dg[d][u] = t[d];
+        }
+        const long o = ((long)(c >> 6) * rows + row) * 64 + (c & 63);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) *(uint2*)(Zd + d * plane + o) = make_uint2(pack4(dg[d]), pack4(dg[d] + 4));
     }
 }
 
@@ -475,24 +488,28 @@ __global__ __launch_bounds__(256) void zdig_grouped_kernel(const ZdigJob* __rest
 
 // ---------------------------------------------------------------------------
 // Stage 2: Sigma^{(n)}[p,q] += sum_{x,P} L[P,x,p] Zt^{(n)}[x,q,P]
-// 128x128 upper tiles, 4 waves of 64x64, promotion to FP64 once per x.
+// 128 x 64 upper tiles, 4 waves of 64 x 32, promotion to FP64 once per x.
 // ---------------------------------------------------------------------------
 
-__device__ inline void upper_tile2(int t, int T, int& bi, int& bj) {
+// Upper tiles of a symmetric M x M result in 128-row x 64-column tiles: row
+// block bi keeps the column blocks bj >= 2 bi (those that reach the diagonal
+// or lie right of it); TN = ceil(M / 64) column blocks.
+__device__ inline void upper_tile_rect(int t, int TN, int& bi, int& bj) {
     int r = 0;
-    while (t >= T - r) { t -= T - r; ++r; }
+    while (t >= TN - 2 * r) { t -= TN - 2 * r; ++r; }
     bi = r;
-    bj = r + t;
+    bj = 2 * r + t;
 }
 
-// One work group: a 128 x 128 upper tile of Sigma^{(n)} for one sector and
+// One work group: a 128 x 64 upper tile of Sigma^{(n)} for one sector and
 // one split of that sector's x range.  The (x, k-block) steps form one
-// double-buffered LDS-DMA pipeline; the FP32 digit-weight accumulators are
+// double-buffered LDS-DMA pipeline; the int32 digit-weight accumulators are
 // promoted to FP64 with the row and column scales at the end of every x.
-constexpr int C_OPS = ND * 128 * 32;  // u16 per operand slab of stage 2 (32 KB)
+constexpr int C_OPA = ND * 128 * 64;  // bytes of the A (128-row) slab (32 KB)
+constexpr int C_OPB = ND * 64 * 64;   // bytes of the B (64-row) slab (16 KB)
+constexpr int C_BUF = C_OPA + C_OPB;
 
-__device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, int split, int zi, u16* lds) {
-    constexpr int OPS = C_OPS;
+__device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, int split, int zi, lds_t* lds) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -504,8 +521,8 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
     const int xs0 = sector ? g.xs0[1] : g.xs0[0];
     if (nxs <= 0) return;
     int bi, bj;
-    upper_tile2(tile, g.tiles_T, bi, bj);
-    const int m0 = bi * 128, n0 = bj * 128;
+    upper_tile_rect(tile, g.tilesN, bi, bj);
+    const int m0 = bi * 128, n0 = bj * 64;
     const int per = (nxs + g.nsplit - 1) / g.nsplit;
     const int xa = xs0 + split * per;
     const int xb = min(xs0 + nxs, xa + per);
@@ -513,57 +530,55 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
     const int M = g.nmo;
     const long M2 = (long)M * M;
     const long zrows = (long)g.nt * g.ncol;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 32;
 
     // LDS-DMA staging as in stage 1: vector s of wave w fills slab rows
-    // s * 64 + 16 w + (lane >> 2) = (d, i) with d = s >> 1,
-    // i = 64 (s & 1) + 16 w + (lane >> 2); rows past nmo read clamped rows.
+    // s * 64 + 16 w + (lane >> 2).  A slab (d, i): d = s >> 1, i = 64 (s & 1)
+    // + 16 w + (lane >> 2); B slab (d, i): d = s, i = 16 w + (lane >> 2).
+    // Rows past nmo read clamped rows.
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const int lrow = lane >> 2;
     const int gch = swz(lrow, lane & 3);
-    unsigned offA[2], offB[2];
+    unsigned offA[2];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int i = h * 64 + wv * 16 + lrow;
-        offA[h] = (unsigned)(min(m0 + i, M - 1) * 32 + gch * 8) * 2u;
-        offB[h] = (unsigned)(min(n0 + i, M - 1) * 32 + gch * 8) * 2u;
-    }
+    for (int h = 0; h < 2; ++h) offA[h] = (unsigned)(min(m0 + h * 64 + wv * 16 + lrow, M - 1) * 64 + gch * 16);
+    const unsigned offB = (unsigned)(min(n0 + wv * 16 + lrow, M - 1) * 64 + gch * 16);
     auto load = [&](int x, int kt, int buf) {
-        u16* A = lds + buf * 2 * OPS + wv * 16 * 32;
-        u16* B = A + OPS;
+        lds_t* A = lds + buf * C_BUF + wv * 16 * 64;
+        lds_t* B = A + C_OPA;
         const unsigned soA = (unsigned)x * M * 64u;
         const unsigned soB = (unsigned)((long)n * g.ncol + (long)(x - g.x0) * M) * 64u;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void*)(g.Ld + (s >> 1) * g.lplane + (long)kt * M2 * 32), (short)0, (int)(M2 * 64), 0x00020000);
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(A + s * 64 * 32),
+                (void*)(g.Ld + (s >> 1) * g.lplane + (long)kt * M2 * 64), (short)0, (int)(M2 * 64), 0x00020000);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(A + s * 64 * 64),
                                                      16, offA[s & 1], soA, 0, 0);
         }
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
+        for (int s = 0; s < ND; ++s) {
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void*)(g.Zd + (s >> 1) * g.zplane + (long)kt * zrows * 32), (short)0, (int)(zrows * 64), 0x00020000);
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(B + s * 64 * 32),
-                                                     16, offB[s & 1], soB, 0, 0);
+                (void*)(g.Zd + s * g.zplane + (long)kt * zrows * 64), (short)0, (int)(zrows * 64), 0x00020000);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(B + s * 64 * 64),
+                                                     16, offB, soB, 0, 0);
         }
     };
 
-    double acc64[4][4][4];
-    f32x4 acc0[4][4], acc1[4][4];
+    double acc64[4][2][4];
+    i32x4 acc[MAXW + 1][4][2];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            acc0[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-            acc1[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+            for (int w = 0; w <= MAXW; ++w) acc[w][i][j] = (i32x4){0, 0, 0, 0};
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
         }
     const int* eZn = g.eZ + (long)n * g.ncol;
     const int nkt = g.Ap / MK;
     const int total = (xb - xa) * nkt;
-    const int so = swz(lr, lk) * 8;
+    const int so = swz(lr, lk) * 16;
 
     load(xa, 0, 0);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -574,37 +589,31 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
         const int cur = it & 1;
         if (++ktn == nkt) { ktn = 0; ++xn; }
         if (it + 1 < total) load(xn, ktn, cur ^ 1);
-        const u16* A = lds + cur * 2 * OPS;
-        const u16* B = A + OPS;
-        bf16x8 b[4][ND];
+        const lds_t* A = lds + cur * C_BUF;
+        const lds_t* B = A + C_OPA;
+        i32x4 b[2][ND];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int d = 0; d < ND; ++d) b[j][d] = *(const bf16x8*)(B + (d * 128 + wn + j * 16 + lr) * 32 + so);
+            for (int d = 0; d < ND; ++d) b[j][d] = lds_b128(B + (d * 64 + wn + j * 16 + lr) * 64 + so);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            bf16x8 a[ND];
+            i32x4 a[ND];
 #pragma unroll
-            for (int d = 0; d < ND; ++d) a[d] = *(const bf16x8*)(A + (d * 128 + wm + i * 16 + lr) * 32 + so);
+            for (int d = 0; d < ND; ++d) a[d] = lds_b128(A + (d * 128 + wm + i * 16 + lr) * 64 + so);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc0[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][0], acc0[i][j], 0, 0, 0);
-            // each product for all four j before the next: four independent chains
-#pragma unroll
-            for (int w = 1; w <= MAXW; ++w)
+            for (int w = 0; w <= MAXW; ++w)
 #pragma unroll
                 for (int ii = 0; ii <= w; ++ii)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (ii < ND && w - ii < ND)
-                            acc1[i][j] =
-                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ii], b[j][w - ii], acc1[i][j], 0, 0, 0);
+                    for (int j = 0; j < 2; ++j)
+                        if (ii < ND && w - ii < ND) acc[w][i][j] = mfma8(a[ii], b[j][w - ii], acc[w][i][j]);
         }
         if (++kt == nkt) {
             // end of this x: promote with the row (p) and column (q) scales
             const long xl = x - g.x0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < 2; ++j) {
                 const int qg = n0 + wn + j * 16 + lr;
                 const int eq = (qg < M) ? eZn[xl * M + qg] : 0;
 #pragma unroll
@@ -613,10 +622,13 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
                     for (int r = 0; r < 4; ++r) {
                         const int pg = m0 + wm + i * 16 + 4 * lk + r;
                         const int ep = (pg < M) ? g.eL[(long)x * M + pg] : 0;
-                        acc64[i][j][r] += ldexp((double)acc0[i][j][r] + (double)acc1[i][j][r], ep + eq);
+                        double z = 0.0;
+#pragma unroll
+                        for (int w = MAXW; w >= 0; --w) z += (double)acc[w][i][j][r] * wscale(w);
+                        acc64[i][j][r] += ldexp(z, ep + eq);
                     }
-                    acc0[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-                    acc1[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int w = 0; w <= MAXW; ++w) acc[w][i][j] = (i32x4){0, 0, 0, 0};
                 }
             }
             kt = 0;
@@ -629,7 +641,7 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 2; ++j) {
             int col = n0 + wn + j * 16 + lr;
             if (col >= M) continue;
 #pragma unroll
@@ -655,7 +667,7 @@ __device__ __forceinline__ bool xcd_group_item(int tiles, int groups, int& tile,
 
 // One work group per (upper tile, split, sector * nt + n); groups are (split, z).
 __global__ __launch_bounds__(256, 1) void contract_mixed_kernel(ContractArgs g, int tiles) {
-    __shared__ __attribute__((aligned(16))) u16 lds[2 * 2 * C_OPS];
+    __shared__ __attribute__((aligned(16))) lds_t lds[2 * C_BUF];
     int tile, grp;
     if (!xcd_group_item(tiles, g.nsplit * 2 * g.nt, tile, grp)) return;
     contract_tile(g, tile, grp % g.nsplit, grp / g.nsplit, lds);
@@ -666,10 +678,10 @@ __global__ __launch_bounds__(256, 1) void contract_mixed_kernel(ContractArgs g, 
 // starts loading the next one.
 __global__ __launch_bounds__(256, 1) void contract_grouped_kernel(const ContractArgs* __restrict__ jobs, int njobs,
                                                                   long total) {
-    __shared__ __attribute__((aligned(16))) u16 lds[2 * 2 * C_OPS];
+    __shared__ __attribute__((aligned(16))) lds_t lds[2 * C_BUF];
     for (long it = blockIdx.x; it < total; it += gridDim.x) {
         const ContractArgs g = jobs[find_job(jobs, njobs, it)];
-        const int tiles = g.tiles_T * (g.tiles_T + 1) / 2;
+        const int tiles = g.tiles;
         long local = it - g.item0;
         const int tile = (int)(local % tiles);
         local /= tiles;
@@ -681,23 +693,23 @@ __global__ __launch_bounds__(256, 1) void contract_grouped_kernel(const Contract
 
 // ---------------------------------------------------------------------------
 // Digit GEMM: C[m][n] = sum_k A[m][k] B[n][k] with A, B given as k-blocked digit
-// planes with one exponent per row (the digit format above).  FP32 digit-
-// weight accumulators are promoted to FP64 every kc k-blocks (kc * 32 <= 1024
-// keeps the weight-0 sums exact).  128 x 128 tiles, 4 waves of 64 x 64, the
-// same LDS-DMA pipeline as stage 2.  Epilogues: FP64 split partials (upper
+// planes with one exponent per row (the digit format above).  Every split
+// covers at most KEXACT k, so its int32 digit-weight sums are exact and are
+// combined in FP64 once, in the epilogue.  128 x 64 tiles, 4 waves of 64 x 32,
+// the same LDS-DMA pipeline as stage 2.  Epilogues: FP64 split partials (upper
 // tiles only when sym) or Xout = Dv[n] * Xin + alpha * C (in place allowed).
 // ---------------------------------------------------------------------------
 struct DgemmArgs {
-    const u16* A;
+    const i8* A;
     long aplane;
     int arows;
     const int* eA;
-    const u16* B;
+    const i8* B;
     long bplane;
     int brows;
     const int* eB;
-    int M, N, nkb;    // output rows / cols; k-blocks of 32
-    int nsplit, kc;   // splits of the k-block range; promotion interval (k-blocks)
+    int M, N, nkb;    // output rows / cols; k-blocks of 64
+    int nsplit;       // splits of the k-block range (at most KEXACT / 64 k-blocks each)
     int sym, tilesN;  // upper tiles only (M == N); column tiles
     double* part;     // [nsplit][M][N] (Xout == nullptr)
     double* Xout;
@@ -706,132 +718,106 @@ struct DgemmArgs {
     double alpha;
 };
 
-// W4: also keep the weight-4 products d2 x d2, d1 x d3 and d3 x d1.  In a
-// Gram-type product (B = A or A o D) the diagonal d2 x d2 terms are squares and
-// accumulate coherently over k, and for rows with a wide dynamic range (most
-// entries far below the row maximum, whose leading digit is then d1) d1 x d3 is
-// the leading-times-last product of those entries: without them the moments
-// carry ~1e-8 relative error, with them ~5e-10.
+// W4: also keep the weight-4 products d2 x d2, d1 x d3 and d3 x d1 (a fifth
+// accumulator).  In a Gram-type product (B = A or A o D) the diagonal d2 x d2
+// terms are squares and accumulate coherently over k, and for rows with a wide
+// dynamic range (most entries far below the row maximum, whose leading digit
+// is then d1) d1 x d3 is the leading-times-last product of those entries:
+// without them the moments carry ~1e-8 relative error, with them ~5e-10.
 template <bool W4>
-__device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int split, u16* lds) {
-    constexpr int OPS = C_OPS;
+__device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int split, lds_t* lds) {
+    constexpr int NW = W4 ? MAXW + 2 : MAXW + 1;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int lr = lane & 15;
     const int lk = lane >> 4;
     int bi, bj;
-    if (g.sym) upper_tile2(tile, g.tilesN, bi, bj);
+    if (g.sym) upper_tile_rect(tile, g.tilesN, bi, bj);
     else {
         bi = tile / g.tilesN;
         bj = tile - bi * g.tilesN;
     }
-    const int m0 = bi * 128, n0 = bj * 128;
+    const int m0 = bi * 128, n0 = bj * 64;
     const int per = (g.nkb + g.nsplit - 1) / g.nsplit;
     const int ka = split * per;
     const int kb_end = min(g.nkb, ka + per);
     const int total = kb_end - ka;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 32;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const int lrow = lane >> 2;
     const int gch = swz(lrow, lane & 3);
-    unsigned offA[2], offB[2];
+    unsigned offA[2];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int i = h * 64 + wv * 16 + lrow;
-        offA[h] = (unsigned)(min(m0 + i, g.M - 1) * 32 + gch * 8) * 2u;
-        offB[h] = (unsigned)(min(n0 + i, g.N - 1) * 32 + gch * 8) * 2u;
-    }
+    for (int h = 0; h < 2; ++h) offA[h] = (unsigned)(min(m0 + h * 64 + wv * 16 + lrow, g.M - 1) * 64 + gch * 16);
+    const unsigned offB = (unsigned)(min(n0 + wv * 16 + lrow, g.N - 1) * 64 + gch * 16);
     auto load = [&](int kb, int buf) {
-        u16* A = lds + buf * 2 * OPS + wv * 16 * 32;
-        u16* B = A + OPS;
+        lds_t* A = lds + buf * C_BUF + wv * 16 * 64;
+        lds_t* B = A + C_OPA;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void*)(g.A + (s >> 1) * g.aplane + (long)kb * g.arows * 32), (short)0, g.arows * 64, 0x00020000);
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(A + s * 64 * 32),
+                (void*)(g.A + (s >> 1) * g.aplane + (long)kb * g.arows * 64), (short)0, g.arows * 64, 0x00020000);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(A + s * 64 * 64),
                                                      16, offA[s & 1], 0, 0, 0);
         }
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
+        for (int s = 0; s < ND; ++s) {
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void*)(g.B + (s >> 1) * g.bplane + (long)kb * g.brows * 32), (short)0, g.brows * 64, 0x00020000);
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(B + s * 64 * 32),
-                                                     16, offB[s & 1], 0, 0, 0);
+                (void*)(g.B + s * g.bplane + (long)kb * g.brows * 64), (short)0, g.brows * 64, 0x00020000);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(B + s * 64 * 64),
+                                                     16, offB, 0, 0, 0);
         }
     };
-    double acc64[4][4][4];
-    f32x4 acc0[4][4], acc1[4][4];
+    i32x4 acc[NW][4][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int w = 0; w < NW; ++w)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            acc0[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-            acc1[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
-        }
-    const int so = swz(lr, lk) * 8;
+            for (int j = 0; j < 2; ++j) acc[w][i][j] = (i32x4){0, 0, 0, 0};
+    const int so = swz(lr, lk) * 16;
     if (total > 0) {
         load(ka, 0);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
     }
-    int since = 0;
     for (int it = 0; it < total; ++it) {
         const int cur = it & 1;
         if (it + 1 < total) load(ka + it + 1, cur ^ 1);
-        const u16* A = lds + cur * 2 * OPS;
-        const u16* B = A + OPS;
-        bf16x8 b[4][ND];
+        const lds_t* A = lds + cur * C_BUF;
+        const lds_t* B = A + C_OPA;
+        i32x4 b[2][ND];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int d = 0; d < ND; ++d) b[j][d] = *(const bf16x8*)(B + (d * 128 + wn + j * 16 + lr) * 32 + so);
+            for (int d = 0; d < ND; ++d) b[j][d] = lds_b128(B + (d * 64 + wn + j * 16 + lr) * 64 + so);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            bf16x8 a[ND];
+            i32x4 a[ND];
 #pragma unroll
-            for (int d = 0; d < ND; ++d) a[d] = *(const bf16x8*)(A + (d * 128 + wm + i * 16 + lr) * 32 + so);
+            for (int d = 0; d < ND; ++d) a[d] = lds_b128(A + (d * 128 + wm + i * 16 + lr) * 64 + so);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc0[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][0], acc0[i][j], 0, 0, 0);
-#pragma unroll
-            for (int w = 1; w <= MAXW; ++w)
+            for (int w = 0; w <= MAXW; ++w)
 #pragma unroll
                 for (int ii = 0; ii <= w; ++ii)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (ii < ND && w - ii < ND)
-                            acc1[i][j] =
-                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ii], b[j][w - ii], acc1[i][j], 0, 0, 0);
+                    for (int j = 0; j < 2; ++j)
+                        if (ii < ND && w - ii < ND) acc[w][i][j] = mfma8(a[ii], b[j][w - ii], acc[w][i][j]);
             if (W4)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    acc1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[j][2], acc1[i][j], 0, 0, 0);
-                    acc1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[j][3], acc1[i][j], 0, 0, 0);
-                    acc1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[3], b[j][1], acc1[i][j], 0, 0, 0);
+                for (int j = 0; j < 2; ++j) {
+                    acc[NW - 1][i][j] = mfma8(a[2], b[j][2], acc[NW - 1][i][j]);
+                    acc[NW - 1][i][j] = mfma8(a[1], b[j][3], acc[NW - 1][i][j]);
+                    acc[NW - 1][i][j] = mfma8(a[3], b[j][1], acc[NW - 1][i][j]);
                 }
-        }
-        if (++since == g.kc || it + 1 == total) {
-            // promote: the row / column exponents are constant along k
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc0[i][j][r] + (double)acc1[i][j][r];
-                    acc0[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-                    acc1[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-                }
-            since = 0;
         }
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
     }
-    // scale by 2^(e_row + e_col) once, then the epilogue
+    // combine the weights and scale by 2^(e_row + e_col) once, then the epilogue
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 2; ++j) {
         const int col = n0 + wn + j * 16 + lr;
         if (col >= g.N) continue;
         const int ec = g.eB[col];
@@ -841,7 +827,10 @@ __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int spl
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + wm + i * 16 + 4 * lk + r;
                 if (row >= g.M) continue;
-                const double c = ldexp(acc64[i][j][r], g.eA[row] + ec);
+                double z = 0.0;
+#pragma unroll
+                for (int w = NW - 1; w >= 0; --w) z += (double)acc[w][i][j][r] * wscale(w);
+                const double c = ldexp(z, g.eA[row] + ec);
                 const long o = (long)row * g.N + col;
                 if (g.Xout) g.Xout[o] = g.Dv[col] * g.Xin[o] + g.alpha * c;
                 else g.part[(long)split * g.M * g.N + o] = c;
@@ -854,7 +843,7 @@ __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int spl
 // share a column block of B meet in one L2.
 template <bool W4>
 __global__ __launch_bounds__(256, 1) void dgemm_mixed_kernel(DgemmArgs g, int gtiles, int groups) {
-    __shared__ __attribute__((aligned(16))) u16 lds[2 * 2 * C_OPS];
+    __shared__ __attribute__((aligned(16))) lds_t lds[2 * C_BUF];
     if (g.nsplit > 1 || g.sym) {
         dgemm_tile<W4>(g, blockIdx.x, blockIdx.y, lds);
     } else {
@@ -890,33 +879,33 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
     const int Ap = (naux + MK - 1) / MK * MK;
     if (nt > 12) return set_err(h, GW_EINVAL, "mixed precision: nmom_max must be <= 11");
     if (Ap > 512 * ZPASS) return set_err(h, GW_EINVAL, "mixed precision: naux must be <= 4096");
+    static_assert(512 * ZPASS <= KEXACT, "exact int32 digit sums over the aux index");
     if ((long)nt * naux * 64 >= (1L << 31) || M2 * 64 >= (1L << 31))
         return set_err(h, GW_EINVAL, "mixed precision: digit plane rows exceed 31-bit byte offsets");
     // --- operand digits
     const long lplane = M2 * Ap;
     const long rrows = (long)nt * naux;
     const long rplane = rrows * Ap;
-    u16* Ld = (u16*)ws_get(h, WS_MIX0, sizeof(u16) * ND * lplane);
+    i8* Ld = (i8*)ws_get(h, WS_MIX0, sizeof(i8) * ND * lplane);
     int* eL = (int*)ws_get(h, WS_MIX1, sizeof(int) * (M2 + rrows));
-    u16* Rd = (u16*)ws_get(h, WS_MIX2, sizeof(u16) * ND * rplane);
+    i8* Rd = (i8*)ws_get(h, WS_MIX2, sizeof(i8) * ND * rplane);
     if (!Ld || !eL || !Rd) return GW_ENOMEM;
     int* eR = eL + M2;
     GW_TRY(mixed_prep(h, naux, nmo, nt, L, R, Ld, eL, Rd, eR));
     // --- chunk over x so that the stage-1 intermediates (FP32 + BF16 residual
-    // and the ND digit planes) fit the cap
+    // and the ND int8 digit planes) fit the cap
     size_t cap = (opts && opts->zchunk_bytes) ? opts->zchunk_bytes : ((size_t)16 << 30);
-    size_t per_x = (size_t)nt * nmo * Ap * (sizeof(float) + sizeof(u16) + ND * sizeof(u16));
+    size_t per_x = (size_t)nt * nmo * Ap * (sizeof(float) + sizeof(u16) + ND * sizeof(i8));
     int nx = (int)std::max<size_t>(1, std::min<size_t>((size_t)nmo, cap / per_x));
     // the stage-2 kernel addresses a chunk's digit plane rows with 31-bit byte offsets
     nx = (int)std::max<long>(1, std::min<long>(nx, ((1L << 31) - 1) / ((long)nt * nmo * 64)));
     const long zrows_max = (long)nt * nx * nmo;
     float* Zt = (float*)ws_get(h, WS_MIX3, sizeof(float) * zrows_max * Ap);
     u16* Zl = (u16*)ws_get(h, WS_MIX5, sizeof(u16) * zrows_max * Ap);
-    u16* Zd = (u16*)ws_get(h, WS_MIX6, sizeof(u16) * ND * zrows_max * Ap);
+    i8* Zd = (i8*)ws_get(h, WS_MIX6, sizeof(i8) * ND * zrows_max * Ap);
     int* eZ = (int*)ws_get(h, WS_MIX4, sizeof(int) * zrows_max);
     if (!Zt || !Zl || !Zd || !eZ) return GW_ENOMEM;
-    const int T = (nmo + 127) / 128;
-    const int tiles = T * (T + 1) / 2;
+    const int tiles = mixed_upper_tiles(nmo);
     int S = std::max(1, std::min(64, (2048 + tiles * nt - 1) / (tiles * nt)));
     const long part_per_sector = (long)nt * S * M2;
     double* acc = (double*)ws_get(h, WS_SIGACC, sizeof(double) * 2 * part_per_sector);
@@ -961,7 +950,7 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
             a.xs0[s] = xs0;
             a.nxs[s] = std::max(0, xs1 - xs0);
         }
-        a.nt = nt; a.nsplit = S; a.tiles_T = T; a.ncol = ncol;
+        a.nt = nt; a.nsplit = S; a.tilesN = (nmo + 63) / 64; a.tiles = tiles; a.ncol = ncol;
         a.part = acc;
         a.nsplit_total = S; a.split_off = 0; a.item0 = 0;
         {
@@ -978,7 +967,7 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
     return GW_OK;
 }
 
-FoldJob make_fold_job(const u16* Rd, const int* eR, const u16* Ld, const int* eL, const double* eps, int naux,
+FoldJob make_fold_job(const i8* Rd, const int* eR, const i8* Ld, const int* eL, const double* eps, int naux,
                       int Ap, int nmo, int nocc, long j0, long ncol, long rplane, long lplane, float* Zt, u16* Zl) {
     FoldJob g;
     g.Rd = Rd; g.eR = eR; g.Ld = Ld; g.eL = eL; g.eps = eps;
@@ -991,8 +980,8 @@ FoldJob make_fold_job(const u16* Rd, const int* eR, const u16* Ld, const int* eL
     return g;
 }
 
-gw_status mixed_prep(Handle* h, int naux, int nmo, int nt, const double* L, const double* R, u16* Ld, int* eL,
-                     u16* Rd, int* eR) {
+gw_status mixed_prep(Handle* h, int naux, int nmo, int nt, const double* L, const double* R, i8* Ld, int* eL,
+                     i8* Rd, int* eR) {
     const long M2 = (long)nmo * nmo;
     const int Ap = mixed_Ap(naux);
     const long rrows = (long)nt * naux;
@@ -1043,16 +1032,17 @@ gw_status launch_contract_grouped(Handle* h, const ContractArgs* jobs, int njobs
 // TDA moments with digit GEMMs (half-order form, as in the FP64 path):
 //   R_2k = X_k X_k^T,  R_2k+1 = X_k D X_k^T + 2 R_k R_k,  X_k+1 = D o X_k + 2 R_k V.
 // X stays FP64; each product digitises its operands (X rows, (X o D) rows,
-// R_k rows, V^T rows once) and accumulates in FP64.  R_k R_k stays FP64.  The
-// symmetric products keep the three weight-4 digit products as well (thirteen).
+// R_k rows, V^T rows once) and combines its exact int32 digit sums in FP64.
+// R_k R_k stays FP64.  The symmetric products keep the three weight-4 digit
+// products as well (thirteen).
 // ---------------------------------------------------------------------------
 namespace {
 
 gw_status launch_dgemm(Handle* h, const DgemmArgs& g0, const char* tag) {
     DgemmArgs g = g0;
     const int T = (g.M + 127) / 128;
-    g.tilesN = g.sym ? T : (g.N + 127) / 128;
-    const long tiles = g.sym ? (long)T * (T + 1) / 2 : (long)T * g.tilesN;
+    g.tilesN = (g.N + 63) / 64;
+    const long tiles = g.sym ? (long)mixed_upper_tiles(g.M) : (long)T * g.tilesN;
     int gtiles = 0, groups = 0;
     dim3 grid((unsigned)tiles, (unsigned)g.nsplit);
     if (!(g.sym || g.nsplit > 1)) {
@@ -1069,7 +1059,7 @@ gw_status launch_dgemm(Handle* h, const DgemmArgs& g0, const char* tag) {
 }
 
 // digit planes (rows x kpad, k-blocked) of X[rows][cols] (times cs[c] when cs is set)
-gw_status digitise_rows(Handle* h, long rows, long cols, int kpad, const double* X, const double* cs, int* e, u16* Xd) {
+gw_status digitise_rows(Handle* h, long rows, long cols, int kpad, const double* X, const double* cs, int* e, i8* Xd) {
     hipLaunchKernelGGL(digitise_rows_kernel, dim3((unsigned)rows), dim3(256), 0, h->stream, rows, (int)cols, kpad, X,
                        cs, e, Xd);
     GW_CHECK_LAUNCH(h);
@@ -1085,21 +1075,23 @@ gw_status tda_moments_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_ma
     const int Ap = mixed_Ap(naux);
     if (ov * 64 >= (1L << 31) || (long)naux * 64 >= (1L << 31))
         return set_err(h, GW_EINVAL, "mixed precision: nocc*nvir too large for the digit recursion");
+    if (Ap > KEXACT) return set_err(h, GW_EINVAL, "mixed precision: naux must be <= 32768 for the digit recursion");
     const long asz = (long)naux * naux;
     double* V = (double*)ws_get(h, WS_V, sizeof(double) * naux * ov);
     double* D = (double*)ws_get(h, WS_D, sizeof(double) * ov);
     double* X = (double*)ws_get(h, WS_X0, sizeof(double) * naux * ov);
-    u16* Vt = (u16*)ws_get(h, WS_RC0, sizeof(u16) * ND * ov * Ap);
-    u16* Xd = (u16*)ws_get(h, WS_RC1, sizeof(u16) * ND * (long)naux * Kp);
-    u16* Yd = (u16*)ws_get(h, WS_RC2, sizeof(u16) * ND * (long)naux * Kp);
-    u16* Rk = (u16*)ws_get(h, WS_RC3, sizeof(u16) * ND * (long)naux * Ap);
+    i8* Vt = (i8*)ws_get(h, WS_RC0, sizeof(i8) * ND * ov * Ap);
+    i8* Xd = (i8*)ws_get(h, WS_RC1, sizeof(i8) * ND * (long)naux * Kp);
+    i8* Yd = (i8*)ws_get(h, WS_RC2, sizeof(i8) * ND * (long)naux * Kp);
+    i8* Rk = (i8*)ws_get(h, WS_RC3, sizeof(i8) * ND * (long)naux * Ap);
     int* ex = (int*)ws_get(h, WS_RC4, sizeof(int) * (ov + 3L * naux));
     int ncu = 256;
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device);
-    const int T = (naux + 127) / 128;
-    const int tiles = T * (T + 1) / 2;
+    const int tiles = mixed_upper_tiles(naux);
     const int nkbX = Kp / MK;
-    const int S = std::max(1, std::min(nkbX, (3 * ncu + tiles - 1) / tiles));
+    // enough splits to fill the chip, and at most KEXACT k per split (exact int32 sums)
+    const int S = std::max((nkbX + KEXACT / MK - 1) / (KEXACT / MK),
+                           std::max(1, std::min(nkbX, (3 * ncu + tiles - 1) / tiles)));
     double* part = (double*)ws_get(h, WS_RC5, sizeof(double) * S * asz);
     if (!V || !D || !X || !Vt || !Xd || !Yd || !Rk || !ex || !part) return GW_ENOMEM;
     int *eVt = ex, *eX = ex + ov, *eY = eX + naux, *eR = eY + naux;
@@ -1117,7 +1109,6 @@ gw_status tda_moments_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_ma
     sy.M = sy.N = naux;
     sy.nkb = nkbX;
     sy.nsplit = S;
-    sy.kc = 32;
     sy.sym = 1;
     sy.part = part;
     sy.A = Xd; sy.aplane = (long)naux * Kp; sy.arows = naux; sy.eA = eX;
@@ -1160,7 +1151,7 @@ gw_status tda_moments_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_ma
             DgemmArgs g{};
             g.A = Rk; g.aplane = (long)naux * Ap; g.arows = naux; g.eA = eR;
             g.B = Vt; g.bplane = ov * Ap; g.brows = (int)ov; g.eB = eVt;
-            g.M = naux; g.N = (int)ov; g.nkb = Ap / MK; g.nsplit = 1; g.kc = 32; g.sym = 0;
+            g.M = naux; g.N = (int)ov; g.nkb = Ap / MK; g.nsplit = 1; g.sym = 0;
             g.Xout = X; g.Xin = X; g.Dv = D; g.alpha = 2.0;
             GW_TRY(launch_dgemm(h, g, "recur_rv"));
         }

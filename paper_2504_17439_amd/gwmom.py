@@ -40,7 +40,7 @@ class GWError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("nquad", ctypes.c_int), ("quad_scale", ctypes.c_double),
                 ("pinv_tol", ctypes.c_double), ("neg_tol", ctypes.c_double),
-                ("bf16_slices", ctypes.c_int), ("zchunk_bytes", ctypes.c_size_t),
+                ("zchunk_bytes", ctypes.c_size_t),
                 ("moment_eps", ctypes.c_double)]
 
 

@@ -124,7 +124,7 @@ gw_status build_tables(gw_batch_s* b, int target) {
             u16* Zl = b->Zl + j.zl_off;
             i8* Zd = b->Zd + j.zd_off;
             int* eZ = b->eZ + j.ez_off;
-            FoldJob f = make_fold_job(m.Rd, m.eR, m.Ld, m.eL, s.eps, s.naux, m.Ap, m.nmo, s.nocc,
+            FoldJob f = make_fold_job(nt, m.Rd, m.eR, m.Ld, m.eL, s.eps, s.naux, m.Ap, m.nmo, s.nocc,
                                       (long)j.x0 * m.nmo, ncol, m.rplane, m.lplane, Zt, Zl);
             f.item0 = fi;
             fi += (long)f.nP * f.nC;

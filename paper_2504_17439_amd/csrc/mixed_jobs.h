@@ -55,6 +55,15 @@ struct ContractArgs {
 
 inline int mixed_Ap(int naux) { return (naux + MIX_MK - 1) / MIX_MK * MIX_MK; }
 
+// Stage-1 tile shape for nt moments: each of the 4 waves owns fold_tpw(nt)
+// moments (int32 accumulators for 4 digit weights x 4 column blocks each),
+// fold_tg(nt) groups of waves split the moments, the rest split the columns;
+// the tile is 16 P rows x fold_cols(nt) columns.
+__host__ __device__ constexpr int fold_tpw(int nt) { return nt <= 2 ? 1 : (nt == 4 || nt == 8) ? 2 : 3; }
+__host__ __device__ constexpr int fold_tg(int nt) { return (nt + fold_tpw(nt) - 1) / fold_tpw(nt); }
+__host__ __device__ constexpr int fold_cg(int nt) { return 4 / fold_tg(nt); }
+__host__ __device__ constexpr int fold_cols(int nt) { return 64 * fold_cg(nt); }
+
 // Upper 128-row x 64-column tiles of a symmetric M x M result: row block bi
 // keeps column blocks bj >= 2 bi.
 inline int mixed_upper_tiles(int M) {
@@ -68,7 +77,7 @@ inline int mixed_upper_tiles(int M) {
 gw_status mixed_prep(Handle* h, int naux, int nmo, int nt, const double* L, const double* R, i8* Ld, int* eL,
                      i8* Rd, int* eR);
 
-FoldJob make_fold_job(const i8* Rd, const int* eR, const i8* Ld, const int* eL, const double* eps, int naux,
+FoldJob make_fold_job(int nt, const i8* Rd, const int* eR, const i8* Ld, const int* eL, const double* eps, int naux,
                       int Ap, int nmo, int nocc, long j0, long ncol, long rplane, long lplane, float* Zt, u16* Zl);
 
 // Grouped launches over device job tables (item0 prefix sums set by the caller).

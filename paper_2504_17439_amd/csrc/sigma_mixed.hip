@@ -170,16 +170,24 @@ __device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >>
 
 typedef unsigned char lds_t;
 
-// Tile: 16 P rows x 128 columns j, all NT moments t.  Wave w owns columns
-// [32w, 32w+32) (two 16-column blocks) for every t, so the binomial / eps-power
-// fold over t is done in registers in the epilogue.  LDS holds two K slabs
-// (double buffering, 160 KB at NT = 12); moments are processed in groups so
-// that several independent accumulator chains interleave on the MFMA pipe.
+// Tile: 16 P rows x FC = fold_cols(NT) columns j, all NT moments t.  Wave w
+// owns TPW moments (t group w % TG) for the 64 columns of column group w / TG
+// (four 16-column blocks): 4 weights x TPW x 4 int32 accumulator blocks, at
+// most 192 registers, which stay in AGPRs.  LDS holds two K slabs (double
+// buffering); after the k loop the waves exchange their FP64 values through
+// LDS so that each wave folds all NT moments of its own column blocks.
 template <int NT>
 struct FoldSlab {
+    static constexpr int TPW = fold_tpw(NT);
+    static constexpr int TG = fold_tg(NT);
+    static constexpr int CG = fold_cg(NT);
+    static constexpr int FC = fold_cols(NT);
     static constexpr int A_ROWS = ND * NT * 16;  // (d, t, p) rows of the A slab
-    static constexpr int B_ROWS = ND * 128;      // (d, c) rows of the B slab
+    static constexpr int B_ROWS = ND * FC;       // (d, c) rows of the B slab
     static constexpr int SLAB = (A_ROWS + B_ROWS) * 64;  // bytes per buffer
+    static constexpr int XCH = NT * 4 * CG * 64 * 4 * 8;  // bytes of the epilogue exchange
+    static_assert(TG * CG == 4 && TPW * TG >= NT, "fold wave layout");
+    static_assert(XCH <= 2 * SLAB, "exchange fits the slab buffers");
 };
 
 // Binary search of the job whose first work item is the largest <= item.
@@ -202,6 +210,9 @@ __device__ __forceinline__ i32x4 mfma8(i32x4 a, i32x4 b, i32x4 c) {
 
 template <int NT>
 __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_t* lds) {
+    using FS = FoldSlab<NT>;
+    constexpr int TPW = FS::TPW, TG = FS::TG, CG = FS::CG, FC = FS::FC;
+    constexpr int A_ROWS = FS::A_ROWS, B_ROWS = FS::B_ROWS, SLAB = FS::SLAB;
     const i8* __restrict__ Rd = g.Rd;
     const int* __restrict__ eR = g.eR;
     const i8* __restrict__ Ld = g.Ld;
@@ -211,38 +222,38 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_
     const long j0 = g.j0, ncol = g.ncol, rplane = g.rplane, lplane = g.lplane;
     float* __restrict__ Zt = g.Zt;
     u16* __restrict__ Zl = g.Zl;
-    constexpr int A_ROWS = FoldSlab<NT>::A_ROWS;
-    constexpr int SLAB = FoldSlab<NT>::SLAB;
-    constexpr int B_ROWS = FoldSlab<NT>::B_ROWS;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int lr = lane & 15;
     const int lk = lane >> 4;
-    const long c0 = (long)ct * 128;
+    const long c0 = (long)ct * FC;
     const int P0 = pb * 16;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const int tg = wv % TG, cg = wv / TG;       // this wave's moment group and column group
+    const int t0 = tg * TPW;
 
     // Global -> LDS staging by LDS-DMA buffer loads (16 bytes per lane; one
     // wave instruction fills 1 KB of LDS at M0 + 16 * lane).  Vector s of wave
     // w fills slab rows s * 64 + 16 w + (lane >> 2), slot lane & 3.  For the A
     // slab (rows (d, t, p)) that row has p = lane >> 2 and (d, t) =
-    // divmod(4 s + w, NT); for the B slab (rows (d, c)) c = 64 (s & 1) + 16 w +
-    // (lane >> 2), d = s >> 1.  The lane fetches the global chunk that the
-    // swizzle puts in its slot, so the source is a wave-uniform base plus one
-    // loop-invariant lane offset.  Rows past naux and columns past ncol read
-    // clamped (valid) rows: their products are never stored.
+    // divmod(4 s + w, NT); for the B slab (rows (d, c)) d = s / CG and c =
+    // 64 (s % CG) + 16 w + (lane >> 2).  The lane fetches the global chunk that
+    // the swizzle puts in its slot, so the source is a wave-uniform base plus
+    // one loop-invariant lane offset.  Rows past naux and columns past ncol
+    // read clamped (valid) rows: their products are never stored.
     static_assert((A_ROWS * 4) % 256 == 0 && (B_ROWS * 4) % 256 == 0, "slab vectors per thread");
     constexpr int AVT = A_ROWS * 4 / 256;
     constexpr int BVT = B_ROWS * 4 / 256;
-    const int wv = __builtin_amdgcn_readfirstlane(wave);
     const long M2 = lplane / Ap;                      // rows of an L digit plane
     const int lrow = lane >> 2;
     const int gch = swz(lrow, lane & 3);              // swz is an involution in the chunk
     const unsigned offA = (unsigned)(min(P0 + lrow, naux - 1) * 64 + gch * 16);  // bytes
-    unsigned offB[2];
+    unsigned offB[2];                                 // CG <= 2 column groups
+    static_assert(CG <= 2, "column groups");
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < CG; ++h) {
         long cc = c0 + h * 64 + wv * 16 + lrow;
         if (cc > ncol - 1) cc = ncol - 1;
         offB[h] = (unsigned)((j0 + cc) * 64 + gch * 16);
@@ -265,117 +276,139 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_
 #pragma unroll
         for (int s = 0; s < BVT; ++s) {
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void*)(Ld + (s >> 1) * lplane + (long)kt * M2 * 64), (short)0, (int)(M2 * 64), 0x00020000);
+                (void*)(Ld + (s / CG) * lplane + (long)kt * M2 * 64), (short)0, (int)(M2 * 64), 0x00020000);
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(B + s * 64 * 64),
-                                                     16, offB[s & 1], 0, 0, 0);
+                                                     16, offB[s % CG], 0, 0, 0);
         }
     };
 
-    // one exact int32 accumulator per digit weight
-    i32x4 acc[MAXW + 1][NT][2];
+    // one exact int32 accumulator per digit weight, own moment and column block
+    i32x4 acc[MAXW + 1][TPW][4];
 #pragma unroll
     for (int w = 0; w <= MAXW; ++w)
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int tt = 0; tt < TPW; ++tt)
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb) acc[w][t][cb] = (i32x4){0, 0, 0, 0};
+            for (int cb = 0; cb < 4; ++cb) acc[w][tt][cb] = (i32x4){0, 0, 0, 0};
+    // moments past NT (the last group when TPW does not divide NT) repeat the
+    // last one; their results are never used
+    int arow[TPW];
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt) arow[tt] = min(t0 + tt, NT - 1) * 16 * 64;
 
     const int nkt = Ap / MK;
     load(0, 0);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
+    const int aoff = lr * 64 + swz(lr, lk) * 16;
     for (int kt = 0; kt < nkt; ++kt) {
         const int cur = kt & 1;
-        const bool more = kt + 1 < nkt;
-        // buffer cur ^ 1 was last read before the barrier that ended step kt - 1
-        if (more) load(kt + 1, cur ^ 1);
-        const lds_t* A = lds + cur * SLAB;
-        const lds_t* B = A + A_ROWS * 64;
-        const int aoff = lr * 64 + swz(lr, lk) * 16;
-        i32x4 b[2][ND];
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-            for (int d = 0; d < ND; ++d) b[cb][d] = lds_b128(B + (d * 128 + wave * 32 + cb * 16) * 64 + aoff);
-        // moments in groups of G: every product is issued for all G*2 (t, cb)
-        // accumulators before the next product, so independent MFMA chains
-        // interleave and hide the MFMA dependency latency
-        constexpr int G = (NT % 3 == 0) ? 3 : 2;
-#pragma unroll
-        for (int t0 = 0; t0 < NT; t0 += G) {
-            i32x4 a[G][ND];
-#pragma unroll
-            for (int gg = 0; gg < G; ++gg)
-#pragma unroll
-                for (int d = 0; d < ND; ++d) a[gg][d] = lds_b128(A + (d * NT + t0 + gg) * 16 * 64 + aoff);
-#pragma unroll
-            for (int w = 0; w <= MAXW; ++w)
-#pragma unroll
-                for (int ii = 0; ii <= w; ++ii)
-#pragma unroll
-                    for (int gg = 0; gg < G; ++gg)
-#pragma unroll
-                        for (int cb = 0; cb < 2; ++cb)
-                            if (ii < ND && w - ii < ND)
-                                acc[w][t0 + gg][cb] = mfma8(a[gg][ii], b[cb][w - ii], acc[w][t0 + gg][cb]);
-        }
-        // this wave's DMA writes have landed; the barrier makes every wave's visible
+        // step kt's slabs have landed (this wave's DMA) and are visible (the
+        // barrier), and every wave has finished reading buffer cur ^ 1 (step
+        // kt - 1): its refill for step kt + 1 overlaps all of step kt's MFMAs
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
+        if (kt + 1 < nkt) load(kt + 1, cur ^ 1);
+        const lds_t* A = lds + cur * SLAB;
+        const lds_t* B = A + A_ROWS * 64;
+        i32x4 b[4][ND];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int d = 0; d < ND; ++d) b[cb][d] = lds_b128(B + (d * FC + cg * 64 + cb * 16) * 64 + aoff);
+        i32x4 a[TPW][ND];
+#pragma unroll
+        for (int tt = 0; tt < TPW; ++tt)
+#pragma unroll
+            for (int d = 0; d < ND; ++d) a[tt][d] = lds_b128(A + d * NT * 16 * 64 + arow[tt] + aoff);
+        // every product for all TPW x 4 accumulators before the next product:
+        // independent MFMA chains interleave and hide the dependency latency
+#pragma unroll
+        for (int w = 0; w <= MAXW; ++w)
+#pragma unroll
+            for (int ii = 0; ii <= w; ++ii)
+#pragma unroll
+                for (int tt = 0; tt < TPW; ++tt)
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb)
+                        if (ii < ND && w - ii < ND) acc[w][tt][cb] = mfma8(a[tt][ii], b[cb][w - ii], acc[w][tt][cb]);
     }
+    __syncthreads();
 
-    // epilogue: FP64 combination, scaling, binomial / eps-power fold, FP32 +
-    // BF16 residual store.  Per column block the accumulators are first turned
-    // into FP64 values a[r][t] (which frees them), then each moment n is folded
-    // and stored for the four consecutive rows P0 + 4 lk + r.
+    // epilogue 1: FP64 combination and scaling of this wave's moments into the
+    // exchange X[t][q][lane][r] (q = 4 cg + cb: the column block), with the
+    // sign (-1)^t of the occupied sector; the slab buffers are free (barrier above)
+    double* X = (double*)lds;
+    constexpr int NQ = 4 * CG;
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-        const long c = c0 + wave * 32 + cb * 16 + lr;
-        if (c >= ncol) continue;
-        const long j = j0 + c;
-        const int x = (int)(j / nmo);
-        const double ex = eps[x];
-        const bool occ = x < nocc;
+    for (int cb = 0; cb < 4; ++cb) {
+        const long c = c0 + cg * 64 + cb * 16 + lr;
+        const bool cok = c < ncol;
+        const long j = j0 + (cok ? c : 0);
+        const bool occ = (int)(j / nmo) < nocc;
         const int ej = eL[j];
-        double a[4][NT];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int P = P0 + 4 * lk + r;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                double z = 0.0;
-                if (P < naux) {
-#pragma unroll
-                    for (int w = MAXW; w >= 0; --w) z += (double)acc[w][t][cb][r] * wscale(w);
-                    z = ldexp(z, eR[(long)t * naux + P] + ej);
-                }
-                a[r][t] = (occ && (t & 1)) ? -z : z;
-            }
-        }
-        double pw[NT];
-        pw[0] = 1.0;
-#pragma unroll
-        for (int k = 1; k < NT; ++k) pw[k] = pw[k - 1] * ex;
-#pragma unroll
-        for (int n = 0; n < NT; ++n) {
-            float hv[4];
-            unsigned lv[4];
+        for (int tt = 0; tt < TPW; ++tt) {
+            const int t = t0 + tt;
+            if (t >= NT) continue;
+            double v[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
+                const int P = P0 + 4 * lk + r;
                 double z = 0.0;
+                if (cok && P < naux) {
 #pragma unroll
-                for (int t = 0; t <= n; ++t) z += binom2(n, t) * pw[n - t] * a[r][t];
-                const float hi = (float)z;
-                const unsigned lb = __float_as_uint((float)(z - (double)hi));
-                hv[r] = hi;
-                lv[r] = (lb + 0x7fffu + ((lb >> 16) & 1u)) >> 16;
+                    for (int w = MAXW; w >= 0; --w) z += (double)acc[w][tt][cb][r] * wscale(w);
+                    z = ldexp(z, eR[(long)t * naux + P] + ej);
+                }
+                v[r] = (occ && (t & 1)) ? -z : z;
             }
-            // rows P0 + 4 lk + r are consecutive: one 16-byte + one 8-byte store
-            const long o = ((long)n * ncol + c) * Ap + P0 + 4 * lk;
-            *(float4*)(Zt + o) = make_float4(hv[0], hv[1], hv[2], hv[3]);
-            *(uint2*)(Zl + o) = make_uint2(lv[0] | (lv[1] << 16), lv[2] | (lv[3] << 16));
+            double* dst = X + (((long)t * NQ + cg * 4 + cb) * 64 + lane) * 4;
+            *(double4*)dst = make_double4(v[0], v[1], v[2], v[3]);
         }
     }
+    __syncthreads();
+
+    // epilogue 2: wave w folds all moments of column blocks q = w + 4 i:
+    // binomial / eps-power fold, FP32 + BF16 residual store of the four
+    // consecutive rows P0 + 4 lk + r
+#pragma unroll
+    for (int i = 0; i < CG; ++i) {
+        const int q = wv + 4 * i;
+        const long c = c0 + (q >> 2) * 64 + (q & 3) * 16 + lr;
+        if (c < ncol) {
+            const long j = j0 + c;
+            const double ex = eps[(int)(j / nmo)];
+            double a[NT][4];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const double4 v = *(const double4*)(X + (((long)t * NQ + q) * 64 + lane) * 4);
+                a[t][0] = v.x; a[t][1] = v.y; a[t][2] = v.z; a[t][3] = v.w;
+            }
+            double pw[NT];
+            pw[0] = 1.0;
+#pragma unroll
+            for (int k = 1; k < NT; ++k) pw[k] = pw[k - 1] * ex;
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                float hv[4];
+                unsigned lv[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double z = 0.0;
+#pragma unroll
+                    for (int t = 0; t <= n; ++t) z += binom2(n, t) * pw[n - t] * a[t][r];
+                    const float hi = (float)z;
+                    const unsigned lb = __float_as_uint((float)(z - (double)hi));
+                    hv[r] = hi;
+                    lv[r] = (lb + 0x7fffu + ((lb >> 16) & 1u)) >> 16;
+                }
+                const long o = ((long)n * ncol + c) * Ap + P0 + 4 * lk;
+                *(float4*)(Zt + o) = make_float4(hv[0], hv[1], hv[2], hv[3]);
+                *(uint2*)(Zl + o) = make_uint2(lv[0] | (lv[1] << 16), lv[2] | (lv[3] << 16));
+            }
+        }
+    }
+    // the next tile of a persistent work group reuses the LDS
+    __syncthreads();
 }
 
 // Single job: XCD-aware grouped raster over (P-block, column tile).  Work
@@ -397,8 +430,7 @@ __global__ __launch_bounds__(256, 1) void fold_mixed_kernel(FoldJob g) {
 
 // Grouped, persistent: work items (job, P-block, column tile) over all jobs;
 // the P-block index runs fastest so neighbouring items share a column tile.
-// LDS is free again at the start of each item: every wave has passed the last
-// barrier of the previous item's k loop before any wave reaches the new one.
+// LDS is free again at the start of each item: fold_tile ends with a barrier.
 template <int NT>
 __global__ __launch_bounds__(256, 1) void fold_grouped_kernel(const FoldJob* __restrict__ jobs, int njobs,
                                                               long total) {
@@ -577,65 +609,63 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
         }
     const int* eZn = g.eZ + (long)n * g.ncol;
     const int nkt = g.Ap / MK;
-    const int total = (xb - xa) * nkt;
     const int so = swz(lr, lk) * 16;
 
     load(xa, 0, 0);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-    int x = xa, kt = 0;            // step being computed
-    int xn = xa, ktn = 0;          // step being loaded
-    for (int it = 0; it < total; ++it) {
-        const int cur = it & 1;
-        if (++ktn == nkt) { ktn = 0; ++xn; }
-        if (it + 1 < total) load(xn, ktn, cur ^ 1);
-        const lds_t* A = lds + cur * C_BUF;
-        const lds_t* B = A + C_OPA;
-        i32x4 b[2][ND];
+    // x outer, k-blocks inner: the int32 accumulators are carried by the inner
+    // loop only (they stay in accumulation registers) and promoted after it.
+    // Each step first waits for its own slabs and the barrier, then refills
+    // the other buffer, so that the refill overlaps the whole step.
+    int it = 0;                    // global step: buffer parity
+    for (int x = xa; x < xb; ++x) {
+        for (int kt = 0; kt < nkt; ++kt, ++it) {
+            const int cur = it & 1;
+            const bool wrap = kt + 1 == nkt;
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            if (!wrap || x + 1 < xb) load(wrap ? x + 1 : x, wrap ? 0 : kt + 1, cur ^ 1);
+            const lds_t* A = lds + cur * C_BUF;
+            const lds_t* B = A + C_OPA;
+            i32x4 b[2][ND];
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int d = 0; d < ND; ++d) b[j][d] = lds_b128(B + (d * 64 + wn + j * 16 + lr) * 64 + so);
+                for (int d = 0; d < ND; ++d) b[j][d] = lds_b128(B + (d * 64 + wn + j * 16 + lr) * 64 + so);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            i32x4 a[ND];
+            for (int i = 0; i < 4; ++i) {
+                i32x4 a[ND];
 #pragma unroll
-            for (int d = 0; d < ND; ++d) a[d] = lds_b128(A + (d * 128 + wm + i * 16 + lr) * 64 + so);
+                for (int d = 0; d < ND; ++d) a[d] = lds_b128(A + (d * 128 + wm + i * 16 + lr) * 64 + so);
 #pragma unroll
-            for (int w = 0; w <= MAXW; ++w)
+                for (int w = 0; w <= MAXW; ++w)
 #pragma unroll
-                for (int ii = 0; ii <= w; ++ii)
+                    for (int ii = 0; ii <= w; ++ii)
 #pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        if (ii < ND && w - ii < ND) acc[w][i][j] = mfma8(a[ii], b[j][w - ii], acc[w][i][j]);
-        }
-        if (++kt == nkt) {
-            // end of this x: promote with the row (p) and column (q) scales
-            const long xl = x - g.x0;
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int qg = n0 + wn + j * 16 + lr;
-                const int eq = (qg < M) ? eZn[xl * M + qg] : 0;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int pg = m0 + wm + i * 16 + 4 * lk + r;
-                        const int ep = (pg < M) ? g.eL[(long)x * M + pg] : 0;
-                        double z = 0.0;
-#pragma unroll
-                        for (int w = MAXW; w >= 0; --w) z += (double)acc[w][i][j][r] * wscale(w);
-                        acc64[i][j][r] += ldexp(z, ep + eq);
-                    }
-#pragma unroll
-                    for (int w = 0; w <= MAXW; ++w) acc[w][i][j] = (i32x4){0, 0, 0, 0};
-                }
+                        for (int j = 0; j < 2; ++j)
+                            if (ii < ND && w - ii < ND) acc[w][i][j] = mfma8(a[ii], b[j][w - ii], acc[w][i][j]);
             }
-            kt = 0;
-            ++x;
         }
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
+        // end of this x: promote with the row (p) and column (q) scales
+        const long xl = x - g.x0;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int qg = n0 + wn + j * 16 + lr;
+            const int eq = (qg < M) ? eZn[xl * M + qg] : 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int pg = m0 + wm + i * 16 + 4 * lk + r;
+                    const int ep = (pg < M) ? g.eL[(long)x * M + pg] : 0;
+                    double z = 0.0;
+#pragma unroll
+                    for (int w = MAXW; w >= 0; --w) z += (double)acc[w][i][j][r] * wscale(w);
+                    acc64[i][j][r] += ldexp(z, ep + eq);
+                }
+#pragma unroll
+                for (int w = 0; w <= MAXW; ++w) acc[w][i][j] = (i32x4){0, 0, 0, 0};
+            }
+        }
     }
     double* dst = g.part + (((long)sector * g.nt + n) * g.nsplit_total + g.split_off + split) * M2;
 #pragma unroll
@@ -651,6 +681,9 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
                 dst[(long)row * M + col] += acc64[i][j][r];
             }
         }
+    // the next item of a persistent work group refills buffer 0: every wave
+    // has finished reading the slabs of this one
+    __syncthreads();
 }
 
 // XCD-aware mapping of a 1D grid onto (tile, group): work group b runs on XCD
@@ -674,8 +707,8 @@ __global__ __launch_bounds__(256, 1) void contract_mixed_kernel(ContractArgs g, 
 }
 
 // Grouped, persistent: work items (job, tile, split, sector * nt + n).  As in
-// stage 1, every wave has passed the last barrier of an item before any wave
-// starts loading the next one.
+// stage 1, contract_tile ends with a barrier, so no wave starts loading the
+// next item while another still reads the slabs of the last one.
 __global__ __launch_bounds__(256, 1) void contract_grouped_kernel(const ContractArgs* __restrict__ jobs, int njobs,
                                                                   long total) {
     __shared__ __attribute__((aligned(16))) lds_t lds[2 * C_BUF];
@@ -777,13 +810,13 @@ __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int spl
 #pragma unroll
             for (int j = 0; j < 2; ++j) acc[w][i][j] = (i32x4){0, 0, 0, 0};
     const int so = swz(lr, lk) * 16;
-    if (total > 0) {
-        load(ka, 0);
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-    }
+    if (total > 0) load(ka, 0);
     for (int it = 0; it < total; ++it) {
         const int cur = it & 1;
+        // wait for this step's slabs; the refill of the other buffer then
+        // overlaps the whole step
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
         if (it + 1 < total) load(ka + it + 1, cur ^ 1);
         const lds_t* A = lds + cur * C_BUF;
         const lds_t* B = A + C_OPA;
@@ -812,8 +845,6 @@ __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int spl
                     acc[NW - 1][i][j] = mfma8(a[3], b[j][1], acc[NW - 1][i][j]);
                 }
         }
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
     }
     // combine the weights and scale by 2^(e_row + e_col) once, then the epilogue
 #pragma unroll
@@ -918,7 +949,7 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
         {
             KTimer tm(h, "sigma_fold");
             const FoldJob fj =
-                make_fold_job(Rd, eR, Ld, eL, eps, naux, Ap, nmo, nocc, j0, ncol, rplane, lplane, Zt, Zl);
+                make_fold_job(nt, Rd, eR, Ld, eL, eps, naux, Ap, nmo, nocc, j0, ncol, rplane, lplane, Zt, Zl);
             switch (nt) {
                 case 2: launch_fold_mixed<2>(h, fj); break;
                 case 4: launch_fold_mixed<4>(h, fj); break;
@@ -967,7 +998,7 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
     return GW_OK;
 }
 
-FoldJob make_fold_job(const i8* Rd, const int* eR, const i8* Ld, const int* eL, const double* eps, int naux,
+FoldJob make_fold_job(int nt, const i8* Rd, const int* eR, const i8* Ld, const int* eL, const double* eps, int naux,
                       int Ap, int nmo, int nocc, long j0, long ncol, long rplane, long lplane, float* Zt, u16* Zl) {
     FoldJob g;
     g.Rd = Rd; g.eR = eR; g.Ld = Ld; g.eL = eL; g.eps = eps;
@@ -976,7 +1007,7 @@ FoldJob make_fold_job(const i8* Rd, const int* eR, const i8* Ld, const int* eL, 
     g.Zt = Zt; g.Zl = Zl;
     g.item0 = 0;
     g.nP = Ap / 16;
-    g.nC = (int)((ncol + 127) / 128);
+    g.nC = (int)((ncol + fold_cols(nt) - 1) / fold_cols(nt));
     return g;
 }
 

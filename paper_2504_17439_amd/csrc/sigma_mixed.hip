@@ -173,21 +173,23 @@ typedef unsigned char lds_t;
 // Tile: 16 P rows x FC = fold_cols(NT) columns j, all NT moments t.  Wave w
 // owns TPW moments (t group w % TG) for the 64 columns of column group w / TG
 // (four 16-column blocks): 4 weights x TPW x 4 int32 accumulator blocks, at
-// most 192 registers, which stay in AGPRs.  LDS holds two K slabs (double
-// buffering); after the k loop the waves exchange their FP64 values through
-// LDS so that each wave folds all NT moments of its own column blocks.
+// most 192 registers, which stay in AGPRs.  The R digits (A operand, private
+// to a wave's moments) go from memory straight to registers, double
+// buffered; the L digits (B operand, shared by the waves) go through an
+// NS-stage LDS pipeline.  After the k loop the waves exchange their FP64
+// values through LDS so that each wave folds all NT moments of its columns.
 template <int NT>
 struct FoldSlab {
     static constexpr int TPW = fold_tpw(NT);
     static constexpr int TG = fold_tg(NT);
     static constexpr int CG = fold_cg(NT);
     static constexpr int FC = fold_cols(NT);
-    static constexpr int A_ROWS = ND * NT * 16;  // (d, t, p) rows of the A slab
-    static constexpr int B_ROWS = ND * FC;       // (d, c) rows of the B slab
-    static constexpr int SLAB = (A_ROWS + B_ROWS) * 64;  // bytes per buffer
-    static constexpr int XCH = NT * 4 * CG * 64 * 4 * 8;  // bytes of the epilogue exchange
-    static_assert(TG * CG == 4 && TPW * TG >= NT, "fold wave layout");
-    static_assert(XCH <= 2 * SLAB, "exchange fits the slab buffers");
+    static constexpr int NS = 4;                               // B stages
+    static constexpr int B_ROWS = ND * FC;                     // (d, c) rows of a B stage
+    static constexpr int BST = B_ROWS * 64;                    // bytes per B stage
+    static constexpr int XCH = NT * 4 * CG * 64 * 4 * 8;       // bytes of the epilogue exchange
+    static constexpr int LDS = NS * BST > XCH ? NS * BST : XCH;
+    static_assert(TG * CG == 4 && TPW * TG >= NT && TPW <= 3 && CG <= 2, "fold wave layout");
 };
 
 // Binary search of the job whose first work item is the largest <= item.
@@ -212,7 +214,7 @@ template <int NT>
 __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_t* lds) {
     using FS = FoldSlab<NT>;
     constexpr int TPW = FS::TPW, TG = FS::TG, CG = FS::CG, FC = FS::FC;
-    constexpr int A_ROWS = FS::A_ROWS, B_ROWS = FS::B_ROWS, SLAB = FS::SLAB;
+    constexpr int B_ROWS = FS::B_ROWS, BST = FS::BST, NS = FS::NS;
     const i8* __restrict__ Rd = g.Rd;
     const int* __restrict__ eR = g.eR;
     const i8* __restrict__ Ld = g.Ld;
@@ -234,93 +236,96 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_
     const int tg = wv % TG, cg = wv / TG;       // this wave's moment group and column group
     const int t0 = tg * TPW;
 
-    // Global -> LDS staging by LDS-DMA buffer loads (16 bytes per lane; one
-    // wave instruction fills 1 KB of LDS at M0 + 16 * lane).  Vector s of wave
-    // w fills slab rows s * 64 + 16 w + (lane >> 2), slot lane & 3.  For the A
-    // slab (rows (d, t, p)) that row has p = lane >> 2 and (d, t) =
-    // divmod(4 s + w, NT); for the B slab (rows (d, c)) d = s / CG and c =
-    // 64 (s % CG) + 16 w + (lane >> 2).  The lane fetches the global chunk that
-    // the swizzle puts in its slot, so the source is a wave-uniform base plus
-    // one loop-invariant lane offset.  Rows past naux and columns past ncol
-    // read clamped (valid) rows: their products are never stored.
-    static_assert((A_ROWS * 4) % 256 == 0 && (B_ROWS * 4) % 256 == 0, "slab vectors per thread");
-    constexpr int AVT = A_ROWS * 4 / 256;
+    // A operand: lane (lr, lk) holds row P0 + lr and k chunk lk of the 16 x 64
+    // block of moment t, i.e. byte ((kt * NT * naux) + t * naux + P) * 64 + 16 lk
+    // of each digit plane; rows past naux read a clamped (valid) row.  Moments
+    // past NT (when TPW does not divide NT) repeat the last one; their results
+    // are never used.
+    const int rrows64 = NT * naux * 64;               // bytes per k block of an R plane
+    unsigned voffA[3];
+#pragma unroll
+    for (int tt = 0; tt < 3; ++tt)
+        voffA[tt] = (unsigned)((min(t0 + tt, NT - 1) * naux + min(P0 + lr, naux - 1)) * 64 + lk * 16);
+    auto ldA = [&](int kt, int tt, int d) -> i32x4 {
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void*)(Rd + d * rplane), (short)0, (int)rplane, 0x00020000);
+        return __builtin_bit_cast(i32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voffA[tt], kt * rrows64, 0));
+    };
+
+    // B operand by LDS-DMA buffer loads (16 bytes per lane; one wave
+    // instruction fills 1 KB of LDS at M0 + 16 * lane).  Vector s of wave w
+    // fills stage rows s * 64 + 16 w + (lane >> 2), slot lane & 3: d = s / CG,
+    // c = 64 (s % CG) + 16 w + (lane >> 2).  The lane fetches the global chunk
+    // that the swizzle puts in its slot; columns past ncol read a clamped row.
+    static_assert((B_ROWS * 4) % 256 == 0, "slab vectors per thread");
     constexpr int BVT = B_ROWS * 4 / 256;
     const long M2 = lplane / Ap;                      // rows of an L digit plane
     const int lrow = lane >> 2;
     const int gch = swz(lrow, lane & 3);              // swz is an involution in the chunk
-    const unsigned offA = (unsigned)(min(P0 + lrow, naux - 1) * 64 + gch * 16);  // bytes
-    unsigned offB[2];                                 // CG <= 2 column groups
-    static_assert(CG <= 2, "column groups");
+    unsigned offB[2];
 #pragma unroll
-    for (int h = 0; h < CG; ++h) {
+    for (int h = 0; h < 2; ++h) {
         long cc = c0 + h * 64 + wv * 16 + lrow;
         if (cc > ncol - 1) cc = ncol - 1;
         offB[h] = (unsigned)((j0 + cc) * 64 + gch * 16);
     }
-
-    // the resource (SGPRs) points at the k block of one digit plane, the
-    // wave-uniform row offset goes in soffset, the lane part in voffset
-    auto load = [&](int kt, int buf) {
-        lds_t* A = lds + buf * SLAB + wv * 16 * 64;
-        lds_t* B = A + A_ROWS * 64;
-#pragma unroll
-        for (int s = 0; s < AVT; ++s) {
-            const int dt = 4 * s + wv;
-            const int t = dt % NT, d = dt / NT;
-            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void*)(Rd + d * rplane + (long)kt * NT * naux * 64), (short)0, NT * naux * 64, 0x00020000);
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(A + s * 64 * 64),
-                                                     16, offA, t * naux * 64, 0, 0);
-        }
+    auto ldB = [&](int kt) {
+        lds_t* B = lds + (kt % NS) * BST + wv * 16 * 64;
+        const int kc = min(kt, Ap / MK - 1);          // past the end: refetch a valid block (unused)
 #pragma unroll
         for (int s = 0; s < BVT; ++s) {
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void*)(Ld + (s / CG) * lplane + (long)kt * M2 * 64), (short)0, (int)(M2 * 64), 0x00020000);
+                (void*)(Ld + (s / CG) * lplane + (long)kc * M2 * 64), (short)0, (int)(M2 * 64), 0x00020000);
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(B + s * 64 * 64),
                                                      16, offB[s % CG], 0, 0, 0);
         }
     };
 
-    // one exact int32 accumulator per digit weight, own moment and column block
-    i32x4 acc[MAXW + 1][TPW][4];
+    // one exact int32 accumulator per digit weight, own moment and column
+    // block (sized for TPW <= 3; entries past TPW are never touched)
+    i32x4 acc[MAXW + 1][3][4];
 #pragma unroll
     for (int w = 0; w <= MAXW; ++w)
 #pragma unroll
         for (int tt = 0; tt < TPW; ++tt)
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) acc[w][tt][cb] = (i32x4){0, 0, 0, 0};
-    // moments past NT (the last group when TPW does not divide NT) repeat the
-    // last one; their results are never used
-    int arow[TPW];
-#pragma unroll
-    for (int tt = 0; tt < TPW; ++tt) arow[tt] = min(t0 + tt, NT - 1) * 16 * 64;
 
+    // Every step issues the same loads in the same order: the A blocks of the
+    // next step, then the B stage NS - 1 ahead (past the end: valid refetches
+    // whose data is never read).  So when a step starts, at most the BVT B
+    // loads of the previous step are younger than its own A blocks, and its B
+    // stage (issued earlier still) has landed once vmcnt <= BVT.
     const int nkt = Ap / MK;
-    load(0, 0);
-    const int aoff = lr * 64 + swz(lr, lk) * 16;
-    for (int kt = 0; kt < nkt; ++kt) {
-        const int cur = kt & 1;
-        // step kt's slabs have landed (this wave's DMA) and are visible (the
-        // barrier), and every wave has finished reading buffer cur ^ 1 (step
-        // kt - 1): its refill for step kt + 1 overlaps all of step kt's MFMAs
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        if (kt + 1 < nkt) load(kt + 1, cur ^ 1);
-        const lds_t* A = lds + cur * SLAB;
-        const lds_t* B = A + A_ROWS * 64;
-        i32x4 b[4][ND];
+    i32x4 a0[3][ND], a1[3][ND];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
+    for (int s = 0; s < NS - 2; ++s) ldB(s);
 #pragma unroll
-            for (int d = 0; d < ND; ++d) b[cb][d] = lds_b128(B + (d * FC + cg * 64 + cb * 16) * 64 + aoff);
-        i32x4 a[TPW][ND];
+    for (int tt = 0; tt < TPW; ++tt)
+#pragma unroll
+        for (int d = 0; d < ND; ++d) a0[tt][d] = ldA(0, tt, d);
+    ldB(NS - 2);
+    const int boff = cg * 64 * 64 + lr * 64 + swz(lr, lk) * 16;
+    auto step = [&](int kt, i32x4 (&acur)[3][ND], i32x4 (&anext)[3][ND]) {
+        // own loads up to stage kt done; the plain s_barrier (no fence, which
+        // would wait for every outstanding LDS-DMA load) then makes all waves'
+        // stage kt visible and frees stage kt - 1 for the refill below
+        asm volatile("s_waitcnt vmcnt(%0)" ::"n"(BVT) : "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        const int kn = min(kt + 1, nkt - 1);
 #pragma unroll
         for (int tt = 0; tt < TPW; ++tt)
 #pragma unroll
-            for (int d = 0; d < ND; ++d) a[tt][d] = lds_b128(A + d * NT * 16 * 64 + arow[tt] + aoff);
-        // every product for all TPW x 4 accumulators before the next product:
-        // independent MFMA chains interleave and hide the dependency latency
+            for (int d = 0; d < ND; ++d) anext[tt][d] = ldA(kn, tt, d);
+        ldB(kt + NS - 1);
+        const lds_t* B = lds + (kt % NS) * BST + boff;
+        // B digits in order: the products of weight w need digits <= w
+        i32x4 b[4][ND];
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) b[cb][d] = lds_b128(B + (d * FC + cb * 16) * 64);
 #pragma unroll
         for (int w = 0; w <= MAXW; ++w)
 #pragma unroll
@@ -329,8 +334,23 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_
                 for (int tt = 0; tt < TPW; ++tt)
 #pragma unroll
                     for (int cb = 0; cb < 4; ++cb)
-                        if (ii < ND && w - ii < ND) acc[w][tt][cb] = mfma8(a[tt][ii], b[cb][w - ii], acc[w][tt][cb]);
+                        if (ii < ND && w - ii < ND) acc[w][tt][cb] = mfma8(acur[tt][ii], b[cb][w - ii], acc[w][tt][cb]);
+        // schedule: loads, reads of digits 0 and 1, then per weight w its
+        // products with the reads of digit w + 2 among them
+        __builtin_amdgcn_sched_group_barrier(0x020, 4 * TPW + BVT, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);          // digits 0, 1
+        __builtin_amdgcn_sched_group_barrier(0x008, 4 * TPW, 0);    // weight 0
+        __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);          // digit 2
+        __builtin_amdgcn_sched_group_barrier(0x008, 8 * TPW, 0);    // weight 1
+        __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);          // digit 3
+        __builtin_amdgcn_sched_group_barrier(0x008, 12 * TPW, 0);   // weight 2
+        __builtin_amdgcn_sched_group_barrier(0x008, 16 * TPW, 0);   // weight 3
+    };
+    for (int kt = 0; kt < nkt; kt += 2) {
+        step(kt, a0, a1);
+        if (kt + 1 < nkt) step(kt + 1, a1, a0);
     }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
 
     // epilogue 1: FP64 combination and scaling of this wave's moments into the
@@ -412,18 +432,19 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_
 }
 
 // Single job: XCD-aware grouped raster over (P-block, column tile).  Work
-// group b runs on XCD b % 8; each XCD walks groups of 8 P-blocks x 4 column
-// tiles, which share their L-digit (B) and R-digit (A) slabs through its L2.
+// group b runs on XCD b % 8; each XCD walks groups of 4 P-blocks x 8 column
+// tiles, which share their R-digit (A) and L-digit (B) slabs through its L2
+// (per k step 4 A slabs + 8 B slabs of distinct data for 32 tiles).
 template <int NT>
 __global__ __launch_bounds__(256, 1) void fold_mixed_kernel(FoldJob g) {
-    __shared__ __attribute__((aligned(16))) lds_t lds[2 * FoldSlab<NT>::SLAB];
-    const int nPg = (g.nP + 7) / 8;
+    __shared__ __attribute__((aligned(16))) lds_t lds[FoldSlab<NT>::LDS];
+    const int nPg = (g.nP + 3) / 4;
     const int b = blockIdx.x;
     const int xcd = b & 7, local = b >> 3;
     const int grp = (local >> 5) * 8 + xcd;
     const int w = local & 31;
-    const int pb = (grp % nPg) * 8 + (w & 7);
-    const int ct = (grp / nPg) * 4 + (w >> 3);
+    const int pb = (grp % nPg) * 4 + (w & 3);
+    const int ct = (grp / nPg) * 8 + (w >> 2);
     if (pb >= g.nP || ct >= g.nC) return;
     fold_tile<NT>(g, pb, ct, lds);
 }
@@ -434,7 +455,7 @@ __global__ __launch_bounds__(256, 1) void fold_mixed_kernel(FoldJob g) {
 template <int NT>
 __global__ __launch_bounds__(256, 1) void fold_grouped_kernel(const FoldJob* __restrict__ jobs, int njobs,
                                                               long total) {
-    __shared__ __attribute__((aligned(16))) lds_t lds[2 * FoldSlab<NT>::SLAB];
+    __shared__ __attribute__((aligned(16))) lds_t lds[FoldSlab<NT>::LDS];
     for (long it = blockIdx.x; it < total; it += gridDim.x) {
         const FoldJob g = jobs[find_job(jobs, njobs, it)];
         const long local = it - g.item0;
@@ -891,8 +912,8 @@ __global__ __launch_bounds__(256, 1) void dgemm_mixed_kernel(DgemmArgs g, int gt
 template <int NT>
 void launch_fold_mixed(Handle* h, const FoldJob& g) {
     // every padded row P < Ap is written (zeros for P >= naux): stage 2 reads all Ap rows
-    // groups of 8 P-blocks x 4 column tiles, 8 groups per round of the XCDs
-    const long groups = (long)((g.nP + 7) / 8) * ((g.nC + 3) / 4);
+    // groups of 4 P-blocks x 8 column tiles, 8 groups per round of the XCDs
+    const long groups = (long)((g.nP + 3) / 4) * ((g.nC + 7) / 8);
     const long rounds = (groups + 7) / 8;
     hipLaunchKernelGGL((fold_mixed_kernel<NT>), dim3((unsigned)(rounds * 8 * 32)), dim3(256), 0, h->stream, g);
 }

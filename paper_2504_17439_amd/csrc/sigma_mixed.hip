@@ -88,39 +88,66 @@ __global__ void col_exp_kernel(int naux, long ncol, const double* __restrict__ L
 // Row scales and k-blocked digit planes of X[rows][cols] (times cs[c] when cs is
 // set), zero-padded to kpad (a multiple of 64): one block per row, the row
 // maximum by a block reduction, then 8 consecutive k per thread so that each
-// digit plane gets one 8-byte store per thread and step.
+// digit plane gets one 8-byte store per thread and step.  With Yd set, the
+// same pass also writes the planes of X o D (D = d2[c]) with their own row
+// scales e2, so X is read twice instead of four times.
 __global__ __launch_bounds__(256) void digitise_rows_kernel(long rows, int cols, int kpad,
                                                             const double* __restrict__ X,
                                                             const double* __restrict__ cs, int* __restrict__ e,
-                                                            i8* __restrict__ Xd) {
+                                                            i8* __restrict__ Xd, const double* __restrict__ d2,
+                                                            int* __restrict__ e2, i8* __restrict__ Yd) {
     const long row = blockIdx.x;
     const double* __restrict__ x = X + row * cols;
-    __shared__ double red[256];
-    double m = 0.0;
-    for (int c = threadIdx.x; c < cols; c += 256) m = fmax(m, fabs(x[c] * (cs ? cs[c] : 1.0)));
-    red[threadIdx.x] = m;
+    __shared__ double red[2][256];
+    double m = 0.0, m2 = 0.0;
+    for (int c = threadIdx.x; c < cols; c += 256) {
+        const double v = x[c];
+        m = fmax(m, fabs(v * (cs ? cs[c] : 1.0)));
+        if (Yd) m2 = fmax(m2, fabs(v * d2[c]));
+    }
+    red[0][threadIdx.x] = m;
+    red[1][threadIdx.x] = m2;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        if (threadIdx.x < w) {
+            red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+            red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+        }
         __syncthreads();
     }
-    const int ex = scale_exp(red[0]);
-    if (threadIdx.x == 0) e[row] = ex;
+    const int ex = scale_exp(red[0][0]);
+    const int ex2 = scale_exp(red[1][0]);
+    if (threadIdx.x == 0) {
+        e[row] = ex;
+        if (Yd) e2[row] = ex2;
+    }
     const long plane = rows * (long)kpad;
     for (int c0 = threadIdx.x * 8; c0 < kpad; c0 += 256 * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = c0 + u < cols ? x[c0 + u] : 0.0;
+        const long o = ((long)(c0 >> 6) * rows + row) * 64 + (c0 & 63);
         i8 dg[ND][8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int c = c0 + u;
-            const double v = c < cols ? x[c] * (cs ? cs[c] : 1.0) : 0.0;
             i8 t[ND];
-            digitsN(v, ex, t);
+            digitsN(v[u] * (cs && c0 + u < cols ? cs[c0 + u] : 1.0), ex, t);
 #pragma unroll
             for (int d = 0; d < ND; ++d) dg[d][u] = t[d];
         }
-        const long o = ((long)(c0 >> 6) * rows + row) * 64 + (c0 & 63);
 #pragma unroll
         for (int d = 0; d < ND; ++d) *(uint2*)(Xd + d * plane + o) = make_uint2(pack4(dg[d]), pack4(dg[d] + 4));
+        if (Yd) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                i8 t[ND];
+                digitsN(c0 + u < cols ? v[u] * d2[c0 + u] : 0.0, ex2, t);
+#pragma unroll
+                for (int d = 0; d < ND; ++d) dg[d][u] = t[d];
+            }
+#pragma unroll
+            for (int d = 0; d < ND; ++d) *(uint2*)(Yd + d * plane + o) = make_uint2(pack4(dg[d]), pack4(dg[d] + 4));
+        }
     }
 }
 
@@ -765,6 +792,7 @@ struct DgemmArgs {
     int M, N, nkb;    // output rows / cols; k-blocks of 64
     int nsplit;       // splits of the k-block range (at most KEXACT / 64 k-blocks each)
     int sym, tilesN;  // upper tiles only (M == N); column tiles
+    int eshift;       // extra power of two of the product
     double* part;     // [nsplit][M][N] (Xout == nullptr)
     double* Xout;
     const double* Xin;
@@ -882,7 +910,7 @@ __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int spl
                 double z = 0.0;
 #pragma unroll
                 for (int w = NW - 1; w >= 0; --w) z += (double)acc[w][i][j][r] * wscale(w);
-                const double c = ldexp(z, g.eA[row] + ec);
+                const double c = ldexp(z, g.eA[row] + ec + g.eshift);
                 const long o = (long)row * g.N + col;
                 if (g.Xout) g.Xout[o] = g.Dv[col] * g.Xin[o] + g.alpha * c;
                 else g.part[(long)split * g.M * g.N + o] = c;
@@ -1042,7 +1070,7 @@ gw_status mixed_prep(Handle* h, int naux, int nmo, int nt, const double* L, cons
     hipLaunchKernelGGL(digits_lt_kernel, dim3((unsigned)((M2 + 31) / 32), (unsigned)((Ap + 31) / 32)), dim3(256), 0,
                        h->stream, naux, M2, Ap, L, eL, Ld);
     hipLaunchKernelGGL(digitise_rows_kernel, dim3((unsigned)rrows), dim3(256), 0, h->stream, rrows, naux, Ap, R,
-                       (const double*)nullptr, eR, Rd);
+                       (const double*)nullptr, eR, Rd, (const double*)nullptr, (int*)nullptr, (i8*)nullptr);
     tm.stop();
     GW_CHECK_LAUNCH(h);
     return GW_OK;
@@ -1085,8 +1113,8 @@ gw_status launch_contract_grouped(Handle* h, const ContractArgs* jobs, int njobs
 //   R_2k = X_k X_k^T,  R_2k+1 = X_k D X_k^T + 2 R_k R_k,  X_k+1 = D o X_k + 2 R_k V.
 // X stays FP64; each product digitises its operands (X rows, (X o D) rows,
 // R_k rows, V^T rows once) and combines its exact int32 digit sums in FP64.
-// R_k R_k stays FP64.  The symmetric products keep the three weight-4 digit
-// products as well (thirteen).
+// The symmetric products (X X^T, X D X^T, R_k R_k) keep the three weight-4
+// digit products as well (thirteen).
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -1110,10 +1138,12 @@ gw_status launch_dgemm(Handle* h, const DgemmArgs& g0, const char* tag) {
     return GW_OK;
 }
 
-// digit planes (rows x kpad, k-blocked) of X[rows][cols] (times cs[c] when cs is set)
-gw_status digitise_rows(Handle* h, long rows, long cols, int kpad, const double* X, const double* cs, int* e, i8* Xd) {
+// digit planes (rows x kpad, k-blocked) of X[rows][cols], and with Yd set also
+// those of X o D (D = d2[c])
+gw_status digitise_rows(Handle* h, long rows, long cols, int kpad, const double* X, int* e, i8* Xd,
+                        const double* d2 = nullptr, int* e2 = nullptr, i8* Yd = nullptr) {
     hipLaunchKernelGGL(digitise_rows_kernel, dim3((unsigned)rows), dim3(256), 0, h->stream, rows, (int)cols, kpad, X,
-                       cs, e, Xd);
+                       (const double*)nullptr, e, Xd, d2, e2, Yd);
     GW_CHECK_LAUNCH(h);
     return GW_OK;
 }
@@ -1144,7 +1174,9 @@ gw_status tda_moments_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_ma
     // enough splits to fill the chip, and at most KEXACT k per split (exact int32 sums)
     const int S = std::max((nkbX + KEXACT / MK - 1) / (KEXACT / MK),
                            std::max(1, std::min(nkbX, (3 * ncu + tiles - 1) / tiles)));
-    double* part = (double*)ws_get(h, WS_RC5, sizeof(double) * S * asz);
+    const int nkbR = Ap / MK;                         // k blocks of the R_k R_k product (Ap <= KEXACT)
+    const int S2 = std::max(1, std::min(nkbR, (3 * ncu + tiles - 1) / tiles));
+    double* part = (double*)ws_get(h, WS_RC5, sizeof(double) * (S + S2) * asz);
     if (!V || !D || !X || !Vt || !Xd || !Yd || !Rk || !ex || !part) return GW_ENOMEM;
     int *eVt = ex, *eX = ex + ov, *eY = eX + naux, *eR = eY + naux;
     GW_TRY(gather_ov(h, nocc, nvir, naux, eps, L, V, D));
@@ -1166,40 +1198,42 @@ gw_status tda_moments_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_ma
     sy.A = Xd; sy.aplane = (long)naux * Kp; sy.arows = naux; sy.eA = eX;
     const int K = nmom_max / 2;
     for (int k = 0; k <= K; ++k) {
+        const bool odd = 2 * k + 1 <= nmom_max;
         {
             KTimer tm(h, "recur_digits");
-            GW_TRY(digitise_rows(h, naux, ov, Kp, X, nullptr, eX, Xd));
-            if (2 * k + 1 <= nmom_max) GW_TRY(digitise_rows(h, naux, ov, Kp, X, D, eY, Yd));
+            // X and, for the odd moment, X o D in one pass
+            if (odd) GW_TRY(digitise_rows(h, naux, ov, Kp, X, eX, Xd, D, eY, Yd));
+            else GW_TRY(digitise_rows(h, naux, ov, Kp, X, eX, Xd));
             tm.stop();
         }
-        if (2 * k <= nmom_max) {
+        {
             DgemmArgs g = sy;
             g.B = Xd; g.bplane = (long)naux * Kp; g.brows = naux; g.eB = eX;
             GW_TRY(launch_dgemm(h, g, "recur_xvt"));
             GW_TRY(reduce_splits(h, part, S, asz, 1, naux, naux, naux, true, 1.0, 0.0, R + 2 * k * asz, asz, naux));
         }
-        if (2 * k + 1 <= nmom_max) {
-            double* Ro = R + (2 * k + 1) * asz;
+        if (odd || k < K) {
+            // digits of R_k (complete: k <= 2k), for R_k R_k and the X update
+            KTimer tm(h, "recur_digits");
+            GW_TRY(digitise_rows(h, naux, naux, Ap, R + k * asz, eR, Rk));
+            tm.stop();
+        }
+        if (odd) {
+            // R_2k+1 = X_k D X_k^T + 2 R_k R_k: both symmetric digit products
+            // into one set of split partials (the factor 2 as a power of two)
             DgemmArgs g = sy;
             g.B = Yd; g.bplane = (long)naux * Kp; g.brows = naux; g.eB = eY;
             GW_TRY(launch_dgemm(h, g, "recur_xvt"));
-            GW_TRY(reduce_splits(h, part, S, asz, 1, naux, naux, naux, true, 1.0, 0.0, Ro, asz, naux));
-            // Ro += 2 R_k R_k in FP64 (R_k is complete: k <= 2k)
-            GemmF64 gg;
-            gg.M = naux; gg.N = naux; gg.K = naux;
-            gg.a_kc = true; gg.A = R + k * asz; gg.lda = naux;
-            gg.b_kc = false; gg.B = R + k * asz; gg.b_klo = naux;
-            gg.epi = EPI_AXPBY; gg.alpha = 2.0; gg.X = Ro; gg.ldx = naux;
-            gg.C = Ro; gg.ldc = naux;
-            gg.tag = "recur_rr";
-            GW_TRY(gemm_f64(h, gg));
+            DgemmArgs r = sy;
+            r.A = Rk; r.aplane = (long)naux * Ap; r.arows = naux; r.eA = eR;
+            r.B = Rk; r.bplane = (long)naux * Ap; r.brows = naux; r.eB = eR;
+            r.nkb = nkbR; r.nsplit = S2; r.eshift = 1;
+            r.part = part + (long)S * asz;
+            GW_TRY(launch_dgemm(h, r, "recur_rr"));
+            GW_TRY(reduce_splits(h, part, S + S2, asz, 1, naux, naux, naux, true, 1.0, 0.0, R + (2 * k + 1) * asz,
+                                 asz, naux));
         }
         if (k < K) {
-            {
-                KTimer tm(h, "recur_digits");
-                GW_TRY(digitise_rows(h, naux, naux, Ap, R + k * asz, nullptr, eR, Rk));
-                tm.stop();
-            }
             DgemmArgs g{};
             g.A = Rk; g.aplane = (long)naux * Ap; g.arows = naux; g.eA = eR;
             g.B = Vt; g.bplane = ov * Ap; g.brows = (int)ov; g.eB = eVt;

@@ -14,6 +14,7 @@ quadrature  the mapped Gauss-Legendre grid used for the RPA zeroth moment.
 brute       brute-force references: full TDA/RPA diagonalisation, exact
             Lehmann self-energy moments and the exact upfolded Hamiltonian.
 fsgw        the Fock / chemical-potential self-consistent loop (Alg. 2).
+evgw        the eigenvalue self-consistent loop (App. A, Alg. A1).
 mlp         the per-orbital MLP of the learned warm start (forward,
             gradient, Adam) in FP64.
 """

@@ -85,3 +85,21 @@ def exact_g0w0(eps, L, nocc, screening="tda"):
     E, U = np.linalg.eigh(H)
     return dict(E=E, chi=U[:nmo, :], e_occ=eo, v_occ=vo, e_vir=ev, v_vir=vv,
                 Omega=Omega, XpY=XpY)
+
+
+def exact_ev_step(eps_ref, eps_g, eps_w, L, nocc, screening="tda"):
+    """The loop body of eigenvalue self-consistent GW with the exact
+    full-frequency self-energy: excitations from the screening built on
+    eps_W, Green's-function poles at eps_G -+ Omega, f = diag(eps_ref)."""
+    nmo = eps_ref.shape[0]
+    nvir = nmo - nocc
+    V = np.ascontiguousarray(L[:, :nocc, nocc:]).reshape(L.shape[0], nocc * nvir)
+    D = (eps_w[None, nocc:] - eps_w[:nocc, None]).reshape(-1)
+    Omega, XpY = tda_modes(V, D) if screening == "tda" else rpa_modes(V, D)
+    eo, vo, ev, vv = exact_poles(eps_g, L, nocc, Omega, XpY)
+    H = exact_upfolded(eps_ref, eo, vo, ev, vv)
+    E, U = np.linalg.eigh(H)
+    chi = U[:nmo, :]
+    w = chi ** 2
+    alpha = np.argmax(w, axis=1)
+    return E[alpha], w[np.arange(nmo), alpha]

@@ -1,0 +1,63 @@
+"""Pins of the eigenvalue self-consistent loop (App. A, Alg. A1) of the
+oracle: reduction to G0W0, agreement with the same loop run on the exact
+full-frequency self-energy where the moment expansion is exact, the fixed
+point, and the weak-coupling order of the self-consistency correction."""
+import numpy as np
+import pytest
+
+import gwsynth
+from oracle import brute, evgw, gw
+
+
+def test_g0_w0_is_one_g0w0_evaluation():
+    o = 3
+    eps, L = gwsynth.system(o, 9, 30, 2)
+    r = evgw.evgw(eps, L, o, 5, "tda", g0=True, w0=True)
+    ref = gw.g0w0(eps, L, o, 5, "tda")
+    assert r["iterations"] == 1 and r["converged"]
+    assert np.array_equal(r["qp"], ref["qp"])
+
+
+@pytest.mark.parametrize("screening", ["tda", "rpa"])
+@pytest.mark.parametrize("g0,w0", [(False, False), (False, True), (True, False)])
+def test_matches_exact_self_energy_loop_when_pole_count_fits(screening, g0, w0):
+    """o=1, v=2, naux=3, N=3: the moments resolve every pole of the exact
+    self-energy, so each iteration equals the full-frequency one and the
+    loops converge to the same QP energies."""
+    o = 1
+    eps, L = gwsynth.system(o, 2, 3, 5, amp=1.0)
+    kw = dict(g0=g0, w0=w0, tol=1e-10, max_iter=60)
+    r = evgw.evgw(eps, L, o, 3, screening, nquad=64, **kw)
+    ex = evgw.evgw(eps, L, o, 3, screening,
+                   step=lambda er, eg, ew: brute.exact_ev_step(er, eg, ew, L, o, screening), **kw)
+    assert r["converged"] and ex["converged"]
+    tol = 1e-9 if screening == "tda" else 1e-7   # RPA: the quadrature's eta0
+    assert np.abs(r["qp"] - ex["qp"]).max() < tol
+
+
+def test_converged_energies_are_a_fixed_point():
+    o = 2
+    eps, L = gwsynth.system(o, 6, 20, 4, amp=0.5)
+    r = evgw.evgw(eps, L, o, 5, "tda", tol=1e-10, max_iter=60)
+    assert r["converged"]
+    qp, _ = evgw.ev_step(eps, r["qp"], r["qp"], L, o, 5, "tda")
+    assert np.abs(qp - r["qp"]).max() < 1e-9
+
+
+def test_self_consistency_correction_order():
+    """With L scaled by a, the self-energy (L R L with R ~ V V^T) scales as
+    a^4, and so does the G0W0 shift; updating the energies by O(a^4) changes
+    the self-energy by O(a^4) of that, so evGW - G0W0 is O(a^8): halving a
+    divides the shift by ~16 and the self-consistency correction by ~256."""
+    o = 2
+    shift, corr = [], []
+    for amp in (0.1, 0.05):
+        eps, L = gwsynth.system(o, 6, 20, 7, amp=amp)
+        g = evgw.evgw(eps, L, o, 5, "tda", g0=True, w0=True)
+        e = evgw.evgw(eps, L, o, 5, "tda", tol=1e-14, max_iter=80)
+        assert e["converged"]
+        front = slice(o - 1, o + 1)
+        shift.append(np.abs(g["qp"][front] - eps[front]).max())
+        corr.append(np.abs(e["qp"][front] - g["qp"][front]).max())
+    assert 14.0 < shift[0] / shift[1] < 18.0, shift
+    assert 200.0 < corr[0] / corr[1] < 300.0, corr

@@ -217,6 +217,41 @@ gw_status gw_fsgw(gw_handle h, gw_screening screening, int nocc, int nvir, int n
                   double* F, double* qp_e, double* qp_w, gw_fsgw_info* info);
 
 /*
+ * Eigenvalue self-consistent moment GW (App. A, Alg. A1).  Two sets of orbital
+ * energies start at eps: eps_G enters the eps-power factors of the self-energy
+ * convolution (eqs. convolution_occ / convolution_vir), eps_W the energy
+ * differences of the density-response recursion (eq. energy_differences).
+ * Each iteration runs gw_moments_* (on eps_W), the self-energy moments (on
+ * eps_G) and gw_poles with fock = diag(eps) (eq. StaticSE with Sigma_inf = 0),
+ * then sets eps_G (unless g0) and eps_W (unless w0) to the QP energies.
+ * g0 = w0 = 0: evGW; w0 = 1: evGW0 (W of the reference); g0 = w0 = 1: one
+ * G0W0 evaluation.  Converged when the QP energy of no quasiparticle-like
+ * orbital (QP weight >= 0.9 in both iterations; all orbitals if none is)
+ * changes by more than tol between iterations.
+ * Outputs (device, [nmo]): qp_e, qp_w of the last iteration.  GW_ENOCONV
+ * after max_iter iterations (outputs and info still written); GW_ENUMERIC if
+ * the QP energies of occupied and virtual orbitals cross (the next screening
+ * would have D <= 0).
+ */
+typedef struct {
+    int g0;          /* 1: keep eps_G at the reference */
+    int w0;          /* 1: keep eps_W at the reference */
+    int max_iter;    /* <= 0 -> 30 */
+    double tol;      /* Ha; <= 0 -> 1e-6 */
+} gw_evgw_opts;
+
+typedef struct {
+    int iterations;
+    int converged;
+    double last_change;  /* largest QP change of the last iteration (vs. the previous one or eps) */
+} gw_evgw_info;
+
+gw_status gw_evgw(gw_handle h, gw_screening screening, int nocc, int nvir, int naux,
+                  int nmom_max, const double* eps, const double* L, gw_precision prec,
+                  const gw_opts* opts, const gw_evgw_opts* eopts, double* qp_e, double* qp_w,
+                  gw_evgw_info* info);
+
+/*
  * Batched self-energy moments for many molecules (as gw_sigma_moments for
  * each).  gw_batch_create plans the batch once: per-molecule buffers; x
  * chunks of each molecule ("jobs") whose stage-1 intermediates fit job_bytes;

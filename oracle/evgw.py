@@ -14,9 +14,12 @@ eq. quasiparticle_energy_update, and then replaces eps_G (unless g0) and
 eps_W (unless w0) by them.
 
 Readings taken here (the box gives the loop, not its numerics):
-  * convergence: the largest change of any orbital's QP energy between two
-    iterations is below `tol` (1e-6 Ha); with g0 and w0 both set nothing is
-    updated and the loop is one G0W0 evaluation;
+  * convergence: the largest change between two iterations of the QP energy
+    of the orbitals whose QP weight is at least 0.9 in both (all orbitals if
+    none is) is below `tol` (1e-6 Ha); the QP energy of an orbital embedded in
+    a satellite band has no stable assignment and is left out of the test;
+    with g0 and w0 both set nothing is updated and the loop is one G0W0
+    evaluation;
   * the QP energy of orbital p is the H~ eigenvalue of largest physical
     weight |chi_p alpha|^2 (ties to the lowest alpha), as in G0W0.
 """
@@ -55,13 +58,17 @@ def evgw(eps, L, nocc, nmom_max, screening="tda", g0=False, w0=False, tol=1e-6, 
     eps_g = eps.copy()
     eps_w = eps.copy()
     prev = eps.copy()
+    prev_wt = np.ones_like(eps)
     history = []
     qp = wt = None
     converged = False
     it = 0
     for it in range(1, max_iter + 1):
         qp, wt = step(eps, eps_g, eps_w)
-        change = float(np.abs(qp - prev).max())
+        qpl = (wt >= 0.9) & (prev_wt >= 0.9)
+        if not qpl.any():
+            qpl[:] = True
+        change = float(np.abs(qp - prev)[qpl].max())
         history.append(change)
         if g0 and w0:
             converged = True
@@ -74,4 +81,5 @@ def evgw(eps, L, nocc, nmom_max, screening="tda", g0=False, w0=False, tol=1e-6, 
             converged = True
             break
         prev = qp.copy()
+        prev_wt = wt.copy()
     return dict(qp=qp, qp_weight=wt, iterations=it, converged=converged, history=history)

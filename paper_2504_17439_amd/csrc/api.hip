@@ -297,6 +297,25 @@ gw_status gw_fsgw(gw_handle h, gw_screening screening, int nocc, int nvir, int n
                          info);
 }
 
+gw_status gw_evgw(gw_handle h, gw_screening screening, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                  const double* L, gw_precision prec, const gw_opts* opts, const gw_evgw_opts* eopts, double* qp_e,
+                  double* qp_w, gw_evgw_info* info) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    GW_TRY(validate_common(h, nocc, nvir, naux, nmom_max, eps, L));
+    GW_TRY(check_opts(h, prec, opts));
+    if (screening != GW_TDA && screening != GW_RPA) return gwm::set_err(h, GW_EINVAL, "unknown screening");
+    if (nmom_max % 2 == 0 || nmom_max > 15)
+        return gwm::set_err(h, GW_EINVAL, "evGW: nmom_max must be odd and <= 15");
+    if (prec == GW_MIXED && nmom_max > 11)
+        return gwm::set_err(h, GW_EINVAL, "mixed precision: nmom_max must be <= 11");
+    if (!qp_e || !qp_w) return gwm::set_err(h, GW_EINVAL, "gw_evgw: qp_e and qp_w must be non-null");
+    if (eopts && (eopts->tol < 0 || eopts->max_iter < 0 || eopts->g0 < 0 || eopts->g0 > 1 || eopts->w0 < 0 ||
+                  eopts->w0 > 1))
+        return gwm::set_err(h, GW_EINVAL, "gw_evgw: bad option (g0, w0 in {0, 1}; tol, max_iter >= 0)");
+    return gwm::evgw_run(h, screening, nocc, nvir, naux, nmom_max, eps, L, prec, opts, eopts, qp_e, qp_w, info);
+}
+
 gw_status gw_batch_create(gw_handle h, int nsys, const gw_system* sys, gw_screening screening, int nmom_max,
                           gw_precision prec, const gw_opts* opts, const gw_batch_opts* bopts, gw_batch* batch) {
     if (!h) return GW_EINVAL;

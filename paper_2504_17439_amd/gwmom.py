@@ -26,7 +26,7 @@ _STATUS = {GW_EINVAL: "GW_EINVAL", GW_ENOMEM: "GW_ENOMEM", GW_EHIP: "GW_EHIP",
 # every symbol declared in include/gwmom.h
 EXPORTS = ("gw_create", "gw_set_stream", "gw_synchronize", "gw_destroy", "gw_last_error",
            "gw_moments_tda", "gw_moments_rpa", "gw_sigma_moments", "gw_sigma_from_R", "gw_poles",
-           "gw_fsgw", "gw_batch_create", "gw_batch_run", "gw_batch_info", "gw_batch_destroy",
+           "gw_fsgw", "gw_evgw", "gw_batch_create", "gw_batch_run", "gw_batch_info", "gw_batch_destroy",
            "gw_mlp_param_count", "gw_mlp_features", "gw_mlp_forward", "gw_mlp_backward",
            "gw_mlp_adam", "gw_timing_enable", "gw_timing_reset", "gw_timing_read")
 
@@ -64,6 +64,14 @@ class FsgwOpts(ctypes.Structure):
 class FsgwInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("fock_steps", ctypes.c_int), ("eig_calls", ctypes.c_int),
                 ("converged", ctypes.c_int), ("zeta", ctypes.c_double), ("last_dqp", ctypes.c_double)]
+
+
+class EvgwOpts(ctypes.Structure):
+    _fields_ = [("g0", ctypes.c_int), ("w0", ctypes.c_int), ("max_iter", ctypes.c_int), ("tol", ctypes.c_double)]
+
+
+class EvgwInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("last_change", ctypes.c_double)]
 
 
 _lib = None
@@ -258,6 +266,25 @@ class Handle:
         return dict(F=F, qp=qe, qp_weight=qw, iterations=info.iterations, fock_steps=info.fock_steps,
                     eig_calls=info.eig_calls, converged=bool(info.converged), zeta=info.zeta,
                     last_dqp=info.last_dqp)
+
+    def evgw(self, eps, L, nocc, nmom_max, screening="tda", precision="fp64", g0=False, w0=False, tol=1e-6,
+             max_iter=30, opts=None, allow_noconv=False):
+        """Eigenvalue self-consistent loop (g0 / w0 keep G / W at the reference);
+        returns dict(qp, qp_weight, iterations, converged, last_change)."""
+        naux, nmo = L.shape[0], L.shape[1]
+        _check_dev(eps, "eps", (nmo,))
+        _check_dev(L, "L", (naux, nmo, nmo))
+        qe, qw = self._new(nmo), self._new(nmo)
+        eo = EvgwOpts(int(bool(g0)), int(bool(w0)), int(max_iter), float(tol))
+        info = EvgwInfo()
+        scr = GW_TDA if screening == "tda" else GW_RPA
+        self._sync_stream()
+        st = self.lib.gw_evgw(self.h, scr, nocc, nmo - nocc, naux, nmom_max, _ptr(eps), _ptr(L), _prec(precision),
+                              _opts(opts), ctypes.byref(eo), _ptr(qe), _ptr(qw), ctypes.byref(info))
+        if st != GW_OK and not (st == GW_ENOCONV and allow_noconv):
+            raise GWError(st, self.lib.gw_last_error(self.h).decode())
+        return dict(qp=qe, qp_weight=qw, iterations=info.iterations, converged=bool(info.converged),
+                    last_change=info.last_change)
 
     # ------------------------------------------------------------------ batches
     def batch(self, systems, nmom_max, screening="tda", precision="mixed", opts=None, bopts=None):

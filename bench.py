@@ -165,9 +165,43 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_evgw(args):
+    """evGW at the c3 size: wall time and iterations of the device loop in
+    FP64 and in mixed precision (one JSON line; not the headline metric)."""
+    import torch
+    import gwsynth
+    from paper_2504_17439_amd import gwmom
+
+    o, v, A, N = args.nocc, args.nvir, args.naux, args.nmom
+    print(f"[bench] evgw inputs o={o} v={v} A={A} N={N}", file=sys.stderr, flush=True)
+    eps, L = gwsynth.system(o, v, A, args.seed)
+    h = gwmom.Handle(0)
+    e = torch.from_numpy(eps).to("cuda:0")
+    l = torch.from_numpy(L).to("cuda:0")
+    del L
+    out = {"metric": "evgw_seconds", "unit": "s", "higher_is_better": False, "n_gpus": 1,
+           "config": {"workload": f"evGW, TDA, nocc={o} nvir={v} naux={A} nmom_max={N}", "tol_ha": 1e-6}}
+    for prec in ("fp64", "mixed"):
+        opts = {"moment_eps": 1e-9} if prec == "mixed" else None
+        h.sigma_moments(e, l, o, N, "tda", prec)       # warm-up (workspace, code objects)
+        torch.cuda.synchronize()
+        print(f"[bench] evgw {prec}", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        r = h.evgw(e, l, o, N, "tda", prec, tol=1e-6, max_iter=20, opts=opts, allow_noconv=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        q = r["qp"].cpu().numpy()
+        out[prec] = {"seconds": el, "iterations": r["iterations"], "converged": r["converged"],
+                     "seconds_per_iteration": el / max(r["iterations"], 1), "last_change": r["last_change"],
+                     "homo_lumo_qp": [float(q[o - 1]), float(q[o])]}
+    out["frontier_qp_diff_mixed_vs_fp64"] = max(abs(out["mixed"]["homo_lumo_qp"][i] - out["fp64"]["homo_lumo_qp"][i])
+                                               for i in range(2))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="single", choices=["single", "batched"])
+    ap.add_argument("--workload", default="single", choices=["single", "batched", "evgw"])
     ap.add_argument("--nsys", type=int, default=64)
     ap.add_argument("--branches", type=int, default=4, help="batched: concurrent per-molecule streams")
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,6 +225,9 @@ def main():
 
     if args.workload == "batched":
         bench_batched(args)
+        return
+    if args.workload == "evgw":
+        bench_evgw(args)
         return
 
     import numpy as np

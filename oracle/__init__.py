@@ -15,6 +15,7 @@ brute       brute-force references: full TDA/RPA diagonalisation, exact
             Lehmann self-energy moments and the exact upfolded Hamiltonian.
 fsgw        the Fock / chemical-potential self-consistent loop (Alg. 2).
 evgw        the eigenvalue self-consistent loop (App. A, Alg. A1).
+naf         natural auxiliary functions (Sec. 2.1, eq. NAF).
 mlp         the per-orbital MLP of the learned warm start (forward,
             gradient, Adam) in FP64.
 """

@@ -217,6 +217,23 @@ gw_status gw_fsgw(gw_handle h, gw_screening screening, int nocc, int nvir, int n
                   double* F, double* qp_e, double* qp_w, gw_fsgw_info* info);
 
 /*
+ * Natural auxiliary functions (Sec. 2.1, eq. NAF).  M_PQ = sum_{vw} L[P][v][w]
+ * L[Q][v][w] over the particle-hole pairs (v, w) = (i, nocc + a), each once
+ * (full_space = 0), or over all nmo^2 pairs (full_space = 1); its eigenvectors
+ * with eigenvalue > eps_naf (absolute) span the NAF basis, and
+ *   L_naf[k][p][q] = sum_P U[P][k] L[P][p][q],  k = 0 .. nnaf-1,
+ * kept vectors in ascending eigenvalue order (each vector's sign is that of
+ * the eigensolver).  Any of the moment / self-energy entry points can then be
+ * called with naux = nnaf and L_naf.
+ * Inputs: L device [naux][nmo][nmo].  Outputs: L_naf device, capacity
+ * [naux][nmo][nmo] (the first nnaf slabs are written); nnaf host; eigenvalues
+ * device [naux] (all eigenvalues of M, ascending; nullable).
+ * GW_ENUMERIC if no eigenvalue exceeds eps_naf.
+ */
+gw_status gw_naf(gw_handle h, int nocc, int nvir, int naux, const double* L, double eps_naf,
+                 int full_space, double* L_naf, int* nnaf, double* eigenvalues);
+
+/*
  * Eigenvalue self-consistent moment GW (App. A, Alg. A1).  Two sets of orbital
  * energies start at eps: eps_G enters the eps-power factors of the self-energy
  * convolution (eqs. convolution_occ / convolution_vir), eps_W the energy

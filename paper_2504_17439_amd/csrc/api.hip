@@ -297,6 +297,21 @@ gw_status gw_fsgw(gw_handle h, gw_screening screening, int nocc, int nvir, int n
                          info);
 }
 
+gw_status gw_naf(gw_handle h, int nocc, int nvir, int naux, const double* L, double eps_naf, int full_space,
+                 double* L_naf, int* nnaf, double* eigenvalues) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    if (nocc < 1 || nvir < 1 || naux < 1) return gwm::set_err(h, GW_EINVAL, "nocc, nvir and naux must be >= 1");
+    if (!L || !L_naf || !nnaf) return gwm::set_err(h, GW_EINVAL, "gw_naf: L, L_naf and nnaf must be non-null");
+    if (!(eps_naf >= 0.0) || !std::isfinite(eps_naf)) return gwm::set_err(h, GW_EINVAL, "gw_naf: eps_naf must be >= 0");
+    if (full_space != 0 && full_space != 1) return gwm::set_err(h, GW_EINVAL, "gw_naf: full_space must be 0 or 1");
+    const long long nmo = nocc + nvir;
+    if (nmo * nmo > 0x7fffffffLL || (long long)naux * nmo * nmo > (1LL << 40))
+        return gwm::set_err(h, GW_EINVAL, "gw_naf: problem too large");
+    *nnaf = 0;
+    return gwm::naf_run(h, nocc, nvir, naux, L, eps_naf, full_space, L_naf, nnaf, eigenvalues);
+}
+
 gw_status gw_evgw(gw_handle h, gw_screening screening, int nocc, int nvir, int naux, int nmom_max, const double* eps,
                   const double* L, gw_precision prec, const gw_opts* opts, const gw_evgw_opts* eopts, double* qp_e,
                   double* qp_w, gw_evgw_info* info) {

@@ -196,6 +196,9 @@ gw_status upfold_eigh(Handle* h, int M, int np, const double* fock, const double
 // QP energies / weights from an H~ eigensystem (device outputs).
 gw_status qp_assign_dev(Handle* h, int M, int dim, const double* Ut, const double* E, double* qp_e, double* qp_w);
 
+gw_status naf_run(Handle* h, int nocc, int nvir, int naux, const double* L, double eps_naf, int full_space,
+                  double* L_naf, int* nnaf, double* eigenvalues);
+
 gw_status evgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int naux, int nmom_max, const double* eps,
                    const double* L, gw_precision prec, const gw_opts* opts, const gw_evgw_opts* eo, double* qp_e,
                    double* qp_w, gw_evgw_info* info);

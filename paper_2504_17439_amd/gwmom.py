@@ -26,7 +26,7 @@ _STATUS = {GW_EINVAL: "GW_EINVAL", GW_ENOMEM: "GW_ENOMEM", GW_EHIP: "GW_EHIP",
 # every symbol declared in include/gwmom.h
 EXPORTS = ("gw_create", "gw_set_stream", "gw_synchronize", "gw_destroy", "gw_last_error",
            "gw_moments_tda", "gw_moments_rpa", "gw_sigma_moments", "gw_sigma_from_R", "gw_poles",
-           "gw_fsgw", "gw_evgw", "gw_batch_create", "gw_batch_run", "gw_batch_info", "gw_batch_destroy",
+           "gw_fsgw", "gw_evgw", "gw_naf", "gw_batch_create", "gw_batch_run", "gw_batch_info", "gw_batch_destroy",
            "gw_mlp_param_count", "gw_mlp_features", "gw_mlp_forward", "gw_mlp_backward",
            "gw_mlp_adam", "gw_timing_enable", "gw_timing_reset", "gw_timing_read")
 
@@ -99,6 +99,8 @@ def load_library(path: str = LIB_PATH):
         "gw_sigma_from_R": ([H, I, I, I, I, P, P, P, I, P, P, P], I),
         "gw_poles": ([H, I, I, P, P, P, P, ctypes.POINTER(I), ctypes.POINTER(I), P, P, P, P, P, P], I),
         "gw_fsgw": ([H, I, I, I, I, I, P, P, P, I, P, P, P, P, P, P], I),
+        "gw_evgw": ([H, I, I, I, I, I, P, P, I, P, P, P, P, P], I),
+        "gw_naf": ([H, I, I, I, P, D, I, P, ctypes.POINTER(I), P], I),
         "gw_batch_create": ([H, I, P, I, I, I, P, P, ctypes.POINTER(ctypes.c_void_p)], I),
         "gw_batch_run": ([P], I),
         "gw_batch_info": ([P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)], I),
@@ -266,6 +268,19 @@ class Handle:
         return dict(F=F, qp=qe, qp_weight=qw, iterations=info.iterations, fock_steps=info.fock_steps,
                     eig_calls=info.eig_calls, converged=bool(info.converged), zeta=info.zeta,
                     last_dqp=info.last_dqp)
+
+    def naf(self, L, nocc, eps_naf=1e-5, full_space=False):
+        """Natural auxiliary functions: returns (L_naf [nnaf][nmo][nmo], all
+        eigenvalues of M ascending)."""
+        naux, nmo = L.shape[0], L.shape[1]
+        _check_dev(L, "L", (naux, nmo, nmo))
+        out = self._new(naux, nmo, nmo)
+        w = self._new(naux)
+        n = ctypes.c_int(0)
+        self._sync_stream()
+        self._call("gw_naf", nocc, nmo - nocc, naux, _ptr(L), ctypes.c_double(eps_naf), int(bool(full_space)),
+                   _ptr(out), ctypes.byref(n), _ptr(w))
+        return out[: n.value], w
 
     def evgw(self, eps, L, nocc, nmom_max, screening="tda", precision="fp64", g0=False, w0=False, tol=1e-6,
              max_iter=30, opts=None, allow_noconv=False):

@@ -16,6 +16,9 @@ brute       brute-force references: full TDA/RPA diagonalisation, exact
 fsgw        the Fock / chemical-potential self-consistent loop (Alg. 2).
 evgw        the eigenvalue self-consistent loop (App. A, Alg. A1).
 naf         natural auxiliary functions (Sec. 2.1, eq. NAF).
+spectral    spectral function, Aufbau filling, Dyson orbitals and the
+            electron-number shift of a one-shot calculation (eqs. ret_GF,
+            spectrum, density; Sec. 3.5).
 mlp         the per-orbital MLP of the learned warm start (forward,
             gradient, Adam) in FP64.
 """

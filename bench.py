@@ -199,9 +199,76 @@ def bench_evgw(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_spectral(args):
+    """Green's-function post-processing at the c3 size (one JSON line; not the
+    headline metric): mixed self-energy moments and FP64 poles, then the
+    spectral function over nomega frequencies (per orbital and total), the
+    Aufbau filling and the electron-number shift of the auxiliary energies.
+    gw_spectral (Lorentzian matrix + FP64 GEMM) is timed with HIP events on
+    the handle's stream and set against the FP64 matrix peak (2 flops per
+    orbital, state and frequency)."""
+    import numpy as np
+    import torch
+    import gwsynth
+    from paper_2504_17439_amd import gwmom
+
+    o, v, A, N = args.nocc, args.nvir, args.naux, args.nmom
+    M = o + v
+    nw = args.nomega
+    print(f"[bench] spectral inputs o={o} v={v} A={A} N={N} nomega={nw}", file=sys.stderr, flush=True)
+    eps, L = gwsynth.system(o, v, A, args.seed)
+    h = gwmom.Handle(0)
+    e = torch.from_numpy(eps).to("cuda:0")
+    l = torch.from_numpy(L).to("cuda:0")
+    del L
+    so, sv = h.sigma_moments(e, l, o, N, "tda", "mixed")
+    fock = torch.diag(e).contiguous()
+    p = h.poles(so, sv, fock, opts={"moment_eps": 1e-9})
+    E, chi = p["E"], p["chi"]
+    dim = E.shape[0]
+    omega = torch.linspace(float(eps.min()) - 0.5, float(eps.max()) + 0.5, nw, dtype=torch.float64, device="cuda:0")
+    delta = 0.01
+    print(f"[bench] spectral dim={dim}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        h.spectral(E, chi, omega, delta, per_orbital=True)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        Atot, Ap = h.spectral(E, chi, omega, delta, per_orbital=True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    flops = 2.0 * M * dim * nw                       # A_p(w) for every orbital, state and frequency
+    peak = 78.6e12
+    t0 = time.perf_counter()
+    st = h.aufbau(E, chi, 2.0 * o)
+    torch.cuda.synchronize()
+    t_auf = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    z = h.zeta_shift(p, fock, 2.0 * o)
+    torch.cuda.synchronize()
+    t_zeta = time.perf_counter() - t0
+    q0, qz = p["qp"].cpu().numpy(), z["qp"].cpu().numpy()
+    out = {"metric": "spectral_function_ms", "value": ms, "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"spectral function, TDA mixed moments, nocc={o} nvir={v} naux={A} "
+                                  f"nmom_max={N}, nomega={nw}, delta={delta}", "dim": dim},
+           "roofline": {"bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12, "peak": peak / 1e12,
+                        "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / peak, "traffic": None},
+           "aufbau": {"seconds": t_auf, "nfill": st["nfill"], "nelec": st["nelec"], "mu": st["mu"]},
+           "zeta_shift": {"seconds": t_zeta, "zeta": z["zeta"], "nelec": z["nelec"], "eig_calls": z["eig_calls"],
+                          "max_qp_shift": float(np.abs(qz - q0).max()),
+                          "frontier_qp_shift": float(max(abs(qz[o - 1] - q0[o - 1]), abs(qz[o] - q0[o])))},
+           "sum_rule_check": float(Atot.sum().item() * float(omega[1] - omega[0]) / M)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="single", choices=["single", "batched", "evgw"])
+    ap.add_argument("--workload", default="single", choices=["single", "batched", "evgw", "spectral"])
+    ap.add_argument("--nomega", type=int, default=2048, help="spectral: frequencies")
     ap.add_argument("--nsys", type=int, default=64)
     ap.add_argument("--branches", type=int, default=4, help="batched: concurrent per-molecule streams")
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,6 +295,9 @@ def main():
         return
     if args.workload == "evgw":
         bench_evgw(args)
+        return
+    if args.workload == "spectral":
+        bench_spectral(args)
         return
 
     import numpy as np

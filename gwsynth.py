@@ -89,3 +89,20 @@ def system_device(nocc: int, nvir: int, naux: int, seed: int = 0, device: str = 
         G = torch.randn((P1 - P0, nmo, nmo), generator=g, device=device, dtype=f64)
         L[P0:P1] = (G + G.transpose(1, 2)) * envelope
     return eps, L
+
+
+def eigensystem(nmo: int, dim: int, seed: int = 0, orthonormal: bool = True,
+                e_lo: float = -3.0, e_hi: float = 4.0):
+    """Synthetic eigenpairs of an upfolded Hamiltonian: E [dim] ascending,
+    uniform in [e_lo, e_hi] Ha, and chi [nmo][dim], the first nmo rows of a
+    random orthogonal matrix (or, for large dim, Gaussian rows scaled to unit
+    norm, which keeps the shapes without the O(dim^3) factorisation)."""
+    rng = np.random.default_rng(seed)
+    E = np.sort(rng.uniform(e_lo, e_hi, dim))
+    if orthonormal:
+        Q = np.linalg.qr(rng.standard_normal((dim, dim)))[0]
+        chi = np.ascontiguousarray(Q[:nmo])
+    else:
+        chi = rng.standard_normal((nmo, dim))
+        chi /= np.linalg.norm(chi, axis=1, keepdims=True)
+    return E, chi

@@ -234,6 +234,74 @@ gw_status gw_naf(gw_handle h, int nocc, int nvir, int naux, const double* L, dou
                  int full_space, double* L_naf, int* nnaf, double* eigenvalues);
 
 /*
+ * Spectral function of the upfolded Green's function (eqs. ret_GF, spectrum).
+ * From the eigenpairs (E_a, chi) of H~, each pole carrying one broadening
+ * delta > 0,
+ *   G_pp(w)  = sum_a chi_{pa}^2 / (w - E_a + i delta),
+ *   A_p(w)   = -(1/pi) Im G_pp(w) = (delta/pi) sum_a chi_{pa}^2 / ((w - E_a)^2 + delta^2),
+ *   A(w)     = sum_p A_p(w).
+ * Inputs (device): E [dim]; chi [nmo][ld_chi] (physical rows of the
+ * eigenvectors, ld_chi >= dim; gw_poles writes ld_chi = nmo*(nmom_max+2));
+ * omega [nomega] (Ha).  Outputs (device; either may be NULL, not both):
+ * A [nomega]; A_orb [nmo][nomega].  FP64, asynchronous on the handle's stream.
+ */
+gw_status gw_spectral(gw_handle h, int nmo, int dim, int ld_chi, const double* E, const double* chi,
+                      int nomega, const double* omega, double delta, double* A, double* A_orb);
+
+/*
+ * Aufbau filling of the eigenstates of H~ and the correlated density matrix
+ * (eq. density): the n lowest states are filled, n minimising
+ * |2 sum_{a<n} |chi_a|^2 - nelec| (lowest n on ties), and
+ *   rho = 2 sum_{a<n} chi_a chi_a^T.
+ * The Dyson orbitals (MO basis) of the ionisation and of the attachment are
+ * columns homo = n-1 and lumo = n of chi; their squared norms are the pole
+ * strengths, -E[homo] and -E[lumo] the ionisation energy and the electron
+ * affinity.  Inputs (device): E [dim] ascending, chi [nmo][ld_chi].
+ * Outputs: rho device [nmo][nmo] (nullable); info host (nullable).
+ * GW_EINVAL if E is not ascending.  Synchronises the stream.
+ */
+typedef struct {
+    int nfill;      /* filled states n */
+    double nelec;   /* 2 sum_{a<n} |chi_a|^2 */
+    double mu;      /* midway between E[homo] and E[lumo] (the existing one if n = 0 or dim) */
+    int homo;       /* n - 1, or -1 */
+    int lumo;       /* n, or -1 if n = dim */
+} gw_aufbau_info;
+
+gw_status gw_aufbau(gw_handle h, int nmo, int dim, int ld_chi, const double* E, const double* chi,
+                    double nelec, double* rho, gw_aufbau_info* info);
+
+/*
+ * Electron-number conserving one-shot GW (Sec. 3.5): every auxiliary energy
+ * (the diagonal of d~) is shifted by zeta, the physical block fixed, until the
+ * Aufbau filling of H~(zeta) (as in gw_aufbau) holds nelec electrons.  The
+ * shift is searched from 0 outwards: bracket +-1e-3 Ha, widened tenfold
+ * within [zeta_lo, zeta_hi] until Tr rho - nelec changes sign, then false
+ * position (Illinois) with bisection safeguards, to zeta_tol electrons or a
+ * 1e-13 Ha bracket; without a sign change, the end with the smaller residual.
+ * Inputs (device): fock [nmo][nmo]; pole_e, pole_v as gw_poles writes them for
+ * the same nmo and nmom_max (npole_occ + npole_vir packed columns, leading
+ * dimension nmo*(nmom_max+1)).  Outputs (device): E, chi (nullable), qp_e,
+ * qp_w as in gw_poles, at the final zeta; info host (nullable).
+ * Synchronises the stream.
+ */
+typedef struct {
+    double zeta_lo, zeta_hi;   /* search interval [-1, 1] Ha (used when zeta_hi > zeta_lo) */
+    double zeta_tol;           /* electrons [1e-13] */
+} gw_zeta_opts;
+
+typedef struct {
+    double zeta;     /* final shift (Ha) */
+    int nfill;       /* filled states of H~(zeta) */
+    double nelec;    /* their electron count */
+    int eig_calls;   /* eigensolves of H~ */
+} gw_zeta_info;
+
+gw_status gw_zeta_shift(gw_handle h, int nmo, int nmom_max, int npole_occ, int npole_vir, const double* fock,
+                        const double* pole_e, const double* pole_v, double nelec, const gw_zeta_opts* zopts,
+                        double* E, double* chi, double* qp_e, double* qp_w, gw_zeta_info* info);
+
+/*
  * Eigenvalue self-consistent moment GW (App. A, Alg. A1).  Two sets of orbital
  * energies start at eps: eps_G enters the eps-power factors of the self-energy
  * convolution (eqs. convolution_occ / convolution_vir), eps_W the energy

@@ -312,6 +312,52 @@ gw_status gw_naf(gw_handle h, int nocc, int nvir, int naux, const double* L, dou
     return gwm::naf_run(h, nocc, nvir, naux, L, eps_naf, full_space, L_naf, nnaf, eigenvalues);
 }
 
+gw_status gw_spectral(gw_handle h, int nmo, int dim, int ld_chi, const double* E, const double* chi, int nomega,
+                      const double* omega, double delta, double* A, double* A_orb) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    if (nmo < 1 || dim < 1 || ld_chi < dim || nomega < 1)
+        return gwm::set_err(h, GW_EINVAL, "gw_spectral: need nmo, dim, nomega >= 1 and ld_chi >= dim");
+    if ((long long)nmo * ld_chi > (1LL << 40) || (long long)nmo * nomega > (1LL << 40))
+        return gwm::set_err(h, GW_EINVAL, "gw_spectral: problem too large");
+    if (!(delta > 0.0) || !std::isfinite(delta)) return gwm::set_err(h, GW_EINVAL, "gw_spectral: delta must be > 0");
+    if (!E || !chi || !omega) return gwm::set_err(h, GW_EINVAL, "gw_spectral: E, chi and omega must be non-null");
+    if (!A && !A_orb) return gwm::set_err(h, GW_EINVAL, "gw_spectral: A and A_orb are both null");
+    return gwm::spectral_run(h, nmo, dim, ld_chi, E, chi, nomega, omega, delta, A, A_orb);
+}
+
+gw_status gw_aufbau(gw_handle h, int nmo, int dim, int ld_chi, const double* E, const double* chi, double nelec,
+                    double* rho, gw_aufbau_info* info) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    if (nmo < 1 || dim < 1 || ld_chi < dim)
+        return gwm::set_err(h, GW_EINVAL, "gw_aufbau: need nmo, dim >= 1 and ld_chi >= dim");
+    if ((long long)nmo * ld_chi > (1LL << 40)) return gwm::set_err(h, GW_EINVAL, "gw_aufbau: problem too large");
+    if (!(nelec >= 0.0) || !std::isfinite(nelec)) return gwm::set_err(h, GW_EINVAL, "gw_aufbau: nelec must be >= 0");
+    if (!E || !chi) return gwm::set_err(h, GW_EINVAL, "gw_aufbau: E and chi must be non-null");
+    return gwm::aufbau_run(h, nmo, dim, ld_chi, E, chi, nelec, rho, info);
+}
+
+gw_status gw_zeta_shift(gw_handle h, int nmo, int nmom_max, int npole_occ, int npole_vir, const double* fock,
+                        const double* pole_e, const double* pole_v, double nelec, const gw_zeta_opts* zopts,
+                        double* E, double* chi, double* qp_e, double* qp_w, gw_zeta_info* info) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    if (nmo < 1) return gwm::set_err(h, GW_EINVAL, "nmo must be >= 1");
+    if (nmom_max < 1 || nmom_max % 2 == 0 || nmom_max > 15)
+        return gwm::set_err(h, GW_EINVAL, "nmom_max must be odd and in [1, 15]");
+    const long long cap = (long long)nmo * (nmom_max + 1) / 2;
+    if (npole_occ < 0 || npole_vir < 0 || npole_occ > cap || npole_vir > cap)
+        return gwm::set_err(h, GW_EINVAL, "gw_zeta_shift: pole counts out of range");
+    if (!(nelec >= 0.0) || !std::isfinite(nelec)) return gwm::set_err(h, GW_EINVAL, "gw_zeta_shift: nelec must be >= 0");
+    if (zopts && (zopts->zeta_tol < 0 || !std::isfinite(zopts->zeta_lo) || !std::isfinite(zopts->zeta_hi)))
+        return gwm::set_err(h, GW_EINVAL, "gw_zeta_shift: invalid options");
+    if (!fock || !pole_e || !pole_v || !E || !qp_e || !qp_w)
+        return gwm::set_err(h, GW_EINVAL, "gw_zeta_shift: a required pointer is null");
+    return gwm::zeta_shift_run(h, nmo, nmom_max, npole_occ, npole_vir, fock, pole_e, pole_v, nelec, zopts, E, chi,
+                               qp_e, qp_w, info);
+}
+
 gw_status gw_evgw(gw_handle h, gw_screening screening, int nocc, int nvir, int naux, int nmom_max, const double* eps,
                   const double* L, gw_precision prec, const gw_opts* opts, const gw_evgw_opts* eopts, double* qp_e,
                   double* qp_w, gw_evgw_info* info) {

@@ -158,6 +158,84 @@ struct Diis {
 
 }  // namespace
 
+gw_status zeta_trace(Handle* h, ZetaSearch& s, double z, double nelec, double* tr, int* nfill) {
+    GW_TRY(upfold_eigh(h, s.M, s.np, s.F, s.pole_e, z, s.pole_v, s.ldv, s.H, s.w, s.work, s.info));
+    ++s.eig_calls;
+    const int dim = s.M + s.np;
+    hipLaunchKernelGGL(phys_weight_kernel, dim3((unsigned)((dim + 3) / 4)), dim3(256), 0, h->stream, dim, s.M, s.H,
+                       s.wt);
+    GW_CHECK_LAUNCH(h);
+    s.hw.resize(dim);
+    GW_HIP(h, hipMemcpyAsync(s.hw.data(), s.wt, sizeof(double) * dim, hipMemcpyDeviceToHost, h->stream));
+    GW_HIP(h, hipStreamSynchronize(h->stream));
+    double cum = 0.0, best = std::fabs(nelec);
+    int nb = 0;
+    for (int a = 0; a < dim; ++a) {
+        cum += 2.0 * s.hw[a];
+        if (std::fabs(cum - nelec) < best) {
+            best = std::fabs(cum - nelec);
+            nb = a + 1;
+        }
+    }
+    double t = 0.0;
+    for (int a = 0; a < nb; ++a) t += 2.0 * s.hw[a];
+    *tr = t;
+    *nfill = nb;
+    return GW_OK;
+}
+
+gw_status zeta_solve(Handle* h, ZetaSearch& s, double nelec, double z0in, double zlo, double zhi, double ztol,
+                     double* zeta, double* tr, int* nfill) {
+    double lo, hi, flo, fhi;
+    double half = 1e-3;
+    const double z0 = std::min(std::max(z0in, zlo), zhi);
+    for (;;) {
+        lo = std::max(zlo, z0 - half);
+        hi = std::min(zhi, z0 + half);
+        GW_TRY(zeta_trace(h, s, lo, nelec, tr, nfill));
+        flo = *tr - nelec;
+        GW_TRY(zeta_trace(h, s, hi, nelec, tr, nfill));
+        fhi = *tr - nelec;
+        if (flo * fhi <= 0.0 || (lo == zlo && hi == zhi)) break;
+        half *= 10.0;
+    }
+    double best = std::fabs(flo) < std::fabs(fhi) ? lo : hi;
+    double fbest = std::fabs(flo) < std::fabs(fhi) ? flo : fhi;
+    double last = hi;
+    if (flo * fhi < 0.0) {
+        int side = 0;
+        double width = hi - lo;
+        for (int it = 0; it < 100; ++it) {
+            double z = (lo * fhi - hi * flo) / (fhi - flo);
+            // bisect when false position leaves the bracket or the bracket stops halving
+            if (!(z > lo && z < hi) || (it % 3 == 2 && hi - lo > 0.5 * width)) z = 0.5 * (lo + hi);
+            if (it % 3 == 2) width = hi - lo;
+            GW_TRY(zeta_trace(h, s, z, nelec, tr, nfill));
+            last = z;
+            const double f = *tr - nelec;
+            if (std::fabs(f) < std::fabs(fbest)) {
+                best = z;
+                fbest = f;
+            }
+            if (std::fabs(f) < ztol || hi - lo < 1e-13) break;
+            if ((f < 0) == (flo < 0)) {
+                lo = z;
+                flo = f;
+                if (side == -1) fhi *= 0.5;
+                side = -1;
+            } else {
+                hi = z;
+                fhi = f;
+                if (side == 1) flo *= 0.5;
+                side = 1;
+            }
+        }
+    }
+    *zeta = best;
+    if (last != best) GW_TRY(zeta_trace(h, s, best, nelec, tr, nfill));
+    return GW_OK;
+}
+
 gw_status fsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int naux, int nmom_max, const double* eps,
                    const double* L, const double* F0, gw_precision prec, const gw_opts* opts,
                    const gw_fsgw_opts* fo, double* F, double* qp_e, double* qp_w, gw_fsgw_info* info) {
@@ -225,38 +303,24 @@ gw_status fsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
         GW_CHECK_LAUNCH(h);
     }
 
-    std::vector<double> hrho((size_t)M2), hrho_old((size_t)M2), hFn((size_t)M2), herr((size_t)M2), hw(dim_max),
+    std::vector<double> hrho((size_t)M2), hrho_old((size_t)M2), hFn((size_t)M2), herr((size_t)M2),
         hqp(M), hqp_prev(M);
-    int outer = 0, fock_steps = 0, eig_calls = 0;
+    int outer = 0, fock_steps = 0;
     bool converged = false;
     double zeta = 0.0, last_dqp = -1.0;
     int np = 0;
 
-    // Tr rho(z) for the current Fc and poles; leaves the eigensystem of H~(z) in Hh
-    auto trace_at = [&](double z, double* tr, int* nfill) -> gw_status {
-        GW_TRY(upfold_eigh(h, M, np, Fc, pole_e, z, pole_v, ldv, Hh, Hw, Hwork, dinfo));
-        ++eig_calls;
-        const int dim = M + np;
-        hipLaunchKernelGGL(phys_weight_kernel, dim3((unsigned)((dim + 3) / 4)), dim3(256), 0, h->stream, dim, M, Hh,
-                           Hwt);
-        GW_CHECK_LAUNCH(h);
-        GW_HIP(h, hipMemcpyAsync(hw.data(), Hwt, sizeof(double) * dim, hipMemcpyDeviceToHost, h->stream));
-        GW_HIP(h, hipStreamSynchronize(h->stream));
-        double cum = 0.0, best = std::fabs(nelec);
-        int nb = 0;
-        for (int a = 0; a < dim; ++a) {
-            cum += 2.0 * hw[a];
-            if (std::fabs(cum - nelec) < best) {
-                best = std::fabs(cum - nelec);
-                nb = a + 1;
-            }
-        }
-        double t = 0.0;
-        for (int a = 0; a < nb; ++a) t += 2.0 * hw[a];
-        *tr = t;
-        *nfill = nb;
-        return GW_OK;
-    };
+    ZetaSearch zs;
+    zs.M = M;
+    zs.F = Fc;
+    zs.pole_e = pole_e;
+    zs.pole_v = pole_v;
+    zs.ldv = ldv;
+    zs.H = Hh;
+    zs.w = Hw;
+    zs.work = Hwork;
+    zs.wt = Hwt;
+    zs.info = dinfo;
 
     for (outer = 0; outer < max_outer; ++outer) {
         // orbitals of the current F
@@ -284,57 +348,11 @@ gw_status fsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
         for (int p = 0; p < nocc; ++p) hrho_old[(size_t)p * M + p] = 2.0;
         Diis diis{diis_space, (size_t)M2, {}, {}, {}};
         for (int step = 0; step < max_fock; ++step) {
-            // zeta: root of Tr rho(zeta) - N_e.  Bracket: +-1e-3 Ha around the
-            // previous zeta, widened tenfold (within [zeta_lo, zeta_hi]) until it
-            // holds a sign change; then safeguarded false position (Illinois).
-            double tr = 0.0, lo, hi, flo, fhi;
+            // zeta: root of Tr rho(zeta) - N_e, from the previous zeta
+            double tr = 0.0;
             int nf = 0;
-            double half = 1e-3;
-            const double z0 = std::min(std::max(zeta, zlo), zhi);
-            for (;;) {
-                lo = std::max(zlo, z0 - half);
-                hi = std::min(zhi, z0 + half);
-                GW_TRY(trace_at(lo, &tr, &nf));
-                flo = tr - nelec;
-                GW_TRY(trace_at(hi, &tr, &nf));
-                fhi = tr - nelec;
-                if (flo * fhi <= 0.0 || (lo == zlo && hi == zhi)) break;
-                half *= 10.0;
-            }
-            double best = std::fabs(flo) < std::fabs(fhi) ? lo : hi;
-            double fbest = std::fabs(flo) < std::fabs(fhi) ? flo : fhi;
-            double last = hi;
-            if (flo * fhi < 0.0) {
-                int side = 0;
-                double width = hi - lo;
-                for (int it = 0; it < 100; ++it) {
-                    double z = (lo * fhi - hi * flo) / (fhi - flo);
-                    // bisect when false position leaves the bracket or the bracket stops halving
-                    if (!(z > lo && z < hi) || (it % 3 == 2 && hi - lo > 0.5 * width)) z = 0.5 * (lo + hi);
-                    if (it % 3 == 2) width = hi - lo;
-                    GW_TRY(trace_at(z, &tr, &nf));
-                    last = z;
-                    const double f = tr - nelec;
-                    if (std::fabs(f) < std::fabs(fbest)) {
-                        best = z;
-                        fbest = f;
-                    }
-                    if (std::fabs(f) < zeta_tol || hi - lo < 1e-13) break;
-                    if ((f < 0) == (flo < 0)) {
-                        lo = z;
-                        flo = f;
-                        if (side == -1) fhi *= 0.5;
-                        side = -1;
-                    } else {
-                        hi = z;
-                        fhi = f;
-                        if (side == 1) flo *= 0.5;
-                        side = 1;
-                    }
-                }
-            }
-            zeta = best;
-            if (last != best) GW_TRY(trace_at(best, &tr, &nf));
+            zs.np = np;
+            GW_TRY(zeta_solve(h, zs, nelec, zeta, zlo, zhi, zeta_tol, &zeta, &tr, &nf));
             // rho = 2 sum_{a < nf} chi_a chi_a^T (physical rows of the lowest nf eigenvectors)
             GW_TRY(gemm_rowmajor(h, true, false, M, M, nf, 2.0, Hh, M + np, Hh, M + np, 0.0, rho, M));
             GW_TRY(jk(h, A, M, Lc, rho, J, K, T, jv));
@@ -361,7 +379,7 @@ gw_status fsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
         }
         // QP energies of this iteration, F back to the reference basis
         GW_TRY(upfold_eigh(h, M, np, Fc, pole_e, zeta, pole_v, ldv, Hh, Hw, Hwork, dinfo));
-        ++eig_calls;
+        ++zs.eig_calls;
         GW_TRY(qp_assign_dev(h, M, M + np, Hh, Hw, qp_e, qp_w));
         GW_TRY(gemm_rowmajor(h, false, false, M, M, M, 1.0, Fc, M, Ut, M, 0.0, tmp, M));
         GW_TRY(gemm_rowmajor(h, true, false, M, M, M, 1.0, Ut, M, tmp, M, 0.0, Fr, M));
@@ -384,7 +402,7 @@ gw_status fsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
     if (info) {
         info->iterations = outer;
         info->fock_steps = fock_steps;
-        info->eig_calls = eig_calls;
+        info->eig_calls = zs.eig_calls;
         info->converged = converged ? 1 : 0;
         info->zeta = zeta;
         info->last_dqp = last_dqp;

@@ -193,11 +193,50 @@ gw_status poles_lanczos(Handle* h, int nmo, int nmom_max, const double* sigma_oc
 gw_status upfold_eigh(Handle* h, int M, int np, const double* fock, const double* pole_e, double zeta,
                       const double* pole_v, long ldv, double* H, double* w, double* work, int* info);
 
+// Electron-number search over the shift zeta of the auxiliary energies
+// (eq. density, Sec. 3.5).  The system is H~(zeta) as in upfold_eigh; H, w,
+// work, wt (each sized for dim = M + np) and info are device scratch, and
+// after every evaluation H / w hold the eigensystem at the last zeta asked.
+struct ZetaSearch {
+    int M = 0, np = 0;
+    const double* F = nullptr;
+    const double* pole_e = nullptr;
+    const double* pole_v = nullptr;
+    long ldv = 0;
+    double* H = nullptr;
+    double* w = nullptr;
+    double* work = nullptr;
+    double* wt = nullptr;
+    int* info = nullptr;
+    int eig_calls = 0;
+    std::vector<double> hw;
+};
+
+// Aufbau filling of H~(z): nfill minimises |2 sum_{a<n} |chi_a|^2 - nelec|
+// (lowest n on ties), tr = 2 sum_{a<nfill} |chi_a|^2.
+gw_status zeta_trace(Handle* h, ZetaSearch& s, double z, double nelec, double* tr, int* nfill);
+
+// Root of Tr rho(zeta) - nelec: bracket +-1e-3 Ha around z0 (clamped to
+// [zlo, zhi]), widened tenfold until the sign changes or the bracket is
+// [zlo, zhi]; then Illinois false position with bisection safeguards, to
+// ztol electrons or a 1e-13 Ha bracket.  Without a sign change, the end with
+// the smaller residual.  On return s.H / s.w hold the eigensystem at *zeta.
+gw_status zeta_solve(Handle* h, ZetaSearch& s, double nelec, double z0, double zlo, double zhi, double ztol,
+                     double* zeta, double* tr, int* nfill);
+
 // QP energies / weights from an H~ eigensystem (device outputs).
 gw_status qp_assign_dev(Handle* h, int M, int dim, const double* Ut, const double* E, double* qp_e, double* qp_w);
 
 gw_status naf_run(Handle* h, int nocc, int nvir, int naux, const double* L, double eps_naf, int full_space,
                   double* L_naf, int* nnaf, double* eigenvalues);
+
+gw_status spectral_run(Handle* h, int nmo, int dim, int ld_chi, const double* E, const double* chi, int nomega,
+                       const double* omega, double delta, double* A, double* A_orb);
+gw_status aufbau_run(Handle* h, int nmo, int dim, int ld_chi, const double* E, const double* chi, double nelec,
+                     double* rho, gw_aufbau_info* info);
+gw_status zeta_shift_run(Handle* h, int nmo, int nmom_max, int npole_occ, int npole_vir, const double* fock,
+                         const double* pole_e, const double* pole_v, double nelec, const gw_zeta_opts* zo, double* E,
+                         double* chi, double* qp_e, double* qp_w, gw_zeta_info* info);
 
 gw_status evgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int naux, int nmom_max, const double* eps,
                    const double* L, gw_precision prec, const gw_opts* opts, const gw_evgw_opts* eo, double* qp_e,

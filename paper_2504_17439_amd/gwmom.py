@@ -26,7 +26,7 @@ _STATUS = {GW_EINVAL: "GW_EINVAL", GW_ENOMEM: "GW_ENOMEM", GW_EHIP: "GW_EHIP",
 # every symbol declared in include/gwmom.h
 EXPORTS = ("gw_create", "gw_set_stream", "gw_synchronize", "gw_destroy", "gw_last_error",
            "gw_moments_tda", "gw_moments_rpa", "gw_sigma_moments", "gw_sigma_from_R", "gw_poles",
-           "gw_fsgw", "gw_evgw", "gw_naf", "gw_batch_create", "gw_batch_run", "gw_batch_info", "gw_batch_destroy",
+           "gw_fsgw", "gw_evgw", "gw_naf", "gw_spectral", "gw_aufbau", "gw_zeta_shift", "gw_batch_create", "gw_batch_run", "gw_batch_info", "gw_batch_destroy",
            "gw_mlp_param_count", "gw_mlp_features", "gw_mlp_forward", "gw_mlp_backward",
            "gw_mlp_adam", "gw_timing_enable", "gw_timing_reset", "gw_timing_read")
 
@@ -66,6 +66,20 @@ class FsgwInfo(ctypes.Structure):
                 ("converged", ctypes.c_int), ("zeta", ctypes.c_double), ("last_dqp", ctypes.c_double)]
 
 
+class AufbauInfo(ctypes.Structure):
+    _fields_ = [("nfill", ctypes.c_int), ("nelec", ctypes.c_double), ("mu", ctypes.c_double),
+                ("homo", ctypes.c_int), ("lumo", ctypes.c_int)]
+
+
+class ZetaOpts(ctypes.Structure):
+    _fields_ = [("zeta_lo", ctypes.c_double), ("zeta_hi", ctypes.c_double), ("zeta_tol", ctypes.c_double)]
+
+
+class ZetaInfo(ctypes.Structure):
+    _fields_ = [("zeta", ctypes.c_double), ("nfill", ctypes.c_int), ("nelec", ctypes.c_double),
+                ("eig_calls", ctypes.c_int)]
+
+
 class EvgwOpts(ctypes.Structure):
     _fields_ = [("g0", ctypes.c_int), ("w0", ctypes.c_int), ("max_iter", ctypes.c_int), ("tol", ctypes.c_double)]
 
@@ -101,6 +115,9 @@ def load_library(path: str = LIB_PATH):
         "gw_fsgw": ([H, I, I, I, I, I, P, P, P, I, P, P, P, P, P, P], I),
         "gw_evgw": ([H, I, I, I, I, I, P, P, I, P, P, P, P, P], I),
         "gw_naf": ([H, I, I, I, P, D, I, P, ctypes.POINTER(I), P], I),
+        "gw_spectral": ([H, I, I, I, P, P, I, P, D, P, P], I),
+        "gw_aufbau": ([H, I, I, I, P, P, D, P, P], I),
+        "gw_zeta_shift": ([H, I, I, I, I, P, P, P, D, P, P, P, P, P, P], I),
         "gw_batch_create": ([H, I, P, I, I, I, P, P, ctypes.POINTER(ctypes.c_void_p)], I),
         "gw_batch_run": ([P], I),
         "gw_batch_info": ([P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)], I),
@@ -146,6 +163,16 @@ def _check_dev(t, name, shape=None):
         raise ValueError(f"{name} must be a contiguous float64 device tensor")
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _check_rows(t, name, rows, cols):
+    """float64 device matrix [rows][cols] whose rows may be strided (a column
+    slice of a wider array); returns the leading dimension."""
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.dim() == 2):
+        raise ValueError(f"{name} must be a 2-D float64 device tensor")
+    if tuple(t.shape) != (rows, cols) or (cols > 1 and t.stride(1) != 1) or (rows > 1 and t.stride(0) < cols):
+        raise ValueError(f"{name}: expected [{rows}][{cols}] with unit column stride")
+    return max(cols, t.stride(0))
 
 
 def _check_f32(t, name):
@@ -357,7 +384,53 @@ class Handle:
         no, nv = no.value, nv.value
         dim = nmo + no + nv
         return dict(e_occ=pe[:no], v_occ=pv[:, :no], e_vir=pe[no:no + nv], v_vir=pv[:, no:no + nv],
-                    E=E[:dim], chi=None if chi is None else chi[:, :dim], qp=qe, qp_weight=qw)
+                    E=E[:dim], chi=None if chi is None else chi[:, :dim], qp=qe, qp_weight=qw,
+                    packed=(pe, pv, no, nv, nmom_max))
+
+    # ------------------------------------------------------------------ Green's function
+    def spectral(self, E, chi, omega, delta, per_orbital=False):
+        """A(omega) (and A_p(omega) [nmo][nomega] if per_orbital) from the
+        eigenpairs of H~ (E [dim], chi [nmo][dim], rows may be strided)."""
+        dim = E.shape[0]
+        nmo = chi.shape[0]
+        _check_dev(E, "E", (dim,))
+        _check_dev(omega, "omega", (omega.shape[0],))
+        ld = _check_rows(chi, "chi", nmo, dim)
+        nw = omega.shape[0]
+        A = self._new(nw)
+        Ap = self._new(nmo, nw) if per_orbital else None
+        self._call("gw_spectral", nmo, dim, ld, _ptr(E), _ptr(chi), nw, _ptr(omega), ctypes.c_double(delta),
+                   _ptr(A), _ptr(Ap))
+        return (A, Ap) if per_orbital else A
+
+    def aufbau(self, E, chi, nelec):
+        """Aufbau filling of H~'s eigenstates: dict(rho, nfill, nelec, mu, homo, lumo)."""
+        dim = E.shape[0]
+        nmo = chi.shape[0]
+        _check_dev(E, "E", (dim,))
+        ld = _check_rows(chi, "chi", nmo, dim)
+        rho = self._new(nmo, nmo)
+        info = AufbauInfo()
+        self._call("gw_aufbau", nmo, dim, ld, _ptr(E), _ptr(chi), ctypes.c_double(nelec), _ptr(rho),
+                   ctypes.byref(info))
+        return dict(rho=rho, nfill=info.nfill, nelec=info.nelec, mu=info.mu, homo=info.homo, lumo=info.lumo)
+
+    def zeta_shift(self, poles, fock, nelec, zeta_lo=0.0, zeta_hi=0.0, zeta_tol=0.0):
+        """Electron-number conserving one-shot GW from the output of poles():
+        dict(E, chi, qp, qp_weight, zeta, nfill, nelec, eig_calls)."""
+        pe, pv, no, nv, nmom_max = poles["packed"]
+        nmo = pv.shape[0]
+        _check_dev(fock, "fock", (nmo, nmo))
+        dim_max = nmo * (nmom_max + 2)
+        E, chi = self._new(dim_max), self._new(nmo, dim_max)
+        qe, qw = self._new(nmo), self._new(nmo)
+        zo = ZetaOpts(float(zeta_lo), float(zeta_hi), float(zeta_tol))
+        info = ZetaInfo()
+        self._call("gw_zeta_shift", nmo, nmom_max, no, nv, _ptr(fock), _ptr(pe), _ptr(pv), ctypes.c_double(nelec),
+                   ctypes.byref(zo), _ptr(E), _ptr(chi), _ptr(qe), _ptr(qw), ctypes.byref(info))
+        dim = nmo + no + nv
+        return dict(E=E[:dim], chi=chi[:, :dim], qp=qe, qp_weight=qw, zeta=info.zeta, nfill=info.nfill,
+                    nelec=info.nelec, eig_calls=info.eig_calls)
 
 
 class Batch:

@@ -15,6 +15,7 @@ brute       brute-force references: full TDA/RPA diagonalisation, exact
             Lehmann self-energy moments and the exact upfolded Hamiltonian.
 fsgw        the Fock / chemical-potential self-consistent loop (Alg. 2).
 evgw        the eigenvalue self-consistent loop (App. A, Alg. A1).
+qsgw        the quasiparticle self-consistent loop (Sec. 3.3, App. A Alg. A2).
 naf         natural auxiliary functions (Sec. 2.1, eq. NAF).
 spectral    spectral function, Aufbau filling, Dyson orbitals and the
             electron-number shift of a one-shot calculation (eqs. ret_GF,

@@ -199,6 +199,42 @@ def bench_evgw(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_qsgw(args):
+    """qsGW (SRG) at the c3 size: wall time and iterations of the device loop
+    with FP64 and with mixed self-energy moments (one JSON line; not the
+    headline metric)."""
+    import torch
+    import gwsynth
+    from paper_2504_17439_amd import gwmom
+
+    o, v, A, N = args.nocc, args.nvir, args.naux, args.nmom
+    print(f"[bench] qsgw inputs o={o} v={v} A={A} N={N}", file=sys.stderr, flush=True)
+    eps, L = gwsynth.system(o, v, A, args.seed)
+    h = gwmom.Handle(0)
+    e = torch.from_numpy(eps).to("cuda:0")
+    l = torch.from_numpy(L).to("cuda:0")
+    del L
+    out = {"metric": "qsgw_seconds", "unit": "s", "higher_is_better": False, "n_gpus": 1,
+           "config": {"workload": f"qsGW (SRG s=500), TDA, nocc={o} nvir={v} naux={A} nmom_max={N}",
+                      "tol_ha": 1e-6}}
+    for prec in ("fp64", "mixed"):
+        opts = {"moment_eps": 1e-9} if prec == "mixed" else None
+        h.sigma_moments(e, l, o, N, "tda", prec)       # warm-up (workspace, code objects)
+        torch.cuda.synchronize()
+        print(f"[bench] qsgw {prec}", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        r = h.qsgw(e, l, o, N, "tda", prec, tol=1e-6, max_iter=20, opts=opts, allow_noconv=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        q = r["qp"].cpu().numpy()
+        out[prec] = {"seconds": el, "iterations": r["iterations"], "converged": r["converged"],
+                     "scf_steps": r["scf_steps"], "seconds_per_iteration": el / max(r["iterations"], 1),
+                     "last_change": r["last_change"], "homo_lumo": [float(q[o - 1]), float(q[o])]}
+    out["frontier_diff_mixed_vs_fp64"] = max(abs(out["mixed"]["homo_lumo"][i] - out["fp64"]["homo_lumo"][i])
+                                             for i in range(2))
+    print(json.dumps(out), flush=True)
+
+
 def bench_spectral(args):
     """Green's-function post-processing at the c3 size (one JSON line; not the
     headline metric): mixed self-energy moments and FP64 poles, then the
@@ -267,7 +303,7 @@ def bench_spectral(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="single", choices=["single", "batched", "evgw", "spectral"])
+    ap.add_argument("--workload", default="single", choices=["single", "batched", "evgw", "qsgw", "spectral"])
     ap.add_argument("--nomega", type=int, default=2048, help="spectral: frequencies")
     ap.add_argument("--nsys", type=int, default=64)
     ap.add_argument("--branches", type=int, default=4, help="batched: concurrent per-molecule streams")
@@ -295,6 +331,9 @@ def main():
         return
     if args.workload == "evgw":
         bench_evgw(args)
+        return
+    if args.workload == "qsgw":
+        bench_qsgw(args)
         return
     if args.workload == "spectral":
         bench_spectral(args)

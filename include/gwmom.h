@@ -234,6 +234,51 @@ gw_status gw_naf(gw_handle h, int nocc, int nvir, int naux, const double* L, dou
                  int full_space, double* L_naf, int* nnaf, double* eigenvalues);
 
 /*
+ * Quasiparticle self-consistent GW (Sec. 3.3, App. A Alg. A2).  The state is
+ * the quasiparticle mean field: orbitals C (columns, reference MO basis) and
+ * energies e, from C = 1, e = eps.  One iteration: the self-energy moments
+ * and auxiliary poles (e_l, v_pl) of a one-shot calculation in the basis C
+ * with energies e (screening, precision as in gw_sigma_moments); the static
+ * potential at eps_p = e_p, D_pl = e_p - e_l,
+ *   scheme 0 (SRG, eq. qsgw_se_srg):
+ *     V_pq = sum_l v_pl v_ql (D_pl + D_ql)/(D_pl^2 + D_ql^2) (1 - exp(-(D_pl^2 + D_ql^2) s)),
+ *   scheme 1 (Lorentzian, eq. qsgw_v with the real part of eq. qsgw_se_eta):
+ *     V_pq = 1/2 sum_l v_pl v_ql [D_pl/(D_pl^2 + delta^2) + D_ql/(D_ql^2 + delta^2)];
+ * then the self-consistent field of eq. qp_scf, (f[rho] + C V C^T) C' = C' e',
+ * f[rho] = h + J[rho] - K[rho]/2 with the core Hamiltonian of gw_fsgw
+ * (f[rho0] = diag(eps)), rho = 2 sum_{i<nocc} C'_i C'_i^T, DIIS over the Fock
+ * matrices with the commutator F rho - rho F as error, until the density
+ * changes by less than scf_tol.  Converged when the sorted e change by less
+ * than tol.  The QP energies are the final mean-field energies (unit weights).
+ * Inputs (device): eps [nmo], L [naux][nmo][nmo].  Outputs (device): qp_e [nmo]
+ * ascending; C [nmo][nmo] (C[p][k]: reference orbital p in QP orbital k;
+ * nullable); F [nmo][nmo] = f[rho] + V in the reference basis (nullable);
+ * info host (nullable).  Returns GW_ENOCONV (outputs still written) when
+ * max_iter is reached.  Synchronises the stream.
+ */
+typedef struct {
+    int scheme;        /* 0: SRG [default], 1: Lorentzian */
+    double srg_s;      /* SRG flow parameter s [500 Ha^-2] */
+    double delta;      /* Lorentzian broadening [1e-3 Ha] */
+    double tol;        /* max |change of the sorted mean-field energies| [1e-6 Ha] */
+    int max_iter;      /* [30] */
+    int max_scf;       /* SCF steps per iteration [200] */
+    double scf_tol;    /* max |density change| ending the SCF [1e-10] */
+    int diis_space;    /* [12] */
+} gw_qsgw_opts;
+
+typedef struct {
+    int iterations;    /* self-energy rebuilds */
+    int scf_steps;     /* SCF steps, all iterations */
+    int converged;
+    double last_change;
+} gw_qsgw_info;
+
+gw_status gw_qsgw(gw_handle h, gw_screening screening, int nocc, int nvir, int naux, int nmom_max,
+                  const double* eps, const double* L, gw_precision prec, const gw_opts* opts,
+                  const gw_qsgw_opts* qopts, double* qp_e, double* C, double* F, gw_qsgw_info* info);
+
+/*
  * Spectral function of the upfolded Green's function (eqs. ret_GF, spectrum).
  * From the eigenpairs (E_a, chi) of H~, each pole carrying one broadening
  * delta > 0,

@@ -312,6 +312,26 @@ gw_status gw_naf(gw_handle h, int nocc, int nvir, int naux, const double* L, dou
     return gwm::naf_run(h, nocc, nvir, naux, L, eps_naf, full_space, L_naf, nnaf, eigenvalues);
 }
 
+gw_status gw_qsgw(gw_handle h, gw_screening screening, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                  const double* L, gw_precision prec, const gw_opts* opts, const gw_qsgw_opts* qopts, double* qp_e,
+                  double* C, double* F, gw_qsgw_info* info) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    GW_TRY(validate_common(h, nocc, nvir, naux, nmom_max, eps, L));
+    GW_TRY(check_opts(h, prec, opts));
+    if (screening != GW_TDA && screening != GW_RPA) return gwm::set_err(h, GW_EINVAL, "unknown screening");
+    if (nmom_max % 2 == 0 || nmom_max > 15)
+        return gwm::set_err(h, GW_EINVAL, "qsGW: nmom_max must be odd and <= 15");
+    if (prec == GW_MIXED && nmom_max > 11)
+        return gwm::set_err(h, GW_EINVAL, "mixed precision: nmom_max must be <= 11");
+    if (!qp_e) return gwm::set_err(h, GW_EINVAL, "gw_qsgw: qp_e must be non-null");
+    if (qopts && (qopts->scheme < 0 || qopts->scheme > 1 || qopts->srg_s < 0 || qopts->delta < 0 ||
+                  qopts->tol < 0 || qopts->max_iter < 0 || qopts->max_scf < 0 || qopts->scf_tol < 0 ||
+                  qopts->diis_space < 0 || !std::isfinite(qopts->srg_s) || !std::isfinite(qopts->delta)))
+        return gwm::set_err(h, GW_EINVAL, "gw_qsgw: invalid option");
+    return gwm::qsgw_run(h, screening, nocc, nvir, naux, nmom_max, eps, L, prec, opts, qopts, qp_e, C, F, info);
+}
+
 gw_status gw_spectral(gw_handle h, int nmo, int dim, int ld_chi, const double* E, const double* chi, int nomega,
                       const double* omega, double delta, double* A, double* A_orb) {
     if (!h) return GW_EINVAL;

@@ -39,18 +39,6 @@ gw_status blas_st(Handle* h, rocblas_status st, const char* what) {
     return GW_OK;
 }
 
-// Row-major batched C_b = op(A_b) op(B_b) (strides in elements, 0 = shared operand).
-gw_status gemm_rm_batched(Handle* h, bool ta, bool tb, int m, int n, int k, const double* A, int lda, long sA,
-                          const double* B, int ldb, long sB, double* C, int ldc, long sC, int batch) {
-    const double one = 1.0, zero = 0.0;
-    rocblas_operation oa = ta ? rocblas_operation_transpose : rocblas_operation_none;
-    rocblas_operation ob = tb ? rocblas_operation_transpose : rocblas_operation_none;
-    return blas_st(h,
-                   rocblas_dgemm_strided_batched(h->blas, ob, oa, n, m, k, &one, B, ldb, sB, A, lda, sA, &zero, C,
-                                                 ldc, sC, batch),
-                   "rocblas_dgemm_strided_batched");
-}
-
 __global__ void set_diag_kernel(int M, const double* __restrict__ d, double s, int nlead, double* __restrict__ X) {
     // X = diag(d) (d non-null) or diag(s * 1_{p < nlead})
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -81,7 +69,21 @@ __global__ void phys_weight_kernel(int dim, int M, const double* __restrict__ H,
 }
 
 // J = sum_P L_P tr(L_P rho),  K = sum_P L_P rho L_P  for L [A][M][M] (each L_P symmetric).
-gw_status jk(Handle* h, int A, int M, const double* L, const double* rho, double* J, double* K, double* T,
+}  // namespace
+
+// Row-major batched C_b = op(A_b) op(B_b) (strides in elements, 0 = shared operand).
+gw_status gemm_rm_batched(Handle* h, bool ta, bool tb, int m, int n, int k, const double* A, int lda, long sA,
+                          const double* B, int ldb, long sB, double* C, int ldc, long sC, int batch) {
+    const double one = 1.0, zero = 0.0;
+    rocblas_operation oa = ta ? rocblas_operation_transpose : rocblas_operation_none;
+    rocblas_operation ob = tb ? rocblas_operation_transpose : rocblas_operation_none;
+    return blas_st(h,
+                   rocblas_dgemm_strided_batched(h->blas, ob, oa, n, m, k, &one, B, ldb, sB, A, lda, sA, &zero, C,
+                                                 ldc, sC, batch),
+                   "rocblas_dgemm_strided_batched");
+}
+
+gw_status fock_jk(Handle* h, int A, int M, const double* L, const double* rho, double* J, double* K, double* T,
              double* v) {
     const long M2 = (long)M * M;
     const double one = 1.0, zero = 0.0;
@@ -95,68 +97,6 @@ gw_status jk(Handle* h, int A, int M, const double* L, const double* rho, double
     GW_TRY(gemm_rm_batched(h, false, false, M, M, M, rho, M, 0, L, M, M2, T, M, M2, A));
     return gemm_rowmajor(h, true, false, M, M, A * M, 1.0, T, M, L, M, 0.0, K, M);
 }
-
-// Pulay extrapolation over the last `space` pairs (x_i, e_i): sum_i c_i x_i with
-// sum_i c_i = 1 minimising |sum_i c_i e_i|^2.  Host vectors of length n.
-struct Diis {
-    int space;
-    size_t n;
-    std::vector<std::vector<double>> xs, es;
-    std::vector<double> out;
-
-    void push(const double* x, const double* e) {
-        xs.emplace_back(x, x + n);
-        es.emplace_back(e, e + n);
-        if ((int)xs.size() > space) {
-            xs.erase(xs.begin());
-            es.erase(es.begin());
-        }
-    }
-    // Solve the bordered system by Gaussian elimination with partial pivoting;
-    // a vanishing pivot falls back to the newest vector.
-    const double* extrapolate() {
-        const int m = (int)xs.size();
-        const int d = m + 1;
-        std::vector<double> B((size_t)d * d, 0.0), rhs(d, 0.0);
-        for (int i = 0; i < m; ++i)
-            for (int j = 0; j <= i; ++j) {
-                double s = 0.0;
-                for (size_t t = 0; t < n; ++t) s += es[i][t] * es[j][t];
-                B[(size_t)i * d + j] = B[(size_t)j * d + i] = s;
-            }
-        for (int i = 0; i < m; ++i) B[(size_t)m * d + i] = B[(size_t)i * d + m] = -1.0;
-        rhs[m] = -1.0;
-        out.assign(xs.back().begin(), xs.back().end());
-        for (int c = 0; c < d; ++c) {
-            int piv = c;
-            for (int r = c + 1; r < d; ++r)
-                if (std::fabs(B[(size_t)r * d + c]) > std::fabs(B[(size_t)piv * d + c])) piv = r;
-            if (std::fabs(B[(size_t)piv * d + c]) < 1e-300) return out.data();
-            if (piv != c) {
-                for (int k = 0; k < d; ++k) std::swap(B[(size_t)c * d + k], B[(size_t)piv * d + k]);
-                std::swap(rhs[c], rhs[piv]);
-            }
-            for (int r = c + 1; r < d; ++r) {
-                double f = B[(size_t)r * d + c] / B[(size_t)c * d + c];
-                if (f == 0.0) continue;
-                for (int k = c; k < d; ++k) B[(size_t)r * d + k] -= f * B[(size_t)c * d + k];
-                rhs[r] -= f * rhs[c];
-            }
-        }
-        std::vector<double> coef(d);
-        for (int r = d - 1; r >= 0; --r) {
-            double s = rhs[r];
-            for (int k = r + 1; k < d; ++k) s -= B[(size_t)r * d + k] * coef[k];
-            coef[r] = s / B[(size_t)r * d + r];
-        }
-        std::fill(out.begin(), out.end(), 0.0);
-        for (int i = 0; i < m; ++i)
-            for (size_t t = 0; t < n; ++t) out[t] += coef[i] * xs[i][t];
-        return out.data();
-    }
-};
-
-}  // namespace
 
 gw_status zeta_trace(Handle* h, ZetaSearch& s, double z, double nelec, double* tr, int* nfill) {
     GW_TRY(upfold_eigh(h, s.M, s.np, s.F, s.pole_e, z, s.pole_v, s.ldv, s.H, s.w, s.work, s.info));
@@ -292,7 +232,7 @@ gw_status fsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
     hipLaunchKernelGGL(set_diag_kernel, dim3(nbk(M2)), dim3(256), 0, h->stream, M, (const double*)nullptr, 2.0, nocc,
                        rho);
     GW_CHECK_LAUNCH(h);
-    GW_TRY(jk(h, A, M, L, rho, J, K, T, jv));
+    GW_TRY(fock_jk(h, A, M, L, rho, J, K, T, jv));
     hipLaunchKernelGGL(set_diag_kernel, dim3(nbk(M2)), dim3(256), 0, h->stream, M, eps, 0.0, 0, tmp);
     GW_CHECK_LAUNCH(h);
     hipLaunchKernelGGL(comb3_kernel, dim3(nbk(M2)), dim3(256), 0, h->stream, M2, tmp, -1.0, J, 0.5, K, hcore);
@@ -355,7 +295,7 @@ gw_status fsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
             GW_TRY(zeta_solve(h, zs, nelec, zeta, zlo, zhi, zeta_tol, &zeta, &tr, &nf));
             // rho = 2 sum_{a < nf} chi_a chi_a^T (physical rows of the lowest nf eigenvectors)
             GW_TRY(gemm_rowmajor(h, true, false, M, M, nf, 2.0, Hh, M + np, Hh, M + np, 0.0, rho, M));
-            GW_TRY(jk(h, A, M, Lc, rho, J, K, T, jv));
+            GW_TRY(fock_jk(h, A, M, Lc, rho, J, K, T, jv));
             hipLaunchKernelGGL(comb3_kernel, dim3(nbk(M2)), dim3(256), 0, h->stream, M2, hc, 1.0, J, -0.5, K, Fn);
             GW_CHECK_LAUNCH(h);
             ++fock_steps;

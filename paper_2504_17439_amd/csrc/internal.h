@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -193,6 +195,77 @@ gw_status poles_lanczos(Handle* h, int nmo, int nmom_max, const double* sigma_oc
 gw_status upfold_eigh(Handle* h, int M, int np, const double* fock, const double* pole_e, double zeta,
                       const double* pole_v, long ldv, double* H, double* w, double* work, int* info);
 
+// Row-major batched C_b = op(A_b) op(B_b) (strides in elements, 0 = shared operand).
+gw_status gemm_rm_batched(Handle* h, bool ta, bool tb, int m, int n, int k, const double* A, int lda, long sA,
+                          const double* B, int ldb, long sB, double* C, int ldc, long sC, int batch);
+
+// Density-fitted Coulomb and exchange matrices of a density rho (M x M):
+// J_pq = sum_P L[P][p][q] sum_rs L[P][r][s] rho_rs, K_pq = sum_P (L_P rho L_P)_pq.
+// Scratch: T [A][M][M], v [A].
+gw_status fock_jk(Handle* h, int A, int M, const double* L, const double* rho, double* J, double* K, double* T,
+                  double* v);
+
+// Pulay extrapolation over the last `space` pairs (x_i, e_i): sum_i c_i x_i with
+// sum_i c_i = 1 minimising |sum_i c_i e_i|^2.  Host vectors of length n.
+struct Diis {
+    int space;
+    size_t n;
+    std::vector<std::vector<double>> xs, es;
+    std::vector<double> out;
+
+    void push(const double* x, const double* e) {
+        xs.emplace_back(x, x + n);
+        es.emplace_back(e, e + n);
+        if ((int)xs.size() > space) {
+            xs.erase(xs.begin());
+            es.erase(es.begin());
+        }
+    }
+    // Solve the bordered system by Gaussian elimination with partial pivoting;
+    // a vanishing pivot falls back to the newest vector.
+    const double* extrapolate() {
+        const int m = (int)xs.size();
+        const int d = m + 1;
+        std::vector<double> B((size_t)d * d, 0.0), rhs(d, 0.0);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j <= i; ++j) {
+                double s = 0.0;
+                for (size_t t = 0; t < n; ++t) s += es[i][t] * es[j][t];
+                B[(size_t)i * d + j] = B[(size_t)j * d + i] = s;
+            }
+        for (int i = 0; i < m; ++i) B[(size_t)m * d + i] = B[(size_t)i * d + m] = -1.0;
+        rhs[m] = -1.0;
+        out.assign(xs.back().begin(), xs.back().end());
+        for (int c = 0; c < d; ++c) {
+            int piv = c;
+            for (int r = c + 1; r < d; ++r)
+                if (std::fabs(B[(size_t)r * d + c]) > std::fabs(B[(size_t)piv * d + c])) piv = r;
+            if (std::fabs(B[(size_t)piv * d + c]) < 1e-300) return out.data();
+            if (piv != c) {
+                for (int k = 0; k < d; ++k) std::swap(B[(size_t)c * d + k], B[(size_t)piv * d + k]);
+                std::swap(rhs[c], rhs[piv]);
+            }
+            for (int r = c + 1; r < d; ++r) {
+                double f = B[(size_t)r * d + c] / B[(size_t)c * d + c];
+                if (f == 0.0) continue;
+                for (int k = c; k < d; ++k) B[(size_t)r * d + k] -= f * B[(size_t)c * d + k];
+                rhs[r] -= f * rhs[c];
+            }
+        }
+        std::vector<double> coef(d);
+        for (int r = d - 1; r >= 0; --r) {
+            double s = rhs[r];
+            for (int k = r + 1; k < d; ++k) s -= B[(size_t)r * d + k] * coef[k];
+            coef[r] = s / B[(size_t)r * d + r];
+        }
+        std::fill(out.begin(), out.end(), 0.0);
+        for (int i = 0; i < m; ++i)
+            for (size_t t = 0; t < n; ++t) out[t] += coef[i] * xs[i][t];
+        return out.data();
+    }
+};
+
+
 // Electron-number search over the shift zeta of the auxiliary energies
 // (eq. density, Sec. 3.5).  The system is H~(zeta) as in upfold_eigh; H, w,
 // work, wt (each sized for dim = M + np) and info are device scratch, and
@@ -237,6 +310,10 @@ gw_status aufbau_run(Handle* h, int nmo, int dim, int ld_chi, const double* E, c
 gw_status zeta_shift_run(Handle* h, int nmo, int nmom_max, int npole_occ, int npole_vir, const double* fock,
                          const double* pole_e, const double* pole_v, double nelec, const gw_zeta_opts* zo, double* E,
                          double* chi, double* qp_e, double* qp_w, gw_zeta_info* info);
+
+gw_status qsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                   const double* L, gw_precision prec, const gw_opts* opts, const gw_qsgw_opts* qo, double* qp_e,
+                   double* C, double* F, gw_qsgw_info* info);
 
 gw_status evgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int naux, int nmom_max, const double* eps,
                    const double* L, gw_precision prec, const gw_opts* opts, const gw_evgw_opts* eo, double* qp_e,

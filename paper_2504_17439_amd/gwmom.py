@@ -26,7 +26,7 @@ _STATUS = {GW_EINVAL: "GW_EINVAL", GW_ENOMEM: "GW_ENOMEM", GW_EHIP: "GW_EHIP",
 # every symbol declared in include/gwmom.h
 EXPORTS = ("gw_create", "gw_set_stream", "gw_synchronize", "gw_destroy", "gw_last_error",
            "gw_moments_tda", "gw_moments_rpa", "gw_sigma_moments", "gw_sigma_from_R", "gw_poles",
-           "gw_fsgw", "gw_evgw", "gw_naf", "gw_spectral", "gw_aufbau", "gw_zeta_shift", "gw_batch_create", "gw_batch_run", "gw_batch_info", "gw_batch_destroy",
+           "gw_fsgw", "gw_evgw", "gw_naf", "gw_qsgw", "gw_spectral", "gw_aufbau", "gw_zeta_shift", "gw_batch_create", "gw_batch_run", "gw_batch_info", "gw_batch_destroy",
            "gw_mlp_param_count", "gw_mlp_features", "gw_mlp_forward", "gw_mlp_backward",
            "gw_mlp_adam", "gw_timing_enable", "gw_timing_reset", "gw_timing_read")
 
@@ -64,6 +64,17 @@ class FsgwOpts(ctypes.Structure):
 class FsgwInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("fock_steps", ctypes.c_int), ("eig_calls", ctypes.c_int),
                 ("converged", ctypes.c_int), ("zeta", ctypes.c_double), ("last_dqp", ctypes.c_double)]
+
+
+class QsgwOpts(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int), ("srg_s", ctypes.c_double), ("delta", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("max_scf", ctypes.c_int),
+                ("scf_tol", ctypes.c_double), ("diis_space", ctypes.c_int)]
+
+
+class QsgwInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("scf_steps", ctypes.c_int), ("converged", ctypes.c_int),
+                ("last_change", ctypes.c_double)]
 
 
 class AufbauInfo(ctypes.Structure):
@@ -115,6 +126,7 @@ def load_library(path: str = LIB_PATH):
         "gw_fsgw": ([H, I, I, I, I, I, P, P, P, I, P, P, P, P, P, P], I),
         "gw_evgw": ([H, I, I, I, I, I, P, P, I, P, P, P, P, P], I),
         "gw_naf": ([H, I, I, I, P, D, I, P, ctypes.POINTER(I), P], I),
+        "gw_qsgw": ([H, I, I, I, I, I, P, P, I, P, P, P, P, P, P], I),
         "gw_spectral": ([H, I, I, I, P, P, I, P, D, P, P], I),
         "gw_aufbau": ([H, I, I, I, P, P, D, P, P], I),
         "gw_zeta_shift": ([H, I, I, I, I, P, P, P, D, P, P, P, P, P, P], I),
@@ -327,6 +339,26 @@ class Handle:
             raise GWError(st, self.lib.gw_last_error(self.h).decode())
         return dict(qp=qe, qp_weight=qw, iterations=info.iterations, converged=bool(info.converged),
                     last_change=info.last_change)
+
+    def qsgw(self, eps, L, nocc, nmom_max, screening="tda", precision="fp64", scheme="srg", s=500.0, delta=1e-3,
+             tol=1e-6, max_iter=30, scf_tol=1e-10, max_scf=200, diis_space=12, opts=None, allow_noconv=False):
+        """Quasiparticle self-consistent loop; returns dict(qp, C, F, iterations,
+        scf_steps, converged, last_change)."""
+        naux, nmo = L.shape[0], L.shape[1]
+        _check_dev(eps, "eps", (nmo,))
+        _check_dev(L, "L", (naux, nmo, nmo))
+        qe, C, F = self._new(nmo), self._new(nmo, nmo), self._new(nmo, nmo)
+        qo = QsgwOpts({"srg": 0, "lorentzian": 1}[scheme], float(s), float(delta), float(tol), int(max_iter),
+                      int(max_scf), float(scf_tol), int(diis_space))
+        info = QsgwInfo()
+        scr = GW_TDA if screening == "tda" else GW_RPA
+        self._sync_stream()
+        st = self.lib.gw_qsgw(self.h, scr, nocc, nmo - nocc, naux, nmom_max, _ptr(eps), _ptr(L), _prec(precision),
+                              _opts(opts), ctypes.byref(qo), _ptr(qe), _ptr(C), _ptr(F), ctypes.byref(info))
+        if st != GW_OK and not (st == GW_ENOCONV and allow_noconv):
+            raise GWError(st, self.lib.gw_last_error(self.h).decode())
+        return dict(qp=qe, C=C, F=F, iterations=info.iterations, scf_steps=info.scf_steps,
+                    converged=bool(info.converged), last_change=info.last_change)
 
     # ------------------------------------------------------------------ batches
     def batch(self, systems, nmom_max, screening="tda", precision="mixed", opts=None, bopts=None):

@@ -716,6 +716,19 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
         }
     }
     double* dst = g.part + (((long)sector * g.nt + n) * g.nsplit_total + g.split_off + split) * M2;
+    // read every old value before the first store (the stores could alias
+    // the later loads as far as the compiler knows)
+    double old[4][2][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int col = min(n0 + wn + j * 16 + lr, M - 1);
+                const int row = min(m0 + wm + i * 16 + 4 * lk + r, M - 1);
+                old[i][j][r] = dst[(long)row * M + col];
+            }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -726,7 +739,7 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
             for (int r = 0; r < 4; ++r) {
                 int row = m0 + wm + i * 16 + 4 * lk + r;
                 if (row >= M) continue;
-                dst[(long)row * M + col] += acc64[i][j][r];
+                dst[(long)row * M + col] = old[i][j][r] + acc64[i][j][r];
             }
         }
     // the next item of a persistent work group refills buffer 0: every wave
@@ -895,12 +908,38 @@ __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int spl
                 }
         }
     }
-    // combine the weights and scale by 2^(e_row + e_col) once, then the epilogue
+    // combine the weights and scale by 2^(e_row + e_col) once, then the
+    // epilogue.  Every input of the epilogue is loaded before the first
+    // store: the stores could alias those arrays as far as the compiler
+    // knows, so interleaved loads would each wait for a memory round trip.
+    int ec[2], er[4][4];
+    double dv[2], xin[2][4][4];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int col = min(n0 + wn + j * 16 + lr, g.N - 1);
+        ec[j] = g.eB[col];
+        dv[j] = g.Xout ? g.Dv[col] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) er[i][r] = g.eA[min(m0 + wm + i * 16 + 4 * lk + r, g.M - 1)];
+    if (g.Xout) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int col = min(n0 + wn + j * 16 + lr, g.N - 1);
+                    const int row = min(m0 + wm + i * 16 + 4 * lk + r, g.M - 1);
+                    xin[j][i][r] = g.Xin[(long)row * g.N + col];
+                }
+    }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int col = n0 + wn + j * 16 + lr;
         if (col >= g.N) continue;
-        const int ec = g.eB[col];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -910,9 +949,9 @@ __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int spl
                 double z = 0.0;
 #pragma unroll
                 for (int w = NW - 1; w >= 0; --w) z += (double)acc[w][i][j][r] * wscale(w);
-                const double c = ldexp(z, g.eA[row] + ec + g.eshift);
+                const double c = ldexp(z, er[i][r] + ec[j] + g.eshift);
                 const long o = (long)row * g.N + col;
-                if (g.Xout) g.Xout[o] = g.Dv[col] * g.Xin[o] + g.alpha * c;
+                if (g.Xout) g.Xout[o] = dv[j] * xin[j][i][r] + g.alpha * c;
                 else g.part[(long)split * g.M * g.N + o] = c;
             }
     }

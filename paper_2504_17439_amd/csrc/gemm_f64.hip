@@ -164,9 +164,33 @@ __global__ __launch_bounds__(NTHR, 2) void gemm_f64_kernel(GemmF64 g, int tiles_
         cur ^= 1;
     }
 
-    // --- epilogue: lane holds rows (lane>>4) + 4r, column lane&15 of each 16x16 block
+    // --- epilogue: lane holds rows (lane>>4) + 4r, column lane&15 of each 16x16 block.
+    // Per row block i, every value the epilogue reads is loaded before its
+    // first store: the stores could alias those arrays as far as the
+    // compiler knows, so interleaved loads would each wait for a round trip.
+    const bool partial = g.epi == EPI_PARTIAL;
+    const bool rd = partial ? g.accumulate : (g.X != nullptr);
+    double dgc[4], csc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = min(n0 + wn + j * 16 + lrow, g.N - 1);
+        dgc[j] = (!partial && g.X && g.dg) ? g.dg[col] : 1.0;
+        csc[j] = (!partial && g.cs) ? g.cs[col] : 1.0;
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
+        double in[4][4];
+        if (rd) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int col = min(n0 + wn + j * 16 + lrow, g.N - 1);
+                    const int row = min(m0 + wm + i * 16 + lk + 4 * r, g.M - 1);
+                    in[j][r] = partial ? g.C[((long)batch * g.nsplit + split) * g.c_ps + (long)row * g.ldc + col]
+                                       : g.X[(long)batch * g.x_bs + (long)row * g.ldx + col];
+                }
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             int col = n0 + wn + j * 16 + lrow;
@@ -176,18 +200,13 @@ __global__ __launch_bounds__(NTHR, 2) void gemm_f64_kernel(GemmF64 g, int tiles_
                 int row = m0 + wm + i * 16 + lk + 4 * r;
                 if (row >= g.M) continue;
                 double v = acc[i][j][r];
-                if (g.epi == EPI_PARTIAL) {
+                if (partial) {
                     double* dst = g.C + ((long)batch * g.nsplit + split) * g.c_ps + (long)row * g.ldc + col;
-                    if (g.accumulate) *dst += v;
-                    else *dst = v;
+                    *dst = rd ? in[j][r] + v : v;
                 } else {
                     v *= g.alpha;
-                    if (g.X) {
-                        double xv = g.X[(long)batch * g.x_bs + (long)row * g.ldx + col];
-                        v += g.dg ? xv * g.dg[col] : xv;
-                    }
-                    if (g.cs) v *= g.cs[col];
-                    g.C[(long)batch * g.c_bs + (long)row * g.ldc + col] = v;
+                    if (rd) v += in[j][r] * dgc[j];
+                    g.C[(long)batch * g.c_bs + (long)row * g.ldc + col] = v * csc[j];
                 }
             }
         }

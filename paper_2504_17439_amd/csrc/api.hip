@@ -222,6 +222,7 @@ gw_status gw_moments_rpa(gw_handle h, int nocc, int nvir, int naux, int nmom_max
     GW_TRY(validate_common(h, nocc, nvir, naux, nmom_max, eps, L));
     GW_TRY(check_opts(h, prec, opts));
     if (!R) return gwm::set_err(h, GW_EINVAL, "R must be non-null");
+    if (prec == GW_MIXED && !eta) return gwm::rpa_moments_mixed(h, nocc, nvir, naux, nmom_max, eps, L, opts, R);
     return gwm::rpa_moments_f64(h, nocc, nvir, naux, nmom_max, eps, L, opts, R, eta);
 }
 
@@ -256,6 +257,8 @@ gw_status gw_sigma_moments(gw_handle h, gw_screening screening, int nocc, int nv
         GW_TRY(gwm::tda_moments_mixed(h, nocc, nvir, naux, nmom_max, eps, L, R));
     else if (screening == GW_TDA)
         GW_TRY(gwm::tda_moments_f64(h, nocc, nvir, naux, nmom_max, eps, L, R, nullptr));
+    else if (prec == GW_MIXED)
+        GW_TRY(gwm::rpa_moments_mixed(h, nocc, nvir, naux, nmom_max, eps, L, opts, R));
     else
         GW_TRY(gwm::rpa_moments_f64(h, nocc, nvir, naux, nmom_max, eps, L, opts, R, nullptr));
     if (prec == GW_MIXED)

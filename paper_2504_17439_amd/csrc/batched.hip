@@ -171,6 +171,8 @@ gw_status molecule_work(gw_batch_s* b, Handle* hb, int i) {
         GW_TRY(tda_moments_mixed(hb, s.nocc, s.nvir, s.naux, b->nmom_max, s.eps, s.L, m.R));
     else if (b->screening == GW_TDA)
         GW_TRY(tda_moments_f64(hb, s.nocc, s.nvir, s.naux, b->nmom_max, s.eps, s.L, m.R, nullptr));
+    else if (b->prec == GW_MIXED)
+        GW_TRY(rpa_moments_mixed(hb, s.nocc, s.nvir, s.naux, b->nmom_max, s.eps, s.L, opts, m.R));
     else
         GW_TRY(rpa_moments_f64(hb, s.nocc, s.nvir, s.naux, b->nmom_max, s.eps, s.L, opts, m.R, nullptr));
     if (b->prec == GW_MIXED) GW_TRY(mixed_prep(hb, s.naux, m.nmo, nt, s.L, m.R, m.Ld, m.eL, m.Rd, m.eR));

@@ -70,6 +70,7 @@ gw_status evgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
         // screening on eps_W, convolution on eps_G
         if (screening == GW_TDA && prec == GW_MIXED) GW_TRY(tda_moments_mixed(h, nocc, nvir, naux, nmom_max, eW, L, R));
         else if (screening == GW_TDA) GW_TRY(tda_moments_f64(h, nocc, nvir, naux, nmom_max, eW, L, R, nullptr));
+        else if (prec == GW_MIXED) GW_TRY(rpa_moments_mixed(h, nocc, nvir, naux, nmom_max, eW, L, opts, R));
         else GW_TRY(rpa_moments_f64(h, nocc, nvir, naux, nmom_max, eW, L, opts, R, nullptr));
         if (prec == GW_MIXED) GW_TRY(sigma_from_R_mixed(h, nocc, nvir, naux, nmom_max, eG, L, R, opts, so, sv));
         else GW_TRY(sigma_from_R_f64(h, nocc, nvir, naux, nmom_max, eG, L, R, opts, so, sv));

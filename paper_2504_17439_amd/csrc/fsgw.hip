@@ -274,6 +274,7 @@ gw_status fsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
         // self-energy moments and auxiliary poles in this basis
         if (screening == GW_TDA && prec == GW_MIXED) GW_TRY(tda_moments_mixed(h, nocc, nvir, A, nmom_max, ecur, Lc, R));
         else if (screening == GW_TDA) GW_TRY(tda_moments_f64(h, nocc, nvir, A, nmom_max, ecur, Lc, R, nullptr));
+        else if (prec == GW_MIXED) GW_TRY(rpa_moments_mixed(h, nocc, nvir, A, nmom_max, ecur, Lc, opts, R));
         else GW_TRY(rpa_moments_f64(h, nocc, nvir, A, nmom_max, ecur, Lc, opts, R, nullptr));
         if (prec == GW_MIXED) GW_TRY(sigma_from_R_mixed(h, nocc, nvir, A, nmom_max, ecur, Lc, R, opts, so, sv));
         else GW_TRY(sigma_from_R_f64(h, nocc, nvir, A, nmom_max, ecur, Lc, R, opts, so, sv));

@@ -172,6 +172,16 @@ gw_status rpa_moments_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max,
                           const double* eps, const double* L, const gw_opts* opts,
                           double* R, double* eta);
 
+// eta~^{(0)} [naux][nocc*nvir] of RPA screening by the FP64 quadrature (Sec. 2.2),
+// from the gathered V [naux][ov] and D [ov].
+gw_status rpa_eta0(Handle* h, int nocc, int nvir, int naux, const double* eps, const double* V, const double* D,
+                   const gw_opts* opts, double* eta0);
+
+// RPA density-response moments with the recursion as int8 digit products
+// (eta~^{(0)} from the FP64 quadrature): R [nmom_max+1][naux][naux].
+gw_status rpa_moments_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                            const double* L, const gw_opts* opts, double* R);
+
 gw_status poles_f64(Handle* h, int nmo, int nmom_max, const double* sigma_occ,
                     const double* sigma_vir, const double* fock, const gw_opts* opts,
                     int* npole_occ, int* npole_vir, double* pole_e, double* pole_v,

@@ -284,6 +284,11 @@ static gw_status rpa_eta0_f64(Handle* h, int nocc, int nvir, int naux, const dou
     return GW_OK;
 }
 
+gw_status rpa_eta0(Handle* h, int nocc, int nvir, int naux, const double* eps, const double* V, const double* D,
+                   const gw_opts* opts, double* eta0) {
+    return rpa_eta0_f64(h, nocc, nvir, naux, eps, V, D, opts, eta0);
+}
+
 gw_status rpa_moments_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
                           const double* L, const gw_opts* opts, double* R, double* eta) {
     const long ov = (long)nocc * nvir;

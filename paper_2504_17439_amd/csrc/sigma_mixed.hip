@@ -1187,6 +1187,16 @@ gw_status digitise_rows(Handle* h, long rows, long cols, int kpad, const double*
     return GW_OK;
 }
 
+// RPA recursion operands: X1 = V o D (the odd chain's start) and D2 = D o D.
+__global__ void rpa_prep_kernel(long rows, long ov, const double* __restrict__ V, const double* __restrict__ D,
+                                double* __restrict__ X1, double* __restrict__ D2) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * ov) return;
+    const double d = D[i % ov];
+    X1[i] = V[i] * d;
+    if (i < ov) D2[i] = d * d;
+}
+
 }  // namespace
 
 gw_status tda_moments_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps, const double* L,
@@ -1279,6 +1289,89 @@ gw_status tda_moments_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_ma
             g.M = naux; g.N = (int)ov; g.nkb = Ap / MK; g.nsplit = 1; g.sym = 0;
             g.Xout = X; g.Xin = X; g.Dv = D; g.alpha = 2.0;
             GW_TRY(launch_dgemm(h, g, "recur_rv"));
+        }
+    }
+    return GW_OK;
+}
+
+// RPA (Sec. 2.2): eta~^{(0)} by the FP64 quadrature, eta~^{(1)} = V o D, then on
+// the even and odd chains R_n = eta~^{(n)} V^T and
+//   eta~^{(n+2)} = D^2 o eta~^{(n)} + 4 R_n (V o D),
+// both products as int8 digit GEMMs: R_n on the upper tiles (thirteen digit
+// products, mirrored, as the FP64 form), the update with the row digits of R_n
+// against the digits of V o D transposed (k = P) and the D^2 / 4 epilogue.
+gw_status rpa_moments_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                            const double* L, const gw_opts* opts, double* R) {
+    const long ov = (long)nocc * nvir;
+    const int Kp = (int)((ov + MK - 1) / MK * MK);
+    const int Ap = mixed_Ap(naux);
+    if (ov * 64 >= (1L << 31) || (long)naux * 64 >= (1L << 31))
+        return set_err(h, GW_EINVAL, "mixed precision: nocc*nvir too large for the digit recursion");
+    if (Ap > KEXACT) return set_err(h, GW_EINVAL, "mixed precision: naux must be <= 32768 for the digit recursion");
+    const long asz = (long)naux * naux;
+    const long xsz = (long)naux * ov;
+    double* V = (double*)ws_get(h, WS_V, sizeof(double) * xsz);
+    double* D = (double*)ws_get(h, WS_D, sizeof(double) * ov);
+    double* X[2] = {(double*)ws_get(h, WS_X0, sizeof(double) * xsz), (double*)ws_get(h, WS_X1, sizeof(double) * xsz)};
+    i8* VDt = (i8*)ws_get(h, WS_RC0, sizeof(i8) * ND * ov * Ap);
+    i8* Xd = (i8*)ws_get(h, WS_RC1, sizeof(i8) * ND * (long)naux * Kp);
+    i8* Vd = (i8*)ws_get(h, WS_RC2, sizeof(i8) * ND * (long)naux * Kp);
+    i8* Rk = (i8*)ws_get(h, WS_RC3, sizeof(i8) * ND * (long)naux * Ap);
+    int* ex = (int*)ws_get(h, WS_RC4, sizeof(int) * (ov + 3L * naux));
+    double* D2 = (double*)ws_get(h, WS_MISC, sizeof(double) * (ov + 16));
+    int ncu = 256;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device);
+    const int tiles = mixed_upper_tiles(naux);
+    const int nkbX = Kp / MK;
+    const int S = std::max((nkbX + KEXACT / MK - 1) / (KEXACT / MK),
+                           std::max(1, std::min(nkbX, (3 * ncu + tiles - 1) / tiles)));
+    double* part = (double*)ws_get(h, WS_RC5, sizeof(double) * S * asz);
+    if (!V || !D || !X[0] || !X[1] || !VDt || !Xd || !Vd || !Rk || !ex || !D2 || !part) return GW_ENOMEM;
+    int *eVDt = ex, *eX = ex + ov, *eV = eX + naux, *eR = eV + naux;
+    GW_TRY(gather_ov(h, nocc, nvir, naux, eps, L, V, D));
+    GW_TRY(rpa_eta0(h, nocc, nvir, naux, eps, V, D, opts, X[0]));
+    hipLaunchKernelGGL(rpa_prep_kernel, dim3(nb256(xsz)), dim3(256), 0, h->stream, (long)naux, ov, V, D, X[1], D2);
+    GW_CHECK_LAUNCH(h);
+    {
+        KTimer tm(h, "recur_digits");
+        // the update's B operand: V o D, transposed digit planes (k = P, per-column scales)
+        hipLaunchKernelGGL(col_exp_kernel, dim3(nb256(ov)), dim3(256), 0, h->stream, naux, ov, X[1], eVDt);
+        hipLaunchKernelGGL(digits_lt_kernel, dim3((unsigned)((ov + 31) / 32), (unsigned)((Ap + 31) / 32)), dim3(256),
+                           0, h->stream, naux, ov, Ap, X[1], eVDt, VDt);
+        GW_CHECK_LAUNCH(h);
+        // the B operand of R_n = eta~^{(n)} V^T: row digit planes of V (k = ia)
+        GW_TRY(digitise_rows(h, naux, ov, Kp, V, eV, Vd));
+        tm.stop();
+    }
+    for (int n = 0; n <= nmom_max; ++n) {
+        double* Xn = X[n & 1];
+        {
+            KTimer tm(h, "recur_digits");
+            GW_TRY(digitise_rows(h, naux, ov, Kp, Xn, eX, Xd));
+            tm.stop();
+        }
+        DgemmArgs g{};
+        g.M = g.N = naux;
+        g.nkb = nkbX;
+        g.nsplit = S;
+        g.sym = 1;
+        g.part = part;
+        g.A = Xd; g.aplane = (long)naux * Kp; g.arows = naux; g.eA = eX;
+        g.B = Vd; g.bplane = (long)naux * Kp; g.brows = naux; g.eB = eV;
+        GW_TRY(launch_dgemm(h, g, "recur_xvt"));
+        GW_TRY(reduce_splits(h, part, S, asz, 1, naux, naux, naux, true, 1.0, 0.0, R + n * asz, asz, naux));
+        if (n + 2 <= nmom_max) {
+            {
+                KTimer tm(h, "recur_digits");
+                GW_TRY(digitise_rows(h, naux, naux, Ap, R + n * asz, eR, Rk));
+                tm.stop();
+            }
+            DgemmArgs u{};
+            u.A = Rk; u.aplane = (long)naux * Ap; u.arows = naux; u.eA = eR;
+            u.B = VDt; u.bplane = ov * Ap; u.brows = (int)ov; u.eB = eVDt;
+            u.M = naux; u.N = (int)ov; u.nkb = Ap / MK; u.nsplit = 1; u.sym = 0;
+            u.Xout = Xn; u.Xin = Xn; u.Dv = D2; u.alpha = 4.0;
+            GW_TRY(launch_dgemm(h, u, "recur_rv"));
         }
     }
     return GW_OK;

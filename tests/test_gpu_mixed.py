@@ -51,6 +51,8 @@ def rel(a, b):
     (12, 30, 150, 11, 5, "tda"),
     (3, 45, 260, 7, 4, "tda"),
     (6, 20, 50, 5, 1, "rpa"),
+    (7, 37, 131, 7, 3, "rpa"),
+    (12, 30, 150, 11, 5, "rpa"),
 ])
 def test_mixed_sigma_matches_oracle(handle, o, v, A, N, seed, scr):
     print(f"\n[case] mixed sigma {scr} o={o} v={v} A={A} N={N} seed={seed}", flush=True)
@@ -79,6 +81,27 @@ def test_mixed_tda_moments_match_oracle(handle, o, v, A, N, seed):
     V, D = ogw.particle_hole(eps, L, o)
     R_ref = ogw.w_core(ogw.tda_eta(V, D, N), V)
     R = host(handle.moments(dev(eps), dev(L), o, N, "tda", precision="mixed"))
+    for n in range(N + 1):
+        assert rel(R[n], R_ref[n]) < MIXED_TOL, (n, rel(R[n], R_ref[n]))
+        assert np.array_equal(R[n], R[n].T)
+
+
+@pytest.mark.parametrize("o,v,A,N,seed", [
+    (1, 1, 1, 1, 0),
+    (6, 20, 50, 5, 1),
+    (7, 37, 131, 7, 3),
+    (12, 30, 150, 11, 5),
+    (3, 45, 260, 7, 4),
+])
+def test_mixed_rpa_moments_match_oracle(handle, o, v, A, N, seed):
+    """The RPA recursion as digit products (eta~^{(0)} from the FP64
+    quadrature): every R_n within the format's tolerance of the oracle's
+    recursion on the same 48-point rule, and exactly symmetric."""
+    print(f"\n[case] mixed rpa moments o={o} v={v} A={A} N={N} seed={seed}", flush=True)
+    eps, L = gwsynth.system(o, v, A, seed)
+    V, D = ogw.particle_hole(eps, L, o)
+    R_ref = ogw.w_core(ogw.rpa_eta(V, D, N, nquad=48), V)
+    R = host(handle.moments(dev(eps), dev(L), o, N, "rpa", precision="mixed"))
     for n in range(N + 1):
         assert rel(R[n], R_ref[n]) < MIXED_TOL, (n, rel(R[n], R_ref[n]))
         assert np.array_equal(R[n], R[n].T)

@@ -235,6 +235,47 @@ def bench_qsgw(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_scaling(args):
+    """Time per self-energy moment set against system size (the paper's
+    scaling study: TDA, N = 7, growing molecules; here synthetic systems with
+    nocc = nmo/5 and naux = 3 nmo), mixed and FP64, with the fitted exponent
+    of time against nmo (one JSON line; not the headline metric)."""
+    import numpy as np
+    import torch
+    import gwsynth
+    from paper_2504_17439_amd import gwmom
+
+    h = gwmom.Handle(0)
+    sizes = [100, 150, 200, 300, 400, 500]
+    N = 7
+    rows = []
+    for M in sizes:
+        o, v, A = M // 5, M - M // 5, 3 * M
+        print(f"[bench] scaling nmo={M} nocc={o} naux={A}", file=sys.stderr, flush=True)
+        e, l = gwsynth.system_device(o, v, A, args.seed)
+        row = {"nmo": M, "nocc": o, "naux": A}
+        for prec in ("mixed", "fp64"):
+            for _ in range(max(args.warmup, 1)):
+                h.sigma_moments(e, l, o, N, "tda", prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                h.sigma_moments(e, l, o, N, "tda", prec)
+            torch.cuda.synchronize()
+            row[f"{prec}_ms"] = (time.perf_counter() - t0) / args.steps * 1e3
+        rows.append(row)
+        del e, l
+    out = {"metric": "sigma_set_ms_vs_nmo", "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+           "config": {"workload": "TDA self-energy moment sets, nmom_max=7, nocc=nmo/5, naux=3 nmo, synthetic"},
+           "rows": rows}
+    x = np.log([r["nmo"] for r in rows])
+    for prec in ("mixed", "fp64"):
+        y = np.log([r[f"{prec}_ms"] for r in rows])
+        out[f"{prec}_exponent_all"] = float(np.polyfit(x, y, 1)[0])
+        out[f"{prec}_exponent_nmo_ge_200"] = float(np.polyfit(x[2:], y[2:], 1)[0])
+    print(json.dumps(out), flush=True)
+
+
 def bench_spectral(args):
     """Green's-function post-processing at the c3 size (one JSON line; not the
     headline metric): mixed self-energy moments and FP64 poles, then the
@@ -303,7 +344,7 @@ def bench_spectral(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="single", choices=["single", "batched", "evgw", "qsgw", "spectral"])
+    ap.add_argument("--workload", default="single", choices=["single", "batched", "evgw", "qsgw", "spectral", "scaling"])
     ap.add_argument("--nomega", type=int, default=2048, help="spectral: frequencies")
     ap.add_argument("--nsys", type=int, default=64)
     ap.add_argument("--branches", type=int, default=4, help="batched: concurrent per-molecule streams")
@@ -334,6 +375,9 @@ def main():
         return
     if args.workload == "qsgw":
         bench_qsgw(args)
+        return
+    if args.workload == "scaling":
+        bench_scaling(args)
         return
     if args.workload == "spectral":
         bench_spectral(args)

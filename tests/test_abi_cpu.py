@@ -38,3 +38,14 @@ def test_binding_has_no_cpu_fallback():
     assert "oracle" not in src
     for bad in ("torch.linalg", "torch.matmul", "torch.einsum", "numpy"):
         assert bad not in src
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """One GPU: bench.py --gpus N with N > 1 exits with a message before
+    touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr

@@ -362,8 +362,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in the design notes, not implemented)",
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design, not implemented)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
 The paper integrates G_main (Sec. 2.2, eq. Gmain) over the whole real axis
 and the offset term over the positive half axis, each with an exponentially
-convergent rule.  This build reads the rule as an n-point Gauss-Legendre rule
+convergent rule.  The rule is read here as an n-point Gauss-Legendre rule
 on (-1, 1) mapped onto (0, inf) by
 
     z(x) = s (1 + x) / (1 - x),      dz/dx = 2 s / (1 - x)^2,

@@ -13,7 +13,7 @@ L   : [naux][nmo][nmo] three-index factor, symmetric in its last two indices;
 V   : [naux][nocc*nvir], V[P, i*nvir + a] = L[P, i, nocc + a]  (particle-hole block).
 D   : [nocc*nvir],       D[i*nvir + a] = eps[nocc + a] - eps[i]  (eq. energy_differences).
 
-Readings of the paper taken here (each one is listed in the design notes):
+Readings of the paper taken here:
   * the W^{(n)} inside the t-sum of eqs. convolution_occ / convolution_vir
     is read as W^{(t)};
   * the self-energy moments of a closed-shell (spin-restricted) reference

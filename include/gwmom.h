@@ -98,9 +98,13 @@ gw_status gw_moments_tda(gw_handle h, int nocc, int nvir, int naux, int nmom_max
  * RPA density-response moments (Sec. 2.2): eta~^{(0)} = G D^-1 (I - 4 V^T
  * (I + 4 V D^-1 V^T)^-1 V D^-1) with G = G_main + G_offset by opts->nquad-point
  * mapped Gauss-Legendre quadrature, eta~^{(1)} = V D,
- * eta~^{(n)} = eta~^{(n-2)} (D^2 + 4 V^T V D).  Outputs as gw_moments_tda;
- * computed in FP64 for either prec (in GW_MIXED only the self-energy stages
- * of gw_sigma_moments use digit products).
+ * eta~^{(n)} = eta~^{(n-2)} (D^2 + 4 V^T V D).  Outputs as gw_moments_tda.
+ * The quadrature is FP64 for either prec.  GW_MIXED with eta NULL: the
+ * recursion on the even and odd chains, R_n = eta~^{(n)} V^T (upper tiles,
+ * mirrored) and eta~^{(n+2)} = D^2 o eta~^{(n)} + 4 R_n (V o D), uses the
+ * four-digit int8 operands of gw_moments_tda with exact int32 sums combined in
+ * FP64; with eta requested the FP64 form is used.  GW_MIXED needs
+ * naux <= 32768.
  */
 gw_status gw_moments_rpa(gw_handle h, int nocc, int nvir, int naux, int nmom_max,
                          const double* eps, const double* L, gw_precision prec,

@@ -118,8 +118,9 @@ gw_status gw_moments_rpa(gw_handle h, int nocc, int nvir, int naux, int nmom_max
  *   W^{(t)}_{px,qx}  = sum_PQ L[P][p][x] R_t[P][Q] L[Q][q][x]
  * with R_t from the chosen screening.  Outputs (symmetric):
  *   sigma_occ, sigma_vir  [nmom_max+1][nmo][nmo].
- * prec GW_MIXED: both contraction stages (R_t L with the eps-power fold, then
- * the sum over x and P) run on four-digit int8 operands (base 255, one
+ * prec GW_MIXED: the moments R_t as gw_moments_tda / gw_moments_rpa in
+ * GW_MIXED, and both contraction stages (R_t L with the eps-power fold, then
+ * the sum over x and P) on four-digit int8 operands (base 255, one
  * power-of-two scale per row or column) on the integer MFMA with exact int32
  * sums per digit weight, combined in FP64; the folded intermediate is kept as
  * FP32 + BF16 residual.  GW_MIXED needs nmom_max <= 11 and naux <= 4096.

@@ -358,11 +358,14 @@ gw_status gw_zeta_shift(gw_handle h, int nmo, int nmom_max, int npole_occ, int n
  * differences of the density-response recursion (eq. energy_differences).
  * Each iteration runs gw_moments_* (on eps_W), the self-energy moments (on
  * eps_G) and gw_poles with fock = diag(eps) (eq. StaticSE with Sigma_inf = 0),
- * then sets eps_G (unless g0) and eps_W (unless w0) to the QP energies.
+ * then sets eps_G (unless g0) and eps_W (unless w0) to the QP energies, or,
+ * with diis_space > 0, to the Pulay (DIIS) extrapolation over the last
+ * diis_space pairs (QP energies, QP energies - energies they came from).
  * g0 = w0 = 0: evGW; w0 = 1: evGW0 (W of the reference); g0 = w0 = 1: one
- * G0W0 evaluation.  Converged when the QP energy of no quasiparticle-like
- * orbital (QP weight >= 0.9 in both iterations; all orbitals if none is)
- * changes by more than tol between iterations.
+ * G0W0 evaluation.  Converged when, for every quasiparticle-like orbital (QP
+ * weight >= 0.9 in both iterations; all orbitals if none is), the QP energy
+ * differs by at most tol from the energy that went into the iteration (for
+ * the plain loop: its change since the previous iteration).
  * Outputs (device, [nmo]): qp_e, qp_w of the last iteration.  GW_ENOCONV
  * after max_iter iterations (outputs and info still written); GW_ENUMERIC if
  * the QP energies of occupied and virtual orbitals cross (the next screening
@@ -373,12 +376,13 @@ typedef struct {
     int w0;          /* 1: keep eps_W at the reference */
     int max_iter;    /* <= 0 -> 30 */
     double tol;      /* Ha; <= 0 -> 1e-6 */
+    int diis_space;  /* DIIS vectors; 0 -> 12 (the paper's setting), < 0: plain loop */
 } gw_evgw_opts;
 
 typedef struct {
     int iterations;
     int converged;
-    double last_change;  /* largest QP change of the last iteration (vs. the previous one or eps) */
+    double last_change;  /* fixed-point residual of the last iteration (see above) */
 } gw_evgw_info;
 
 gw_status gw_evgw(gw_handle h, gw_screening screening, int nocc, int nvir, int naux,

@@ -14,9 +14,15 @@ eq. quasiparticle_energy_update, and then replaces eps_G (unless g0) and
 eps_W (unless w0) by them.
 
 Readings taken here (the box gives the loop, not its numerics):
-  * convergence: the largest change between two iterations of the QP energy
-    of the orbitals whose QP weight is at least 0.9 in both (all orbitals if
-    none is) is below `tol` (1e-6 Ha); the QP energy of an orbital embedded in
+  * convergence: the largest difference between the QP energies of an
+    iteration and the energies that went into it (for the plain loop: the
+    previous iteration's QP energies), over the orbitals whose QP weight is
+    at least 0.9 in both iterations (all orbitals if none is), is below
+    `tol` (1e-6 Ha);
+  * the updated energies are the Pulay (DIIS, 12 vectors) extrapolation of
+    the QP energies with those differences as error vectors (the paper's
+    self-consistent runs keep a DIIS space of 12); diis_space = 0 gives the
+    plain loop; the QP energy of an orbital embedded in
     a satellite band has no stable assignment and is left out of the test;
     with g0 and w0 both set nothing is updated and the loop is one G0W0
     evaluation;
@@ -27,7 +33,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import gw
+from . import fsgw, gw
 
 
 def ev_step(eps_ref, eps_g, eps_w, L, nocc, nmom_max, screening="tda", nquad=48, scale=None):
@@ -49,18 +55,22 @@ def ev_step(eps_ref, eps_g, eps_w, L, nocc, nmom_max, screening="tda", nquad=48,
 
 
 def evgw(eps, L, nocc, nmom_max, screening="tda", g0=False, w0=False, tol=1e-6, max_iter=30,
-         nquad=48, scale=None, step=None):
+         nquad=48, scale=None, step=None, diis_space=12):
     """Alg. A1.  Returns dict(qp, qp_weight, iterations, converged, history).
     `step` replaces the loop body (same signature as ``ev_step``), e.g. by a
-    brute-force one."""
+    brute-force one.  With diis_space > 0 the updated energies are the Pulay
+    extrapolation (the paper's self-consistent runs keep a DIIS space of 12)
+    over the pairs (QP energies, QP energies - the energies they came from);
+    diis_space = 0 is the plain loop."""
     step = step or (lambda er, eg, ew: ev_step(er, eg, ew, L, nocc, nmom_max, screening, nquad, scale))
     eps = np.asarray(eps, dtype=np.float64)
     eps_g = eps.copy()
     eps_w = eps.copy()
-    prev = eps.copy()
     prev_wt = np.ones_like(eps)
     history = []
     qp = wt = None
+    x = eps.copy()
+    diis = fsgw.DIIS(diis_space) if diis_space > 0 else None
     converged = False
     it = 0
     for it in range(1, max_iter + 1):
@@ -68,18 +78,19 @@ def evgw(eps, L, nocc, nmom_max, screening="tda", g0=False, w0=False, tol=1e-6, 
         qpl = (wt >= 0.9) & (prev_wt >= 0.9)
         if not qpl.any():
             qpl[:] = True
-        change = float(np.abs(qp - prev)[qpl].max())
+        change = float(np.abs(qp - x)[qpl].max())
         history.append(change)
         if g0 and w0:
             converged = True
             break
+        nxt = qp.copy() if diis is None else diis.update(qp, qp - x)
         if not g0:
-            eps_g = qp.copy()
+            eps_g = nxt.copy()
         if not w0:
-            eps_w = qp.copy()
+            eps_w = nxt.copy()
+        x = nxt
         if change < tol:
             converged = True
             break
-        prev = qp.copy()
         prev_wt = wt.copy()
     return dict(qp=qp, qp_weight=wt, iterations=it, converged=converged, history=history)

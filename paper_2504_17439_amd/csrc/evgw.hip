@@ -6,10 +6,14 @@
 // (eq. energy_differences).  Every iteration runs the hot path (moments,
 // self-energy moments, block Lanczos, upfolded Hamiltonian with f =
 // diag(eps_ref), QP assignment by eq. quasiparticle_energy_update) and replaces
-// eps_G and / or eps_W by the QP energies; the loop stops when no
-// quasiparticle-like orbital (QP weight >= 0.9 in both iterations; all
-// orbitals if none is) moved by more than tol: an orbital embedded in a
-// satellite band has no stable QP assignment.
+// eps_G and / or eps_W by the QP energies (or their DIIS extrapolation over
+// the last iterations, error vector = QP energies - input energies, on the
+// host: nmo-vectors); the loop stops when, for every quasiparticle-like
+// orbital (QP weight >= 0.9 in both iterations; all orbitals if none is), the
+// QP energy differs by at most tol from the energy that went into the
+// iteration (the fixed-point residual; for the plain loop the change since
+// the previous iteration): an orbital embedded in a satellite band has no
+// stable QP assignment.
 #include "internal.h"
 
 #include <algorithm>
@@ -35,6 +39,7 @@ gw_status evgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
     const bool g0 = eo && eo->g0, w0 = eo && eo->w0;
     const double tol = (eo && eo->tol > 0) ? eo->tol : 1e-6;
     const int max_iter = (eo && eo->max_iter > 0) ? eo->max_iter : 30;
+    const int diis_space = (eo && eo->diis_space != 0) ? eo->diis_space : 12;
     const int M = nocc + nvir, nt = nmom_max + 1;
     const long M2 = (long)M * M;
     const int cap = M * nt / 2;
@@ -43,7 +48,7 @@ gw_status evgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
 
     double* sig = (double*)ws_get(h, WS_FS2, sizeof(double) * 2 * nt * M2);
     double* pol = (double*)ws_get(h, WS_FS3, sizeof(double) * (2 * cap + (long)M * ldv));
-    double* vec = (double*)ws_get(h, WS_FS4, sizeof(double) * (dim_max + 2 * M + M2));
+    double* vec = (double*)ws_get(h, WS_FS4, sizeof(double) * (dim_max + 3 * M + M2));
     double* R = (double*)ws_get(h, WS_R, sizeof(double) * nt * (long)naux * naux);
     if (!sig || !pol || !vec || !R) return GW_ENOMEM;
     double* so = sig;
@@ -59,9 +64,11 @@ gw_status evgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
     GW_CHECK_LAUNCH(h);
     GW_TRY(copy_f64(h, eG, eps, M));
     GW_TRY(copy_f64(h, eW, eps, M));
-    std::vector<double> prev(M), cur(M), wcur(M), wprev(M, 1.0);
+    std::vector<double> prev(M), cur(M), wcur(M), wprev(M, 1.0), xin(M), err(M), next(M);
     GW_HIP(h, hipMemcpyAsync(prev.data(), eps, sizeof(double) * M, hipMemcpyDeviceToHost, h->stream));
     GW_HIP(h, hipStreamSynchronize(h->stream));
+    xin = prev;                      // the energies the updated set(s) hold
+    Diis diis{std::max(diis_space, 1), (size_t)M, {}, {}, {}};
 
     int it = 0;
     bool converged = false;
@@ -83,27 +90,38 @@ gw_status evgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
         for (int p = 0; p < M; ++p) any = any || (wcur[p] >= 0.9 && wprev[p] >= 0.9);
         change = 0.0;
         for (int p = 0; p < M; ++p)
-            if (!any || (wcur[p] >= 0.9 && wprev[p] >= 0.9)) change = std::max(change, std::fabs(cur[p] - prev[p]));
+            if (!any || (wcur[p] >= 0.9 && wprev[p] >= 0.9)) change = std::max(change, std::fabs(cur[p] - xin[p]));
         if (g0 && w0) {
             converged = true;
             break;
         }
-        if (!g0) GW_TRY(copy_f64(h, eG, qp_e, M));
+        if (diis_space > 0) {
+            for (int p = 0; p < M; ++p) err[p] = cur[p] - xin[p];
+            diis.push(cur.data(), err.data());
+            const double* x = diis.extrapolate();
+            next.assign(x, x + M);
+        } else {
+            next = cur;
+        }
         if (!w0) {
             // the next screening needs D_ia = eps_a - eps_i > 0
-            const double ho = *std::max_element(cur.begin(), cur.begin() + nocc);
-            const double lv = *std::min_element(cur.begin() + nocc, cur.end());
+            const double ho = *std::max_element(next.begin(), next.begin() + nocc);
+            const double lv = *std::min_element(next.begin() + nocc, next.end());
             if (!(ho < lv)) {
                 if (info) *info = gw_evgw_info{it, 0, change};
                 return set_err(h, GW_ENUMERIC, "evGW: occupied and virtual QP energies cross");
             }
-            GW_TRY(copy_f64(h, eW, qp_e, M));
         }
+        GW_HIP(h, hipMemcpyAsync(vec + dim_max + 2 * M + M2, next.data(), sizeof(double) * M, hipMemcpyHostToDevice,
+                                 h->stream));
+        if (!g0) GW_TRY(copy_f64(h, eG, vec + dim_max + 2 * M + M2, M));
+        if (!w0) GW_TRY(copy_f64(h, eW, vec + dim_max + 2 * M + M2, M));
+        GW_HIP(h, hipStreamSynchronize(h->stream));
+        xin = next;
         if (change < tol) {
             converged = true;
             break;
         }
-        prev = cur;
         wprev = wcur;
     }
     if (info) *info = gw_evgw_info{std::min(it, max_iter), converged ? 1 : 0, change};

@@ -92,7 +92,8 @@ class ZetaInfo(ctypes.Structure):
 
 
 class EvgwOpts(ctypes.Structure):
-    _fields_ = [("g0", ctypes.c_int), ("w0", ctypes.c_int), ("max_iter", ctypes.c_int), ("tol", ctypes.c_double)]
+    _fields_ = [("g0", ctypes.c_int), ("w0", ctypes.c_int), ("max_iter", ctypes.c_int), ("tol", ctypes.c_double),
+                ("diis_space", ctypes.c_int)]
 
 
 class EvgwInfo(ctypes.Structure):
@@ -322,14 +323,14 @@ class Handle:
         return out[: n.value], w
 
     def evgw(self, eps, L, nocc, nmom_max, screening="tda", precision="fp64", g0=False, w0=False, tol=1e-6,
-             max_iter=30, opts=None, allow_noconv=False):
+             max_iter=30, opts=None, allow_noconv=False, diis_space=12):
         """Eigenvalue self-consistent loop (g0 / w0 keep G / W at the reference);
         returns dict(qp, qp_weight, iterations, converged, last_change)."""
         naux, nmo = L.shape[0], L.shape[1]
         _check_dev(eps, "eps", (nmo,))
         _check_dev(L, "L", (naux, nmo, nmo))
         qe, qw = self._new(nmo), self._new(nmo)
-        eo = EvgwOpts(int(bool(g0)), int(bool(w0)), int(max_iter), float(tol))
+        eo = EvgwOpts(int(bool(g0)), int(bool(w0)), int(max_iter), float(tol), int(diis_space) if diis_space else -1)
         info = EvgwInfo()
         scr = GW_TDA if screening == "tda" else GW_RPA
         self._sync_stream()

@@ -196,6 +196,11 @@ static gw_status rpa_eta0_f64(Handle* h, int nocc, int nvir, int naux, const dou
     }
     // Q_j (b < nq) and T_j (b >= nq) in one batched symmetric product
     GW_TRY(batched_sym(h, naux, ov, 2 * nq, V, as, 1.0, 0.0, QT));
+    // scratch for the column-scaled copies of V in the G accumulation below
+    double* Vb = (double*)ws_get(h, WS_X1, sizeof(double) * naux * ov);
+    if (!Vb) return GW_ENOMEM;
+    const long xsz = (long)naux * ov;
+    const unsigned xblk = (unsigned)((xsz + 255) / 256);
     // (I + Q_j)^-1 by batched Cholesky
     GW_TRY(copy_f64(h, Minv, QT, (size_t)nq * n2));
     {
@@ -224,17 +229,20 @@ static gw_status rpa_eta0_f64(Handle* h, int nocc, int nvir, int naux, const dou
                            nq, naux, dcoef, Minv, QT);
         GW_CHECK_LAUNCH(h);
     }
-    // G = V o D + sum_{b,Q} S_b[P][Q] V[Q][ia] g_b[ia]   (S_b symmetric: read as S_b[Q][P])
+    // G = V o D + sum_b S_b (V o g_b): per node one rocBLAS GEMM accumulating
+    // into G (beta = 1), the column scaling g_b applied to a scratch copy of V
     {
-        GemmF64 g;
-        g.M = naux; g.N = (int)ov; g.K = 2 * nq * naux;
-        g.a_kc = false; g.A = QT; g.a_off = 0; g.a_kdiv = naux; g.a_khi = n2; g.a_klo = naux;
-        g.b_kc = false; g.B = V; g.b_off = 0; g.b_kdiv = naux; g.b_khi = 0; g.b_klo = ov;
-        g.bscale = bs; g.bscale_ld = ov;
-        g.epi = EPI_AXPBY; g.alpha = 1.0; g.X = V; g.ldx = ov; g.dg = D;
-        g.C = G; g.ldc = ov;
-        g.tag = "rpa_quad";
-        GW_TRY(gemm_f64(h, g));
+        KTimer tm(h, "rpa_quad");
+        hipLaunchKernelGGL(scale_cols_kernel, dim3(xblk), dim3(256), 0, h->stream, (long)naux, ov, V, D, G);
+        GW_CHECK_LAUNCH(h);
+        for (int b = 0; b < 2 * nq; ++b) {
+            hipLaunchKernelGGL(scale_cols_kernel, dim3(xblk), dim3(256), 0, h->stream, (long)naux, ov, V,
+                               bs + (long)b * ov, Vb);
+            GW_CHECK_LAUNCH(h);
+            GW_TRY(gemm_rowmajor(h, false, false, naux, (int)ov, naux, 1.0, QT + b * n2, naux, Vb, (int)ov, 1.0, G,
+                                 (int)ov));
+        }
+        tm.stop();
     }
     // Woodbury: Hm = (G o D^-1) V^T, Pm = I + 4 (V o D^-1) V^T, Y = Hm Pm^-1,
     // eta~0 = D^-1 o (G - 4 Y V)

@@ -249,7 +249,11 @@ gw_status gw_naf(gw_handle h, int nocc, int nvir, int naux, const double* L, dou
  *     V_pq = sum_l v_pl v_ql (D_pl + D_ql)/(D_pl^2 + D_ql^2) (1 - exp(-(D_pl^2 + D_ql^2) s)),
  *   scheme 1 (Lorentzian, eq. qsgw_v with the real part of eq. qsgw_se_eta):
  *     V_pq = 1/2 sum_l v_pl v_ql [D_pl/(D_pl^2 + delta^2) + D_ql/(D_ql^2 + delta^2)];
- * then the self-consistent field of eq. qp_scf, (f[rho] + C V C^T) C' = C' e',
+ * the potential that enters the SCF is the DIIS extrapolation (space
+ * outer_diis) over the potentials C V C^T built so far, error vector
+ * V_out - V_in (the potential just built minus the one that entered the
+ * previous SCF, zero at the start), or C V C^T itself when outer_diis < 0;
+ * then the self-consistent field of eq. qp_scf, (f[rho] + V_in) C' = C' e',
  * f[rho] = h + J[rho] - K[rho]/2 with the core Hamiltonian of gw_fsgw
  * (f[rho0] = diag(eps)), rho = 2 sum_{i<nocc} C'_i C'_i^T, DIIS over the Fock
  * matrices with the commutator F rho - rho F as error, until the density
@@ -257,7 +261,7 @@ gw_status gw_naf(gw_handle h, int nocc, int nvir, int naux, const double* L, dou
  * than tol.  The QP energies are the final mean-field energies (unit weights).
  * Inputs (device): eps [nmo], L [naux][nmo][nmo].  Outputs (device): qp_e [nmo]
  * ascending; C [nmo][nmo] (C[p][k]: reference orbital p in QP orbital k;
- * nullable); F [nmo][nmo] = f[rho] + V in the reference basis (nullable);
+ * nullable); F [nmo][nmo] = f[rho] + V_in in the reference basis (nullable);
  * info host (nullable).  Returns GW_ENOCONV (outputs still written) when
  * max_iter is reached.  Synchronises the stream.
  */
@@ -269,7 +273,8 @@ typedef struct {
     int max_iter;      /* [30] */
     int max_scf;       /* SCF steps per iteration [200] */
     double scf_tol;    /* max |density change| ending the SCF [1e-10] */
-    int diis_space;    /* [12] */
+    int diis_space;    /* SCF DIIS space [12] */
+    int outer_diis;    /* DIIS space over the static potential [0 -> 12]; < 0: none */
 } gw_qsgw_opts;
 
 typedef struct {

@@ -25,6 +25,11 @@ One iteration:
      the Fock matrices with the commutator F rho - rho F as error, until the
      density changes by less than scf_tol (max element);
   4. converged when the sorted eps_mf change by less than tol.
+The potential that enters step 3 is, as in the paper's other self-consistent
+loops, a DIIS extrapolation (space outer_diis, default 12) over the potentials
+built so far, with error vector V_out - V_in (the potential just built minus
+the one that went into the previous SCF, V_in = 0 at the start); outer_diis <= 0
+takes V_out as it is.
 
 Readings taken here (the paper gives no values): SRG is the default with
 s = 500 Ha^-2; the Lorentzian broadening defaults to delta = 1e-3 Ha; the QP
@@ -89,10 +94,10 @@ def one_shot_poles(eps_mf, C, L, nocc, nmom_max, screening="tda"):
 
 
 def qsgw(eps, L, nocc, nmom_max, screening="tda", scheme="srg", s=500.0, delta=1e-3, tol=1e-6,
-         max_iter=30, scf_tol=1e-10, max_scf=200, diis_space=12, pole_fn=None):
+         max_iter=30, scf_tol=1e-10, max_scf=200, diis_space=12, pole_fn=None, outer_diis=12):
     """Alg. A2.  pole_fn(eps_mf, C) may replace step 1 (the brute-force pins
     pass the exact self-energy poles).  Returns dict(qp, C, F, V, iterations,
-    scf_steps, converged, last_change)."""
+    scf_steps, converged, last_change); V is the potential of the last SCF."""
     nmo = eps.shape[0]
     hcore = fsgw.core_hamiltonian(eps, L, nocc)
     C = np.eye(nmo)
@@ -101,13 +106,15 @@ def qsgw(eps, L, nocc, nmom_max, screening="tda", scheme="srg", s=500.0, delta=1
     converged, last, steps, it = False, -1.0, 0, 0
     F = np.diag(e_mf)
     V = np.zeros((nmo, nmo))
+    outer = fsgw.DIIS(outer_diis) if outer_diis > 0 else None
     for it in range(1, max_iter + 1):
         if pole_fn is None:
             e_aux, W = one_shot_poles(e_mf, C, L, nocc, nmom_max, screening)
         else:
             e_aux, W = pole_fn(e_mf, C)
         Vc = static_potential(e_mf, e_aux, W, scheme, s, delta)
-        V = C @ Vc @ C.T
+        V_out = C @ Vc @ C.T
+        V = V_out if outer is None else outer.update(V_out, V_out - V)
         e_new, C_new, rho, F, n = scf(hcore, L, V, nocc, rho, scf_tol, max_scf, diis_space)
         steps += n
         last = float(np.abs(np.sort(e_new) - np.sort(e_mf)).max())

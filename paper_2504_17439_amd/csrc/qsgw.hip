@@ -8,7 +8,9 @@
 //   static potential at eps_p = e_p (static_potential_kernel):
 //     SRG        V_pq = sum_l v_pl v_ql (D_pl + D_ql) / (D_pl^2 + D_ql^2) (1 - exp(-(D_pl^2 + D_ql^2) s)),
 //     Lorentzian V_pq = 1/2 sum_l v_pl v_ql [D_pl / (D_pl^2 + delta^2) + D_ql / (D_ql^2 + delta^2)],
-//   D_pl = e_p - e_l; V moved to the reference basis, Vr = C V C^T;
+//   D_pl = e_p - e_l; V moved to the reference basis, Vr = C V C^T, and
+//   replaced by the DIIS extrapolation over the potentials built so far
+//   (error vector Vr - the potential of the previous SCF, zero at the start);
 //   SCF of (f[rho] + Vr) C = C e with f[rho] = h + J[rho] - K[rho]/2 (the core
 //   Hamiltonian of the Fock loop, f[rho0] = diag(eps)), rho from the nocc
 //   lowest orbitals, DIIS over the Fock matrices with the commutator
@@ -18,8 +20,8 @@
 //
 // Device work: GEMMs and eigensolves through rocBLAS / rocSOLVER, the static
 // potential as a tiled kernel (O(nmo^2 npole), one exp per element and pole);
-// the host keeps the DIIS extrapolation (at most diis_space nmo^2 vectors)
-// and the convergence tests.
+// the host keeps the two DIIS extrapolations (at most diis_space and
+// outer_diis pairs of nmo^2 vectors) and the convergence tests.
 #include "internal.h"
 
 #include <algorithm>
@@ -140,6 +142,7 @@ gw_status qsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
     const int max_scf = (qo && qo->max_scf > 0) ? qo->max_scf : 200;
     const double scf_tol = (qo && qo->scf_tol > 0) ? qo->scf_tol : 1e-10;
     const int diis_space = (qo && qo->diis_space > 0) ? qo->diis_space : 12;
+    const int outer_space = (qo && qo->outer_diis != 0) ? qo->outer_diis : 12;
     const int M = nocc + nvir, A = naux, nt = nmom_max + 1;
     const long M2 = (long)M * M;
     const int cap = M * nt / 2;
@@ -192,6 +195,13 @@ gw_status qsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
     GW_TRY(copy_f64(h, ecur, eps, (size_t)M));
 
     std::vector<double> hF((size_t)M2), hE((size_t)M2), hr((size_t)M2), hrn((size_t)M2), he(M), hen(M);
+    std::vector<double> hVo, hVi, hVe;   // outer DIIS: built potential, potential in use, their difference
+    Diis outer{std::max(outer_space, 1), (size_t)M2, {}, {}, {}};
+    if (outer_space > 0) {
+        hVo.resize((size_t)M2);
+        hVi.assign((size_t)M2, 0.0);
+        hVe.resize((size_t)M2);
+    }
     GW_HIP(h, hipMemcpyAsync(hr.data(), rho, sizeof(double) * M2, hipMemcpyDeviceToHost, h->stream));
     GW_HIP(h, hipMemcpyAsync(he.data(), eps, sizeof(double) * M, hipMemcpyDeviceToHost, h->stream));
     GW_HIP(h, hipStreamSynchronize(h->stream));
@@ -234,6 +244,15 @@ gw_status qsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
         }
         GW_TRY(gemm_rowmajor(h, false, false, M, M, M, 1.0, Vc, M, Ut, M, 0.0, tmp, M));
         GW_TRY(gemm_rowmajor(h, true, false, M, M, M, 1.0, Ut, M, tmp, M, 0.0, Vr, M));
+        if (outer_space > 0) {
+            GW_HIP(h, hipMemcpyAsync(hVo.data(), Vr, sizeof(double) * M2, hipMemcpyDeviceToHost, h->stream));
+            GW_HIP(h, hipStreamSynchronize(h->stream));
+            for (long i = 0; i < M2; ++i) hVe[i] = hVo[i] - hVi[i];
+            outer.push(hVo.data(), hVe.data());
+            const double* x = outer.extrapolate();
+            hVi.assign(x, x + M2);
+            GW_HIP(h, hipMemcpyAsync(Vr, hVi.data(), sizeof(double) * M2, hipMemcpyHostToDevice, h->stream));
+        }
 
         // SCF of eq. qp_scf from the current density
         Diis diis{diis_space, (size_t)M2, {}, {}, {}};

@@ -69,7 +69,7 @@ class FsgwInfo(ctypes.Structure):
 class QsgwOpts(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int), ("srg_s", ctypes.c_double), ("delta", ctypes.c_double),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("max_scf", ctypes.c_int),
-                ("scf_tol", ctypes.c_double), ("diis_space", ctypes.c_int)]
+                ("scf_tol", ctypes.c_double), ("diis_space", ctypes.c_int), ("outer_diis", ctypes.c_int)]
 
 
 class QsgwInfo(ctypes.Structure):
@@ -342,15 +342,17 @@ class Handle:
                     last_change=info.last_change)
 
     def qsgw(self, eps, L, nocc, nmom_max, screening="tda", precision="fp64", scheme="srg", s=500.0, delta=1e-3,
-             tol=1e-6, max_iter=30, scf_tol=1e-10, max_scf=200, diis_space=12, opts=None, allow_noconv=False):
+             tol=1e-6, max_iter=30, scf_tol=1e-10, max_scf=200, diis_space=12, outer_diis=12, opts=None,
+             allow_noconv=False):
         """Quasiparticle self-consistent loop; returns dict(qp, C, F, iterations,
-        scf_steps, converged, last_change)."""
+        scf_steps, converged, last_change).  outer_diis <= 0: no DIIS over the
+        static potential."""
         naux, nmo = L.shape[0], L.shape[1]
         _check_dev(eps, "eps", (nmo,))
         _check_dev(L, "L", (naux, nmo, nmo))
         qe, C, F = self._new(nmo), self._new(nmo, nmo), self._new(nmo, nmo)
         qo = QsgwOpts({"srg": 0, "lorentzian": 1}[scheme], float(s), float(delta), float(tol), int(max_iter),
-                      int(max_scf), float(scf_tol), int(diis_space))
+                      int(max_scf), float(scf_tol), int(diis_space), int(outer_diis) if outer_diis > 0 else -1)
         info = QsgwInfo()
         scr = GW_TDA if screening == "tda" else GW_RPA
         self._sync_stream()

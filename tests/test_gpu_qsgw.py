@@ -29,12 +29,15 @@ def host(t):
     return t.cpu().numpy()
 
 
-@pytest.mark.parametrize("o,v,A,N,seed,scr,scheme", [
-    (3, 9, 20, 5, 1, "tda", "srg"), (3, 9, 20, 5, 3, "tda", "lorentzian"), (3, 9, 20, 3, 1, "rpa", "srg"),
-    (4, 12, 30, 5, 2, "tda", "srg"), (5, 19, 80, 3, 0, "tda", "srg")])
-def test_qsgw_matches_oracle(handle, o, v, A, N, seed, scr, scheme):
+@pytest.mark.parametrize("o,v,A,N,seed,scr,scheme,outer", [
+    (3, 9, 20, 5, 1, "tda", "srg", 12), (3, 9, 20, 5, 1, "tda", "srg", 0), (3, 9, 20, 5, 3, "tda", "lorentzian", 12),
+    (3, 9, 20, 5, 0, "tda", "lorentzian", 12), (3, 9, 20, 5, 4, "tda", "lorentzian", 12),
+    (3, 9, 20, 3, 1, "rpa", "srg", 12), (4, 12, 30, 5, 2, "tda", "srg", 12), (5, 19, 80, 3, 0, "tda", "srg", 12)])
+def test_qsgw_matches_oracle(handle, o, v, A, N, seed, scr, scheme, outer):
+    """outer = 0: the plain loop; seeds 0 and 4 with the Lorentzian potential
+    converge only with DIIS over the static potential."""
     eps, L = gwsynth.system(o, v, A, seed)
-    kw = dict(scheme=scheme, tol=1e-10, max_iter=80)
+    kw = dict(scheme=scheme, tol=1e-10, max_iter=80, outer_diis=outer)
     ref = qsgw.qsgw(eps, L, o, N, scr, **kw)
     out = handle.qsgw(dev(eps), dev(L), o, N, scr, "fp64", **kw)
     assert ref["converged"] and out["converged"]

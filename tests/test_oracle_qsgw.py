@@ -162,3 +162,31 @@ def test_fixed_point_equation_in_the_reference_basis():
     rho = 2.0 * C[:, :o] @ C[:, :o].T
     F = fsgw.fock(fsgw.core_hamiltonian(eps, L, o), L, rho) + V
     assert np.abs(F @ C - C * e[None, :]).max() < 1e-9
+
+
+def test_outer_diis_reaches_the_plain_loop_fixed_point():
+    """DIIS over the static potential changes the path, not the fixed point."""
+    o = 3
+    eps, L = gwsynth.system(o, 9, 20, 1)
+    a = qsgw.qsgw(eps, L, o, 5, "tda", tol=1e-11, max_iter=80, outer_diis=12)
+    b = qsgw.qsgw(eps, L, o, 5, "tda", tol=1e-11, max_iter=80, outer_diis=0)
+    assert a["converged"] and b["converged"] and a["iterations"] < b["iterations"]
+    assert np.abs(a["qp"] - b["qp"]).max() < 1e-9
+
+
+@pytest.mark.parametrize("seed", [0, 4])
+def test_outer_diis_converges_where_the_plain_loop_stalls(seed):
+    """Lorentzian potential, delta = 1e-3: the plain loop still moves after 40
+    rebuilds; with DIIS the loop ends on a state that one more plain rebuild
+    (poles, potential, SCF) leaves in place."""
+    o, N = 3, 5
+    eps, L = gwsynth.system(o, 9, 20, seed)
+    plain = qsgw.qsgw(eps, L, o, N, "tda", scheme="lorentzian", tol=1e-8, max_iter=40, outer_diis=0)
+    assert not plain["converged"]
+    r = qsgw.qsgw(eps, L, o, N, "tda", scheme="lorentzian", tol=1e-10, max_iter=60)
+    assert r["converged"]
+    e_aux, W = qsgw.one_shot_poles(r["qp"], r["C"], L, o, N, "tda")
+    V = r["C"] @ qsgw.static_potential(r["qp"], e_aux, W, "lorentzian") @ r["C"].T
+    rho = 2.0 * r["C"][:, :o] @ r["C"][:, :o].T
+    e, _, _, _, _ = qsgw.scf(fsgw.core_hamiltonian(eps, L, o), L, V, o, rho)
+    assert np.abs(e - r["qp"]).max() < 1e-8

@@ -98,6 +98,20 @@ gw_status fock_jk(Handle* h, int A, int M, const double* L, const double* rho, d
     return gemm_rowmajor(h, true, false, M, M, A * M, 1.0, T, M, L, M, 0.0, K, M);
 }
 
+gw_status fock_jk_occ(Handle* h, int A, int M, const double* L, const double* rho, const double* Co, int nocc,
+                      double* J, double* K, double* B, double* v) {
+    const long M2 = (long)M * M;
+    const double one = 1.0, zero = 0.0;
+    GW_TRY(blas_st(h, rocblas_dgemv(h->blas, rocblas_operation_transpose, (int)M2, A, &one, L, (int)M2, rho, 1, &zero,
+                                    v, 1),
+                   "rocblas_dgemv"));
+    GW_TRY(blas_st(h, rocblas_dgemv(h->blas, rocblas_operation_none, (int)M2, A, &one, L, (int)M2, v, 1, &zero, J, 1),
+                   "rocblas_dgemv"));
+    // B_P = Co L_P (nocc x M), then K = 2 sum_{(P,i)} B[(P,i)][p] B[(P,i)][q]
+    GW_TRY(gemm_rm_batched(h, false, false, nocc, M, M, Co, M, 0, L, M, M2, B, M, (long)nocc * M, A));
+    return gemm_rowmajor(h, true, false, M, M, A * nocc, 2.0, B, M, B, M, 0.0, K, M);
+}
+
 gw_status zeta_trace(Handle* h, ZetaSearch& s, double z, double nelec, double* tr, int* nfill) {
     GW_TRY(upfold_eigh(h, s.M, s.np, s.F, s.pole_e, z, s.pole_v, s.ldv, s.H, s.w, s.work, s.info));
     ++s.eig_calls;

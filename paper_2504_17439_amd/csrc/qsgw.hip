@@ -13,7 +13,8 @@
 //   (error vector Vr - the potential of the previous SCF, zero at the start);
 //   SCF of (f[rho] + Vr) C = C e with f[rho] = h + J[rho] - K[rho]/2 (the core
 //   Hamiltonian of the Fock loop, f[rho0] = diag(eps)), rho from the nocc
-//   lowest orbitals, DIIS over the Fock matrices with the commutator
+//   lowest orbitals (exchange built from those orbitals, K = 2 sum_P
+//   (Co L_P)^T (Co L_P)), DIIS over the Fock matrices with the commutator
 //   F rho - rho F as error vector, until max |rho_k - rho_{k-1}| < scf_tol;
 //   converged when the sorted e change by less than tol.
 // The QP energies are the final mean-field e (unit weights).
@@ -152,7 +153,7 @@ gw_status qsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
     double* T = (double*)ws_get(h, WS_FS1, sizeof(double) * A * M2);
     double* sig = (double*)ws_get(h, WS_FS2, sizeof(double) * 2 * nt * M2);
     double* pol = (double*)ws_get(h, WS_FS3, sizeof(double) * (2 * cap + (long)M * ldv));
-    double* mat = (double*)ws_get(h, WS_FS5, sizeof(double) * (12 * M2 + 4 * M + A + 64));
+    double* mat = (double*)ws_get(h, WS_FS5, sizeof(double) * (13 * M2 + 4 * M + A + 64));
     double* R = (double*)ws_get(h, WS_R, sizeof(double) * nt * (long)A * A);
     int* dinfo = (int*)ws_get(h, WS_FS6, sizeof(int) * 64);
     if (!Lc || !T || !sig || !pol || !mat || !R || !dinfo) return GW_ENOMEM;
@@ -176,6 +177,7 @@ gw_status qsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
     double* enew = ecur + M;          // [M]
     double* wtmp = enew + M;          // [M] eig work
     double* jv = wtmp + M;            // [A]
+    double* Co = jv + A;              // [nocc][M] occupied orbitals (rows), rho = 2 Co^T Co
 
     if (rocblas_set_stream(h->blas, h->stream) != rocblas_status_success)
         return set_err(h, GW_ELIB, "rocblas_set_stream");
@@ -191,6 +193,10 @@ gw_status qsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
                        (const double*)nullptr, hcore);
     GW_CHECK_LAUNCH(h);
     hipLaunchKernelGGL(qs_diag_kernel, dim3(nbq(M2)), dim3(256), 0, h->stream, M, (const double*)nullptr, 1.0, M, Ut);
+    GW_CHECK_LAUNCH(h);
+    // the first nocc rows of diag(1_{p < nocc}) are the reference occupied orbitals
+    hipLaunchKernelGGL(qs_diag_kernel, dim3(nbq(M2)), dim3(256), 0, h->stream, M, (const double*)nullptr, 1.0, nocc,
+                       Co);
     GW_CHECK_LAUNCH(h);
     GW_TRY(copy_f64(h, ecur, eps, (size_t)M));
 
@@ -209,9 +215,9 @@ gw_status qsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
     int it = 0, scf_steps = 0;
     bool converged = false;
     double last = -1.0;
-    // Fock matrix of the current rho plus Vr into F
+    // Fock matrix of the current rho (= 2 Co^T Co) plus Vr into F
     auto build_fock = [&]() -> gw_status {
-        GW_TRY(fock_jk(h, A, M, L, rho, J, K, T, jv));
+        GW_TRY(fock_jk_occ(h, A, M, L, rho, Co, nocc, J, K, T, jv));
         hipLaunchKernelGGL(qs_comb_kernel, dim3(nbq(M2)), dim3(256), 0, h->stream, M2, hcore, J, 1.0, K, -0.5,
                            (const double*)Vr, F);
         GW_CHECK_LAUNCH(h);
@@ -275,6 +281,7 @@ gw_status qsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
             double change = 0.0;
             for (long i = 0; i < M2; ++i) change = std::max(change, std::fabs(hrn[i] - hr[i]));
             GW_TRY(copy_f64(h, rho, rhon, (size_t)M2));
+            GW_TRY(copy_f64(h, Co, Fx, (size_t)nocc * M));
             hr.swap(hrn);
             if (change < scf_tol) break;
         }

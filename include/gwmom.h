@@ -370,7 +370,11 @@ gw_status gw_zeta_shift(gw_handle h, int nmo, int nmom_max, int npole_occ, int n
  * G0W0 evaluation.  Converged when, for every quasiparticle-like orbital (QP
  * weight >= 0.9 in both iterations; all orbitals if none is), the QP energy
  * differs by at most tol from the energy that went into the iteration (for
- * the plain loop: its change since the previous iteration).
+ * the plain loop: its change since the previous iteration).  When
+ * opts->moment_eps is not set (<= 0) the loop's block Lanczos deflates at
+ * 1e-12 (FP64) or 1e-9 (mixed) instead of 2^-52: directions resolved from
+ * the moments' rounding noise give satellite poles whose QP assignment moves
+ * by ~1e-5 Ha between iterations.
  * Outputs (device, [nmo]): qp_e, qp_w of the last iteration.  GW_ENOCONV
  * after max_iter iterations (outputs and info still written); GW_ENUMERIC if
  * the QP energies of occupied and virtual orbitals cross (the next screening

@@ -27,7 +27,12 @@ Readings taken here (the box gives the loop, not its numerics):
     with g0 and w0 both set nothing is updated and the loop is one G0W0
     evaluation;
   * the QP energy of orbital p is the H~ eigenvalue of largest physical
-    weight |chi_p alpha|^2 (ties to the lowest alpha), as in G0W0.
+    weight |chi_p alpha|^2 (ties to the lowest alpha), as in G0W0;
+  * the block Lanczos inside the loop deflates at a moment accuracy of
+    1e-12 (relative), not the unit roundoff: the recursion and the
+    convolution leave the FP64 moments a few digits short of it, and
+    directions resolved from that rounding noise give satellite poles whose
+    QP assignment moves by ~1e-5 Ha from one iteration to the next.
 """
 from __future__ import annotations
 
@@ -36,7 +41,7 @@ import numpy as np
 from . import fsgw, gw
 
 
-def ev_step(eps_ref, eps_g, eps_w, L, nocc, nmom_max, screening="tda", nquad=48, scale=None):
+def ev_step(eps_ref, eps_g, eps_w, L, nocc, nmom_max, screening="tda", nquad=48, scale=None, moment_eps=gw.EPS):
     """One pass of the loop body of Alg. A1: moments with eps_W, convolution
     with eps_G, poles, H~ with f = diag(eps_ref), QP assignment."""
     V, D = gw.particle_hole(eps_w, L, nocc)
@@ -46,8 +51,8 @@ def ev_step(eps_ref, eps_g, eps_w, L, nocc, nmom_max, screening="tda", nquad=48,
         eta = gw.rpa_eta(V, D, nmom_max, nquad, scale)
     R = gw.w_core(eta, V)
     so, sv, _ = gw.sigma_moments(eps_g, L, nocc, R)
-    eo, vo = gw.poles_from_moments(list(so))
-    ev, vv = gw.poles_from_moments(list(sv))
+    eo, vo = gw.poles_from_moments(list(so), moment_eps=moment_eps)
+    ev, vv = gw.poles_from_moments(list(sv), moment_eps=moment_eps)
     H = gw.upfolded_hamiltonian(np.diag(eps_ref), eo, vo, ev, vv)
     E, U = np.linalg.eigh(H)
     qp, wt, _ = gw.qp_assign(E, U[: eps_ref.shape[0]])
@@ -55,14 +60,14 @@ def ev_step(eps_ref, eps_g, eps_w, L, nocc, nmom_max, screening="tda", nquad=48,
 
 
 def evgw(eps, L, nocc, nmom_max, screening="tda", g0=False, w0=False, tol=1e-6, max_iter=30,
-         nquad=48, scale=None, step=None, diis_space=12):
+         nquad=48, scale=None, step=None, diis_space=12, moment_eps=1e-12):
     """Alg. A1.  Returns dict(qp, qp_weight, iterations, converged, history).
     `step` replaces the loop body (same signature as ``ev_step``), e.g. by a
     brute-force one.  With diis_space > 0 the updated energies are the Pulay
     extrapolation (the paper's self-consistent runs keep a DIIS space of 12)
     over the pairs (QP energies, QP energies - the energies they came from);
     diis_space = 0 is the plain loop."""
-    step = step or (lambda er, eg, ew: ev_step(er, eg, ew, L, nocc, nmom_max, screening, nquad, scale))
+    step = step or (lambda er, eg, ew: ev_step(er, eg, ew, L, nocc, nmom_max, screening, nquad, scale, moment_eps))
     eps = np.asarray(eps, dtype=np.float64)
     eps_g = eps.copy()
     eps_w = eps.copy()

@@ -13,7 +13,11 @@
 // QP energy differs by at most tol from the energy that went into the
 // iteration (the fixed-point residual; for the plain loop the change since
 // the previous iteration): an orbital embedded in a satellite band has no
-// stable QP assignment.
+// stable QP assignment.  Unless the caller sets opts->moment_eps, the
+// Lanczos inside the loop deflates at the moments' accuracy (FP64 1e-12,
+// mixed 1e-9), not the unit roundoff: directions resolved from rounding
+// noise give satellite poles whose assignment moves by ~1e-5 Ha between
+// iterations and keep the loop from converging.
 #include "internal.h"
 
 #include <algorithm>
@@ -40,6 +44,9 @@ gw_status evgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
     const double tol = (eo && eo->tol > 0) ? eo->tol : 1e-6;
     const int max_iter = (eo && eo->max_iter > 0) ? eo->max_iter : 30;
     const int diis_space = (eo && eo->diis_space != 0) ? eo->diis_space : 12;
+    gw_opts lo = opts ? *opts : gw_opts{};
+    if (!(lo.moment_eps > 0)) lo.moment_eps = prec == GW_MIXED ? 1e-9 : 1e-12;
+    opts = &lo;
     const int M = nocc + nvir, nt = nmom_max + 1;
     const long M2 = (long)M * M;
     const int cap = M * nt / 2;

@@ -159,7 +159,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--train", type=int, default=2000, help="training systems (seeds seed0 .. seed0+n-1)")
     ap.add_argument("--seed0", type=int, default=1)
-    ap.add_argument("--test", type=int, default=100, help="test systems (seeds 10001..)")
+    ap.add_argument("--test", type=int, default=100, help="test systems (seeds test_seed0..)")
+    ap.add_argument("--test-seed0", type=int, default=10001)
     ap.add_argument("--mmin", type=int, default=40)
     ap.add_argument("--mmax", type=int, default=200)
     ap.add_argument("--mtest", type=int, default=300)
@@ -198,21 +199,23 @@ def main(argv=None):
     t0 = time.time()
     hist = model.train(X, T, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
     train_s = time.time() - t0
-    res = evaluate(h, model, list(range(10001, 10001 + args.test)), args.mtest, args.nmom, log)
+    res = evaluate(h, model, list(range(args.test_seed0, args.test_seed0 + args.test)), args.mtest, args.nmom, log)
     ci = np.array([r["cold_iterations"] for r in res], dtype=float)
     wi = np.array([r["warm_iterations"] for r in res], dtype=float)
     cf = np.array([r["cold_fock_steps"] for r in res], dtype=float)
     wf = np.array([r["warm_fock_steps"] for r in res], dtype=float)
     summary = dict(
         train=gen, train_loss_first=hist[0], train_loss_last=hist[-1], train_seconds=train_s,
-        test_systems=len(res), test_M=args.mtest, nmom_max=args.nmom,
+        test_systems=len(res), test_seed0=args.test_seed0, test_M=args.mtest, nmom_max=args.nmom,
         cold_iterations_mean=float(ci.mean()), warm_iterations_mean=float(wi.mean()),
         iteration_ratio=float(ci.mean() / wi.mean()),
         cold_fock_steps_mean=float(cf.mean()), warm_fock_steps_mean=float(wf.mean()),
         fock_step_ratio=float(cf.mean() / wf.mean()),
         max_diag_error=float(max(r["max_diag_error"] for r in res)),
         max_qp_difference=float(max(r["max_qp_difference"] for r in res)),
-        all_converged=all(r["converged"] for r in res))
+        all_converged=all(r["converged"] for r in res),
+        per_system=[(r["seed"], r["cold_iterations"], r["warm_iterations"], r["cold_fock_steps"],
+                     r["warm_fock_steps"]) for r in res])
     print(json.dumps(summary), flush=True)
     return 0
 

@@ -99,3 +99,25 @@ def test_evgw_rejects_bad_options_and_reports_no_convergence(handle):
         handle.evgw(e, l, o, 5, "tda", tol=1e-14, max_iter=2)
     r = handle.evgw(e, l, o, 5, "tda", tol=1e-14, max_iter=2, allow_noconv=True)
     assert r["iterations"] == 2 and not r["converged"] and r["last_change"] > 0
+
+
+def test_fp64_evgw_converges_at_full_size_with_the_loop_deflation(handle):
+    """nocc=100, nvir=400, naux=1500, N=11 (seed 0): deflating at the unit
+    roundoff the FP64 loop keeps poles resolved from rounding noise and stays
+    above a 1e-6 Ha residual; at the loop's default deflation (1e-12) it
+    converges in a few iterations, the frontier QPs where the stalled loop
+    has them."""
+    o, v, A, N = 100, 400, 1500, 11
+    print(f"\n[case] evgw fp64 full size o={o} v={v} A={A} N={N}", flush=True)
+    eps, L = gwsynth.system(o, v, A, 0)
+    e, l = dev(eps), dev(L)
+    del L
+    r = handle.evgw(e, l, o, N, "tda", tol=1e-6, max_iter=10)
+    assert r["converged"] and r["iterations"] <= 6
+    s = handle.evgw(e, l, o, N, "tda", tol=1e-6, max_iter=8, opts={"moment_eps": float(np.finfo(float).eps)},
+                    allow_noconv=True)
+    assert not s["converged"]
+    q, qs = host(r["qp"]), host(s["qp"])
+    print(f"frontier difference {np.abs(q[o - 1:o + 1] - qs[o - 1:o + 1]).max():.2e} Ha, stalled residual "
+          f"{s['last_change']:.2e}", flush=True)
+    assert np.abs(q[o - 1:o + 1] - qs[o - 1:o + 1]).max() < 1e-7

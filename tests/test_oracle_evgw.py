@@ -89,3 +89,16 @@ def test_diis_converges_where_the_plain_loop_stalls(seed):
     d = evgw.evgw(eps, L, o, 5, "tda", max_iter=40, diis_space=12)
     assert not plain["converged"] and d["converged"]
     assert d["iterations"] < 15 and d["history"][-1] < 1e-6
+
+
+@pytest.mark.parametrize("screening", ["tda", "rpa"])
+def test_loop_deflation_level_leaves_resolved_poles_alone(screening):
+    """The loop's Lanczos deflates at 1e-12 instead of the unit roundoff; on a
+    system whose moments carry no direction at that level both loops take the
+    same steps to the same energies."""
+    o = 3
+    eps, L = gwsynth.system(o, 9, 30, 4, amp=0.3)
+    a = evgw.evgw(eps, L, o, 5, screening, tol=1e-10, max_iter=40)
+    b = evgw.evgw(eps, L, o, 5, screening, tol=1e-10, max_iter=40, moment_eps=np.finfo(float).eps)
+    assert a["converged"] and b["converged"] and a["iterations"] == b["iterations"]
+    assert np.abs(a["qp"] - b["qp"]).max() < 1e-12

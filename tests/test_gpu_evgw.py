@@ -106,7 +106,7 @@ def test_fp64_evgw_converges_at_full_size_with_the_loop_deflation(handle):
     roundoff the FP64 loop keeps poles resolved from rounding noise and stays
     above a 1e-6 Ha residual; at the loop's default deflation (1e-12) it
     converges in a few iterations, the frontier QPs where the stalled loop
-    has them."""
+    has them; the mixed loop's frontier QPs within 1e-6 Ha of the FP64 loop's."""
     o, v, A, N = 100, 400, 1500, 11
     print(f"\n[case] evgw fp64 full size o={o} v={v} A={A} N={N}", flush=True)
     eps, L = gwsynth.system(o, v, A, 0)
@@ -121,3 +121,6 @@ def test_fp64_evgw_converges_at_full_size_with_the_loop_deflation(handle):
     print(f"frontier difference {np.abs(q[o - 1:o + 1] - qs[o - 1:o + 1]).max():.2e} Ha, stalled residual "
           f"{s['last_change']:.2e}", flush=True)
     assert np.abs(q[o - 1:o + 1] - qs[o - 1:o + 1]).max() < 1e-7
+    m = handle.evgw(e, l, o, N, "tda", precision="mixed", tol=1e-6, max_iter=10, opts={"moment_eps": 1e-9})
+    assert m["converged"]
+    assert np.abs(host(m["qp"])[o - 1:o + 1] - q[o - 1:o + 1]).max() < 1e-6

@@ -85,3 +85,25 @@ def test_qsgw_iteration_cap_and_bad_arguments(handle):
         handle.qsgw(e, l, o, 4, "tda")
     with pytest.raises(gwmom.GWError):
         handle.qsgw(e, l, o, 5, "tda", s=-1.0)
+
+
+def test_qsgw_full_size_fp64_and_mixed(handle):
+    """nocc=100, nvir=400, naux=1500, N=11 (seed 0), SRG: both precisions
+    converge (1e-6 Ha), the frontier QPs agree to 1e-6 Ha, and each result is
+    a mean field: orthonormal orbitals that diagonalise F with the QP
+    energies."""
+    o, v, A, N = 100, 400, 1500, 11
+    print(f"\n[case] qsgw full size o={o} v={v} A={A} N={N}", flush=True)
+    eps, L = gwsynth.system(o, v, A, 0)
+    e, l = dev(eps), dev(L)
+    del L
+    a = handle.qsgw(e, l, o, N, "tda", "fp64", tol=1e-6, max_iter=20)
+    b = handle.qsgw(e, l, o, N, "tda", "mixed", tol=1e-6, max_iter=20, opts={"moment_eps": 1e-9})
+    assert a["converged"] and b["converged"]
+    qa, qb = host(a["qp"]), host(b["qp"])
+    print(f"frontier difference {np.abs(qa[o - 1:o + 1] - qb[o - 1:o + 1]).max():.2e} Ha", flush=True)
+    assert np.abs(qa[o - 1:o + 1] - qb[o - 1:o + 1]).max() < 1e-6
+    for r in (a, b):
+        C, F, q = host(r["C"]), host(r["F"]), host(r["qp"])
+        assert np.abs(C.T @ C - np.eye(o + v)).max() < 1e-12
+        assert np.abs(F @ C - C * q[None, :]).max() < 1e-9 * np.abs(F).max()

@@ -69,6 +69,35 @@ __global__ void phys_weight_kernel(int dim, int M, const double* __restrict__ H,
 }
 
 // J = sum_P L_P tr(L_P rho),  K = sum_P L_P rho L_P  for L [A][M][M] (each L_P symmetric).
+// B[P][i][p] = G[P][p][i] for blocks of M x n (one z-slice per P), 32 x 32
+// tiles through LDS so that both the reads and the writes are coalesced.
+__global__ __launch_bounds__(256) void blk_transpose_kernel(int M, int n, const double* __restrict__ G,
+                                                            double* __restrict__ B) {
+    __shared__ double t[32][33];
+    const long off = (long)blockIdx.z * M * n;
+    const int i0 = blockIdx.x * 32, p0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int p = p0 + r, i = i0 + tx;
+        t[r][tx] = (p < M && i < n) ? G[off + (long)p * n + i] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int i = i0 + r, p = p0 + tx;
+        if (i < n && p < M) B[off + (long)i * M + p] = t[tx][r];
+    }
+}
+
+// K = alpha sum_s part[s] (fixed order over the S split-k partial products)
+__global__ void sum_parts_kernel(long n, int S, double alpha, const double* __restrict__ part,
+                                 double* __restrict__ K) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int s = 0; s < S; ++s) acc += part[(long)s * n + i];
+    K[i] = alpha * acc;
+}
+
 }  // namespace
 
 // Row-major batched C_b = op(A_b) op(B_b) (strides in elements, 0 = shared operand).
@@ -99,7 +128,7 @@ gw_status fock_jk(Handle* h, int A, int M, const double* L, const double* rho, d
 }
 
 gw_status fock_jk_occ(Handle* h, int A, int M, const double* L, const double* rho, const double* Co, int nocc,
-                      double* J, double* K, double* B, double* v) {
+                      double* J, double* K, double* B, size_t bcap, double* v) {
     const long M2 = (long)M * M;
     const double one = 1.0, zero = 0.0;
     GW_TRY(blas_st(h, rocblas_dgemv(h->blas, rocblas_operation_transpose, (int)M2, A, &one, L, (int)M2, rho, 1, &zero,
@@ -107,8 +136,37 @@ gw_status fock_jk_occ(Handle* h, int A, int M, const double* L, const double* rh
                    "rocblas_dgemv"));
     GW_TRY(blas_st(h, rocblas_dgemv(h->blas, rocblas_operation_none, (int)M2, A, &one, L, (int)M2, v, 1, &zero, J, 1),
                    "rocblas_dgemv"));
-    // B_P = Co L_P (nocc x M), then K = 2 sum_{(P,i)} B[(P,i)][p] B[(P,i)][q]
-    GW_TRY(gemm_rm_batched(h, false, false, nocc, M, M, Co, M, 0, L, M, M2, B, M, (long)nocc * M, A));
+    // B_P = Co L_P (nocc x M), then K = 2 sum_{(P,i)} B[(P,i)][p] B[(P,i)][q].
+    // L_P is symmetric, so B_P^T = L_P Co^T: all P at once as one tall GEMM
+    // G = [L_0; L_1; ...] Co^T ((A M) x nocc), then a per-P transpose; the
+    // batched form is the fallback when B cannot hold both copies.
+    const long bsz = (long)A * M * nocc;
+    if (2 * bsz <= (long)bcap && A <= 65535) {
+        double* G = B + bsz;
+        GW_TRY(gemm_rowmajor(h, false, true, A * M, nocc, M, 1.0, L, M, Co, M, 0.0, G, nocc));
+        hipLaunchKernelGGL(blk_transpose_kernel, dim3((unsigned)((nocc + 31) / 32), (unsigned)((M + 31) / 32), (unsigned)A),
+                           dim3(256), 0, h->stream, M, nocc, (const double*)G, B);
+        GW_CHECK_LAUNCH(h);
+        // K has only (M/128)(M/64) output tiles for a contraction over A nocc
+        // rows: split that sum over S groups of P (S | A) into partial
+        // products in the freed G region, then add them in a fixed order.
+        int S = 1;
+        for (int c = std::min(16, A); c >= 2; --c)
+            if (A % c == 0) {
+                S = c;
+                break;
+            }
+        if (S > 1 && (long)S * M2 <= bsz) {
+            const int kc = (A / S) * nocc;
+            GW_TRY(gemm_rm_batched(h, true, false, M, M, kc, B, M, (long)kc * M, B, M, (long)kc * M, G, M, M2, S));
+            hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((M2 + 255) / 256)), dim3(256), 0, h->stream, M2, S,
+                               2.0, (const double*)G, K);
+            GW_CHECK_LAUNCH(h);
+            return GW_OK;
+        }
+    } else {
+        GW_TRY(gemm_rm_batched(h, false, false, nocc, M, M, Co, M, 0, L, M, M2, B, M, (long)nocc * M, A));
+    }
     return gemm_rowmajor(h, true, false, M, M, A * nocc, 2.0, B, M, B, M, 0.0, K, M);
 }
 

@@ -216,9 +216,10 @@ gw_status fock_jk(Handle* h, int A, int M, const double* L, const double* rho, d
                   double* v);
 // The same with rho = 2 Co^T Co given by its nocc occupied orbitals (rows of
 // Co, length M): K = 2 sum_P (Co L_P)^T (Co L_P), a factor M / nocc fewer
-// flops.  B: nocc * M * A doubles.
+// flops.  B: bcap doubles, at least nocc * M * A (twice that for the
+// one-GEMM form).
 gw_status fock_jk_occ(Handle* h, int A, int M, const double* L, const double* rho, const double* Co, int nocc,
-                      double* J, double* K, double* B, double* v);
+                      double* J, double* K, double* B, size_t bcap, double* v);
 
 // Pulay extrapolation over the last `space` pairs (x_i, e_i): sum_i c_i x_i with
 // sum_i c_i = 1 minimising |sum_i c_i e_i|^2.  Host vectors of length n.

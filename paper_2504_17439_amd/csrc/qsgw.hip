@@ -217,7 +217,7 @@ gw_status qsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
     double last = -1.0;
     // Fock matrix of the current rho (= 2 Co^T Co) plus Vr into F
     auto build_fock = [&]() -> gw_status {
-        GW_TRY(fock_jk_occ(h, A, M, L, rho, Co, nocc, J, K, T, jv));
+        GW_TRY(fock_jk_occ(h, A, M, L, rho, Co, nocc, J, K, T, (size_t)A * M2, jv));
         hipLaunchKernelGGL(qs_comb_kernel, dim3(nbq(M2)), dim3(256), 0, h->stream, M2, hcore, J, 1.0, K, -0.5,
                            (const double*)Vr, F);
         GW_CHECK_LAUNCH(h);

@@ -98,6 +98,14 @@ __global__ void sum_parts_kernel(long n, int S, double alpha, const double* __re
     K[i] = alpha * acc;
 }
 
+// Number of groups of P for a split-k exchange product: the largest divisor
+// of A up to 16 (1 if there is none).
+int split_groups(int A) {
+    for (int c = std::min(16, A); c >= 2; --c)
+        if (A % c == 0) return c;
+    return 1;
+}
+
 }  // namespace
 
 // Row-major batched C_b = op(A_b) op(B_b) (strides in elements, 0 = shared operand).
@@ -122,9 +130,19 @@ gw_status fock_jk(Handle* h, int A, int M, const double* L, const double* rho, d
                    "rocblas_dgemv"));
     GW_TRY(blas_st(h, rocblas_dgemv(h->blas, rocblas_operation_none, (int)M2, A, &one, L, (int)M2, v, 1, &zero, J, 1),
                    "rocblas_dgemv"));
-    // T_P = rho L_P, then K = sum_{(P,r)} T[(P,r)][p] L[(P,r)][q]
+    // T_P = rho L_P, then K = sum_{(P,r)} T[(P,r)][p] L[(P,r)][q]; that sum
+    // runs over A M terms into only (M/128)(M/64) output tiles, so it is split
+    // over groups of P into partial products added in a fixed order.
     GW_TRY(gemm_rm_batched(h, false, false, M, M, M, rho, M, 0, L, M, M2, T, M, M2, A));
-    return gemm_rowmajor(h, true, false, M, M, A * M, 1.0, T, M, L, M, 0.0, K, M);
+    const int S = split_groups(A);
+    double* part = S > 1 ? (double*)ws_get(h, WS_KPART, sizeof(double) * S * M2) : nullptr;
+    if (!part) return gemm_rowmajor(h, true, false, M, M, A * M, 1.0, T, M, L, M, 0.0, K, M);
+    const int kc = (A / S) * M;
+    GW_TRY(gemm_rm_batched(h, true, false, M, M, kc, T, M, (long)kc * M, L, M, (long)kc * M, part, M, M2, S));
+    hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((M2 + 255) / 256)), dim3(256), 0, h->stream, M2, S, 1.0,
+                       (const double*)part, K);
+    GW_CHECK_LAUNCH(h);
+    return GW_OK;
 }
 
 gw_status fock_jk_occ(Handle* h, int A, int M, const double* L, const double* rho, const double* Co, int nocc,
@@ -150,12 +168,7 @@ gw_status fock_jk_occ(Handle* h, int A, int M, const double* L, const double* rh
         // K has only (M/128)(M/64) output tiles for a contraction over A nocc
         // rows: split that sum over S groups of P (S | A) into partial
         // products in the freed G region, then add them in a fixed order.
-        int S = 1;
-        for (int c = std::min(16, A); c >= 2; --c)
-            if (A % c == 0) {
-                S = c;
-                break;
-            }
+        const int S = split_groups(A);
         if (S > 1 && (long)S * M2 <= bsz) {
             const int kc = (A / S) * nocc;
             GW_TRY(gemm_rm_batched(h, true, false, M, M, kc, B, M, (long)kc * M, B, M, (long)kc * M, G, M, M2, S));

@@ -50,6 +50,7 @@ enum WsSlot {
     WS_MIX0, WS_MIX1, WS_MIX2, WS_MIX3, WS_MIX4, WS_MIX5, WS_MIX6,
     WS_FS0, WS_FS1, WS_FS2, WS_FS3, WS_FS4, WS_FS5, WS_FS6, WS_FS7,
     WS_RC0, WS_RC1, WS_RC2, WS_RC3, WS_RC4, WS_RC5,
+    WS_KPART,
     WS_COUNT
 };
 

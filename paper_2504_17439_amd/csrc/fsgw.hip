@@ -136,7 +136,11 @@ gw_status fock_jk(Handle* h, int A, int M, const double* L, const double* rho, d
     GW_TRY(gemm_rm_batched(h, false, false, M, M, M, rho, M, 0, L, M, M2, T, M, M2, A));
     const int S = split_groups(A);
     double* part = S > 1 ? (double*)ws_get(h, WS_KPART, sizeof(double) * S * M2) : nullptr;
-    if (!part) return gemm_rowmajor(h, true, false, M, M, A * M, 1.0, T, M, L, M, 0.0, K, M);
+    if (!part) {
+        // no room for the partial products: the unsplit product (same result)
+        if (S > 1) h->last_error.clear();
+        return gemm_rowmajor(h, true, false, M, M, A * M, 1.0, T, M, L, M, 0.0, K, M);
+    }
     const int kc = (A / S) * M;
     GW_TRY(gemm_rm_batched(h, true, false, M, M, kc, T, M, (long)kc * M, L, M, (long)kc * M, part, M, M2, S));
     hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((M2 + 255) / 256)), dim3(256), 0, h->stream, M2, S, 1.0,

@@ -140,6 +140,31 @@ gw_status gw_sigma_from_R(gw_handle h, int nocc, int nvir, int naux, int nmom_ma
                           double* sigma_occ, double* sigma_vir);
 
 /*
+ * Allocation-free self-energy moments, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same result as gw_sigma_moments with
+ * GW_TDA screening and GW_FP64 precision (half-order moments, then both
+ * contraction stages), computed with the same kernels; every scratch buffer
+ * (V, D, X, R_t, split-K partials, the folded intermediate) is carved from
+ * one static device array of GW_NOALLOC_SCRATCH_BYTES per device, which the
+ * library holds until the process ends.  The call itself allocates no device
+ * memory and calls no allocating library routine; the caller passes eps, L
+ * and the outputs sigma_occ, sigma_vir [nmom_max+1][nmo][nmo] as in
+ * gw_sigma_moments.  Returns GW_EINVAL (nothing launched) when the system's
+ * buffers do not fit the static array: roughly
+ *   8 (2 naux nocc nvir + (nmom_max+2) naux^2 + (nmom_max+1) naux nmo
+ *      + 2 (nmom_max+1) nmo^2) bytes must not exceed it.
+ * Every call on one device shares that device's array and leaves its
+ * contents behind (the path clears what must start at zero itself): calls
+ * that overlap on one device race, whatever their handles or streams.
+ */
+#define GW_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+gw_status gw_sigma_moments_noalloc(gw_handle h, int nocc, int nvir, int naux, int nmom_max,
+                                   const double* eps, const double* L,
+                                   double* sigma_occ, double* sigma_vir);
+
+/*
  * Auxiliary poles and upfolded Hamiltonian (eq. effH; eqs. ret_GF and
  * quasiparticle_energy_update), all FP64 on the device.
  * Per sector, block Lanczos on the moments gives (nmom_max+1)/2 blocks;

@@ -39,6 +39,18 @@ void* ws_get(Handle* h, int slot, size_t bytes) {
     return b.ptr;
 }
 
+double* scratch_get(Handle* h, const Scratch& s, size_t n) {
+    if (s.slot >= 0) return (double*)ws_get(h, s.slot, sizeof(double) * std::max<size_t>(n, 1));
+    if (n > s.cap || !s.ptr) {
+        set_err(h, GW_ENOMEM, "fixed scratch region too small (" + std::to_string(n) + " doubles needed, " +
+                                  std::to_string(s.cap) + " available)");
+        return nullptr;
+    }
+    return s.ptr;
+}
+
+size_t scratch_max(const Scratch& s) { return s.slot >= 0 ? SIZE_MAX : s.cap; }
+
 KTimer::KTimer(Handle* hh, const char* family) : h(hh) {
     if (!h->timing || !family) return;
     TimedLaunch t;
@@ -138,6 +150,12 @@ gw_status gw_create(gw_handle* out, int device) {
         return GW_ELIB;
     }
     rocblas_set_stream(h->blas, h->stream);
+    // device address of the allocation-free entry point's static scratch, once
+    // per device (a failure is reported by that entry point, not here)
+    {
+        std::string ignored;
+        (void)gwm::noalloc_resolve(device, &ignored);
+    }
     *out = h;
     return GW_OK;
 }
@@ -264,6 +282,15 @@ gw_status gw_sigma_moments(gw_handle h, gw_screening screening, int nocc, int nv
     if (prec == GW_MIXED)
         return gwm::sigma_from_R_mixed(h, nocc, nvir, naux, nmom_max, eps, L, R, opts, sigma_occ, sigma_vir);
     return gwm::sigma_from_R_f64(h, nocc, nvir, naux, nmom_max, eps, L, R, opts, sigma_occ, sigma_vir);
+}
+
+gw_status gw_sigma_moments_noalloc(gw_handle h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                                   const double* L, double* sigma_occ, double* sigma_vir) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    GW_TRY(validate_common(h, nocc, nvir, naux, nmom_max, eps, L));
+    if (!sigma_occ || !sigma_vir) return gwm::set_err(h, GW_EINVAL, "sigma outputs must be non-null");
+    return gwm::sigma_moments_noalloc(h, nocc, nvir, naux, nmom_max, eps, L, sigma_occ, sigma_vir);
 }
 
 gw_status gw_poles(gw_handle h, int nmo, int nmom_max, const double* sigma_occ, const double* sigma_vir,

@@ -246,6 +246,16 @@ void plan_split(GemmF64& g, int target_wg) {
     g.kchunk = std::max(chunk, TBK);
 }
 
+void limit_split(GemmF64& g, size_t max_doubles) {
+    const size_t per = (size_t)std::max(g.batch, 1) * (size_t)std::max<long>(g.c_ps, 1);
+    if ((size_t)g.nsplit * per <= max_doubles) return;
+    int ns = (int)std::max<size_t>(1, max_doubles / per);
+    int chunk = (g.K + ns - 1) / ns;
+    chunk = (chunk + TBK - 1) / TBK * TBK;
+    g.kchunk = std::max(chunk, TBK);
+    g.nsplit = std::max(1, (g.K + g.kchunk - 1) / g.kchunk);
+}
+
 gw_status gemm_f64(Handle* h, const GemmF64& g0) {
     GemmF64 g = g0;
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return GW_OK;

@@ -57,6 +57,19 @@ enum WsSlot {
 // Returns nullptr on failure (and records the message).
 void* ws_get(Handle* h, int slot, size_t bytes);
 
+// Device scratch of doubles: a handle workspace slot (grown on demand), or a
+// fixed region supplied by the caller (slot < 0), which never grows.
+struct Scratch {
+    int slot = -1;
+    double* ptr = nullptr;
+    size_t cap = 0;  // doubles, fixed region only
+};
+// Pointer to at least n doubles, or nullptr (a fixed region that is too small,
+// or a failed allocation; the message is recorded).
+double* scratch_get(Handle* h, const Scratch& s, size_t n);
+// Largest request scratch_get can serve (SIZE_MAX for a workspace slot).
+size_t scratch_max(const Scratch& s);
+
 // Error plumbing: every internal routine returns gw_status.
 gw_status set_err(Handle* h, gw_status st, const std::string& msg);
 
@@ -132,6 +145,9 @@ gw_status gemm_f64(Handle* h, const GemmF64& g);
 
 // Choose nsplit / kchunk so that the launch has at least `target_wg` groups.
 void plan_split(GemmF64& g, int target_wg);
+// Lower nsplit (re-chunking K) so that the partials, nsplit * batch * c_ps
+// doubles, fit in max_doubles; nsplit stays >= 1.
+void limit_split(GemmF64& g, size_t max_doubles);
 
 // out[b][m][n] = alpha * sum_s part[(b*nsplit+s)*ps + m*ld + n] (+ diag on m == n),
 // read from the upper triangle (m <= n) when `mirror`, which makes out exactly symmetric.
@@ -165,7 +181,20 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
 gw_status tda_moments_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max,
                           const double* eps, const double* L, double* R, double* eta);
 
-// TDA moments R[nmom_max+1][naux][naux] with digit-split (BF16 / FP32 / FP64) products.
+// The half-order FP64 TDA moments on caller buffers: V [naux][ov], D [ov],
+// X [naux][ov], split-K partials in `part` (at least naux^2 doubles).
+gw_status tda_moments_half_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                               const double* L, double* R, double* V, double* D, double* X, const Scratch& part);
+
+// FP64 self-energy moments from R_t on caller buffers: the folded
+// intermediate in `zt` (at least (nmom_max+1) naux nmo doubles: one x per
+// chunk; at most zchunk_bytes per chunk) and the contraction's split
+// partials in `acc` (at least 2 (nmom_max+1) nmo^2 doubles).
+gw_status sigma_from_R_f64_bufs(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                                const double* L, const double* R, size_t zchunk_bytes, const Scratch& zt,
+                                const Scratch& acc, double* sigma_occ, double* sigma_vir);
+
+// TDA moments R[nmom_max+1][naux][naux] with int8 digit products (mixed precision).
 gw_status tda_moments_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_max,
                             const double* eps, const double* L, double* R);
 
@@ -339,6 +368,12 @@ gw_status evgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int na
 gw_status fsgw_run(Handle* h, gw_screening screening, int nocc, int nvir, int naux, int nmom_max, const double* eps,
                    const double* L, const double* F0, gw_precision prec, const gw_opts* opts,
                    const gw_fsgw_opts* fo, double* F, double* qp_e, double* qp_w, gw_fsgw_info* info);
+
+// Allocation-free FP64 TDA self-energy moments on the library's static
+// scratch (noalloc.hip); noalloc_resolve finds the scratch on the current device.
+gw_status noalloc_resolve(int device, std::string* err);
+gw_status sigma_moments_noalloc(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                                const double* L, double* sigma_occ, double* sigma_vir);
 
 gw_status batch_create(Handle* h, int nsys, const gw_system* sys, gw_screening screening, int nmom_max,
                        gw_precision prec, const gw_opts* opts, const gw_batch_opts* bo, gw_batch* out);

@@ -59,9 +59,9 @@ gw_status gather_ov(Handle* h, int nocc, int nvir, int naux, const double* eps, 
 }
 
 // R = X diag(s) V^T (symmetric when X = V or s = 1 with X V^T symmetric):
-// upper tiles, split-K partials, mirrored reduction.  s is nullable.
+// upper tiles, split-K partials in `part`, mirrored reduction.  s is nullable.
 static gw_status syrk_xvt(Handle* h, int naux, long ov, const double* X, const double* V, double* R,
-                          const double* s = nullptr) {
+                          const Scratch& part, const double* s = nullptr) {
     GemmF64 g;
     g.M = naux; g.N = naux; g.K = (int)ov;
     g.a_kc = true; g.A = X; g.lda = ov; g.ascale = s;
@@ -69,13 +69,14 @@ static gw_status syrk_xvt(Handle* h, int naux, long ov, const double* X, const d
     g.sym_upper = true;
     g.epi = EPI_PARTIAL;
     g.tag = "recur_xvt";
-    plan_split(g, 1024);
     g.ldc = naux; g.c_ps = (long)naux * naux;
-    double* part = (double*)ws_get(h, WS_SPLIT, sizeof(double) * g.nsplit * g.c_ps);
-    if (!part) return GW_ENOMEM;
-    g.C = part;
+    plan_split(g, 1024);
+    limit_split(g, scratch_max(part));
+    double* buf = scratch_get(h, part, (size_t)g.nsplit * g.c_ps);
+    if (!buf) return set_err(h, GW_ENOMEM, "syrk_xvt: split-K scratch too small");
+    g.C = buf;
     GW_TRY(gemm_f64(h, g));
-    return reduce_splits(h, part, g.nsplit, g.c_ps, 1, naux, naux, naux, true, 1.0, 0.0, R, 0, naux);
+    return reduce_splits(h, buf, g.nsplit, g.c_ps, 1, naux, naux, naux, true, 1.0, 0.0, R, 0, naux);
 }
 
 // Xn = cs o (alpha * R V + dg o X)   (row-wise: every column ia scaled)
@@ -98,16 +99,16 @@ static gw_status update_rv(Handle* h, int naux, long ov, const double* R, const 
 //   R_{2k+1} = V A^{2k+1} V^T = X_k D X_k^T + 2 R_k R_k
 // so only X_0 .. X_{N/2} are formed (22 instead of 34 naux^2 ov flop units at N = 11).
 static gw_status tda_moments_half(Handle* h, int naux, long ov, int nmom_max, const double* V, const double* D,
-                                  double* X, double* R) {
+                                  double* X, double* R, const Scratch& part) {
     const long asz = (long)naux * naux;
     const long xsz = (long)naux * ov;
     GW_TRY(copy_f64(h, X, V, xsz));
     const int K = nmom_max / 2;
     for (int k = 0; k <= K; ++k) {
-        if (2 * k <= nmom_max) GW_TRY(syrk_xvt(h, naux, ov, X, X, R + 2 * k * asz));
+        if (2 * k <= nmom_max) GW_TRY(syrk_xvt(h, naux, ov, X, X, R + 2 * k * asz, part));
         if (2 * k + 1 <= nmom_max) {
             double* Ro = R + (2 * k + 1) * asz;
-            GW_TRY(syrk_xvt(h, naux, ov, X, X, Ro, D));
+            GW_TRY(syrk_xvt(h, naux, ov, X, X, Ro, part, D));
             // Ro += 2 R_k R_k   (R_k is complete: k <= 2k)
             GemmF64 g;
             g.M = naux; g.N = naux; g.K = naux;
@@ -123,6 +124,13 @@ static gw_status tda_moments_half(Handle* h, int naux, long ov, int nmom_max, co
     return GW_OK;
 }
 
+gw_status tda_moments_half_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                               const double* L, double* R, double* V, double* D, double* X, const Scratch& part) {
+    const long ov = (long)nocc * nvir;
+    GW_TRY(gather_ov(h, nocc, nvir, naux, eps, L, V, D));
+    return tda_moments_half(h, naux, ov, nmom_max, V, D, X, R, part);
+}
+
 gw_status tda_moments_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
                           const double* L, double* R, double* eta) {
     const long ov = (long)nocc * nvir;
@@ -134,7 +142,7 @@ gw_status tda_moments_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max,
     if (!eta) {
         double* X = (double*)ws_get(h, WS_X0, sizeof(double) * xsz);
         if (!X) return GW_ENOMEM;
-        return tda_moments_half(h, naux, ov, nmom_max, V, D, X, R);
+        return tda_moments_half(h, naux, ov, nmom_max, V, D, X, R, Scratch{WS_SPLIT});
     }
     double* xb[2] = {nullptr, nullptr};
     if (!eta) {
@@ -147,7 +155,7 @@ gw_status tda_moments_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max,
     const double* Xc = eta ? eta : V;
     const long asz = (long)naux * naux;
     for (int n = 0; n <= nmom_max; ++n) {
-        GW_TRY(syrk_xvt(h, naux, ov, Xc, V, R + n * asz));
+        GW_TRY(syrk_xvt(h, naux, ov, Xc, V, R + n * asz, Scratch{WS_SPLIT}));
         if (n == nmom_max) break;
         double* Xn = eta ? eta + (n + 1) * xsz : xb[n & 1];
         GW_TRY(update_rv(h, naux, ov, R + n * asz, V, 2.0, Xc, D, nullptr, Xn));

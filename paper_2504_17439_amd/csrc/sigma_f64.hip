@@ -172,23 +172,25 @@ gw_status sigma_fold_f64(Handle* h, int nt, int naux, int nmo, int nocc, const d
     return GW_OK;
 }
 
-gw_status sigma_from_R_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
-                           const double* L, const double* R, const gw_opts* opts, double* sigma_occ,
-                           double* sigma_vir) {
+gw_status sigma_from_R_f64_bufs(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                                const double* L, const double* R, size_t zchunk_bytes, const Scratch& zt,
+                                const Scratch& accs, double* sigma_occ, double* sigma_vir) {
     const int nmo = nocc + nvir;
     const int nt = nmom_max + 1;
     const long nmo2 = (long)nmo * nmo;
-    size_t cap = (opts && opts->zchunk_bytes) ? opts->zchunk_bytes : ((size_t)8 << 30);
-    size_t per_x = (size_t)nt * naux * nmo * sizeof(double);
-    int nx = (int)std::max<size_t>(1, std::min<size_t>((size_t)nmo, cap / per_x));
-    double* Zt = (double*)ws_get(h, WS_Z, per_x * nx);
+    const size_t per_x = (size_t)nt * naux * nmo;  // doubles of the folded intermediate per x
+    size_t nxc = std::min<size_t>((size_t)nmo, std::max<size_t>(1, zchunk_bytes / (per_x * sizeof(double))));
+    nxc = std::min(nxc, std::max<size_t>(1, scratch_max(zt) / per_x));
+    const int nx = (int)nxc;
+    double* Zt = scratch_get(h, zt, per_x * nx);
     if (!Zt) return GW_ENOMEM;
 
     const int T = (nmo + 127) / 128;
     const int tiles = T * (T + 1) / 2;
     int S = std::max(1, std::min(64, (1024 + tiles * nt - 1) / (tiles * nt)));
+    S = (int)std::min<size_t>((size_t)S, std::max<size_t>(1, scratch_max(accs) / (2 * (size_t)nt * nmo2)));
     const long part_per_sector = (long)nt * S * nmo2;
-    double* acc = (double*)ws_get(h, WS_SIGACC, sizeof(double) * 2 * part_per_sector);
+    double* acc = scratch_get(h, accs, (size_t)2 * part_per_sector);
     if (!acc) return GW_ENOMEM;
     GW_TRY(fill_f64(h, acc, (size_t)2 * part_per_sector, 0.0));
 
@@ -219,6 +221,14 @@ gw_status sigma_from_R_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max
     GW_TRY(reduce_splits(h, acc + part_per_sector, S, nmo2, nt, nmo, nmo, nmo, true, 1.0, 0.0, sigma_vir,
                          nmo2, nmo));
     return GW_OK;
+}
+
+gw_status sigma_from_R_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
+                           const double* L, const double* R, const gw_opts* opts, double* sigma_occ,
+                           double* sigma_vir) {
+    const size_t cap = (opts && opts->zchunk_bytes) ? opts->zchunk_bytes : ((size_t)8 << 30);
+    return sigma_from_R_f64_bufs(h, nocc, nvir, naux, nmom_max, eps, L, R, cap, Scratch{WS_Z}, Scratch{WS_SIGACC},
+                                 sigma_occ, sigma_vir);
 }
 
 }  // namespace gwm

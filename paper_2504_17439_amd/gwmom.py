@@ -25,7 +25,8 @@ _STATUS = {GW_EINVAL: "GW_EINVAL", GW_ENOMEM: "GW_ENOMEM", GW_EHIP: "GW_EHIP",
 
 # every symbol declared in include/gwmom.h
 EXPORTS = ("gw_create", "gw_set_stream", "gw_synchronize", "gw_destroy", "gw_last_error",
-           "gw_moments_tda", "gw_moments_rpa", "gw_sigma_moments", "gw_sigma_from_R", "gw_poles",
+           "gw_moments_tda", "gw_moments_rpa", "gw_sigma_moments", "gw_sigma_from_R", "gw_sigma_moments_noalloc",
+           "gw_poles",
            "gw_fsgw", "gw_evgw", "gw_naf", "gw_qsgw", "gw_spectral", "gw_aufbau", "gw_zeta_shift", "gw_batch_create", "gw_batch_run", "gw_batch_info", "gw_batch_destroy",
            "gw_mlp_param_count", "gw_mlp_features", "gw_mlp_forward", "gw_mlp_backward",
            "gw_mlp_adam", "gw_timing_enable", "gw_timing_reset", "gw_timing_read")
@@ -123,6 +124,7 @@ def load_library(path: str = LIB_PATH):
         "gw_moments_rpa": ([H, I, I, I, I, P, P, I, P, P, P], I),
         "gw_sigma_moments": ([H, I, I, I, I, I, P, P, I, P, P, P], I),
         "gw_sigma_from_R": ([H, I, I, I, I, P, P, P, I, P, P, P], I),
+        "gw_sigma_moments_noalloc": ([H, I, I, I, I, P, P, P, P], I),
         "gw_poles": ([H, I, I, P, P, P, P, ctypes.POINTER(I), ctypes.POINTER(I), P, P, P, P, P, P], I),
         "gw_fsgw": ([H, I, I, I, I, I, P, P, P, I, P, P, P, P, P, P], I),
         "gw_evgw": ([H, I, I, I, I, I, P, P, I, P, P, P, P, P], I),
@@ -271,6 +273,22 @@ class Handle:
         scr = GW_TDA if screening == "tda" else GW_RPA
         self._call("gw_sigma_moments", scr, nocc, nmo - nocc, naux, nmom_max, _ptr(eps), _ptr(L),
                    _prec(precision), _opts(opts), _ptr(so), _ptr(sv))
+        return so, sv
+
+    def sigma_moments_noalloc(self, eps, L, nocc, nmom_max, out=None):
+        """FP64 TDA self-energy moments on the library's static scratch (the
+        call allocates no device memory; outputs come from `out` or torch)."""
+        naux, nmo = L.shape[0], L.shape[1]
+        _check_dev(eps, "eps", (nmo,))
+        _check_dev(L, "L", (naux, nmo, nmo))
+        if out is None:
+            so, sv = self._new(nmom_max + 1, nmo, nmo), self._new(nmom_max + 1, nmo, nmo)
+        else:
+            so, sv = out
+            _check_dev(so, "sigma_occ", (nmom_max + 1, nmo, nmo))
+            _check_dev(sv, "sigma_vir", (nmom_max + 1, nmo, nmo))
+        self._call("gw_sigma_moments_noalloc", nocc, nmo - nocc, naux, nmom_max, _ptr(eps), _ptr(L), _ptr(so),
+                   _ptr(sv))
         return so, sv
 
     def sigma_from_R(self, eps, L, R, nocc, precision="fp64", opts=None):

@@ -143,6 +143,11 @@ gw_status gw_create(gw_handle* out, int device) {
         return GW_EHIP;
     }
     h->stream = h->own_stream;
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+            h->cus = cus;
+    }
     if (rocblas_create_handle(&h->blas) != rocblas_status_success) {
         g_static_err = "gw_create: rocblas_create_handle failed";
         (void)hipStreamDestroy(h->own_stream);

@@ -34,6 +34,7 @@ struct Handle {
     bool timing = false;
     std::vector<TimedLaunch> timed;
     int device = 0;
+    int cus = 256;           // compute units of the device (split planning)
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
     rocblas_handle blas = nullptr;
@@ -50,7 +51,7 @@ enum WsSlot {
     WS_MIX0, WS_MIX1, WS_MIX2, WS_MIX3, WS_MIX4, WS_MIX5, WS_MIX6,
     WS_FS0, WS_FS1, WS_FS2, WS_FS3, WS_FS4, WS_FS5, WS_FS6, WS_FS7,
     WS_RC0, WS_RC1, WS_RC2, WS_RC3, WS_RC4, WS_RC5,
-    WS_KPART,
+    WS_KPART, WS_RPA_PART,
     WS_COUNT
 };
 
@@ -110,7 +111,6 @@ struct KTimer {
 // Operand B:
 //   b_kc = true :  B(k,n) = B[n*ldb + k]
 //   b_kc = false:  B(k,n) = B[b_off + (k/b_kdiv)*b_khi + (k%b_kdiv)*b_klo + n]
-//   bscale (b_kc false only, nullable): B(k,n) *= bscale[(k/b_kdiv)*bscale_ld + n]
 // Batch b adds a_bs*b, b_bs*b, c_bs*b to the A, B, C base pointers.
 // Split s of nsplit covers k in [s*kchunk, min(K, (s+1)*kchunk)).
 // sym_upper: only 128x128 tiles with tile_row <= tile_col are computed (M == N).
@@ -127,7 +127,6 @@ struct GemmF64 {
     const double* A = nullptr; long lda = 0; long a_off = 0, a_kdiv = 1L << 62, a_khi = 0, a_klo = 0;
     const double* ascale = nullptr; long ascale_bs = 0;
     const double* B = nullptr; long ldb = 0; long b_off = 0, b_kdiv = 1L << 62, b_khi = 0, b_klo = 0;
-    const double* bscale = nullptr; long bscale_ld = 0;
     long a_bs = 0, b_bs = 0, c_bs = 0;
     int nsplit = 1; int kchunk = 0;
     bool sym_upper = false;
@@ -143,11 +142,23 @@ struct GemmF64 {
 
 gw_status gemm_f64(Handle* h, const GemmF64& g);
 
-// Choose nsplit / kchunk so that the launch has at least `target_wg` groups.
-void plan_split(GemmF64& g, int target_wg);
+// Choose nsplit / kchunk for a launch on `slots` concurrent work groups (two
+// per CU): the split count minimising (rounds of work groups) x (K per work
+// group), the smaller count on near ties (fewer partials to reduce).
+void plan_split(GemmF64& g, int slots);
+// The same choice for `items` independent work items of K each.
+int best_splits(long items, int K, int slots, int max_ns);
 // Lower nsplit (re-chunking K) so that the partials, nsplit * batch * c_ps
 // doubles, fit in max_doubles; nsplit stays >= 1.
 void limit_split(GemmF64& g, size_t max_doubles);
+
+// Node sum of the RPA quadrature on the FP64 MFMA:
+//   G[P][ia] = X0[P][ia] d0[ia] + sum_{b < nb} sum_Q S[b][P][Q] V[Q][ia] gtab[b][ia]
+// S [nb][naux][naux], V and X0 [naux][ov], gtab [nb][ov], d0 [ov]; node groups
+// accumulate into partials in `part` (up to 8 x naux x ov doubles), reduced
+// in a fixed order.
+gw_status node_sum_f64(Handle* h, int naux, long ov, int nb, const double* S, const double* V, const double* gtab,
+                       const double* X0, const double* d0, double* G, const Scratch& part);
 
 // out[b][m][n] = alpha * sum_s part[(b*nsplit+s)*ps + m*ld + n] (+ diag on m == n),
 // read from the upper triangle (m <= n) when `mirror`, which makes out exactly symmetric.

@@ -70,7 +70,7 @@ static gw_status syrk_xvt(Handle* h, int naux, long ov, const double* X, const d
     g.epi = EPI_PARTIAL;
     g.tag = "recur_xvt";
     g.ldc = naux; g.c_ps = (long)naux * naux;
-    plan_split(g, 1024);
+    plan_split(g, 2 * h->cus);
     limit_split(g, scratch_max(part));
     double* buf = scratch_get(h, part, (size_t)g.nsplit * g.c_ps);
     if (!buf) return set_err(h, GW_ENOMEM, "syrk_xvt: split-K scratch too small");

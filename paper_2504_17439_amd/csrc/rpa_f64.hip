@@ -8,8 +8,9 @@
 //
 // All 2n aux-space matrices (Q_j and T_j = V D E_j V^T) come from ONE batched
 // symmetric product; (I+Q_j)^-1 from one batched Cholesky; and the 2n
-// contributions to G from ONE GEMM whose K index runs over (node, Q) with the
-// per-node column factors F_j / E_j applied while the V tile is loaded.
+// contributions to G from ONE launch whose K index runs over (Q block, node),
+// node innermost, with the per-node column factors F_j / E_j applied to the
+// V fragments in registers (node_sum_f64).
 // Recursion: eta~^{(1)} = V D, eta~^{(n)} = D o (4 R_{n-2} V + D o eta~^{(n-2)}).
 #include "internal.h"
 
@@ -128,7 +129,7 @@ gw_status batched_sym(Handle* h, int naux, long ov, int batch, const double* V, 
     g.sym_upper = true;
     g.epi = EPI_PARTIAL;
     g.tag = "rpa_quad";
-    plan_split(g, 1024);
+    plan_split(g, 2 * h->cus);
     g.ldc = naux; g.c_ps = (long)naux * naux;
     double* part = (double*)ws_get(h, WS_SPLIT, sizeof(double) * (size_t)g.nsplit * batch * g.c_ps);
     if (!part) return GW_ENOMEM;
@@ -196,11 +197,6 @@ static gw_status rpa_eta0_f64(Handle* h, int nocc, int nvir, int naux, const dou
     }
     // Q_j (b < nq) and T_j (b >= nq) in one batched symmetric product
     GW_TRY(batched_sym(h, naux, ov, 2 * nq, V, as, 1.0, 0.0, QT));
-    // scratch for the column-scaled copies of V in the G accumulation below
-    double* Vb = (double*)ws_get(h, WS_X1, sizeof(double) * naux * ov);
-    if (!Vb) return GW_ENOMEM;
-    const long xsz = (long)naux * ov;
-    const unsigned xblk = (unsigned)((xsz + 255) / 256);
     // (I + Q_j)^-1 by batched Cholesky
     GW_TRY(copy_f64(h, Minv, QT, (size_t)nq * n2));
     {
@@ -229,21 +225,9 @@ static gw_status rpa_eta0_f64(Handle* h, int nocc, int nvir, int naux, const dou
                            nq, naux, dcoef, Minv, QT);
         GW_CHECK_LAUNCH(h);
     }
-    // G = V o D + sum_b S_b (V o g_b): per node one rocBLAS GEMM accumulating
-    // into G (beta = 1), the column scaling g_b applied to a scratch copy of V
-    {
-        KTimer tm(h, "rpa_quad");
-        hipLaunchKernelGGL(scale_cols_kernel, dim3(xblk), dim3(256), 0, h->stream, (long)naux, ov, V, D, G);
-        GW_CHECK_LAUNCH(h);
-        for (int b = 0; b < 2 * nq; ++b) {
-            hipLaunchKernelGGL(scale_cols_kernel, dim3(xblk), dim3(256), 0, h->stream, (long)naux, ov, V,
-                               bs + (long)b * ov, Vb);
-            GW_CHECK_LAUNCH(h);
-            GW_TRY(gemm_rowmajor(h, false, false, naux, (int)ov, naux, 1.0, QT + b * n2, naux, Vb, (int)ov, 1.0, G,
-                                 (int)ov));
-        }
-        tm.stop();
-    }
+    // G = V o D + sum_b S_b (V o g_b): one launch over all nodes, the node
+    // index innermost in K so that each V slab is loaded once for all nodes
+    GW_TRY(node_sum_f64(h, naux, ov, 2 * nq, QT, V, bs, V, D, G, Scratch{WS_RPA_PART}));
     // Woodbury: Hm = (G o D^-1) V^T, Pm = I + 4 (V o D^-1) V^T, Y = Hm Pm^-1,
     // eta~0 = D^-1 o (G - 4 Y V)
     double* Dinv = as;  // the quadrature scale tables are no longer needed
@@ -260,7 +244,7 @@ static gw_status rpa_eta0_f64(Handle* h, int nocc, int nvir, int naux, const dou
         g.a_kc = true; g.A = G; g.lda = ov; g.ascale = Dinv;
         g.b_kc = true; g.B = V; g.ldb = ov;
         g.epi = EPI_PARTIAL;
-        plan_split(g, 1024);
+        plan_split(g, 2 * h->cus);
         g.ldc = naux; g.c_ps = n2;
         double* part = (double*)ws_get(h, WS_SPLIT, sizeof(double) * (size_t)g.nsplit * n2);
         if (!part) return GW_ENOMEM;
@@ -344,7 +328,7 @@ gw_status rpa_moments_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max,
         g.sym_upper = true;
         g.epi = EPI_PARTIAL;
         g.tag = "recur_xvt";
-        plan_split(g, 1024);
+        plan_split(g, 2 * h->cus);
         g.ldc = naux; g.c_ps = n2;
         double* part = (double*)ws_get(h, WS_SPLIT, sizeof(double) * (size_t)g.nsplit * n2);
         if (!part) return GW_ENOMEM;

@@ -187,7 +187,7 @@ gw_status sigma_from_R_f64_bufs(Handle* h, int nocc, int nvir, int naux, int nmo
 
     const int T = (nmo + 127) / 128;
     const int tiles = T * (T + 1) / 2;
-    int S = std::max(1, std::min(64, (1024 + tiles * nt - 1) / (tiles * nt)));
+    int S = best_splits((long)tiles * nt, naux * std::max(nocc, nvir), 2 * h->cus, 64);
     S = (int)std::min<size_t>((size_t)S, std::max<size_t>(1, scratch_max(accs) / (2 * (size_t)nt * nmo2)));
     const long part_per_sector = (long)nt * S * nmo2;
     double* acc = scratch_get(h, accs, (size_t)2 * part_per_sector);

@@ -6,7 +6,11 @@ itself, written by this script (which calls only ``oracle/`` and the seeded
 input generator): a later change to the oracle's arithmetic shows up as a
 mismatch in ``tests/test_oracle_golden.py`` and has to be justified.
 
-    python tests/golden/make_golden.py
+    python tests/golden/make_golden.py [small] [c3_tda] [c3_rpa]
+
+The full-size fixtures (``c3_*.npz``: sampled rows and QP energies at nocc=100,
+nvir=400, naux=1500, nmom_max=11) take minutes of CPU; the GPU tests at that
+size compare the device against them instead of running the oracle there.
 """
 import os
 import sys
@@ -36,6 +40,31 @@ def c1_tda():
     return "\n".join(lines) + "\n"
 
 
+C3 = (100, 400, 1500, 11)                 # nocc, nvir, naux, nmom_max of the full-size configuration
+C3_R_ROWS = [0, 733, 1499]                 # sampled rows P of every R_n
+C3_SIGMA_ROWS = [0, 57, 99, 100, 101, 250, 499]   # deepest hole, HOMO, LUMO, ..., highest virtual
+
+
+def c3_fixture(screening):
+    """Oracle one-shot GW at nocc=100, nvir=400, naux=1500, nmom_max=11 (seed 0):
+    sampled rows of every R_n and of both self-energy moment sectors, and the
+    QP energies / weights of every orbital from the oracle's block Lanczos and
+    upfolded diagonalisation.  Minutes of CPU (RPA: the 48-node quadrature)."""
+    o, v, A, N = C3
+    eps, L = gwsynth.system(o, v, A, 0)
+    r = gw.g0w0(eps, L, o, N, screening)
+    R = np.asarray(r["R"])
+    return dict(
+        nocc=o, nvir=v, naux=A, nmom_max=N, seed=0,
+        r_rows=np.array(C3_R_ROWS), R_rows=R[:, C3_R_ROWS, :],
+        sigma_rows=np.array(C3_SIGMA_ROWS),
+        so_rows=r["sigma_occ"][:, C3_SIGMA_ROWS, :], sv_rows=r["sigma_vir"][:, C3_SIGMA_ROWS, :],
+        so_absmax=np.abs(r["sigma_occ"]).reshape(N + 1, -1).max(axis=1),
+        sv_absmax=np.abs(r["sigma_vir"]).reshape(N + 1, -1).max(axis=1),
+        R_absmax=np.abs(R).reshape(N + 1, -1).max(axis=1),
+        qp=r["qp"], qp_weight=r["qp_weight"])
+
+
 def exact_tiny():
     """Exact full-frequency one-shot GW by brute force: nocc=1, nvir=2, naux=3, seed 5, amp 1."""
     out = []
@@ -51,8 +80,13 @@ def exact_tiny():
 
 
 if __name__ == "__main__":
-    with open(os.path.join(HERE, "c1_tda_g0w0.txt"), "w") as f:
-        f.write(c1_tda())
-    with open(os.path.join(HERE, "exact_tiny_g0w0.txt"), "w") as f:
-        f.write(exact_tiny())
-    print("written")
+    which = sys.argv[1:] or ["small", "c3_tda", "c3_rpa"]
+    if "small" in which:
+        with open(os.path.join(HERE, "c1_tda_g0w0.txt"), "w") as f:
+            f.write(c1_tda())
+        with open(os.path.join(HERE, "exact_tiny_g0w0.txt"), "w") as f:
+            f.write(exact_tiny())
+    for scr in ("tda", "rpa"):
+        if f"c3_{scr}" in which:
+            np.savez_compressed(os.path.join(HERE, f"c3_{scr}_g0w0.npz"), **c3_fixture(scr))
+    print("written", " ".join(which))

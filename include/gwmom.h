@@ -60,7 +60,8 @@ typedef struct {
     double quad_scale;  /* RPA grid scale s in z = s(1+x)/(1-x); <= 0 -> median(D)  */
     double pinv_tol;    /* Lanczos pseudo-inverse cut (relative); <= 0 -> 1e-12      */
     double neg_tol;     /* Lanczos non-PSD tolerance (relative);  <= 0 -> 1e-8       */
-    size_t zchunk_bytes;/* cap on the folded-intermediate chunk; 0 -> 16 GiB         */
+    size_t zchunk_bytes;/* cap on the folded intermediate of the self-energy stage
+                           (bytes; GW_ENOMEM above it); 0 -> no cap              */
     double moment_eps;  /* relative accuracy of the moments given to gw_poles; sets
                            the Lanczos deflation level; <= 0 -> 2^-52 (FP64 moments) */
 } gw_opts;
@@ -152,7 +153,7 @@ gw_status gw_sigma_from_R(gw_handle h, int nocc, int nvir, int naux, int nmom_ma
  * and the outputs sigma_occ, sigma_vir [nmom_max+1][nmo][nmo] as in
  * gw_sigma_moments.  Returns GW_EINVAL (nothing launched) when the system's
  * buffers do not fit the static array: roughly
- *   8 (2 naux nocc nvir + (nmom_max+2) naux^2 + (nmom_max+1) naux nmo
+ *   8 (2 naux nocc nvir + (nmom_max+2) naux^2 + (nmom_max+1) naux nmo^2
  *      + 2 (nmom_max+1) nmo^2) bytes must not exceed it.
  * Every call on one device shares that device's array and leaves its
  * contents behind (the path clears what must start at zero itself): calls

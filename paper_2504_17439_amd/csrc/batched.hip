@@ -119,13 +119,13 @@ gw_status build_tables(gw_batch_s* b, int target) {
             const auto& j = b->jobs[id];
             const auto& m = b->mol[j.m];
             const gw_system& s = b->sys[j.m];
-            const long ncol = (long)(j.x1 - j.x0) * m.nmo;
+            const long ncol = m.M2;
             float* Zt = b->Zt + j.zt_off;
             u16* Zl = b->Zl + j.zl_off;
             i8* Zd = b->Zd + j.zd_off;
             int* eZ = b->eZ + j.ez_off;
-            FoldJob f = make_fold_job(nt, m.Rd, m.eR, m.Ld, m.eL, s.eps, s.naux, m.Ap, m.nmo, s.nocc,
-                                      (long)j.x0 * m.nmo, ncol, m.rplane, m.lplane, Zt, Zl);
+            FoldJob f = make_fold_job(nt, m.Rd, m.eR, m.Ld, m.eL, s.eps, s.naux, m.Ap, m.nmo, s.nocc, m.rplane,
+                                      m.lplane, Zt, Zl);
             f.item0 = fi;
             fi += (long)f.nP * f.nC;
             fj.push_back(f);
@@ -338,21 +338,20 @@ gw_status batch_create(Handle* h, int nsys, const gw_system* sys, gw_screening s
         if (prec == GW_MIXED) {
             bytes += align(sizeof(i8) * MIX_ND * m.lplane) + align(sizeof(int) * (m.M2 + m.rrows)) +
                      align(sizeof(i8) * MIX_ND * m.rplane);
-            // stage-1 intermediates per x: FP32 + BF16 residual + ND digit planes, plus one exponent per row
-            const size_t per_x = (size_t)nt * m.nmo * ((size_t)m.Ap * (sizeof(float) + sizeof(u16) +
-                                                                      MIX_ND * sizeof(i8)) + sizeof(int));
-            int nx = (int)std::max<size_t>(1, std::min<size_t>((size_t)m.nmo, job_bytes / per_x));
-            nx = (int)std::max<long>(1, std::min<long>(nx, ((1L << 31) - 1) / ((long)nt * m.nmo * 64)));
-            int slots_max = 0;
-            for (int x0 = 0; x0 < m.nmo; x0 += nx) {
-                Job j{};
-                j.m = i;
-                j.x0 = x0;
-                j.x1 = std::min(m.nmo, x0 + nx);
-                j.zrows = (long)nt * (j.x1 - j.x0) * m.nmo;
-                b->jobs.push_back(j);
-                slots_max += job_split(b, m.nmo, j.x1 - j.x0, max_target);
+            // one job per molecule: stage 1 forms each symmetric (x, y) pair once
+            // and writes both of its columns, so all nmo^2 columns are kept at once
+            if ((long)nt * m.M2 * 64 >= (1L << 31)) {
+                release(b);
+                delete b;
+                return set_err(h, GW_EINVAL, "batch: a molecule's nt * nmo^2 rows exceed 31-bit offsets");
             }
+            Job j{};
+            j.m = i;
+            j.x0 = 0;
+            j.x1 = m.nmo;
+            j.zrows = (long)nt * m.M2;
+            b->jobs.push_back(j);
+            const int slots_max = job_split(b, m.nmo, m.nmo, max_target);
             bytes += align(sizeof(double) * 2 * nt * (size_t)slots_max * m.M2);
             m.slots = slots_max;
         }

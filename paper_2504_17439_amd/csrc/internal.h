@@ -174,12 +174,12 @@ gw_status reduce_splits(Handle* h, const double* part, int nsplit, long ps, int 
 gw_status gather_ov(Handle* h, int nocc, int nvir, int naux, const double* eps,
                     const double* L, double* V, double* D);
 
-// Stage 1 of the self-energy contraction for columns j in [j0, j1) of L viewed
-// as [naux][nmo*nmo] (j = x*nmo + q, with x whole rows so j0, j1 are multiples
-// of nmo):  Zt[n][P][j-j0] = sum_{t<=n} s_{n,t}(x) sum_Q R_t[P][Q] L[Q][j],
-// s_{n,t}(x) = 2 C(n,t) sigma_x^t eps_x^{n-t}, sigma_x = -1 (x < nocc) or +1.
+// Stage 1 of the self-energy contraction over every column j = x*nmo + q of L
+// viewed as [naux][nmo*nmo]:  Zt[n][P][j] = sum_{t<=n} s_{n,t}(x) sum_Q R_t[P][Q] L[Q][j],
+// s_{n,t}(x) = 2 C(n,t) sigma_x^t eps_x^{n-t}, sigma_x = -1 (x < nocc) or +1;
+// each symmetric pair (x, q), x <= q, is formed once (Zt: nt naux nmo^2 doubles).
 gw_status sigma_fold_f64(Handle* h, int nt, int naux, int nmo, int nocc, const double* eps,
-                         const double* R, const double* L, int x0, int x1, double* Zt);
+                         const double* R, const double* L, double* Zt);
 
 gw_status sigma_from_R_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max,
                            const double* eps, const double* L, const double* R,
@@ -198,11 +198,11 @@ gw_status tda_moments_half_f64(Handle* h, int nocc, int nvir, int naux, int nmom
                                const double* L, double* R, double* V, double* D, double* X, const Scratch& part);
 
 // FP64 self-energy moments from R_t on caller buffers: the folded
-// intermediate in `zt` (at least (nmom_max+1) naux nmo doubles: one x per
-// chunk; at most zchunk_bytes per chunk) and the contraction's split
-// partials in `acc` (at least 2 (nmom_max+1) nmo^2 doubles).
+// intermediate in `zt` ((nmom_max+1) naux nmo^2 doubles, refused with
+// GW_ENOMEM above zcap_bytes) and the contraction's split partials in `acc`
+// (at least 2 (nmom_max+1) nmo^2 doubles).
 gw_status sigma_from_R_f64_bufs(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
-                                const double* L, const double* R, size_t zchunk_bytes, const Scratch& zt,
+                                const double* L, const double* R, size_t zcap_bytes, const Scratch& zt,
                                 const Scratch& acc, double* sigma_occ, double* sigma_vir);
 
 // TDA moments R[nmom_max+1][naux][naux] with int8 digit products (mixed precision).

@@ -14,8 +14,11 @@ typedef signed char i8;      // one base-255 digit
 constexpr int MIX_ND = 4;   // int8 digits per operand
 constexpr int MIX_MK = 64;  // k per MFMA step (64 B per row); digit planes are padded to a multiple of it
 
-// One stage-1 job: a molecule's R_t digits and the x range [j0, j0 + ncol) of
-// its L digit columns.  item0 / nP / nC index its tiles in grouped launches.
+// One stage-1 job: a molecule's R_t digits and all its L digit columns, taken
+// as 8 x 8 blocks of orbital pairs (x, y), x <= y (nblk upper blocks of nb
+// per side); every pair is written to both of its rows (x, y) and (y, x) of
+// Zt / Zl [nt][ncol = nmo^2][Ap].  item0 / nP / nC index its tiles in grouped
+// launches.
 struct FoldJob {
     const i8* Rd;
     const int* eR;
@@ -23,11 +26,12 @@ struct FoldJob {
     const int* eL;
     const double* eps;
     int naux, Ap, nmo, nocc;
-    long j0, ncol, rplane, lplane;
+    long ncol, rplane, lplane;
+    int nb, nblk;
     float* Zt;
     u16* Zl;
     long item0;
-    int nP, nC;  // P-blocks (Ap / 16) and 128-column tiles
+    int nP, nC;  // P-blocks (Ap / 16) and column tiles (fold_cols / 64 pair blocks each)
 };
 
 struct ZdigJob {
@@ -78,7 +82,7 @@ gw_status mixed_prep(Handle* h, int naux, int nmo, int nt, const double* L, cons
                      i8* Rd, int* eR);
 
 FoldJob make_fold_job(int nt, const i8* Rd, const int* eR, const i8* Ld, const int* eL, const double* eps, int naux,
-                      int Ap, int nmo, int nocc, long j0, long ncol, long rplane, long lplane, float* Zt, u16* Zl);
+                      int Ap, int nmo, int nocc, long rplane, long lplane, float* Zt, u16* Zl);
 
 // Grouped launches over device job tables (item0 prefix sums set by the caller).
 gw_status launch_fold_grouped(Handle* h, int nt, const FoldJob* jobs, int njobs, long total, int grid);

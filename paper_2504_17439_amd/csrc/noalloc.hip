@@ -63,10 +63,9 @@ static void* noalloc_ptr(int device) {
 
 // Layout of the scratch for one call (bytes, each region 256-aligned):
 // V, D, X (recursion), R (moments), the split-K partials of R_n, the folded
-// intermediate of the contraction and its split partials.  The minimum of
-// each region is what the path needs with one split and one x per chunk;
-// what is left goes to the splits and the chunk, capped at what the default
-// path would use.
+// intermediate of the contraction (all nmo^2 columns) and its split
+// partials.  The minimum of a split region is one split; what is left goes
+// to more splits, capped at what the default path would use.
 struct NoallocPlan {
     size_t off_V, off_D, off_X, off_R, off_part, off_zt, off_acc, total;
     size_t part_cap, zt_cap, acc_cap;  // doubles
@@ -81,17 +80,15 @@ static bool noalloc_plan(int nocc, int nvir, int naux, int nmom_max, NoallocPlan
     p.off_D = off; off += up256(ov * d);
     p.off_X = off; off += up256(A * ov * d);
     p.off_R = off; off += up256(nt * A * A * d);
-    const size_t part_min = A * A, zt_min = nt * A * nmo, acc_min = 2 * nt * nmo * nmo;
+    const size_t part_min = A * A, zt_min = nt * A * nmo * nmo, acc_min = 2 * nt * nmo * nmo;
     const size_t fixed = off + up256(part_min * d) + up256(zt_min * d) + up256(acc_min * d);
     if (fixed > GW_NOALLOC_SCRATCH_BYTES) return false;
     size_t spare = (GW_NOALLOC_SCRATCH_BYTES - fixed) / d;
-    // extra splits of R_n = X V^T (up to 16), then contraction splits (up
-    // to 64), then more x per chunk of the folded intermediate
+    // extra splits of R_n = X V^T (up to 16), then contraction splits (up to 64)
     size_t part_extra = std::min(spare, 15 * part_min);
     spare -= part_extra;
     size_t acc_extra = std::min(spare, 63 * acc_min);
-    spare -= acc_extra;
-    size_t zt_extra = std::min(spare, (nmo - 1) * zt_min);
+    size_t zt_extra = 0;
     p.part_cap = part_min + part_extra;
     p.acc_cap = acc_min + acc_extra;
     p.zt_cap = zt_min + zt_extra;

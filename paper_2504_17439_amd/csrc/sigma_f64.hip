@@ -6,13 +6,15 @@
 //              = 2 C(n,t)        eps_x^{n-t}  (x virtual:  particle moments)
 //
 // Stage 1 (sigma_fold_kernel): Zt^{(n)}[P,x,q] = sum_t s_{n,t}(x) (R_t L)[P,x,q]
-//   -- all t for one (P-block, column-block) tile stay in registers, and the
+//   -- all t for one (P-block, pair-block) tile stay in registers, and the
 //   binomial / eps-power fold happens in the epilogue, so the per-t products
 //   never reach HBM.  L symmetric in (p,q) means L[Q,q,x] = L[Q,x,q], so the
-//   column index j = x*nmo + q walks L's rows contiguously.
-// Stage 2 (gemm_f64): Sigma^{(n)}[p,q] += sum_{P, x in sector} L[P,x,p] Zt^{(n)}[P,x,q],
-//   upper 128x128 tiles only, split-K partials accumulated over x chunks,
-//   then one reduction that mirrors the upper triangle (exactly symmetric).
+//   column index j = x*nmo + q walks L's rows contiguously, and (R_t L) is
+//   symmetric in (x, q): each pair x <= q is formed once and folded into
+//   both of its columns (half the products of the full column range).
+// Stage 2 (gemm_f64): Sigma^{(n)}[p,q] = sum_{P, x in sector} L[P,x,p] Zt^{(n)}[P,x,q],
+//   upper 128x128 tiles only, split-K partials, then one reduction that
+//   mirrors the upper triangle (exactly symmetric).
 #include "internal.h"
 
 #include <algorithm>
@@ -35,11 +37,24 @@ constexpr double binom2(int n, int k) {
     return 2.0 * c;
 }
 
+// Pair blocks of stage 1: Z_t[P, x, q] = sum_Q R_t[P,Q] L[Q,x,q] is symmetric
+// in (x, q) because L[Q] is, so only the pairs x <= q are formed, in 8 x 8
+// blocks (X, Y) with X <= Y over nb = ceil(nmo / 8) blocks per side; column
+// c of a block is x = 8X + (c >> 3), q = 8Y + (c & 7).  Diagonal blocks form
+// all 64 pairs (and each writes only its own output), the others write the
+// fold of each pair twice: with eps_x at (x, q) and with eps_q at (q, x).
+__device__ __forceinline__ void pair_block(int t, int nb, int& X, int& Y) {
+    int r = 0;
+    while (t >= nb - r) { t -= nb - r; ++r; }
+    X = r;
+    Y = r + t;
+}
+
 template <int NT>
 __global__ __launch_bounds__(FTHR, 2) void sigma_fold_kernel(const double* __restrict__ R,
                                                               const double* __restrict__ L,
                                                               const double* __restrict__ eps, int naux,
-                                                              int nmo, int nocc, long j0, long ncol,
+                                                              int nmo, int nocc, int nb,
                                                               double* __restrict__ Zt) {
     __shared__ double Ra[2][NT][FBK][FBP];
     __shared__ double Lb[2][FBK][FBN + 2];
@@ -49,9 +64,15 @@ __global__ __launch_bounds__(FTHR, 2) void sigma_fold_kernel(const double* __res
     const int wave = tid >> 6;
     const int lrow = lane & 15;
     const int lk = lane >> 4;
-    const long c0 = (long)blockIdx.x * FBN;
+    int BX, BY;
+    pair_block(blockIdx.x, nb, BX, BY);
     const int P0 = blockIdx.y * FBP;
     const long nmo2 = (long)nmo * nmo;
+
+    // the L column this thread loads: pair c = tid & 63 of the block
+    const int cl = tid & 63;
+    const int xl = 8 * BX + (cl >> 3), ql = 8 * BY + (cl & 7);
+    const long jl = (xl < nmo && ql < nmo) ? (long)xl * nmo + ql : 0;
 
     double rr[NT];
     double rl[4];
@@ -67,11 +88,9 @@ __global__ __launch_bounds__(FTHR, 2) void sigma_fold_kernel(const double* __res
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            int idx = e * FTHR + tid;
-            int c = idx & (FBN - 1), k = idx >> 6;
+            int k = e * 4 + (tid >> 6);
             int Q = q0 + k;
-            long cc = c0 + c;
-            rl[e] = (Q < naux && cc < ncol) ? L[(long)Q * nmo2 + j0 + cc] : 0.0;
+            rl[e] = Q < naux ? L[(long)Q * nmo2 + jl] : 0.0;
         }
     };
     auto store = [&](int buf) {
@@ -79,10 +98,7 @@ __global__ __launch_bounds__(FTHR, 2) void sigma_fold_kernel(const double* __res
 #pragma unroll
         for (int t = 0; t < NT; ++t) Ra[buf][t][k][p] = rr[t];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            int idx = e * FTHR + tid;
-            Lb[buf][idx >> 6][idx & (FBN - 1)] = rl[e];
-        }
+        for (int e = 0; e < 4; ++e) Lb[buf][e * 4 + (tid >> 6)][cl] = rl[e];
     };
 
     v4d acc[NT];
@@ -111,60 +127,67 @@ __global__ __launch_bounds__(FTHR, 2) void sigma_fold_kernel(const double* __res
         cur ^= 1;
     }
 
-    // epilogue: binomial / eps-power fold, lane owns column c and rows lk + 4r
-    const long c = c0 + wave * 16 + lrow;
-    if (c >= ncol) return;
-    const long j = j0 + c;
-    const int x = (int)(j / nmo);
-    const double ex = eps[x];
-    const bool occ = x < nocc;
-    double pw[NT];
-    pw[0] = 1.0;
+    // epilogue: lane owns pair c and rows lk + 4r; binomial / eps-power fold
+    // for each output of the pair
+    const int c = wave * 16 + lrow;
+    const int x = 8 * BX + (c >> 3), q = 8 * BY + (c & 7);
+    if (x >= nmo || q >= nmo) return;
+    const bool twin = BX < BY;   // also the transposed output (q, x)
 #pragma unroll
-    for (int k = 1; k < NT; ++k) pw[k] = pw[k - 1] * ex;
+    for (int o = 0; o < 2; ++o) {
+        if (o == 1 && !twin) break;
+        const int xo = o ? q : x;            // the orbital whose energy folds this output
+        const long col = o ? (long)q * nmo + x : (long)x * nmo + q;
+        const double ex = eps[xo];
+        const bool occ = xo < nocc;
+        double pw[NT];
+        pw[0] = 1.0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        int P = P0 + lk + 4 * r;
-        if (P >= naux) continue;
-        double a[NT];
+        for (int k = 1; k < NT; ++k) pw[k] = pw[k - 1] * ex;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) a[t] = (occ && (t & 1)) ? -acc[t][r] : acc[t][r];
+        for (int r = 0; r < 4; ++r) {
+            int P = P0 + lk + 4 * r;
+            if (P >= naux) continue;
+            double a[NT];
 #pragma unroll
-        for (int n = 0; n < NT; ++n) {
-            double z = 0.0;
+            for (int t = 0; t < NT; ++t) a[t] = (occ && (t & 1)) ? -acc[t][r] : acc[t][r];
 #pragma unroll
-            for (int t = 0; t <= n; ++t) z += binom2(n, t) * pw[n - t] * a[t];
-            Zt[((long)n * naux + P) * ncol + c] = z;
+            for (int n = 0; n < NT; ++n) {
+                double z = 0.0;
+#pragma unroll
+                for (int t = 0; t <= n; ++t) z += binom2(n, t) * pw[n - t] * a[t];
+                Zt[((long)n * naux + P) * nmo2 + col] = z;
+            }
         }
     }
 }
 
 template <int NT>
 void launch_fold(Handle* h, int naux, int nmo, int nocc, const double* eps, const double* R,
-                 const double* L, long j0, long ncol, double* Zt) {
-    dim3 grid((unsigned)((ncol + FBN - 1) / FBN), (unsigned)((naux + FBP - 1) / FBP));
+                 const double* L, double* Zt) {
+    const int nb = (nmo + 7) / 8;
+    dim3 grid((unsigned)(nb * (nb + 1) / 2), (unsigned)((naux + FBP - 1) / FBP));
     hipLaunchKernelGGL((sigma_fold_kernel<NT>), grid, dim3(FTHR), 0, h->stream, R, L, eps, naux, nmo,
-                       nocc, j0, ncol, Zt);
+                       nocc, nb, Zt);
 }
 
 }  // namespace
 
 gw_status sigma_fold_f64(Handle* h, int nt, int naux, int nmo, int nocc, const double* eps,
-                         const double* R, const double* L, int x0, int x1, double* Zt) {
-    long j0 = (long)x0 * nmo, ncol = (long)(x1 - x0) * nmo;
-    if (ncol <= 0) return GW_OK;
-    if ((ncol + FBN - 1) / FBN > 0x7fffffffL || (naux + FBP - 1) / FBP > 65535)
+                         const double* R, const double* L, double* Zt) {
+    const long nb = (nmo + 7) / 8;
+    if (nb * (nb + 1) / 2 > 0x7fffffffL || (naux + FBP - 1) / FBP > 65535)
         return set_err(h, GW_EINVAL, "sigma_fold: grid too large");
     KTimer timer(h, "sigma_fold");
     switch (nt) {
-        case 2: launch_fold<2>(h, naux, nmo, nocc, eps, R, L, j0, ncol, Zt); break;
-        case 4: launch_fold<4>(h, naux, nmo, nocc, eps, R, L, j0, ncol, Zt); break;
-        case 6: launch_fold<6>(h, naux, nmo, nocc, eps, R, L, j0, ncol, Zt); break;
-        case 8: launch_fold<8>(h, naux, nmo, nocc, eps, R, L, j0, ncol, Zt); break;
-        case 10: launch_fold<10>(h, naux, nmo, nocc, eps, R, L, j0, ncol, Zt); break;
-        case 12: launch_fold<12>(h, naux, nmo, nocc, eps, R, L, j0, ncol, Zt); break;
-        case 14: launch_fold<14>(h, naux, nmo, nocc, eps, R, L, j0, ncol, Zt); break;
-        case 16: launch_fold<16>(h, naux, nmo, nocc, eps, R, L, j0, ncol, Zt); break;
+        case 2: launch_fold<2>(h, naux, nmo, nocc, eps, R, L, Zt); break;
+        case 4: launch_fold<4>(h, naux, nmo, nocc, eps, R, L, Zt); break;
+        case 6: launch_fold<6>(h, naux, nmo, nocc, eps, R, L, Zt); break;
+        case 8: launch_fold<8>(h, naux, nmo, nocc, eps, R, L, Zt); break;
+        case 10: launch_fold<10>(h, naux, nmo, nocc, eps, R, L, Zt); break;
+        case 12: launch_fold<12>(h, naux, nmo, nocc, eps, R, L, Zt); break;
+        case 14: launch_fold<14>(h, naux, nmo, nocc, eps, R, L, Zt); break;
+        case 16: launch_fold<16>(h, naux, nmo, nocc, eps, R, L, Zt); break;
         default: return set_err(h, GW_EINVAL, "sigma_fold: nmom_max+1 must be even and <= 16");
     }
     timer.stop();
@@ -173,16 +196,19 @@ gw_status sigma_fold_f64(Handle* h, int nt, int naux, int nmo, int nocc, const d
 }
 
 gw_status sigma_from_R_f64_bufs(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
-                                const double* L, const double* R, size_t zchunk_bytes, const Scratch& zt,
+                                const double* L, const double* R, size_t zcap_bytes, const Scratch& zt,
                                 const Scratch& accs, double* sigma_occ, double* sigma_vir) {
     const int nmo = nocc + nvir;
     const int nt = nmom_max + 1;
     const long nmo2 = (long)nmo * nmo;
-    const size_t per_x = (size_t)nt * naux * nmo;  // doubles of the folded intermediate per x
-    size_t nxc = std::min<size_t>((size_t)nmo, std::max<size_t>(1, zchunk_bytes / (per_x * sizeof(double))));
-    nxc = std::min(nxc, std::max<size_t>(1, scratch_max(zt) / per_x));
-    const int nx = (int)nxc;
-    double* Zt = scratch_get(h, zt, per_x * nx);
+    // the folded intermediate of every (x, q) is formed at once (stage 1 writes
+    // each symmetric pair to both of its columns)
+    const size_t zn = (size_t)nt * naux * nmo2;
+    if (zn * sizeof(double) > zcap_bytes)
+        return set_err(h, GW_ENOMEM, "sigma (FP64): the folded intermediate needs " +
+                                         std::to_string(zn * sizeof(double)) + " bytes, above the cap of " +
+                                         std::to_string(zcap_bytes));
+    double* Zt = scratch_get(h, zt, zn);
     if (!Zt) return GW_ENOMEM;
 
     const int T = (nmo + 127) / 128;
@@ -192,41 +218,33 @@ gw_status sigma_from_R_f64_bufs(Handle* h, int nocc, int nvir, int naux, int nmo
     const long part_per_sector = (long)nt * S * nmo2;
     double* acc = scratch_get(h, accs, (size_t)2 * part_per_sector);
     if (!acc) return GW_ENOMEM;
-    GW_TRY(fill_f64(h, acc, (size_t)2 * part_per_sector, 0.0));
 
-    for (int x0 = 0; x0 < nmo; x0 += nx) {
-        int x1 = std::min(nmo, x0 + nx);
-        long ncol = (long)(x1 - x0) * nmo;
-        GW_TRY(sigma_fold_f64(h, nt, naux, nmo, nocc, eps, R, L, x0, x1, Zt));
-        for (int sector = 0; sector < 2; ++sector) {
-            int lo = sector == 0 ? 0 : nocc, hi = sector == 0 ? nocc : nmo;
-            int xs0 = std::max(x0, lo), xs1 = std::min(x1, hi);
-            if (xs1 <= xs0) continue;
-            int nxs = xs1 - xs0;
-            GemmF64 g;
-            g.M = nmo; g.N = nmo; g.K = naux * nxs; g.batch = nt;
-            g.a_kc = false; g.A = L; g.a_off = (long)xs0 * nmo; g.a_kdiv = nxs; g.a_khi = nmo2; g.a_klo = nmo;
-            g.b_kc = false; g.B = Zt; g.b_off = (long)(xs0 - x0) * nmo; g.b_kdiv = nxs; g.b_khi = ncol;
-            g.b_klo = nmo; g.b_bs = (long)naux * ncol;
-            g.sym_upper = true;
-            g.epi = EPI_PARTIAL; g.accumulate = true;
-            g.nsplit = S;
-            g.kchunk = ((g.K + S - 1) / S + 15) / 16 * 16;
-            g.C = acc + sector * part_per_sector; g.ldc = nmo; g.c_ps = nmo2;
-            g.tag = "sigma_contract";
-            GW_TRY(gemm_f64(h, g));
-        }
+    GW_TRY(sigma_fold_f64(h, nt, naux, nmo, nocc, eps, R, L, Zt));
+    for (int sector = 0; sector < 2; ++sector) {
+        const int xs0 = sector == 0 ? 0 : nocc, nxs = sector == 0 ? nocc : nvir;
+        GemmF64 g;
+        g.M = nmo; g.N = nmo; g.K = naux * nxs; g.batch = nt;
+        g.a_kc = false; g.A = L; g.a_off = (long)xs0 * nmo; g.a_kdiv = nxs; g.a_khi = nmo2; g.a_klo = nmo;
+        g.b_kc = false; g.B = Zt; g.b_off = (long)xs0 * nmo; g.b_kdiv = nxs; g.b_khi = nmo2;
+        g.b_klo = nmo; g.b_bs = (long)naux * nmo2;
+        g.sym_upper = true;
+        g.epi = EPI_PARTIAL;
+        g.nsplit = S;
+        g.kchunk = ((g.K + S - 1) / S + 15) / 16 * 16;
+        g.nsplit = (g.K + g.kchunk - 1) / g.kchunk;
+        g.C = acc + sector * part_per_sector; g.ldc = nmo; g.c_ps = nmo2;
+        g.tag = "sigma_contract";
+        GW_TRY(gemm_f64(h, g));
+        GW_TRY(reduce_splits(h, g.C, g.nsplit, nmo2, nt, nmo, nmo, nmo, true, 1.0, 0.0,
+                             sector == 0 ? sigma_occ : sigma_vir, nmo2, nmo));
     }
-    GW_TRY(reduce_splits(h, acc, S, nmo2, nt, nmo, nmo, nmo, true, 1.0, 0.0, sigma_occ, nmo2, nmo));
-    GW_TRY(reduce_splits(h, acc + part_per_sector, S, nmo2, nt, nmo, nmo, nmo, true, 1.0, 0.0, sigma_vir,
-                         nmo2, nmo));
     return GW_OK;
 }
 
 gw_status sigma_from_R_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
                            const double* L, const double* R, const gw_opts* opts, double* sigma_occ,
                            double* sigma_vir) {
-    const size_t cap = (opts && opts->zchunk_bytes) ? opts->zchunk_bytes : ((size_t)8 << 30);
+    const size_t cap = (opts && opts->zchunk_bytes) ? opts->zchunk_bytes : SIZE_MAX;
     return sigma_from_R_f64_bufs(h, nocc, nvir, naux, nmom_max, eps, L, R, cap, Scratch{WS_Z}, Scratch{WS_SIGACC},
                                  sigma_occ, sigma_vir);
 }

@@ -219,6 +219,14 @@ struct FoldSlab {
     static_assert(TG * CG == 4 && TPW * TG >= NT && TPW <= 3 && CG <= 2, "fold wave layout");
 };
 
+// Pair block t of nb x nb upper blocks (X <= Y), row by row.
+__device__ __forceinline__ void pair_block_of(int t, int nb, int& X, int& Y) {
+    int r = 0;
+    while (t >= nb - r) { t -= nb - r; ++r; }
+    X = r;
+    Y = r + t;
+}
+
 // Binary search of the job whose first work item is the largest <= item.
 template <typename Job>
 __device__ __forceinline__ int find_job(const Job* __restrict__ jobs, int njobs, long item) {
@@ -248,7 +256,7 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_
     const int* __restrict__ eL = g.eL;
     const double* __restrict__ eps = g.eps;
     const int naux = g.naux, Ap = g.Ap, nmo = g.nmo, nocc = g.nocc;
-    const long j0 = g.j0, ncol = g.ncol, rplane = g.rplane, lplane = g.lplane;
+    const long ncol = g.ncol, rplane = g.rplane, lplane = g.lplane;
     float* __restrict__ Zt = g.Zt;
     u16* __restrict__ Zl = g.Zl;
 
@@ -289,12 +297,18 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_
     const long M2 = lplane / Ap;                      // rows of an L digit plane
     const int lrow = lane >> 2;
     const int gch = swz(lrow, lane & 3);              // swz is an involution in the chunk
+    // column group h of the tile is pair block ct * CG + h; its column c_in =
+    // 16 w + (lane >> 2) is the pair (8 X + (c_in >> 3), 8 Y + (c_in & 7)).
+    // Past the last block or the orbital range a lane reads a clamped (valid,
+    // unused) row.
     unsigned offB[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        long cc = c0 + h * 64 + wv * 16 + lrow;
-        if (cc > ncol - 1) cc = ncol - 1;
-        offB[h] = (unsigned)((j0 + cc) * 64 + gch * 16);
+        int X, Y;
+        pair_block_of(min(ct * CG + h, g.nblk - 1), g.nb, X, Y);
+        const int cin = wv * 16 + lrow;
+        const int x = min(8 * X + (cin >> 3), nmo - 1), y = min(8 * Y + (cin & 7), nmo - 1);
+        offB[h] = (unsigned)(((long)x * nmo + y) * 64 + gch * 16);
     }
     auto ldB = [&](int kt) {
         lds_t* B = lds + (kt % NS) * BST + wv * 16 * 64;
@@ -381,16 +395,19 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_
     __syncthreads();
 
     // epilogue 1: FP64 combination and scaling of this wave's moments into the
-    // exchange X[t][q][lane][r] (q = 4 cg + cb: the column block), with the
-    // sign (-1)^t of the occupied sector; the slab buffers are free (barrier above)
+    // exchange X[t][q][lane][r] (q = 4 cg + cb: the column block); the slab
+    // buffers are free (barrier above)
     double* X = (double*)lds;
     constexpr int NQ = 4 * CG;
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
-        const long c = c0 + cg * 64 + cb * 16 + lr;
-        const bool cok = c < ncol;
-        const long j = j0 + (cok ? c : 0);
-        const bool occ = (int)(j / nmo) < nocc;
+        const int pbk = ct * CG + cg;
+        int BX, BY;
+        pair_block_of(min(pbk, g.nblk - 1), g.nb, BX, BY);
+        const int cin = cb * 16 + lr;
+        const int x = 8 * BX + (cin >> 3), y = 8 * BY + (cin & 7);
+        const bool cok = pbk < g.nblk && x < nmo && y < nmo;
+        const long j = cok ? (long)x * nmo + y : 0;
         const int ej = eL[j];
 #pragma unroll
         for (int tt = 0; tt < TPW; ++tt) {
@@ -406,7 +423,7 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_
                     for (int w = MAXW; w >= 0; --w) z += (double)acc[w][tt][cb][r] * wscale(w);
                     z = ldexp(z, eR[(long)t * naux + P] + ej);
                 }
-                v[r] = (occ && (t & 1)) ? -z : z;
+                v[r] = z;
             }
             double* dst = X + (((long)t * NQ + cg * 4 + cb) * 64 + lane) * 4;
             *(double4*)dst = make_double4(v[0], v[1], v[2], v[3]);
@@ -414,22 +431,34 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_
     }
     __syncthreads();
 
-    // epilogue 2: wave w folds all moments of column blocks q = w + 4 i:
-    // binomial / eps-power fold, FP32 + BF16 residual store of the four
-    // consecutive rows P0 + 4 lk + r
+    // epilogue 2: wave w folds all moments of column blocks q = w + 4 i (pair
+    // block ct * CG + i, pairs 16 w .. 16 w + 15): binomial / eps-power fold
+    // with the sign (-1)^t of an occupied orbital, FP32 + BF16 residual store
+    // of the four consecutive rows P0 + 4 lk + r, at (x, y) with eps_x and,
+    // off the diagonal blocks, at (y, x) with eps_y
 #pragma unroll
     for (int i = 0; i < CG; ++i) {
         const int q = wv + 4 * i;
-        const long c = c0 + (q >> 2) * 64 + (q & 3) * 16 + lr;
-        if (c < ncol) {
-            const long j = j0 + c;
-            const double ex = eps[(int)(j / nmo)];
-            double a[NT][4];
+        const int pbk = ct * CG + i;
+        if (pbk >= g.nblk) continue;
+        int BX, BY;
+        pair_block_of(pbk, g.nb, BX, BY);
+        const int cin = wv * 16 + lr;
+        const int x = 8 * BX + (cin >> 3), y = 8 * BY + (cin & 7);
+        if (x >= nmo || y >= nmo) continue;
+        double a[NT][4];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const double4 v = *(const double4*)(X + (((long)t * NQ + q) * 64 + lane) * 4);
-                a[t][0] = v.x; a[t][1] = v.y; a[t][2] = v.z; a[t][3] = v.w;
-            }
+        for (int t = 0; t < NT; ++t) {
+            const double4 v = *(const double4*)(X + (((long)t * NQ + q) * 64 + lane) * 4);
+            a[t][0] = v.x; a[t][1] = v.y; a[t][2] = v.z; a[t][3] = v.w;
+        }
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+            if (o == 1 && BX == BY) break;
+            const int xo = o ? y : x;
+            const long row = o ? (long)y * nmo + x : (long)x * nmo + y;
+            const double ex = eps[xo];
+            const bool occ = xo < nocc;
             double pw[NT];
             pw[0] = 1.0;
 #pragma unroll
@@ -442,15 +471,15 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_
                 for (int r = 0; r < 4; ++r) {
                     double z = 0.0;
 #pragma unroll
-                    for (int t = 0; t <= n; ++t) z += binom2(n, t) * pw[n - t] * a[t][r];
+                    for (int t = 0; t <= n; ++t) z += binom2(n, t) * pw[n - t] * ((occ && (t & 1)) ? -a[t][r] : a[t][r]);
                     const float hi = (float)z;
                     const unsigned lb = __float_as_uint((float)(z - (double)hi));
                     hv[r] = hi;
                     lv[r] = (lb + 0x7fffu + ((lb >> 16) & 1u)) >> 16;
                 }
-                const long o = ((long)n * ncol + c) * Ap + P0 + 4 * lk;
-                *(float4*)(Zt + o) = make_float4(hv[0], hv[1], hv[2], hv[3]);
-                *(uint2*)(Zl + o) = make_uint2(lv[0] | (lv[1] << 16), lv[2] | (lv[3] << 16));
+                const long off = ((long)n * ncol + row) * Ap + P0 + 4 * lk;
+                *(float4*)(Zt + off) = make_float4(hv[0], hv[1], hv[2], hv[3]);
+                *(uint2*)(Zl + off) = make_uint2(lv[0] | (lv[1] << 16), lv[2] | (lv[3] << 16));
             }
         }
     }
@@ -1011,75 +1040,66 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
     if (!Ld || !eL || !Rd) return GW_ENOMEM;
     int* eR = eL + M2;
     GW_TRY(mixed_prep(h, naux, nmo, nt, L, R, Ld, eL, Rd, eR));
-    // --- chunk over x so that the stage-1 intermediates (FP32 + BF16 residual
-    // and the ND int8 digit planes) fit the cap
-    size_t cap = (opts && opts->zchunk_bytes) ? opts->zchunk_bytes : ((size_t)16 << 30);
-    size_t per_x = (size_t)nt * nmo * Ap * (sizeof(float) + sizeof(u16) + ND * sizeof(i8));
-    int nx = (int)std::max<size_t>(1, std::min<size_t>((size_t)nmo, cap / per_x));
-    // the stage-2 kernel addresses a chunk's digit plane rows with 31-bit byte offsets
-    nx = (int)std::max<long>(1, std::min<long>(nx, ((1L << 31) - 1) / ((long)nt * nmo * 64)));
-    const long zrows_max = (long)nt * nx * nmo;
-    float* Zt = (float*)ws_get(h, WS_MIX3, sizeof(float) * zrows_max * Ap);
-    u16* Zl = (u16*)ws_get(h, WS_MIX5, sizeof(u16) * zrows_max * Ap);
-    i8* Zd = (i8*)ws_get(h, WS_MIX6, sizeof(i8) * ND * zrows_max * Ap);
-    int* eZ = (int*)ws_get(h, WS_MIX4, sizeof(int) * zrows_max);
+    // --- stage-1 intermediates for every (x, q) column (each symmetric pair is
+    // formed once and written to both of its columns): FP32 + BF16 residual,
+    // the ND int8 digit planes and one exponent per (n, x, q) row
+    const long zrows = (long)nt * M2;
+    const size_t zbytes = (size_t)zrows * Ap * (sizeof(float) + sizeof(u16) + ND * sizeof(i8)) + sizeof(int) * zrows;
+    if (opts && opts->zchunk_bytes && zbytes > opts->zchunk_bytes)
+        return set_err(h, GW_ENOMEM, "sigma (mixed): the folded intermediate needs " + std::to_string(zbytes) +
+                                         " bytes, above the cap of " + std::to_string(opts->zchunk_bytes));
+    // the stage-2 kernel addresses the digit plane rows with 31-bit byte offsets
+    if (zrows * 64 >= (1L << 31)) return set_err(h, GW_EINVAL, "mixed precision: nt * nmo^2 rows exceed 31-bit offsets");
+    float* Zt = (float*)ws_get(h, WS_MIX3, sizeof(float) * zrows * Ap);
+    u16* Zl = (u16*)ws_get(h, WS_MIX5, sizeof(u16) * zrows * Ap);
+    i8* Zd = (i8*)ws_get(h, WS_MIX6, sizeof(i8) * ND * zrows * Ap);
+    int* eZ = (int*)ws_get(h, WS_MIX4, sizeof(int) * zrows);
     if (!Zt || !Zl || !Zd || !eZ) return GW_ENOMEM;
     const int tiles = mixed_upper_tiles(nmo);
-    int S = std::max(1, std::min(64, (2048 + tiles * nt - 1) / (tiles * nt)));
+    const int S = best_splits((long)tiles * nt * 2, naux * std::max(nocc, nvir), h->cus, 64);
     const long part_per_sector = (long)nt * S * M2;
     double* acc = (double*)ws_get(h, WS_SIGACC, sizeof(double) * 2 * part_per_sector);
     if (!acc) return GW_ENOMEM;
     GW_TRY(fill_f64(h, acc, (size_t)2 * part_per_sector, 0.0));
-    for (int x0 = 0; x0 < nmo; x0 += nx) {
-        int x1 = std::min(nmo, x0 + nx);
-        long ncol = (long)(x1 - x0) * nmo;
-        long j0 = (long)x0 * nmo;
-        {
-            KTimer tm(h, "sigma_fold");
-            const FoldJob fj =
-                make_fold_job(nt, Rd, eR, Ld, eL, eps, naux, Ap, nmo, nocc, j0, ncol, rplane, lplane, Zt, Zl);
-            switch (nt) {
-                case 2: launch_fold_mixed<2>(h, fj); break;
-                case 4: launch_fold_mixed<4>(h, fj); break;
-                case 6: launch_fold_mixed<6>(h, fj); break;
-                case 8: launch_fold_mixed<8>(h, fj); break;
-                case 10: launch_fold_mixed<10>(h, fj); break;
-                case 12: launch_fold_mixed<12>(h, fj); break;
-                default: return set_err(h, GW_EINVAL, "mixed precision: nmom_max+1 must be even and <= 12");
-            }
-            tm.stop();
-            GW_CHECK_LAUNCH(h);
+    {
+        KTimer tm(h, "sigma_fold");
+        const FoldJob fj = make_fold_job(nt, Rd, eR, Ld, eL, eps, naux, Ap, nmo, nocc, rplane, lplane, Zt, Zl);
+        switch (nt) {
+            case 2: launch_fold_mixed<2>(h, fj); break;
+            case 4: launch_fold_mixed<4>(h, fj); break;
+            case 6: launch_fold_mixed<6>(h, fj); break;
+            case 8: launch_fold_mixed<8>(h, fj); break;
+            case 10: launch_fold_mixed<10>(h, fj); break;
+            case 12: launch_fold_mixed<12>(h, fj); break;
+            default: return set_err(h, GW_EINVAL, "mixed precision: nmom_max+1 must be even and <= 12");
         }
-        const long zrows = (long)nt * ncol;
-        {
-            KTimer tm(h, "mixed_zdig");
-            const ZdigJob zj{zrows, Ap, Zt, Zl, eZ, Zd, 0};
-            hipLaunchKernelGGL(zdig_kernel, dim3((unsigned)((zrows + 3) / 4)), dim3(256), 0, h->stream, zj);
-            tm.stop();
-            GW_CHECK_LAUNCH(h);
-        }
+        tm.stop();
+        GW_CHECK_LAUNCH(h);
+    }
+    {
+        KTimer tm(h, "mixed_zdig");
+        const ZdigJob zj{zrows, Ap, Zt, Zl, eZ, Zd, 0};
+        hipLaunchKernelGGL(zdig_kernel, dim3((unsigned)((zrows + 3) / 4)), dim3(256), 0, h->stream, zj);
+        tm.stop();
+        GW_CHECK_LAUNCH(h);
+    }
+    {
         ContractArgs a;
         a.Ld = Ld; a.lplane = lplane; a.eL = eL;
         a.Zd = Zd; a.zplane = zrows * Ap; a.eZ = eZ;
         a.nmo = nmo; a.Ap = Ap; a.naux = naux;
-        a.x0 = x0;
-        for (int s = 0; s < 2; ++s) {
-            int lo = s == 0 ? 0 : nocc, hi = s == 0 ? nocc : nmo;
-            int xs0 = std::max(x0, lo), xs1 = std::min(x1, hi);
-            a.xs0[s] = xs0;
-            a.nxs[s] = std::max(0, xs1 - xs0);
-        }
-        a.nt = nt; a.nsplit = S; a.tilesN = (nmo + 63) / 64; a.tiles = tiles; a.ncol = ncol;
+        a.x0 = 0;
+        a.xs0[0] = 0; a.nxs[0] = nocc;
+        a.xs0[1] = nocc; a.nxs[1] = nvir;
+        a.nt = nt; a.nsplit = S; a.tilesN = (nmo + 63) / 64; a.tiles = tiles; a.ncol = M2;
         a.part = acc;
         a.nsplit_total = S; a.split_off = 0; a.item0 = 0;
-        {
-            KTimer tm(h, "sigma_contract");
-            const long rounds = ((long)S * 2 * nt + 7) / 8;
-            hipLaunchKernelGGL(contract_mixed_kernel, dim3((unsigned)(rounds * 8 * tiles)), dim3(256), 0, h->stream, a,
-                               tiles);
-            tm.stop();
-            GW_CHECK_LAUNCH(h);
-        }
+        KTimer tm(h, "sigma_contract");
+        const long rounds = ((long)S * 2 * nt + 7) / 8;
+        hipLaunchKernelGGL(contract_mixed_kernel, dim3((unsigned)(rounds * 8 * tiles)), dim3(256), 0, h->stream, a,
+                           tiles);
+        tm.stop();
+        GW_CHECK_LAUNCH(h);
     }
     GW_TRY(reduce_splits(h, acc, S, M2, nt, nmo, nmo, nmo, true, 1.0, 0.0, sigma_occ, M2, nmo));
     GW_TRY(reduce_splits(h, acc + part_per_sector, S, M2, nt, nmo, nmo, nmo, true, 1.0, 0.0, sigma_vir, M2, nmo));
@@ -1087,15 +1107,18 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
 }
 
 FoldJob make_fold_job(int nt, const i8* Rd, const int* eR, const i8* Ld, const int* eL, const double* eps, int naux,
-                      int Ap, int nmo, int nocc, long j0, long ncol, long rplane, long lplane, float* Zt, u16* Zl) {
+                      int Ap, int nmo, int nocc, long rplane, long lplane, float* Zt, u16* Zl) {
     FoldJob g;
     g.Rd = Rd; g.eR = eR; g.Ld = Ld; g.eL = eL; g.eps = eps;
     g.naux = naux; g.Ap = Ap; g.nmo = nmo; g.nocc = nocc;
-    g.j0 = j0; g.ncol = ncol; g.rplane = rplane; g.lplane = lplane;
+    g.ncol = (long)nmo * nmo; g.rplane = rplane; g.lplane = lplane;
+    g.nb = (nmo + 7) / 8;
+    g.nblk = g.nb * (g.nb + 1) / 2;
     g.Zt = Zt; g.Zl = Zl;
     g.item0 = 0;
     g.nP = Ap / 16;
-    g.nC = (int)((ncol + fold_cols(nt) - 1) / fold_cols(nt));
+    const int cg = fold_cols(nt) / 64;
+    g.nC = (g.nblk + cg - 1) / cg;
     return g;
 }
 

@@ -72,7 +72,7 @@ def test_batch_matches_single_calls(handle, prec, scr, bopts):
     info = b.info()
     print(info, flush=True)
     if bopts:
-        assert info["waves"] > 1 and info["jobs"] > len(SIZES)
+        assert info["waves"] > 1 and info["jobs"] == len(SIZES)
     assert info["graph"] == (scr == "tda")
     for (e, l, o), (so, sv) in zip(tensors, b.sigma):
         ro, rv = handle.sigma_moments(e, l, o, N, screening=scr, precision=prec)

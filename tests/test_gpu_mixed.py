@@ -107,13 +107,22 @@ def test_mixed_rpa_moments_match_oracle(handle, o, v, A, N, seed):
         assert np.array_equal(R[n], R[n].T)
 
 
-def test_mixed_chunking_is_consistent(handle):
+def test_mixed_intermediate_cap(handle):
+    """The mixed stage-1 intermediates (FP32 + BF16 residual, four digit
+    planes and one exponent per row, for all nmo^2 columns) are refused with
+    GW_ENOMEM above opts.zchunk_bytes; at exactly their size the result is the
+    uncapped one."""
+    from paper_2504_17439_amd import gwmom
     o, v, A, N = 4, 21, 70, 5
     eps, L = gwsynth.system(o, v, A, 8)
     e, l = dev(eps), dev(L)
     so1, sv1 = handle.sigma_moments(e, l, o, N, precision="mixed")
-    per_x = (N + 1) * (o + v) * 96 * 4
-    so2, sv2 = handle.sigma_moments(e, l, o, N, precision="mixed", opts={"zchunk_bytes": per_x})
+    Ap = (A + 63) // 64 * 64
+    rows = (N + 1) * (o + v) ** 2
+    need = rows * Ap * (4 + 2 + 4) + 4 * rows
+    with pytest.raises(gwmom.GWError, match="GW_ENOMEM"):
+        handle.sigma_moments(e, l, o, N, precision="mixed", opts={"zchunk_bytes": need - 1})
+    so2, sv2 = handle.sigma_moments(e, l, o, N, precision="mixed", opts={"zchunk_bytes": need})
     assert rel(host(so2), host(so1)) < 1e-13 and rel(host(sv2), host(sv1)) < 1e-13
 
 

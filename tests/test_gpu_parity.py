@@ -85,16 +85,25 @@ def test_tda_sigma(handle, o, v, A, N, seed):
         assert np.array_equal(so[n], so[n].T) and np.array_equal(sv[n], sv[n].T)
 
 
-def test_sigma_chunked_equals_unchunked(handle):
-    """The x-chunking of the folded intermediate does not change the result
-    beyond rounding (a chunk of one orbital at a time vs. the default)."""
+def test_sigma_intermediate_cap(handle):
+    """The folded intermediate ((N+1) naux nmo^2 doubles: every (x, q) column,
+    each symmetric pair formed once) is refused with GW_ENOMEM, outputs
+    untouched, when opts.zchunk_bytes is below it; at exactly its size the
+    result equals the uncapped one."""
+    import torch
+    from paper_2504_17439_amd import gwmom
     o, v, A, N = 4, 21, 70, 5
-    print(f"\n[case] chunking o={o} v={v} A={A} N={N}", flush=True)
+    print(f"\n[case] intermediate cap o={o} v={v} A={A} N={N}", flush=True)
     eps, L = gwsynth.system(o, v, A, 8)
     e, l = dev(eps), dev(L)
     so1, sv1 = handle.sigma_moments(e, l, o, N, "tda")
-    per_x = (N + 1) * A * (o + v) * 8
-    so2, sv2 = handle.sigma_moments(e, l, o, N, "tda", opts={"zchunk_bytes": per_x})
+    need = (N + 1) * A * (o + v) ** 2 * 8
+    out = (torch.full((N + 1, o + v, o + v), 3.0, dtype=torch.float64, device="cuda:0"),
+           torch.full((N + 1, o + v, o + v), 3.0, dtype=torch.float64, device="cuda:0"))
+    with pytest.raises(gwmom.GWError, match="GW_ENOMEM"):
+        handle.sigma_moments(e, l, o, N, "tda", opts={"zchunk_bytes": need - 8}, out=out)
+    assert bool((out[0] == 3.0).all()) and bool((out[1] == 3.0).all())
+    so2, sv2 = handle.sigma_moments(e, l, o, N, "tda", opts={"zchunk_bytes": need})
     so1, sv1, so2, sv2 = map(host, (so1, sv1, so2, sv2))
     assert rel(so2, so1) < 1e-13 and rel(sv2, sv1) < 1e-13
 

@@ -9,7 +9,11 @@ eigensolve are timed once afterwards and reported beside the metric.
 
 Workload (default): nocc=100, nvir=400, naux=1500, nmom_max=11, TDA screening,
 seeded synthetic inputs (occupied eps ~ U[-1.5,-0.3] Ha, virtual eps ~ U[0.1,3.0] Ha,
-L symmetric Gaussian with std 0.3/sqrt(naux) and exp(-|p-q|/8) decay).
+L symmetric Gaussian with std 0.3/sqrt(naux) and exp(-|p-q|/8) decay), mixed
+precision, with the FP64 form timed beside it.  The same JSON line also
+carries the RPA form at that size (mixed and FP64, a few sets) and the
+64-molecule batch (a few graph replays beside sequential calls);
+--no-extra leaves them out.
 
 Prints ONE JSON line (see the keys below).
 """
@@ -34,31 +38,58 @@ def set_flops(o, v, A, N):
     return (4 * N + 2) * A * A * o * v + (N + 1) * 2.0 * A * A * M * M + (N + 1) * 2.0 * A * M ** 3
 
 
+def host_facts():
+    """Cores, CPU model and BLAS of the host the oracle runs on."""
+    import numpy as np
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas, threads = None, None
+    try:
+        from threadpoolctl import threadpool_info
+        info = [d for d in threadpool_info() if d.get("user_api") == "blas"]
+        if info:
+            blas = f"{info[0].get('internal_api')} {info[0].get('version')}"
+            threads = max(int(d.get("num_threads", 1)) for d in info)
+    except Exception:
+        pass
+    return {"cpu_count": os.cpu_count(), "cpu_model": model, "blas": blas or np.__config__.__name__,
+            "blas_threads": threads or os.cpu_count()}
+
+
 def cpu_baseline(o, v, A, N, seed):
     """Time the oracle as it stands on a bounded sample of the same workload:
     the full TDA recursion (eta~ and R_t), plus the self-energy contraction
     restricted to t = 0 (one of the nmom_max+1 identical-cost t passes of the
-    oracle's loop); the set time is the recursion time + (N+1) x the t = 0 time."""
-    import numpy as np
+    oracle's loop); each part best of 3.  The set time is extrapolated as the
+    recursion time + (N+1) x the t = 0 time (the full oracle set takes minutes)."""
     import gwsynth
     from oracle import gw as ogw
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    except Exception:
-        threads = os.cpu_count()
+    facts = host_facts()
     eps, L = gwsynth.system(o, v, A, seed)
     V, D = ogw.particle_hole(eps, L, o)
-    t0 = time.perf_counter()
-    eta = ogw.tda_eta(V, D, N)
-    R = ogw.w_core(eta, V)
-    t1 = time.perf_counter()
-    ogw.sigma_moments(eps, L, o, R[:1])
-    t2 = time.perf_counter()
-    t_set = (t1 - t0) + (N + 1) * (t2 - t1)
-    return {"value": 1.0 / t_set, "unit": "sets/s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"full TDA recursion ({t1 - t0:.1f} s) + self-energy contraction for t=0 "
-                       f"({t2 - t1:.1f} s) x {N + 1} t-passes; same inputs, FP64 NumPy")}
+    t_rec, t_sig = [], []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        eta = ogw.tda_eta(V, D, N)
+        R = ogw.w_core(eta, V)
+        t1 = time.perf_counter()
+        ogw.sigma_moments(eps, L, o, R[:1])
+        t2 = time.perf_counter()
+        t_rec.append(t1 - t0)
+        t_sig.append(t2 - t1)
+        del eta
+    tr, ts = min(t_rec), min(t_sig)
+    t_set = tr + (N + 1) * ts
+    return {"value": 1.0 / t_set, "unit": "sets/s", "cores": int(facts["blas_threads"]), "kind": "oracle",
+            "sample": (f"extrapolated: full TDA recursion ({tr:.2f} s) + self-energy contraction for t=0 "
+                       f"({ts:.2f} s) x {N + 1} t-passes, each best of 3; same inputs, FP64 NumPy"),
+            "host": facts}
 
 
 def fold_kernel_source():
@@ -92,76 +123,80 @@ def recorded_traffic(o, v, A, N):
     return rec["traffic_bytes_per_launch"]
 
 
-def bench_batched(args):
+def measure_batched(nsys, seed, steps, warmup, branches=4):
     """64-molecule batch (nmo uniform over multiples of 5 in [60, 400], nocc =
     nmo/5, naux = 3.5 nmo, TDA, nmom_max = 7, mixed): sets/s of the captured
-    batch replay, beside 64 sequential single-molecule calls in mixed
-    precision and in FP64."""
-    import numpy as np
+    batch replay, beside sequential single-molecule calls in mixed precision
+    and in FP64 (inputs drawn on the device)."""
     import torch
     import gwsynth
     from paper_2504_17439_amd import gwmom
 
     N = 7
-    shapes = gwsynth.batch_shapes(args.nsys, seed=args.seed)
+    shapes = gwsynth.batch_shapes(nsys, seed=seed)
     print(f"[bench] generating {len(shapes)} molecules on the device", file=sys.stderr, flush=True)
     sys_t = []
     for k, (o, v, A) in enumerate(shapes):
-        e, l = gwsynth.system_device(o, v, A, seed=args.seed * 1000 + k)
+        e, l = gwsynth.system_device(o, v, A, seed=seed * 1000 + k)
         sys_t.append((e, l, o))
     torch.cuda.synchronize()
     h = gwmom.Handle(0)
-    print("[bench] sequential single-molecule calls (warmup + timed)", file=sys.stderr, flush=True)
-    for e, l, o in sys_t[:2]:
-        h.sigma_moments(e, l, o, N, precision="mixed")
-    torch.cuda.synchronize()
+    seq = {}
+    for prec in ("mixed", "fp64"):
+        print(f"[bench] sequential single-molecule calls, {prec}", file=sys.stderr, flush=True)
+        for e, l, o in sys_t[:2]:
+            h.sigma_moments(e, l, o, N, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for e, l, o in sys_t:
+            h.sigma_moments(e, l, o, N, precision=prec)
+        torch.cuda.synchronize()
+        seq[prec] = time.perf_counter() - t0
+    print("[bench] planning the batch", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    for e, l, o in sys_t:
-        h.sigma_moments(e, l, o, N, precision="mixed")
-    torch.cuda.synchronize()
-    seq = time.perf_counter() - t0
-    print(f"[bench] sequential mixed {seq:.2f} s; sequential FP64 calls", file=sys.stderr, flush=True)
-    for e, l, o in sys_t[:2]:
-        h.sigma_moments(e, l, o, N, precision="fp64")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for e, l, o in sys_t:
-        h.sigma_moments(e, l, o, N, precision="fp64")
-    torch.cuda.synchronize()
-    seq64 = time.perf_counter() - t0
-    print(f"[bench] sequential FP64 {seq64:.2f} s; planning the batch", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    b = h.batch(sys_t, N, precision="mixed", bopts={"autotune": 1, "branches": args.branches})
+    b = h.batch(sys_t, N, precision="mixed", bopts={"autotune": 1, "branches": branches})
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     info = b.info()
     print(f"[bench] plan {plan_s:.1f} s {info}; warmup", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         b.run()
     torch.cuda.synchronize()
-    print(f"[bench] timed region ({args.steps} batch replays)", file=sys.stderr, flush=True)
+    print(f"[bench] timed region ({steps} batch replays)", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         b.run()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    nsets = len(sys_t) * args.steps
+    b.close()
+    h.close()
+    del sys_t
+    torch.cuda.empty_cache()
+    nsets = len(shapes) * steps
     flops = sum(set_flops(o, v, A, N) for o, v, A in shapes)
+    return {"sets_per_s": nsets / el, "ms_per_replay": 1e3 * el / steps, "replays": steps, "nsys": len(shapes),
+            "sequential_sets_per_s": len(shapes) / seq["mixed"],
+            "speedup_vs_sequential": (nsets / el) / (len(shapes) / seq["mixed"]),
+            "sequential_fp64_sets_per_s": len(shapes) / seq["fp64"],
+            "speedup_vs_sequential_fp64": (nsets / el) / (len(shapes) / seq["fp64"]),
+            "plan_seconds": plan_s, "plan": info, "useful_tflops": flops * steps / el / 1e12,
+            "workload": f"batch of {len(shapes)} molecules, TDA mixed, nmom_max={N}, nmo uniform over multiples "
+                        "of 5 in [60, 400], nocc=nmo/5, naux=3.5 nmo, seed " + str(seed)}
+
+
+def bench_batched(args):
+    """The batch as its own JSON line (one step = one batch replay)."""
+    r = measure_batched(args.nsys, args.seed, args.steps, args.warmup, args.branches)
     out = {
-        "metric": "sigma_moment_sets_per_s", "value": nsets / el, "unit": "sets/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
+        "metric": "sigma_moment_sets_per_s", "value": r["sets_per_s"], "unit": "sets/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_replay"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "i8-digits/i32-acc/f64", "data": "synthetic",
-        "config": {"workload": f"batch of {len(shapes)} molecules, TDA mixed, nmom_max={N}, nmo uniform over "
-                               "multiples of 5 in [60, 400], nocc=nmo/5, naux=3.5 nmo; one step = one batch",
-                   "nsys": len(shapes), "nmom_max": N, "seed": args.seed},
-        "sequential_sets_per_s": len(sys_t) / seq,
-        "speedup_vs_sequential": (nsets / el) / (len(sys_t) / seq),
-        "sequential_fp64_sets_per_s": len(sys_t) / seq64,
-        "speedup_vs_sequential_fp64": (nsets / el) / (len(sys_t) / seq64),
-        "plan_seconds": plan_s, "plan": info,
-        "useful_tflops": flops * args.steps / el / 1e12,
+        "config": {"workload": r["workload"] + "; one step = one batch", "nsys": r["nsys"], "nmom_max": 7,
+                   "seed": args.seed},
     }
+    out.update({k: r[k] for k in ("sequential_sets_per_s", "speedup_vs_sequential", "sequential_fp64_sets_per_s",
+                                  "speedup_vs_sequential_fp64", "plan_seconds", "plan", "useful_tflops")})
     print(json.dumps(out), flush=True)
 
 
@@ -235,47 +270,6 @@ def bench_qsgw(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_scaling(args):
-    """Time per self-energy moment set against system size (the paper's
-    scaling study: TDA, N = 7, growing molecules; here synthetic systems with
-    nocc = nmo/5 and naux = 3 nmo), mixed and FP64, with the fitted exponent
-    of time against nmo (one JSON line; not the headline metric)."""
-    import numpy as np
-    import torch
-    import gwsynth
-    from paper_2504_17439_amd import gwmom
-
-    h = gwmom.Handle(0)
-    sizes = [100, 150, 200, 300, 400, 500]
-    N = 7
-    rows = []
-    for M in sizes:
-        o, v, A = M // 5, M - M // 5, 3 * M
-        print(f"[bench] scaling nmo={M} nocc={o} naux={A}", file=sys.stderr, flush=True)
-        e, l = gwsynth.system_device(o, v, A, args.seed)
-        row = {"nmo": M, "nocc": o, "naux": A}
-        for prec in ("mixed", "fp64"):
-            for _ in range(max(args.warmup, 1)):
-                h.sigma_moments(e, l, o, N, "tda", prec)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                h.sigma_moments(e, l, o, N, "tda", prec)
-            torch.cuda.synchronize()
-            row[f"{prec}_ms"] = (time.perf_counter() - t0) / args.steps * 1e3
-        rows.append(row)
-        del e, l
-    out = {"metric": "sigma_set_ms_vs_nmo", "unit": "ms", "higher_is_better": False, "n_gpus": 1,
-           "config": {"workload": "TDA self-energy moment sets, nmom_max=7, nocc=nmo/5, naux=3 nmo, synthetic"},
-           "rows": rows}
-    x = np.log([r["nmo"] for r in rows])
-    for prec in ("mixed", "fp64"):
-        y = np.log([r[f"{prec}_ms"] for r in rows])
-        out[f"{prec}_exponent_all"] = float(np.polyfit(x, y, 1)[0])
-        out[f"{prec}_exponent_nmo_ge_200"] = float(np.polyfit(x[2:], y[2:], 1)[0])
-    print(json.dumps(out), flush=True)
-
-
 def bench_spectral(args):
     """Green's-function post-processing at the c3 size (one JSON line; not the
     headline metric): mixed self-energy moments and FP64 poles, then the
@@ -344,7 +338,7 @@ def bench_spectral(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="single", choices=["single", "batched", "evgw", "qsgw", "spectral", "scaling"])
+    ap.add_argument("--workload", default="single", choices=["single", "batched", "evgw", "qsgw", "spectral"])
     ap.add_argument("--nomega", type=int, default=2048, help="spectral: frequencies")
     ap.add_argument("--nsys", type=int, default=64)
     ap.add_argument("--branches", type=int, default=4, help="batched: concurrent per-molecule streams")
@@ -360,6 +354,8 @@ def main():
     ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"],
                     help="both: time the mixed form (the reported value) and the FP64 form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="leave out the RPA and batched figures")
+    ap.add_argument("--extra-steps", type=int, default=3, help="RPA sets / batch replays timed")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
@@ -375,9 +371,6 @@ def main():
         return
     if args.workload == "qsgw":
         bench_qsgw(args)
-        return
-    if args.workload == "scaling":
-        bench_scaling(args)
         return
     if args.workload == "spectral":
         bench_spectral(args)
@@ -401,19 +394,19 @@ def main():
     fams_all = ("sigma_fold", "sigma_contract", "recur_xvt", "recur_rv", "recur_rr", "recur_digits", "rpa_quad",
                 "mixed_prep", "mixed_zdig")
 
-    def run(prec, steps, warmup):
+    def run(screening, prec, steps, warmup):
         out = (torch.empty_like(so), torch.empty_like(sv))
 
         def step():
-            h.sigma_moments(e, l, o, N, args.screening, prec, out=out)
+            h.sigma_moments(e, l, o, N, screening, prec, out=out)
 
-        print(f"[bench] {prec}: warmup", file=sys.stderr, flush=True)
+        print(f"[bench] {screening} {prec}: warmup", file=sys.stderr, flush=True)
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
         h.timing(True)
         h.timing_reset()
-        print(f"[bench] {prec}: timed region ({steps} sets)", file=sys.stderr, flush=True)
+        print(f"[bench] {screening} {prec}: timed region ({steps} sets)", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -424,17 +417,32 @@ def main():
         h.timing(False)
         return out, (t1 - t0), fams
 
+    def pole_error(pm, T_occ, T_vir):
+        """Per-pole error of poles pm against FP64 moments T (P10 of the
+        oracle's pins): the largest relative deviation, over n <= N and both
+        sectors, of the moments sum_l v_pl v_ql e_l^n the poles reproduce."""
+        errs = []
+        for e_, v_, T in ((pm["e_occ"], pm["v_occ"], T_occ), (pm["e_vir"], pm["v_vir"], T_vir)):
+            ee = e_.cpu().numpy()
+            vv = v_.cpu().numpy()
+            Tn = T.cpu().numpy()
+            w = np.ones_like(ee)
+            for n in range(N + 1):
+                rec = (vv * w) @ vv.T
+                errs.append(float(np.abs(rec - Tn[n]).max() / np.abs(Tn[n]).max()))
+                w = w * ee
+        return errs
+
     precs = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
     results = {}
     for prec in precs:
-        results[prec] = run(prec, args.steps, args.warmup)
+        results[prec] = run(args.screening, prec, args.steps, args.warmup)
     head = precs[0]
     (so_h, sv_h), elapsed, fams = results[head]
     sets_per_s = args.steps / elapsed
 
     # dominant kernel: stage 1 of the self-energy contraction (the fold GEMM);
-    # its algorithmic flops per set are (N+1) 2 naux^2 nmo^2 whatever the x chunking,
-    # so the per-launch figure is that total over the launches per set
+    # its algorithmic flops per set are (N+1) 2 naux^2 nmo^2 (the method's count)
     fold_ms, fold_n = fams["sigma_fold"]
     launches_per_set = max(fold_n, 1) / args.steps
     avg_flops = (N + 1) * 2.0 * A * A * M * M / launches_per_set
@@ -446,11 +454,21 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                 "kernel": "sigma_fold_kernel" if head == "fp64" else "fold_mixed_kernel",
                 "launch_ms": avg_ms, "launch_flops": avg_flops}
+    # work the kernel issues: the symmetric (x, q) pairs are formed once, in
+    # 8 x 8 blocks of the upper block triangle (diagonal blocks whole)
+    nb = (M + 7) // 8
+    cols = nb * (nb + 1) // 2 * 64
     if head == "mixed":
-        # ten int8 digit products per algorithmic multiply-add are issued
-        roofline["issued_tflops"] = 10 * achieved / 1e12
-        roofline["issued_frac"] = 10 * achieved / peak
+        # ten int8 digit products per multiply-add over the padded aux range
+        Ap = (A + 63) // 64 * 64
+        issued = 2.0 * 10 * (N + 1) * Ap * Ap * cols / launches_per_set
+        roofline["issued_tflops"] = issued / (avg_ms * 1e-3) / 1e12
+        roofline["issued_frac"] = issued / (avg_ms * 1e-3) / peak
         roofline["traffic"] = recorded_traffic(o, v, A, N)
+    else:
+        issued = 2.0 * (N + 1) * A * A * cols / launches_per_set
+        roofline["issued_tflops"] = issued / (avg_ms * 1e-3) / 1e12
+        roofline["issued_frac"] = issued / (avg_ms * 1e-3) / peak
 
     out = {
         "metric": "sigma_moment_sets_per_s",
@@ -482,6 +500,7 @@ def main():
         tp0 = time.perf_counter()
         try:
             ref = h.poles(so64, sv64, fock)
+            torch.cuda.synchronize()
             out["poles_ms"] = 1e3 * (time.perf_counter() - tp0)
         except gwmom.GWError as ex:
             ref = None
@@ -495,6 +514,9 @@ def main():
                                      for n in range(N + 1)]
             try:
                 mres = h.poles(so_h, sv_h, fock, opts={"moment_eps": 1e-9})
+                perr = pole_error(mres, so64, sv64)
+                out["pole_moment_err"] = perr
+                out["pole_moment_err_max"] = max(perr)
                 if ref is not None:
                     q64 = ref["qp"].cpu().numpy()
                     w64 = ref["qp_weight"].cpu().numpy()
@@ -507,6 +529,30 @@ def main():
                 out["mixed_poles_error"] = str(ex)
         elif ref is not None:
             out["homo_lumo_qp"] = [float(ref["qp"][o - 1]), float(ref["qp"][o])]
+    if not args.no_extra and args.screening == "tda":
+        # RPA screening at the same size: the FP64 quadrature of the zeroth
+        # moment in both forms, the recursion and contractions mixed or FP64
+        rpa = {}
+        for prec in ("mixed", "fp64"):
+            _, el_r, fr = run("rpa", prec, args.extra_steps, 1)
+            rpa[prec] = {"sets_per_s": args.extra_steps / el_r,
+                         "kernel_ms_per_set": {k: ms / args.extra_steps for k, (ms, n) in fr.items() if n}}
+        out["rpa_sets_per_s"] = rpa["mixed"]["sets_per_s"]
+        out["rpa_fp64_sets_per_s"] = rpa["fp64"]["sets_per_s"]
+        out["rpa_speedup_vs_fp64"] = rpa["mixed"]["sets_per_s"] / rpa["fp64"]["sets_per_s"]
+        out["rpa_kernel_ms_per_set"] = rpa["mixed"]["kernel_ms_per_set"]
+        out["rpa_fp64_kernel_ms_per_set"] = rpa["fp64"]["kernel_ms_per_set"]
+        out["rpa_steps"] = args.extra_steps
+    h.close()
+    del e, l, so, sv, results, so_h, sv_h
+    torch.cuda.empty_cache()
+    if not args.no_extra and args.screening == "tda":
+        r = measure_batched(args.nsys, args.seed, args.extra_steps, 1, args.branches)
+        out["batched_sets_per_s"] = r["sets_per_s"]
+        out["batched"] = {k: r[k] for k in ("ms_per_replay", "replays", "nsys", "sequential_sets_per_s",
+                                            "speedup_vs_sequential", "sequential_fp64_sets_per_s",
+                                            "speedup_vs_sequential_fp64", "plan_seconds", "useful_tflops",
+                                            "workload")}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(o, v, A, N, args.seed)

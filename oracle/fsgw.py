@@ -16,8 +16,15 @@ its numerics):
     and with it rho, uncertain above the density tolerance of the Fock loop;
   * the Fock loop is a DIIS (12 vectors) extrapolation of the Fock matrices
     F[rho_k] with error vectors rho_k - rho_{k-1}; zeta is re-optimised at
-    every Fock step, and the loop ends when the density stops changing (max
-    element below fock_tol), so at convergence F = F[rho] and Tr rho = N_e;
+    every Fock step (order="interleaved", the default and the device's
+    order), and the loop ends when the density stops changing (max element
+    below fock_tol), so at convergence F = F[rho] and Tr rho = N_e.  The
+    algorithm box nests the two instead: a Fock loop at fixed zeta inside a
+    loop over the electron number (order="nested": zeta from the current F,
+    the Fock loop to convergence at that zeta, zeta again from the converged
+    F, until zeta stops moving).  Both end at the same fixed point
+    (F = F[rho], Tr rho(zeta) = N_e); the interleaved order reaches it in
+    fewer Fock steps;
   * an outer iteration diagonalises the converged F, rotates L into its
     eigenbasis and rebuilds the self-energy moments there; the outer loop
     stops when the QP energies (sorted) change by less than `tol` Ha.
@@ -143,12 +150,47 @@ def qp_energies(F, e_aux, W, zeta):
     return qp, wt
 
 
+def fock_loop_nested(hc, Lc, Fc, e_aux, W, nelec, rho_old, max_fock, fock_tol, diis_space, max_zeta=30,
+                     zeta_tol=1e-10):
+    """The inner loops of the algorithm box in its own nesting: zeta for the
+    current Fock matrix, then the Fock loop (DIIS over F[rho_k], error
+    rho_k - rho_{k-1}) at that fixed zeta until the density settles, then
+    zeta again from the converged F; repeated until zeta moves by less than
+    zeta_tol.  Returns (Fc, rho, zeta, fock_steps)."""
+    steps = 0
+    zeta = None
+    rho = rho_old
+    for _ in range(max_zeta):
+        z_new = solve_zeta(Fc, e_aux, W, nelec)
+        if zeta is not None and abs(z_new - zeta) < zeta_tol:
+            zeta = z_new
+            break
+        zeta = z_new
+        diis = DIIS(diis_space)
+        for _ in range(max_fock):
+            rho, _, _ = density(Fc, e_aux, W, zeta, nelec)
+            Fn = fock(hc, Lc, rho)
+            steps += 1
+            err = rho - rho_old
+            rho_old = rho
+            if np.abs(err).max() < fock_tol:
+                Fc = Fn
+                break
+            Fc = diis.update(Fn, err)
+    return Fc, rho_old, zeta, steps
+
+
 def fsgw(eps, L, nocc, nmom_max, screening="tda", F0=None, tol=1e-6, max_outer=30,
-         max_fock=50, fock_tol=1e-8, diis_space=12, pinv_tol=1e-12):
+         max_fock=50, fock_tol=1e-8, diis_space=12, pinv_tol=1e-12, order="interleaved"):
     """Run fsGW from the reference (eps, L).  F0 (in the reference MO basis)
-    warm-starts the loop; None means F0 = diag(eps).  Returns a dict with the
-    converged Fock matrix F (reference basis), the sorted QP energies per outer
-    iteration, the outer iteration count and the inner (Fock) step count."""
+    warm-starts the loop; None means F0 = diag(eps).  order selects how zeta
+    and the Fock loop are combined ("interleaved": zeta at every Fock step;
+    "nested": the algorithm box's nesting, see fock_loop_nested).  Returns a
+    dict with the converged Fock matrix F (reference basis), the sorted QP
+    energies per outer iteration, the outer iteration count and the inner
+    (Fock) step count."""
+    if order not in ("interleaved", "nested"):
+        raise ValueError(order)
     nmo = eps.shape[0]
     nelec = 2.0 * nocc
     h = core_hamiltonian(eps, L, nocc)
@@ -171,7 +213,11 @@ def fsgw(eps, L, nocc, nmom_max, screening="tda", F0=None, tol=1e-6, max_outer=3
         # mean-field density of Fc = diag(e_cur) (ascending): the first error's reference
         rho_old = np.diag(np.r_[np.full(nocc, 2.0), np.zeros(nmo - nocc)])
         zeta = 0.0
-        for _ in range(max_fock):
+        if order == "nested":
+            Fc, rho_old, zeta, steps = fock_loop_nested(hc, Lc, Fc, e_aux, W, nelec, rho_old, max_fock, fock_tol,
+                                                        diis_space)
+            fock_steps += steps
+        for _ in range(max_fock if order == "interleaved" else 0):
             zeta = solve_zeta(Fc, e_aux, W, nelec)
             rho, _, _ = density(Fc, e_aux, W, zeta, nelec)
             Fn = fock(hc, Lc, rho)

@@ -445,9 +445,12 @@ gw_status batch_create(Handle* h, int nsys, const gw_system* sys, gw_screening s
     }
 
     // ---- branches (TDA: the per-molecule path uses no library handle); molecules
-    // assigned largest first to the least loaded branch by cost ~ nmo^4
+    // assigned largest first to the least loaded branch by cost ~ nmo^4.  A
+    // TDA batch always has at least one branch with its own workspace: the
+    // captured graph then references batch-owned memory only, never the
+    // caller handle's workspace (which a later, larger call may reallocate).
     const int nbr = screening == GW_TDA ? std::min((bo && bo->branches > 0) ? bo->branches : 4, nsys) : 0;
-    if (nbr > 1) {
+    if (nbr >= 1) {
         b->ev.assign(1 + nbr + nsys, nullptr);
         for (auto& e : b->ev)
             if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {

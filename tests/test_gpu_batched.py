@@ -129,6 +129,26 @@ def test_autotuned_plan_gives_the_same_moments(handle):
     b.close()
 
 
+def test_graph_survives_later_workspace_growth(handle):
+    """A one-molecule batch with one branch, then a larger call on the same
+    handle (its workspace slots grow and are reallocated), then a replay: the
+    graph references only batch-owned memory, so the replay still matches."""
+    o, eps, L = systems([25], seed0=21)[0]
+    e, l = dev(eps), dev(L)
+    b = handle.batch([(e, l, o)], 7, bopts={"branches": 1})
+    assert b.info()["graph"]
+    ob, eb, Lb = systems([90], seed0=22)[0]
+    handle.sigma_moments(dev(eb), dev(Lb), ob, 7, precision="mixed")       # grows the handle's workspace
+    handle.sigma_moments(dev(eb), dev(Lb), ob, 7, precision="fp64")
+    so, sv = b.sigma[0]
+    so.zero_()
+    sv.zero_()
+    b.run()
+    ro, rv = handle.sigma_moments(e, l, o, 7, precision="mixed")
+    assert rel(host(so), host(ro)) < 1e-12 and rel(host(sv), host(rv)) < 1e-12
+    b.close()
+
+
 def test_batch_rejects_bad_arguments(handle):
     from paper_2504_17439_amd import gwmom
     o, eps, L = systems([20])[0]

@@ -136,3 +136,25 @@ def test_fsgw_shift_is_fourth_order_in_the_coupling():
         shifts.append(np.abs(r["qp"][o - 1:o + 1] - np.sort(eps)[o - 1:o + 1]))
     ratio = shifts[1] / shifts[0]
     assert np.all(np.abs(ratio - 1.0 / 16.0) < 0.005), ratio
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_nested_and_interleaved_orders_reach_one_fixed_point(seed):
+    """The algorithm box nests a fixed-zeta Fock loop inside the
+    electron-number loop; the oracle (and the device) re-solve zeta at every
+    Fock step.  Both orders stop at F = F[rho], Tr rho(zeta) = N_e, so the
+    converged Fock matrix, density and QP energies agree (to the loop
+    tolerances), whatever the number of Fock steps it takes."""
+    o, v, A, N = 3, 9, 30, 3
+    eps, L = gwsynth.system(o, v, A, seed)
+    a = fs.fsgw(eps, L, o, N, tol=1e-9, fock_tol=1e-10, order="interleaved")
+    b = fs.fsgw(eps, L, o, N, tol=1e-9, fock_tol=1e-10, order="nested")
+    assert a["converged"] and b["converged"]
+    assert np.abs(a["F"] - b["F"]).max() < 1e-7
+    assert np.abs(a["rho"] - b["rho"]).max() < 1e-7
+    assert np.abs(a["qp"] - b["qp"]).max() < 1e-7
+    assert abs(a["zeta"] - b["zeta"]) < 1e-9
+    assert abs(np.trace(b["rho"]) - 2 * o) < 1e-8
+    # the nested order's converged F is a fixed point of the Fock map
+    h = fs.core_hamiltonian(eps, L, o)
+    assert np.abs(fs.fock(h, L, b["rho"]) - b["F"]).max() < 1e-6

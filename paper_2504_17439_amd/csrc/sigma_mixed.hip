@@ -241,6 +241,10 @@ __device__ __forceinline__ int find_job(const Job* __restrict__ jobs, int njobs,
 
 __device__ __forceinline__ i32x4 lds_b128(const lds_t* p) { return *(const i32x4*)p; }
 
+// s_waitcnt immediate that waits for vmcnt <= n (n < 64) and for nothing else:
+// vmcnt bits [3:0] and [15:14], expcnt [6:4] = 7, lgkmcnt [11:8] = 15.
+constexpr int vmcnt_only(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+
 __device__ __forceinline__ i32x4 mfma8(i32x4 a, i32x4 b, i32x4 c) {
     return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
 }
@@ -332,29 +336,73 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) acc[w][tt][cb] = (i32x4){0, 0, 0, 0};
 
-    // Every step issues the same loads in the same order: the A blocks of the
-    // next step, then the B stage NS - 1 ahead (past the end: valid refetches
-    // whose data is never read).  So when a step starts, at most the BVT B
-    // loads of the previous step are younger than its own A blocks, and its B
-    // stage (issued earlier still) has landed once vmcnt <= BVT.
+    // Every step issues the same loads in the same order: the A blocks two
+    // steps ahead (three register buffers: an A block has two steps' MFMAs to
+    // arrive), then the B stage NS - 1 ahead (past the end: valid refetches
+    // whose data is never read).  The prologue issues B(0), A(0), B(1), A(1),
+    // B(2) as if steps -2 and -1 had run.  So when step kt starts, only the
+    // loads of step kt - 1 (A(kt + 1), B(kt + NS - 2)) and the B loads of step
+    // kt - 2 are younger than A(kt), and B(kt) is older still: both have
+    // landed once vmcnt <= 2 BVT + 4 TPW.
+    static_assert(NS >= 3, "B(kt) must be issued before A(kt)");
     const int nkt = Ap / MK;
-    i32x4 a0[3][ND], a1[3][ND];
+
+    // The scales of this lane's results (the exponents of its rows (t, P)
+    // and of its columns, eps of the orbitals of its folded pairs) are
+    // fetched ahead of the k loop, so that the epilogues wait on no memory.
+    int eRv[3][4], eLv[4];
+    bool cokv[4];
 #pragma unroll
-    for (int s = 0; s < NS - 2; ++s) ldB(s);
+    for (int tt = 0; tt < TPW; ++tt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            eRv[tt][r] = eR[(long)min(t0 + tt, NT - 1) * naux + min(P0 + 4 * lk + r, naux - 1)];
+    {
+        const int pbk = ct * CG + cg;
+        int BX, BY;
+        pair_block_of(min(pbk, g.nblk - 1), g.nb, BX, BY);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const int cin = cb * 16 + lr;
+            const int x = 8 * BX + (cin >> 3), y = 8 * BY + (cin & 7);
+            cokv[cb] = pbk < g.nblk && x < nmo && y < nmo;
+            eLv[cb] = eL[cokv[cb] ? (long)x * nmo + y : 0];
+        }
+    }
+    double epx[CG], epy[CG];
+#pragma unroll
+    for (int i = 0; i < CG; ++i) {
+        int BX, BY;
+        pair_block_of(min(ct * CG + i, g.nblk - 1), g.nb, BX, BY);
+        const int cin = wv * 16 + lr;
+        epx[i] = eps[min(8 * BX + (cin >> 3), nmo - 1)];
+        epy[i] = eps[min(8 * BY + (cin & 7), nmo - 1)];
+    }
+
+    i32x4 a0[3][ND], a1[3][ND], a2[3][ND];
+    ldB(0);
 #pragma unroll
     for (int tt = 0; tt < TPW; ++tt)
 #pragma unroll
         for (int d = 0; d < ND; ++d) a0[tt][d] = ldA(0, tt, d);
-    ldB(NS - 2);
+    ldB(1);
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt)
+#pragma unroll
+        for (int d = 0; d < ND; ++d) a1[tt][d] = ldA(min(1, nkt - 1), tt, d);
+    ldB(2);
     const int boff = cg * 64 * 64 + lr * 64 + swz(lr, lk) * 16;
     auto step = [&](int kt, i32x4 (&acur)[3][ND], i32x4 (&anext)[3][ND]) {
         // own loads up to stage kt done; the plain s_barrier (no fence, which
         // would wait for every outstanding LDS-DMA load) then makes all waves'
         // stage kt visible and frees stage kt - 1 for the refill below
-        asm volatile("s_waitcnt vmcnt(%0)" ::"n"(BVT) : "memory");
+        // (the builtin, unlike an asm statement, is seen by the compiler's
+        // own wait placement, which then adds no stricter waits for A(kt))
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_waitcnt(vmcnt_only(2 * BVT + 4 * TPW));
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
-        const int kn = min(kt + 1, nkt - 1);
+        const int kn = min(kt + 2, nkt - 1);
 #pragma unroll
         for (int tt = 0; tt < TPW; ++tt)
 #pragma unroll
@@ -387,10 +435,16 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_
         __builtin_amdgcn_sched_group_barrier(0x008, 12 * TPW, 0);   // weight 2
         __builtin_amdgcn_sched_group_barrier(0x008, 16 * TPW, 0);   // weight 3
     };
-    for (int kt = 0; kt < nkt; kt += 2) {
-        step(kt, a0, a1);
-        if (kt + 1 < nkt) step(kt + 1, a1, a0);
+    // whole triples without conditions (so that the compiler's own waits on
+    // the A registers see one path), then the remainder
+    int kt = 0;
+    for (; kt + 3 <= nkt; kt += 3) {
+        step(kt, a0, a2);
+        step(kt + 1, a1, a0);
+        step(kt + 2, a2, a1);
     }
+    if (kt < nkt) step(kt, a0, a2);
+    if (kt + 1 < nkt) step(kt + 1, a1, a0);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
 
@@ -401,14 +455,6 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_
     constexpr int NQ = 4 * CG;
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
-        const int pbk = ct * CG + cg;
-        int BX, BY;
-        pair_block_of(min(pbk, g.nblk - 1), g.nb, BX, BY);
-        const int cin = cb * 16 + lr;
-        const int x = 8 * BX + (cin >> 3), y = 8 * BY + (cin & 7);
-        const bool cok = pbk < g.nblk && x < nmo && y < nmo;
-        const long j = cok ? (long)x * nmo + y : 0;
-        const int ej = eL[j];
 #pragma unroll
         for (int tt = 0; tt < TPW; ++tt) {
             const int t = t0 + tt;
@@ -416,14 +462,11 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_
             double v[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int P = P0 + 4 * lk + r;
                 double z = 0.0;
-                if (cok && P < naux) {
 #pragma unroll
-                    for (int w = MAXW; w >= 0; --w) z += (double)acc[w][tt][cb][r] * wscale(w);
-                    z = ldexp(z, eR[(long)t * naux + P] + ej);
-                }
-                v[r] = z;
+                for (int w = MAXW; w >= 0; --w) z += (double)acc[w][tt][cb][r] * wscale(w);
+                z = ldexp(z, eRv[tt][r] + eLv[cb]);
+                v[r] = (cokv[cb] && P0 + 4 * lk + r < naux) ? z : 0.0;
             }
             double* dst = X + (((long)t * NQ + cg * 4 + cb) * 64 + lane) * 4;
             *(double4*)dst = make_double4(v[0], v[1], v[2], v[3]);
@@ -457,7 +500,7 @@ __device__ __forceinline__ void fold_tile(const FoldJob& g, int pb, int ct, lds_
             if (o == 1 && BX == BY) break;
             const int xo = o ? y : x;
             const long row = o ? (long)y * nmo + x : (long)x * nmo + y;
-            const double ex = eps[xo];
+            const double ex = o ? epy[i] : epx[i];
             const bool occ = xo < nocc;
             double pw[NT];
             pw[0] = 1.0;

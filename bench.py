@@ -33,9 +33,11 @@ MI355X_PEAK = {"f64": 78.6e12, "bf16": 2.5e15, "i8": 5.0e15, "f32": 157.3e12}
 
 def set_flops(o, v, A, N):
     """Algorithmic flops of one TDA moment set: recursion (4N+2) A^2 ov,
-    W-core contraction (N+1) 2 A^2 M^2, self-energy contraction (N+1) 2 A M^3."""
+    W-core contraction (N+1) A^2 M(M+1) and self-energy contraction
+    (N+1) A M^2 (M+1): R_t L is symmetric in its orbital pair and Sigma^(n)
+    in (p, q), so each symmetric pair is counted once."""
     M = o + v
-    return (4 * N + 2) * A * A * o * v + (N + 1) * 2.0 * A * A * M * M + (N + 1) * 2.0 * A * M ** 3
+    return (4 * N + 2) * A * A * o * v + (N + 1) * A * A * M * (M + 1.0) + (N + 1) * A * M * M * (M + 1.0)
 
 
 def host_facts():
@@ -442,10 +444,11 @@ def main():
     sets_per_s = args.steps / elapsed
 
     # dominant kernel: stage 1 of the self-energy contraction (the fold GEMM);
-    # its algorithmic flops per set are (N+1) 2 naux^2 nmo^2 (the method's count)
+    # its algorithmic flops per set are (N+1) naux^2 nmo (nmo + 1): the
+    # products R_t L over the symmetric orbital pairs x <= q
     fold_ms, fold_n = fams["sigma_fold"]
     launches_per_set = max(fold_n, 1) / args.steps
-    avg_flops = (N + 1) * 2.0 * A * A * M * M / launches_per_set
+    avg_flops = (N + 1) * A * A * M * (M + 1.0) / launches_per_set
     avg_ms = fold_ms / max(fold_n, 1)
     achieved = avg_flops / (avg_ms * 1e-3)
     # the mixed fold runs on the int8 MFMA: its own dtype's dense peak (5.0 POP/s)

@@ -11,23 +11,14 @@
 // range and deposit zeros, which masks ragged rows and the K tail; the one
 // element of a pair that straddles an odd edge is written from a register.
 //
-// LDS layouts (doubles), chosen so that fragment reads are free of bank
-// conflicts for eight lanes of a b128 read and sixteen of a b64 read:
-//   k-contiguous operand X(r, k) = X[r*ld + k]: row r at r*16, its eight
-//     k pairs stored at pair slot c ^ (r & 7); a lane reads one k pair
-//     (ds_read_b128) that feeds two MFMAs;
-//   strided operand X(r, k) = X[off(k) + r]: k row at k*128, element r at
-//     r ^ (16 ((k >> 1) & 3)); two ds_read_b64 (k and k+1) per fragment.
-// Both operands order k the same way: MFMA e of k8-step h takes, in lane
-// group g, the k index 2 (4h + g) + e.
+// The LDS layouts of the two operands are those of lds_f64.h (k-contiguous
+// rows for a k-contiguous operand, k rows of 128 elements for a strided one).
 #include "internal.h"
+#include "lds_f64.h"
 
 #include <algorithm>
 
 namespace gwm {
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef double v2d __attribute__((ext_vector_type(2)));
 
 namespace {
 
@@ -38,19 +29,8 @@ constexpr int NTHR = 256;
 constexpr int SLAB = TBM * TBK;            // doubles per operand slab
 constexpr int STAGE = 2 * SLAB;            // doubles per stage (two stages per workgroup)
 constexpr int GROUP_M = 8;                 // grouped raster: 8 tile rows share one B column slab
-constexpr unsigned MASKED = 0x7ffffff0u;   // buffer offset of a masked lane (>= NREC: reads zero)
-constexpr int NREC = 0x7ffffff0;
-
-typedef __attribute__((address_space(3))) void* lds_ptr_t;
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base) {
-    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, NREC, 0x00020000);
-}
-
-// 16 bytes per lane: one wave instruction fills 1 KB of LDS at lds + 16 * lane
-__device__ __forceinline__ void dma16(__amdgpu_buffer_rsrc_t rs, double* lds, unsigned voff) {
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr_t)lds, 16, voff, 0, 0, 0);
-}
+constexpr unsigned MASKED = LDS_MASKED;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base) { return f64_rsrc(base); }
 
 __device__ inline void upper_tile(int t, int T, int& bi, int& bj) {
     int r = 0;
@@ -176,23 +156,10 @@ __device__ __forceinline__ void loader_fix(const Loader<KC>& L, const Operand& o
     }
 }
 
-// Fragment of a 16-row block (rows rb .. rb+15) for k8-step h: the k index
-// 2 (4h + g) + e of lane group g in element e.
+// Fragment of a 16-row block (rows rb .. rb+15) for k8-step h.
 template <bool KC>
 __device__ __forceinline__ v2d frag(const double* S, int rb, int h, int lane) {
-    const int g = lane >> 4;
-    const int r = rb + (lane & 15);
-    if (KC) {
-        const int kp = 4 * h + g;
-        return *(const v2d*)(S + r * 16 + ((kp ^ (r & 7)) << 1));
-    } else {
-        const int k = 2 * (4 * h + g);
-        const int rs = r ^ (16 * ((k >> 1) & 3));
-        v2d f;
-        f.x = S[k * 128 + rs];
-        f.y = S[(k + 1) * 128 + rs];
-        return f;
-    }
+    return KC ? frag_kc(S, rb, h, lane) : frag_kr<TBM>(S, rb, h, lane);
 }
 
 template <bool AKC, bool BKC>

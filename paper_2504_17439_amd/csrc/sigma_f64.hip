@@ -11,23 +11,24 @@
 //   never reach HBM.  L symmetric in (p,q) means L[Q,q,x] = L[Q,x,q], so the
 //   column index j = x*nmo + q walks L's rows contiguously, and (R_t L) is
 //   symmetric in (x, q): each pair x <= q is formed once and folded into
-//   both of its columns (half the products of the full column range).
+//   both of its columns (half the products of the full column range).  Both
+//   operands reach LDS by direct-to-LDS loads: the rows (t, P) of R_t as
+//   k-contiguous rows, the 64 pair columns of L as k rows.
 // Stage 2 (gemm_f64): Sigma^{(n)}[p,q] = sum_{P, x in sector} L[P,x,p] Zt^{(n)}[P,x,q],
 //   upper 128x128 tiles only, split-K partials, then one reduction that
 //   mirrors the upper triangle (exactly symmetric).
 #include "internal.h"
+#include "lds_f64.h"
 
 #include <algorithm>
 
 namespace gwm {
 
-typedef double v4d __attribute__((ext_vector_type(4)));
-
 namespace {
 
 constexpr int FBP = 16;   // P rows per tile
-constexpr int FBN = 64;   // columns per tile (4 waves x 16)
-constexpr int FBK = 16;   // Q slab
+constexpr int FBC = 64;   // pair columns per tile (one 8 x 8 pair block; 16 per wave)
+constexpr int FBK = 16;   // Q per slab
 constexpr int FTHR = 256;
 
 constexpr double binom2(int n, int k) {
@@ -50,86 +51,163 @@ __device__ __forceinline__ void pair_block(int t, int nb, int& X, int& Y) {
     Y = r + t;
 }
 
+// LDS of one stage: the A slab (rows (t, p), t < NT, p < 16, as k-contiguous
+// rows of 16 Q) then the B slab (16 Q rows of the 64 pair columns).
+template <int NT>
+struct FoldStage {
+    static constexpr int AROWS = NT * FBP;
+    static constexpr int ASLAB = AROWS * FBK;       // doubles
+    static constexpr int BSLAB = FBK * FBC;         // doubles
+    static constexpr int SIZE = ASLAB + BSLAB;
+    static constexpr int AINS = AROWS / 8 / 4;      // A instructions per wave and slab (8 rows each)
+    static constexpr int BINS = BSLAB / 128 / 4;    // B instructions per wave and slab (2 Q rows each)
+    static_assert(AROWS % 32 == 0 && BSLAB % 512 == 0, "fold slab split over four waves");
+};
+
+// Tile: 16 P rows x one pair block, all NT moments; wave w owns pair columns
+// 16 w .. 16 w + 15 (acc[t] = its 16 x 16 block of R_t L).  Work group b runs
+// on XCD b % 8; each XCD walks groups of 4 P-blocks x 8 pair blocks, which
+// share their R rows and L columns through its L2.
 template <int NT>
 __global__ __launch_bounds__(FTHR, 2) void sigma_fold_kernel(const double* __restrict__ R,
                                                               const double* __restrict__ L,
                                                               const double* __restrict__ eps, int naux,
-                                                              int nmo, int nocc, int nb,
+                                                              int nmo, int nocc, int nb, int nblk,
                                                               double* __restrict__ Zt) {
-    __shared__ double Ra[2][NT][FBK][FBP];
-    __shared__ double Lb[2][FBK][FBN + 2];
+    using FS = FoldStage<NT>;
+    __shared__ __attribute__((aligned(16))) double lds[2 * FS::SIZE];
 
+    const int nP = (naux + FBP - 1) / FBP;
+    int pb, ct;
+    {
+        const int nPg = (nP + 3) / 4;
+        const int b = blockIdx.x;
+        const int xcd = b & 7, local = b >> 3;
+        const int grp = (local >> 5) * 8 + xcd;
+        const int w = local & 31;
+        pb = (grp % nPg) * 4 + (w & 3);
+        ct = (grp / nPg) * 8 + (w >> 2);
+        if (pb >= nP || ct >= nblk) return;
+    }
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int lrow = lane & 15;
-    const int lk = lane >> 4;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     int BX, BY;
-    pair_block(blockIdx.x, nb, BX, BY);
-    const int P0 = blockIdx.y * FBP;
+    pair_block(ct, nb, BX, BY);
+    const int P0 = pb * FBP;
     const long nmo2 = (long)nmo * nmo;
+    const int nkt = (naux + FBK - 1) / FBK;
 
-    // the L column this thread loads: pair c = tid & 63 of the block
-    const int cl = tid & 63;
-    const int xl = 8 * BX + (cl >> 3), ql = 8 * BY + (cl & 7);
-    const long jl = (xl < nmo && ql < nmo) ? (long)xl * nmo + ql : 0;
-
-    double rr[NT];
-    double rl[4];
-
-    auto load = [&](int q0) {
-        {
-            int k = tid & 15, p = tid >> 4;
-            int P = P0 + p, Q = q0 + k;
-            bool ok = (P < naux) && (Q < naux);
+    // A instruction i = wv AINS + ii covers rows 8i .. 8i + 7 = moment i / 2,
+    // rows p = 8 (i & 1) + (lane >> 3); lane slot lane & 7 holds the k pair
+    // c = (lane & 7) ^ (lane >> 3) (the row's swizzle).  Rows past naux and
+    // pairs past the Q end are masked.
+    const int ca = (lane & 7) ^ (lane >> 3);
+    unsigned voffA[FS::AINS];
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
-                rr[t] = ok ? R[((long)t * naux + P) * naux + Q] : 0.0;
+    for (int ii = 0; ii < FS::AINS; ++ii) {
+        const int i = wv * FS::AINS + ii;
+        const int p = 8 * (i & 1) + (lane >> 3);
+        voffA[ii] = P0 + p < naux ? (unsigned)(((long)p * naux + 2 * ca) * 8) : LDS_MASKED;
+    }
+    // B instruction j = wv BINS + jj covers Q rows 2j, 2j + 1 (lane >> 5) of
+    // the slab; the lane's slot 2 (lane & 31) holds pair column c = slot ^
+    // sw(2j).  Columns past the orbital range are masked; a pair (q, q + 1)
+    // with only q = nmo - 1 inside is masked and its first element written
+    // after the load (odd nmo).
+    long colB[FS::BINS];
+    unsigned voffB[FS::BINS];
+    bool fixB[FS::BINS];
+#pragma unroll
+    for (int jj = 0; jj < FS::BINS; ++jj) {
+        const int j = wv * FS::BINS + jj;
+        const int c = (2 * (lane & 31)) ^ ksw(2 * j);
+        const int x = 8 * BX + (c >> 3), q = 8 * BY + (c & 7);
+        colB[jj] = (long)x * nmo + q;
+        const bool ok = x < nmo && q + 1 < nmo;
+        fixB[jj] = x < nmo && q + 1 == nmo;
+        voffB[jj] = ok ? (unsigned)(((long)(lane >> 5) * nmo2 + colB[jj]) * 8) : LDS_MASKED;
+    }
+
+    auto issue = [&](int kt, double* S) {
+        const int k0 = kt * FBK;
+        const bool tail = k0 + FBK > naux;
+#pragma unroll
+        for (int ii = 0; ii < FS::AINS; ++ii) {
+            const int i = wv * FS::AINS + ii;
+            const int t = i >> 1;
+            const double* base = R + ((long)t * naux + P0) * naux + k0;
+            const unsigned v = (tail && k0 + 2 * ca + 1 >= naux) ? LDS_MASKED : voffA[ii];
+            dma16(f64_rsrc(base), S + i * 128, v);
         }
+        double* SB = S + FS::ASLAB;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            int k = e * 4 + (tid >> 6);
-            int Q = q0 + k;
-            rl[e] = Q < naux ? L[(long)Q * nmo2 + jl] : 0.0;
+        for (int jj = 0; jj < FS::BINS; ++jj) {
+            const int j = wv * FS::BINS + jj;
+            const int kr = 2 * j + (lane >> 5);
+            const double* base = L + (long)min(k0 + 2 * j, naux - 1) * nmo2;
+            dma16(f64_rsrc(base), SB + j * 128, k0 + kr < naux ? voffB[jj] : LDS_MASKED);
         }
     };
-    auto store = [&](int buf) {
-        int k = tid & 15, p = tid >> 4;
+    // after the loads of slab kt have landed: the lone first elements of
+    // pairs that straddle the Q end (odd naux) or the orbital end (odd nmo)
+    auto fix = [&](int kt, double* S) {
+        const int k0 = kt * FBK;
+        if ((naux & 1) && k0 + FBK > naux) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) Ra[buf][t][k][p] = rr[t];
+            for (int ii = 0; ii < FS::AINS; ++ii) {
+                const int i = wv * FS::AINS + ii;
+                const int p = 8 * (i & 1) + (lane >> 3);
+                if (k0 + 2 * ca == naux - 1 && P0 + p < naux)
+                    S[i * 128 + 2 * lane] = R[((long)(i >> 1) * naux + P0 + p) * naux + naux - 1];
+            }
+        }
+        if (nmo & 1) {
+            double* SB = S + FS::ASLAB;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) Lb[buf][e * 4 + (tid >> 6)][cl] = rl[e];
+            for (int jj = 0; jj < FS::BINS; ++jj) {
+                const int j = wv * FS::BINS + jj;
+                const int kr = 2 * j + (lane >> 5);
+                if (fixB[jj] && k0 + kr < naux) SB[j * 128 + 2 * lane] = L[(long)(k0 + kr) * nmo2 + colB[jj]];
+            }
+        }
     };
 
     v4d acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = (v4d){0.0, 0.0, 0.0, 0.0};
 
-    const int nkt = (naux + FBK - 1) / FBK;
-    load(0);
-    store(0);
-    __syncthreads();
-    int cur = 0;
+    issue(0, lds);
     for (int kt = 0; kt < nkt; ++kt) {
-        bool more = kt + 1 < nkt;
-        if (more) load((kt + 1) * FBK);
-#pragma unroll
-        for (int k4 = 0; k4 < FBK / 4; ++k4) {
-            double b = Lb[cur][k4 * 4 + lk][wave * 16 + lrow];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                double a = Ra[cur][t][k4 * 4 + lk][lrow];
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
-            }
-        }
-        if (more) store(cur ^ 1);
+        double* S = lds + (kt & 1) * FS::SIZE;
+        // own loads of slab kt done (and its fix-ups written); the barrier
+        // makes the slab visible to every wave and frees the other stage,
+        // whose reads all ended before it, for the refill below
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        fix(kt, S);
         __syncthreads();
-        cur ^= 1;
+        if (kt + 1 < nkt) issue(kt + 1, lds + ((kt + 1) & 1) * FS::SIZE);
+        const double* SB = S + FS::ASLAB;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const v2d fb = frag_kr<FBC>(SB, wv * 16, h, lane);
+            v2d fa[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) fa[t] = frag_kc(S, t * 16, h, lane);
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(e ? fa[t].y : fa[t].x, e ? fb.y : fb.x, acc[t],
+                                                                 0, 0, 0);
+        }
     }
 
     // epilogue: lane owns pair c and rows lk + 4r; binomial / eps-power fold
     // for each output of the pair
-    const int c = wave * 16 + lrow;
+    const int lrow = lane & 15;
+    const int lk = lane >> 4;
+    const int c = wv * 16 + lrow;
     const int x = 8 * BX + (c >> 3), q = 8 * BY + (c & 7);
     if (x >= nmo || q >= nmo) return;
     const bool twin = BX < BY;   // also the transposed output (q, x)
@@ -165,10 +243,13 @@ __global__ __launch_bounds__(FTHR, 2) void sigma_fold_kernel(const double* __res
 template <int NT>
 void launch_fold(Handle* h, int naux, int nmo, int nocc, const double* eps, const double* R,
                  const double* L, double* Zt) {
-    const int nb = (nmo + 7) / 8;
-    dim3 grid((unsigned)(nb * (nb + 1) / 2), (unsigned)((naux + FBP - 1) / FBP));
-    hipLaunchKernelGGL((sigma_fold_kernel<NT>), grid, dim3(FTHR), 0, h->stream, R, L, eps, naux, nmo,
-                       nocc, nb, Zt);
+    const int nb = (nmo + 7) / 8, nblk = nb * (nb + 1) / 2;
+    const long nP = (naux + FBP - 1) / FBP;
+    // groups of 4 P-blocks x 8 pair blocks, 8 groups (one per XCD) per round
+    const long groups = (nP + 3) / 4 * ((nblk + 7) / 8);
+    const long rounds = (groups + 7) / 8;
+    hipLaunchKernelGGL((sigma_fold_kernel<NT>), dim3((unsigned)(rounds * 8 * 32)), dim3(FTHR), 0, h->stream, R, L,
+                       eps, naux, nmo, nocc, nb, nblk, Zt);
 }
 
 }  // namespace
@@ -176,8 +257,11 @@ void launch_fold(Handle* h, int naux, int nmo, int nocc, const double* eps, cons
 gw_status sigma_fold_f64(Handle* h, int nt, int naux, int nmo, int nocc, const double* eps,
                          const double* R, const double* L, double* Zt) {
     const long nb = (nmo + 7) / 8;
-    if (nb * (nb + 1) / 2 > 0x7fffffffL || (naux + FBP - 1) / FBP > 65535)
-        return set_err(h, GW_EINVAL, "sigma_fold: grid too large");
+    const long groups = ((naux + FBP - 1) / FBP + 3) / 4 * ((nb * (nb + 1) / 2 + 7) / 8);
+    if ((groups + 7) / 8 * 256 > 0x7fffffffL) return set_err(h, GW_EINVAL, "sigma_fold: grid too large");
+    // slabs are addressed by 32-bit byte offsets: 16 rows of R, two rows of L
+    if ((long)FBP * naux * 8 >= (1L << 31) || 2L * nmo * nmo * 8 >= (1L << 31))
+        return set_err(h, GW_EINVAL, "sigma_fold: naux or nmo too large");
     KTimer timer(h, "sigma_fold");
     switch (nt) {
         case 2: launch_fold<2>(h, naux, nmo, nocc, eps, R, L, Zt); break;

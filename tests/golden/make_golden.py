@@ -6,7 +6,7 @@ itself, written by this script (which calls only ``oracle/`` and the seeded
 input generator): a later change to the oracle's arithmetic shows up as a
 mismatch in ``tests/test_oracle_golden.py`` and has to be justified.
 
-    python tests/golden/make_golden.py [small] [c3_tda] [c3_rpa]
+    python tests/golden/make_golden.py [small] [c3_tda] [c3_rpa] [c4_tda]
 
 The full-size fixtures (``c3_*.npz``: sampled rows and QP energies at nocc=100,
 nvir=400, naux=1500, nmom_max=11) take minutes of CPU; the GPU tests at that
@@ -65,6 +65,30 @@ def c3_fixture(screening):
         qp=r["qp"], qp_weight=r["qp_weight"])
 
 
+C4 = (80, 320, 1400, 7, 400)   # the largest molecule shape of the 64-molecule batch, seed 400
+C4_R_ROWS = [0, 699, 1399]
+C4_SIGMA_ROWS = [0, 79, 80, 81, 250, 399]
+
+
+def c4_fixture():
+    """Oracle TDA self-energy moments at nocc=80, nvir=320, naux=1400,
+    nmom_max=7 (gwsynth.system seed 400; the largest molecule shape of the
+    batch workload): sampled rows of every R_n and of both sectors."""
+    o, v, A, N, seed = C4
+    eps, L = gwsynth.system(o, v, A, seed)
+    V, D = gw.particle_hole(eps, L, o)
+    R = np.asarray(gw.w_core(gw.tda_eta(V, D, N), V))
+    so, sv, _ = gw.sigma_moments(eps, L, o, R)
+    return dict(
+        nocc=o, nvir=v, naux=A, nmom_max=N, seed=seed,
+        r_rows=np.array(C4_R_ROWS), R_rows=R[:, C4_R_ROWS, :],
+        sigma_rows=np.array(C4_SIGMA_ROWS),
+        so_rows=so[:, C4_SIGMA_ROWS, :], sv_rows=sv[:, C4_SIGMA_ROWS, :],
+        so_absmax=np.abs(so).reshape(N + 1, -1).max(axis=1),
+        sv_absmax=np.abs(sv).reshape(N + 1, -1).max(axis=1),
+        R_absmax=np.abs(R).reshape(N + 1, -1).max(axis=1))
+
+
 def exact_tiny():
     """Exact full-frequency one-shot GW by brute force: nocc=1, nvir=2, naux=3, seed 5, amp 1."""
     out = []
@@ -89,4 +113,6 @@ if __name__ == "__main__":
     for scr in ("tda", "rpa"):
         if f"c3_{scr}" in which:
             np.savez_compressed(os.path.join(HERE, f"c3_{scr}_g0w0.npz"), **c3_fixture(scr))
+    if "c4_tda" in which:
+        np.savez_compressed(os.path.join(HERE, "c4_tda_sigma.npz"), **c4_fixture())
     print("written", " ".join(which))

@@ -161,3 +161,42 @@ def test_batch_rejects_bad_arguments(handle):
     bad[o - 1] = bad[o] + 1.0   # occupied above virtual
     with pytest.raises(gwmom.GWError, match="GW_EINVAL"):
         handle.batch([(e, l, o), (dev(bad), l, o)], 7)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_c4_size_batch(handle, prec):
+    """The largest molecule shapes of the 64-molecule batch (nmo 355-400,
+    nocc = nmo/5, naux = 3.5 nmo, nmom_max 7, TDA): the batch against single
+    calls (1e-12), and the nmo = 400 molecule against stored oracle rows
+    (tests/golden/c4_tda_sigma.npz, written by make_golden.py from the oracle
+    alone): FP64 1e-10, mixed 1e-8 relative to the largest element of each
+    moment."""
+    import os
+    import torch
+    f = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c4_tda_sigma.npz"))
+    o0, v0, A0, N, seed = (int(f[k]) for k in ("nocc", "nvir", "naux", "nmom_max", "seed"))
+    print(f"\n[case] c4-size batch {prec}: nmo 400 (seed {seed}), 380, 355", flush=True)
+    sy = [(o0, *gwsynth.system(o0, v0, A0, seed))]
+    for k, M in enumerate((380, 355)):
+        o, v, A = shape(M)
+        sy.append((o, *gwsynth.system(o, v, A, seed + 1 + k)))
+    tensors = [(dev(e), dev(L), o) for o, e, L in sy]
+    b = handle.batch([(e, l, o) for e, l, o in tensors], N, precision=prec)
+    print(b.info(), flush=True)
+    for (e, l, o), (so, sv) in zip(tensors, b.sigma):
+        ro, rv = handle.sigma_moments(e, l, o, N, precision=prec)
+        assert rel(host(so), host(ro)) < 1e-12 and rel(host(sv), host(rv)) < 1e-12
+        del ro, rv
+    tol = 1e-10 if prec == "fp64" else MIXED_TOL
+    rows = list(f["sigma_rows"])
+    so, sv = (host(t) for t in b.sigma[0])
+    worst = 0.0
+    for n in range(N + 1):
+        eo = np.abs(so[n][rows] - f["so_rows"][n]).max() / f["so_absmax"][n]
+        ev = np.abs(sv[n][rows] - f["sv_rows"][n]).max() / f["sv_absmax"][n]
+        worst = max(worst, eo, ev)
+        assert eo < tol and ev < tol, (prec, n, eo, ev)
+    print(f"c4-size {prec}: batch vs oracle rows {worst:.2e}", flush=True)
+    b.close()
+    del tensors
+    torch.cuda.empty_cache()

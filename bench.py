@@ -105,7 +105,7 @@ def fold_kernel_source():
     b = src.index("__device__ __forceinline__ int swz(")
     part2 = src[b:src.index("\n", b)]
     c = src.index("template <int NT>\nstruct FoldSlab {")
-    part3 = src[c:src.index("// Grouped, persistent: work items (job, P-block, column tile)")]
+    part3 = src[c:src.index("// Grouped, persistent, XCD-aware: the tiles of every job")]
     return part1 + part2 + part3
 
 

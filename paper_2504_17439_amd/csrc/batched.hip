@@ -127,7 +127,7 @@ gw_status build_tables(gw_batch_s* b, int target) {
             FoldJob f = make_fold_job(nt, m.Rd, m.eR, m.Ld, m.eL, s.eps, s.naux, m.Ap, m.nmo, s.nocc, m.rplane,
                                       m.lplane, Zt, Zl);
             f.item0 = fi;
-            fi += (long)f.nP * f.nC;
+            fi += fold_groups(f);
             fj.push_back(f);
             ZdigJob z{j.zrows, m.Ap, Zt, Zl, eZ, Zd, zi};
             zi += j.zrows;
@@ -146,7 +146,7 @@ gw_status build_tables(gw_batch_s* b, int target) {
             a.nt = nt; a.nsplit = j.S; a.tilesN = (m.nmo + 63) / 64; a.tiles = contract_tiles(m.nmo); a.ncol = ncol;
             a.part = m.part; a.nsplit_total = m.slots; a.split_off = j.slot0;
             a.item0 = ci;
-            ci += (long)contract_tiles(m.nmo) * j.S * 2 * nt;
+            ci += contract_groups(a);
             cj.push_back(a);
         }
         tab.njobs = (int)ids.size();

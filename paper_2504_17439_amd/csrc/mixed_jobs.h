@@ -18,7 +18,7 @@ constexpr int MIX_MK = 64;  // k per MFMA step (64 B per row); digit planes are 
 // as 8 x 8 blocks of orbital pairs (x, y), x <= y (nblk upper blocks of nb
 // per side); every pair is written to both of its rows (x, y) and (y, x) of
 // Zt / Zl [nt][ncol = nmo^2][Ap].  item0 / nP / nC index its tiles in grouped
-// launches.
+// launches (item0 in tile groups).
 struct FoldJob {
     const i8* Rd;
     const int* eR;
@@ -30,7 +30,7 @@ struct FoldJob {
     int nb, nblk;
     float* Zt;
     u16* Zl;
-    long item0;
+    long item0;  // grouped launches: first tile group (fold_groups) of this job
     int nP, nC;  // P-blocks (Ap / 16) and column tiles (fold_cols / 64 pair blocks each)
 };
 
@@ -54,10 +54,17 @@ struct ContractArgs {
     long ncol;
     double* part;                                // [2][nt][nsplit_total][nmo][nmo] FP64, accumulated
     int nsplit_total, split_off;                 // this job's splits are slots split_off .. + nsplit
-    long item0;                                  // grouped launches: first work item of this job
+    long item0;                                  // grouped launches: first item group (contract_groups)
 };
 
 inline int mixed_Ap(int naux) { return (naux + MIX_MK - 1) / MIX_MK * MIX_MK; }
+
+// Tile groups of a stage-1 job in grouped launches: 4 P-blocks x 8 column tiles.
+inline long fold_groups(const FoldJob& f) { return (long)((f.nP + 3) / 4) * ((f.nC + 7) / 8); }
+
+// Item groups of a stage-2 job in grouped launches: 32 consecutive work items
+// (tile, n, split, sector).
+inline long contract_groups(const ContractArgs& a) { return ((long)a.tiles * a.nt * a.nsplit * 2 + 31) / 32; }
 
 // Stage-1 tile shape for nt moments: each of the 4 waves owns fold_tpw(nt)
 // moments (int32 accumulators for 4 digit weights x 4 column blocks each),
@@ -84,7 +91,9 @@ gw_status mixed_prep(Handle* h, int naux, int nmo, int nt, const double* L, cons
 FoldJob make_fold_job(int nt, const i8* Rd, const int* eR, const i8* Ld, const int* eL, const double* eps, int naux,
                       int Ap, int nmo, int nocc, long rplane, long lplane, float* Zt, u16* Zl);
 
-// Grouped launches over device job tables (item0 prefix sums set by the caller).
+// Grouped launches over device job tables; total = the groups of all jobs
+// (item0 prefix sums of fold_groups / contract_groups, set by the caller;
+// zdig: rows).
 gw_status launch_fold_grouped(Handle* h, int nt, const FoldJob* jobs, int njobs, long total, int grid);
 gw_status launch_zdig_grouped(Handle* h, const ZdigJob* jobs, int njobs, long total_rows);
 gw_status launch_contract_grouped(Handle* h, const ContractArgs* jobs, int njobs, long total, int grid);

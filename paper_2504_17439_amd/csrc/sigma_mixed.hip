@@ -548,17 +548,30 @@ __global__ __launch_bounds__(256, 1) void fold_mixed_kernel(FoldJob g) {
     fold_tile<NT>(g, pb, ct, lds);
 }
 
-// Grouped, persistent: work items (job, P-block, column tile) over all jobs;
-// the P-block index runs fastest so neighbouring items share a column tile.
-// LDS is free again at the start of each item: fold_tile ends with a barrier.
+// Grouped, persistent, XCD-aware: the tiles of every job are cut into groups
+// of 4 P-blocks x 8 column tiles (which share their R- and L-digit slabs),
+// numbered job after job (item0 = a job's first group).  Work group b runs on
+// XCD x = b % 8 and is work group b / 8 of that XCD's W = gridDim / 8; XCD x
+// takes the groups x, x + 8, x + 16, ... and its work groups walk that
+// sequence's tiles (32 per group) with stride W, so the tiles of one group
+// run together on one XCD and meet in its L2.  LDS is free again at the start
+// of each tile: fold_tile ends with a barrier.
 template <int NT>
 __global__ __launch_bounds__(256, 1) void fold_grouped_kernel(const FoldJob* __restrict__ jobs, int njobs,
-                                                              long total) {
+                                                              long groups) {
     __shared__ __attribute__((aligned(16))) lds_t lds[FoldSlab<NT>::LDS];
-    for (long it = blockIdx.x; it < total; it += gridDim.x) {
-        const FoldJob g = jobs[find_job(jobs, njobs, it)];
-        const long local = it - g.item0;
-        fold_tile<NT>(g, (int)(local % g.nP), (int)(local / g.nP), lds);
+    const int x = blockIdx.x & 7;
+    const long W = gridDim.x >> 3;
+    for (long k = blockIdx.x >> 3;; k += W) {
+        const long grp = (k >> 5) * 8 + x;
+        if (grp >= groups) break;
+        const FoldJob g = jobs[find_job(jobs, njobs, grp)];
+        const long gl = grp - g.item0;
+        const int nPg = (g.nP + 3) / 4;
+        const int w = (int)(k & 31);
+        const int pb = (int)(gl % nPg) * 4 + (w & 3);
+        const int ct = (int)(gl / nPg) * 8 + (w >> 2);
+        if (pb < g.nP && ct < g.nC) fold_tile<NT>(g, pb, ct, lds);
     }
 }
 
@@ -839,21 +852,32 @@ __global__ __launch_bounds__(256, 1) void contract_mixed_kernel(ContractArgs g, 
     contract_tile(g, tile, grp % g.nsplit, grp / g.nsplit, lds);
 }
 
-// Grouped, persistent: work items (job, tile, split, sector * nt + n).  As in
-// stage 1, contract_tile ends with a barrier, so no wave starts loading the
-// next item while another still reads the slabs of the last one.
+// Grouped, persistent, XCD-aware: the work items of a job, ordered (tile,
+// n, split, sector) with the tile fastest, are cut into groups of 32
+// consecutive items (consecutive n share the L-digit slabs of their x range),
+// numbered job after job (item0 = a job's first group).  As in stage 1, XCD
+// x takes the groups x, x + 8, ... and its work groups walk their items with
+// stride W = gridDim / 8; contract_tile ends with a barrier, so no wave
+// starts loading the next item while another still reads the slabs of the
+// last one.
 __global__ __launch_bounds__(256, 1) void contract_grouped_kernel(const ContractArgs* __restrict__ jobs, int njobs,
-                                                                  long total) {
+                                                                  long groups) {
     __shared__ __attribute__((aligned(16))) lds_t lds[2 * C_BUF];
-    for (long it = blockIdx.x; it < total; it += gridDim.x) {
-        const ContractArgs g = jobs[find_job(jobs, njobs, it)];
-        const int tiles = g.tiles;
-        long local = it - g.item0;
-        const int tile = (int)(local % tiles);
-        local /= tiles;
-        const int split = (int)(local % g.nsplit);
-        const int zi = (int)(local / g.nsplit);
-        contract_tile(g, tile, split, zi, lds);
+    const int x = blockIdx.x & 7;
+    const long W = gridDim.x >> 3;
+    for (long k = blockIdx.x >> 3;; k += W) {
+        const long grp = (k >> 5) * 8 + x;
+        if (grp >= groups) break;
+        const ContractArgs g = jobs[find_job(jobs, njobs, grp)];
+        const long i = (grp - g.item0) * 32 + (k & 31);
+        const int T = g.tiles;
+        if (i >= (long)T * g.nt * g.nsplit * 2) continue;
+        long r = i / T;
+        const int n = (int)(r % g.nt);
+        r /= g.nt;
+        const int split = (int)(r % g.nsplit);
+        const int sector = (int)(r / g.nsplit);
+        contract_tile(g, (int)(i % T), split, sector * g.nt + n, lds);
     }
 }
 
@@ -1183,7 +1207,8 @@ gw_status mixed_prep(Handle* h, int naux, int nmo, int nt, const double* L, cons
 
 gw_status launch_fold_grouped(Handle* h, int nt, const FoldJob* jobs, int njobs, long total, int grid) {
     if (total <= 0) return GW_OK;
-    const dim3 g((unsigned)std::max<long>(1, std::min<long>(grid, total)));
+    // a whole number of work groups per XCD
+    const dim3 g((unsigned)std::max(8, grid / 8 * 8));
     switch (nt) {
         case 2: hipLaunchKernelGGL((fold_grouped_kernel<2>), g, dim3(256), 0, h->stream, jobs, njobs, total); break;
         case 4: hipLaunchKernelGGL((fold_grouped_kernel<4>), g, dim3(256), 0, h->stream, jobs, njobs, total); break;
@@ -1207,7 +1232,8 @@ gw_status launch_zdig_grouped(Handle* h, const ZdigJob* jobs, int njobs, long to
 
 gw_status launch_contract_grouped(Handle* h, const ContractArgs* jobs, int njobs, long total, int grid) {
     if (total <= 0) return GW_OK;
-    const dim3 g((unsigned)std::max<long>(1, std::min<long>(grid, total)));
+    // a whole number of work groups per XCD
+    const dim3 g((unsigned)std::max(8, grid / 8 * 8));
     hipLaunchKernelGGL(contract_grouped_kernel, g, dim3(256), 0, h->stream, jobs, njobs, total);
     GW_CHECK_LAUNCH(h);
     return GW_OK;

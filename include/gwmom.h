@@ -505,6 +505,21 @@ gw_status gw_mlp_backward(gw_handle h, int rows, const float* params, const floa
                           const float* x, const float* act, const float* y,
                           const float* target, float* grad, float* loss);
 
+/* norm [8] from training rows: the column means and standard deviations
+ * (population, floored at 1e-12) of x [rows][3], then the mean and standard
+ * deviation of the targets t [rows]; FP64 sums in a fixed order. */
+gw_status gw_mlp_norm(gw_handle h, int rows, const float* x, const float* t, float* norm);
+
+/* t [nmo] = F[p][p] - eps[p]: the training target from a converged fsGW Fock
+ * matrix F [nmo][nmo] (reference basis, as returned by gw_fsgw). */
+gw_status gw_mlp_target(gw_handle h, int nmo, const double* F, const double* eps, float* t);
+
+/* F0 [nmo][nmo] = diag(eps + y), y the model's prediction (params, norm) from
+ * the features of (eps, L) (gw_mlp_features): the warm start of gw_fsgw.
+ * nmo = nocc + nvir; L [naux][nmo][nmo]. */
+gw_status gw_mlp_warm_start(gw_handle h, int nocc, int nvir, int naux, const double* eps, const double* L,
+                            const float* params, const float* norm, double* F0);
+
 /* One Adam step (step counts from 1, bias-corrected) on params with moment
  * buffers m, v [33665] (zero before the first step). */
 gw_status gw_mlp_adam(gw_handle h, int step, float lr, float beta1, float beta2, float eps,

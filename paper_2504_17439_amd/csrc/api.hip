@@ -497,6 +497,29 @@ gw_status gw_mlp_backward(gw_handle h, int rows, const float* params, const floa
     return gwm::mlp_backward(h, rows, params, norm, x, act, y, target, grad, loss);
 }
 
+gw_status gw_mlp_norm(gw_handle h, int rows, const float* x, const float* target, float* norm) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    if (rows < 1 || !x || !target || !norm) return gwm::set_err(h, GW_EINVAL, "gw_mlp_norm: bad arguments");
+    return gwm::mlp_norm(h, rows, x, target, norm);
+}
+
+gw_status gw_mlp_target(gw_handle h, int nmo, const double* F, const double* eps, float* target) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    if (nmo < 1 || !F || !eps || !target) return gwm::set_err(h, GW_EINVAL, "gw_mlp_target: bad arguments");
+    return gwm::mlp_target(h, nmo, F, eps, target);
+}
+
+gw_status gw_mlp_warm_start(gw_handle h, int nocc, int nvir, int naux, const double* eps, const double* L,
+                            const float* params, const float* norm, double* F0) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    if (nocc < 1 || nvir < 1 || naux < 1 || !eps || !L || !params || !norm || !F0)
+        return gwm::set_err(h, GW_EINVAL, "gw_mlp_warm_start: bad sizes or null pointer");
+    return gwm::mlp_warm_start(h, nocc, nvir, naux, eps, L, params, norm, F0);
+}
+
 gw_status gw_mlp_adam(gw_handle h, int step, float lr, float beta1, float beta2, float eps, float* params,
                       const float* grad, float* m, float* v) {
     if (!h) return GW_EINVAL;

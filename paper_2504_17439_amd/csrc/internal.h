@@ -393,6 +393,10 @@ gw_status batch_info(gw_batch b, int* njobs, int* nwaves, int* graph, int* split
 void batch_destroy(gw_batch b);
 
 long mlp_param_count();
+gw_status mlp_norm(Handle* h, int rows, const float* x, const float* t, float* norm);
+gw_status mlp_target(Handle* h, int nmo, const double* F, const double* eps, float* t);
+gw_status mlp_warm_start(Handle* h, int nocc, int nvir, int naux, const double* eps, const double* L,
+                         const float* prm, const float* norm, double* F0);
 gw_status mlp_features(Handle* h, int nocc, int nvir, int naux, const double* eps, const double* L, float* feat);
 gw_status mlp_forward(Handle* h, int rows, const float* prm, const float* norm, const float* x, float* act, float* y);
 gw_status mlp_backward(Handle* h, int rows, const float* prm, const float* norm, const float* x, const float* act,

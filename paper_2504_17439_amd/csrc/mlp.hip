@@ -167,9 +167,92 @@ __global__ void adam_kernel(long n, float lr, float b1, float b2, float eps, flo
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// norm = (mean of the three feature columns, their standard deviations, mean
+// and standard deviation of the targets) over rows: one block, FP64 partial
+// sums per thread over a fixed row stride, then a fixed-order tree; two
+// passes (means, then squared deviations); deviations floored at 1e-12.
+__global__ void norm_kernel(int rows, const float* __restrict__ x, const float* __restrict__ t,
+                            float* __restrict__ norm) {
+    __shared__ double sh[4][256];
+    __shared__ double mean[4];
+    const int tid = threadIdx.x;
+    for (int pass = 0; pass < 2; ++pass) {
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int r = tid; r < rows; r += 256) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double v = c < 3 ? (double)x[(long)r * 3 + c] : (double)t[r];
+                const double d = pass ? v - mean[c] : v;
+                s[c] += pass ? d * d : d;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sh[c][tid] = s[c];
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sh[c][tid] += sh[c][tid + w];
+            __syncthreads();
+        }
+        if (tid < 4) {
+            const double v = sh[tid][0] / rows;
+            if (pass == 0) {
+                mean[tid] = v;
+                norm[tid < 3 ? tid : 6] = (float)v;
+            } else {
+                norm[tid < 3 ? 3 + tid : 7] = (float)fmax(sqrt(v), 1e-12);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// t[p] = F[p][p] - eps[p]
+__global__ void target_kernel(int nmo, const double* __restrict__ F, const double* __restrict__ eps,
+                              float* __restrict__ t) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nmo) t[p] = (float)(F[(long)p * nmo + p] - eps[p]);
+}
+
+// F0 = diag(eps + y)
+__global__ void warm_start_kernel(int nmo, const double* __restrict__ eps, const float* __restrict__ y,
+                                  double* __restrict__ F0) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)nmo * nmo) return;
+    const long p = i / nmo, q = i - p * nmo;
+    F0[i] = p == q ? eps[p] + (double)y[p] : 0.0;
+}
+
 }  // namespace
 
 long mlp_param_count() { return NPARAM; }
+
+gw_status mlp_norm(Handle* h, int rows, const float* x, const float* t, float* norm) {
+    hipLaunchKernelGGL(norm_kernel, dim3(1), dim3(256), 0, h->stream, rows, x, t, norm);
+    GW_CHECK_LAUNCH(h);
+    return GW_OK;
+}
+
+gw_status mlp_target(Handle* h, int nmo, const double* F, const double* eps, float* t) {
+    hipLaunchKernelGGL(target_kernel, dim3((unsigned)((nmo + 255) / 256)), dim3(256), 0, h->stream, nmo, F, eps, t);
+    GW_CHECK_LAUNCH(h);
+    return GW_OK;
+}
+
+gw_status mlp_warm_start(Handle* h, int nocc, int nvir, int naux, const double* eps, const double* L,
+                         const float* prm, const float* norm, double* F0) {
+    const int nmo = nocc + nvir;
+    float* buf = (float*)ws_get(h, WS_FS6, sizeof(float) * 4L * nmo);
+    if (!buf) return GW_ENOMEM;
+    float *feat = buf, *y = buf + 3L * nmo;
+    GW_TRY(mlp_features(h, nocc, nvir, naux, eps, L, feat));
+    GW_TRY(mlp_forward(h, nmo, prm, norm, feat, nullptr, y));
+    const long n = (long)nmo * nmo;
+    hipLaunchKernelGGL(warm_start_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream, nmo, eps, y, F0);
+    GW_CHECK_LAUNCH(h);
+    return GW_OK;
+}
 
 gw_status mlp_features(Handle* h, int nocc, int nvir, int naux, const double* eps, const double* L, float* feat) {
     const int nmo = nocc + nvir;

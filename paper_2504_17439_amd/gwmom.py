@@ -29,7 +29,8 @@ EXPORTS = ("gw_create", "gw_set_stream", "gw_synchronize", "gw_destroy", "gw_las
            "gw_poles",
            "gw_fsgw", "gw_evgw", "gw_naf", "gw_qsgw", "gw_spectral", "gw_aufbau", "gw_zeta_shift", "gw_batch_create", "gw_batch_run", "gw_batch_info", "gw_batch_destroy",
            "gw_mlp_param_count", "gw_mlp_features", "gw_mlp_forward", "gw_mlp_backward",
-           "gw_mlp_adam", "gw_timing_enable", "gw_timing_reset", "gw_timing_read")
+           "gw_mlp_adam", "gw_mlp_norm", "gw_mlp_target", "gw_mlp_warm_start", "gw_timing_enable",
+           "gw_timing_reset", "gw_timing_read")
 
 
 class GWError(RuntimeError):
@@ -142,6 +143,9 @@ def load_library(path: str = LIB_PATH):
         "gw_mlp_forward": ([H, I, P, P, P, P, P], I),
         "gw_mlp_backward": ([H, I, P, P, P, P, P, P, P, P], I),
         "gw_mlp_adam": ([H, I, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P, P, P, P], I),
+        "gw_mlp_norm": ([H, I, P, P, P], I),
+        "gw_mlp_target": ([H, I, P, P, P], I),
+        "gw_mlp_warm_start": ([H, I, I, I, P, P, P, P, P], I),
         "gw_timing_enable": ([H, I], I),
         "gw_timing_reset": ([H], I),
         "gw_timing_read": ([H, ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long)], I),
@@ -416,6 +420,35 @@ class Handle:
 
     def mlp_adam(self, step, params, grad, m, v, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         self._call("gw_mlp_adam", step, lr, beta1, beta2, eps, _ptr(params), _ptr(grad), _ptr(m), _ptr(v))
+
+    def mlp_norm(self, x, target):
+        rows = x.shape[0]
+        _check_f32(x, "x")
+        _check_f32(target, "target")
+        if tuple(x.shape) != (rows, 3) or tuple(target.shape) != (rows,):
+            raise ValueError("x must be [rows][3] and target [rows]")
+        norm = self._f32(8)
+        self._call("gw_mlp_norm", rows, _ptr(x), _ptr(target), _ptr(norm))
+        return norm
+
+    def mlp_target(self, F, eps):
+        nmo = eps.shape[0]
+        _check_dev(eps, "eps", (nmo,))
+        _check_dev(F, "F", (nmo, nmo))
+        t = self._f32(nmo)
+        self._call("gw_mlp_target", nmo, _ptr(F), _ptr(eps), _ptr(t))
+        return t
+
+    def mlp_warm_start(self, params, norm, eps, L, nocc):
+        naux, nmo = L.shape[0], L.shape[1]
+        _check_dev(eps, "eps", (nmo,))
+        _check_dev(L, "L", (naux, nmo, nmo))
+        _check_f32(params, "params")
+        _check_f32(norm, "norm")
+        F0 = self._new(nmo, nmo)
+        self._call("gw_mlp_warm_start", nocc, nmo - nocc, naux, _ptr(eps), _ptr(L), _ptr(params), _ptr(norm),
+                   _ptr(F0))
+        return F0
 
     # ------------------------------------------------------------------ poles
     def poles(self, sigma_occ, sigma_vir, fock, opts=None, want_chi=True):

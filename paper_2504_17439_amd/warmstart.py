@@ -1,7 +1,9 @@
 """Learned warm start for the fsGW loop (not in the paper).
 
 A per-orbital MLP (FP32 device kernels behind the C ABI: gw_mlp_features,
-gw_mlp_forward, gw_mlp_backward, gw_mlp_adam) predicts the diagonal shift
+gw_mlp_forward, gw_mlp_backward, gw_mlp_adam, with the standardisation,
+targets and F0 assembly in gw_mlp_norm, gw_mlp_target and gw_mlp_warm_start;
+this module only orders the calls) predicts the diagonal shift
 s_p = F*_pp - eps_p of the converged fsGW Fock matrix in the reference basis
 from (eps_p, (L L^T)_pp, eps_p - mu_mid); the warm start is F0 = diag(eps + s).
 
@@ -63,14 +65,10 @@ class WarmStartModel:
         self.step = 0
 
     def set_norm(self, X: torch.Tensor, T: torch.Tensor):
-        """Standardisation from the training data (host statistics of a
-        [rows][3] feature matrix and its targets)."""
-        x = X.cpu().numpy().astype(np.float64)
-        t = T.cpu().numpy().astype(np.float64)
-        sx = np.maximum(x.std(axis=0), 1e-12)
-        st = max(t.std(), 1e-12)
-        vals = np.r_[x.mean(axis=0), sx, t.mean(), st].astype(np.float32)
-        self.norm = torch.from_numpy(vals).to(self.params.device)
+        """Standardisation from the training data: feature and target means
+        and standard deviations of a [rows][3] feature matrix and its targets
+        (gw_mlp_norm)."""
+        self.norm = self.h.mlp_norm(X.contiguous(), T.contiguous())
 
     def predict(self, X: torch.Tensor) -> torch.Tensor:
         return self.h.mlp_forward(self.params, self.norm, X)
@@ -100,13 +98,15 @@ class WarmStartModel:
         return hist
 
     def warm_start(self, eps: torch.Tensor, L: torch.Tensor, nocc: int) -> torch.Tensor:
-        feat = self.h.mlp_features(eps, L, nocc)
-        s = self.predict(feat)
-        return torch.diag(eps + s.double()).contiguous()
+        """F0 = diag(eps + predicted shift) (gw_mlp_warm_start)."""
+        return self.h.mlp_warm_start(self.params, self.norm, eps, L, nocc)
 
 
 def generate(handle, seeds, sizes, nmom_max=5, log=None):
-    """Cold fsGW solves -> features [rows][3] and targets [rows] (device)."""
+    """Cold fsGW solves -> features [rows][3] and targets [rows] (device).
+    Systems whose cold loop stops at the iteration cap without converging
+    give no rows (their Fock diagonal is not a fixed point); they are kept in
+    the returned statistics with converged = False."""
     xs, ts, stats = [], [], []
     for seed, M in zip(seeds, sizes):
         o, v, A = system_shape(M)
@@ -115,14 +115,16 @@ def generate(handle, seeds, sizes, nmom_max=5, log=None):
         l = torch.from_numpy(L).cuda(handle.device)
         t0 = time.time()
         r = handle.fsgw(e, l, o, nmom_max, allow_noconv=True)
-        F = r["F"]
-        xs.append(handle.mlp_features(e, l, o))
-        ts.append((torch.diagonal(F) - e).float())
-        stats.append(dict(seed=seed, M=M, iterations=r["iterations"], converged=r["converged"]))
+        stats.append(dict(seed=seed, M=M, iterations=r["iterations"], converged=bool(r["converged"])))
+        if r["converged"]:
+            xs.append(handle.mlp_features(e, l, o))
+            ts.append(handle.mlp_target(r["F"], e))
         if log:
             log(f"train system seed {seed} M {M}: {r['iterations']} iterations, {r['fock_steps']} Fock steps, "
-                f"{time.time() - t0:.1f}s")
+                f"{time.time() - t0:.1f}s" + ("" if r["converged"] else " (not converged: dropped)"))
         del e, l
+    if not xs:
+        raise RuntimeError("generate: no cold fsGW solve converged")
     return torch.cat(xs).contiguous(), torch.cat(ts).contiguous(), stats
 
 
@@ -188,8 +190,9 @@ def main(argv=None):
         seeds = list(range(args.seed0, args.seed0 + args.train))
         sizes = [system_size(s, args.mmin, args.mmax) for s in seeds]
         X, T, stats = generate(h, seeds, sizes, args.nmom, log)
-        gen = dict(systems=args.train, rows=int(X.shape[0]), mean_cold_iterations=float(
-            np.mean([s["iterations"] for s in stats])))
+        gen = dict(systems=sum(s["converged"] for s in stats), dropped=sum(not s["converged"] for s in stats),
+                   rows=int(X.shape[0]),
+                   mean_cold_iterations=float(np.mean([s["iterations"] for s in stats if s["converged"]])))
         if args.save_data:
             np.savez(args.save_data, X=X.cpu().numpy(), T=T.cpu().numpy(), meta=json.dumps(gen))
             log(f"saved {X.shape[0]} rows to {args.save_data}")

@@ -1,15 +1,17 @@
-"""Mixed-precision self-energy moments (BF16 fixed-point digits on MFMA,
-exact FP32 accumulation by digit weight, FP64 combination) against the FP64
-oracle, and the quasiparticle energies they give against the FP64 path.
+"""Mixed-precision self-energy moments (int8 base-255 fixed-point digits on the
+integer MFMA, exact int32 accumulation per digit weight, FP64 combination)
+against the FP64 oracle, and the quasiparticle energies they give against
+the FP64 path.
 
 The stated bar for the mixed form is on quasiparticle energies: 1e-6 Ha on
 the frontier orbitals.  The moments themselves are held to a tolerance
-derived from the number format: four 8-bit digits carry each operand to
-~2^-33 of its row or column maximum, the kept digit products (weight <= 3)
-drop ~2^-32 of the leading term, and every FP32 partial sum of weight-0
-products is exact, so the moments carry a normwise relative error of order
-1e-9 (7.5e-10 in a CPU emulation of the same format); 1e-8 relative to the
-largest element of each moment leaves a factor ~10 of margin."""
+derived from the number format: four signed base-255 digits carry each
+operand row or column to ~2^-33 of its power-of-two scale, the kept digit
+products (weight <= 3; <= 4 in symmetric products) drop ~2^-32 of the
+leading term, and every int32 sum is exact, so the moments carry a
+normwise relative error of order 1e-9 (measured <= 7e-10 at full size);
+1e-8 relative to the largest element of each moment leaves a factor ~10 of
+margin."""
 import numpy as np
 import pytest
 
@@ -46,6 +48,7 @@ def rel(a, b):
 
 @pytest.mark.parametrize("o,v,A,N,seed,scr", [
     (1, 1, 1, 1, 0, "tda"),
+    (4, 21, 67, 5, 6, "tda"),
     (5, 19, 80, 3, 0, "tda"),
     (7, 37, 131, 5, 3, "tda"),
     (12, 30, 150, 11, 5, "tda"),

@@ -47,6 +47,7 @@ CASES = [
     (7, 37, 131, 5, 3),
     (3, 45, 260, 7, 4),
     (12, 30, 150, 11, 5),
+    (4, 21, 67, 5, 6),        # odd nmo and odd naux: the lone-element edges of the fold's operands
 ]
 
 
@@ -112,6 +113,7 @@ RPA_CASES = [
     (1, 1, 1, 1, 0),
     (6, 20, 50, 5, 1),
     (7, 37, 131, 7, 3),
+    (4, 21, 67, 5, 6),
 ]
 
 

@@ -521,6 +521,9 @@ def main():
                 out["pole_moment_err"] = perr
                 out["pole_moment_err_max"] = max(perr)
                 if ref is not None:
+                    # the FP64 poles' own reconstruction of the FP64 moments, for reference
+                    out["pole_moment_err_fp64_max"] = max(pole_error(ref, so64, sv64))
+                if ref is not None:
                     q64 = ref["qp"].cpu().numpy()
                     w64 = ref["qp_weight"].cpu().numpy()
                     qm = mres["qp"].cpu().numpy()

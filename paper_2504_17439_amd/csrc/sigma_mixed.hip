@@ -751,6 +751,18 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
     // the other buffer, so that the refill overlaps the whole step.
     int it = 0;                    // global step: buffer parity
     for (int x = xa; x < xb; ++x) {
+        // this x's row (p) and column (q) exponents, fetched before its k
+        // loop so that the promotion after it waits on no memory
+        int ep[4][4], eq[2];
+        {
+            const long xl = x - g.x0;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) eq[j] = eZn[xl * M + min(n0 + wn + j * 16 + lr, M - 1)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ep[i][r] = g.eL[(long)x * M + min(m0 + wm + i * 16 + 4 * lk + r, M - 1)];
+        }
         for (int kt = 0; kt < nkt; ++kt, ++it) {
             const int cur = it & 1;
             const bool wrap = kt + 1 == nkt;
@@ -779,21 +791,18 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
             }
         }
         // end of this x: promote with the row (p) and column (q) scales
-        const long xl = x - g.x0;
+        // (rows and columns past nmo read a clamped exponent; their results
+        // are never stored)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            const int qg = n0 + wn + j * 16 + lr;
-            const int eq = (qg < M) ? eZn[xl * M + qg] : 0;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int pg = m0 + wm + i * 16 + 4 * lk + r;
-                    const int ep = (pg < M) ? g.eL[(long)x * M + pg] : 0;
                     double z = 0.0;
 #pragma unroll
                     for (int w = MAXW; w >= 0; --w) z += (double)acc[w][i][j][r] * wscale(w);
-                    acc64[i][j][r] += ldexp(z, ep + eq);
+                    acc64[i][j][r] += ldexp(z, ep[i][r] + eq[j]);
                 }
 #pragma unroll
                 for (int w = 0; w <= MAXW; ++w) acc[w][i][j] = (i32x4){0, 0, 0, 0};

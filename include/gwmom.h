@@ -214,7 +214,8 @@ gw_status gw_poles(gw_handle h, int nmo, int nmom_max, const double* sigma_occ,
  *   DIIS over the Fock matrices (diis_space vectors) with error vectors
  *   rho_k - rho_{k-1}, until max |rho_k - rho_{k-1}| < fock_tol.
  * The QP energies of H~ (as in gw_poles) end the iteration; the loop stops
- * when the sorted QP energies change by less than tol (Ha).
+ * when the Fock matrix it returns differs from the one it started from (the
+ * first iteration: F0) by less than tol (Ha) in every element.
  * Inputs (device): eps [nmo], L [naux][nmo][nmo], F0 [nmo][nmo] or NULL for
  * diag(eps) (a warm start).  Outputs (device): F [nmo][nmo] (reference basis),
  * qp_e, qp_w [nmo] of the last iteration; info (host, nullable) the counts.
@@ -223,7 +224,7 @@ gw_status gw_poles(gw_handle h, int nmo, int nmom_max, const double* sigma_occ,
  * of gw_sigma_moments and gw_poles otherwise.  Synchronises the stream.
  */
 typedef struct {
-    double tol;        /* outer: max |change of sorted QP energies| [1e-6 Ha] */
+    double tol;        /* outer: max |change of F (reference basis)| per iteration [1e-6 Ha] */
     int max_outer;     /* [30] */
     int max_fock;      /* Fock-loop steps per outer iteration [50] */
     double fock_tol;   /* max |density change| ending the Fock loop [1e-8] */
@@ -239,7 +240,8 @@ typedef struct {
     int eig_calls;     /* eigensolves of H~ */
     int converged;
     double zeta;       /* final auxiliary shift */
-    double last_dqp;   /* QP change of the last iteration (-1 after one iteration) */
+    double last_dqp;   /* sorted-QP change of the last iteration (-1 after one iteration; reported only) */
+    double last_dF;    /* max |change of F| of the last iteration (the convergence test) */
 } gw_fsgw_info;
 
 gw_status gw_fsgw(gw_handle h, gw_screening screening, int nocc, int nvir, int naux,

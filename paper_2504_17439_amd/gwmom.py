@@ -65,7 +65,8 @@ class FsgwOpts(ctypes.Structure):
 
 class FsgwInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("fock_steps", ctypes.c_int), ("eig_calls", ctypes.c_int),
-                ("converged", ctypes.c_int), ("zeta", ctypes.c_double), ("last_dqp", ctypes.c_double)]
+                ("converged", ctypes.c_int), ("zeta", ctypes.c_double), ("last_dqp", ctypes.c_double),
+                ("last_dF", ctypes.c_double)]
 
 
 class QsgwOpts(ctypes.Structure):
@@ -308,7 +309,7 @@ class Handle:
     def fsgw(self, eps, L, nocc, nmom_max, screening="tda", precision="fp64", F0=None, opts=None,
              fopts=None, allow_noconv=False):
         """Self-consistent loop; returns dict(F, qp, qp_weight, iterations, fock_steps,
-        eig_calls, converged, zeta, last_dqp)."""
+        eig_calls, converged, zeta, last_dqp, last_dF)."""
         naux, nmo = L.shape[0], L.shape[1]
         _check_dev(eps, "eps", (nmo,))
         _check_dev(L, "L", (naux, nmo, nmo))
@@ -329,7 +330,7 @@ class Handle:
             raise GWError(st, self.lib.gw_last_error(self.h).decode())
         return dict(F=F, qp=qe, qp_weight=qw, iterations=info.iterations, fock_steps=info.fock_steps,
                     eig_calls=info.eig_calls, converged=bool(info.converged), zeta=info.zeta,
-                    last_dqp=info.last_dqp)
+                    last_dqp=info.last_dqp, last_dF=info.last_dF)
 
     def naf(self, L, nocc, eps_naf=1e-5, full_space=False):
         """Natural auxiliary functions: returns (L_naf [nnaf][nmo][nmo], all

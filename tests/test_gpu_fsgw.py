@@ -1,12 +1,14 @@
 """fsGW on the device (gw_fsgw) against the oracle loop (Sec. 3.6, Alg. 2).
 
 Small systems: the converged Fock matrix and the sorted QP energies agree
-with the oracle (1e-6 Ha, the QP bar; both loops stop at a 1e-6 Ha QP
-change).  At the learned-warm-start test size (nmo = 300, naux = 1050,
-nocc = 60, N = 5, H~ of dimension 2100) the oracle loop is too slow to
-run, so the test checks what holds at any size: the loop converges, a warm
-start from its own converged F is a fixed point (two iterations, same QPs),
-and mixed-precision self-energies give the same frontier QPs.
+with the oracle (1e-6 Ha, the QP bar; both loops stop when an iteration
+changes F by less than 1e-6 Ha).  At the learned-warm-start test size
+(nmo = 300, naux = 1050, nocc = 60, N = 5, H~ of dimension 2100) the oracle
+loop is too slow to run, so the test checks what holds at any size: the loop
+converges, a warm start from its own converged F is a fixed point (one
+iteration, the same QP energies for the orbitals with QP weight >= 0.9 --
+satellite-embedded orbitals have no stable assignment, reading R6), and
+mixed-precision self-energies give the same frontier QPs.
 """
 import numpy as np
 import pytest
@@ -38,6 +40,15 @@ def host(t):
     return t.cpu().numpy()
 
 
+def physical_qp_diff(a, b):
+    """Largest QP difference over the orbitals whose QP weight is >= 0.9 in
+    both loops (orbitals of each loop's final F, ascending)."""
+    qa, wa, qb, wb = host(a["qp"]), host(a["qp_weight"]), host(b["qp"]), host(b["qp_weight"])
+    m = (wa >= 0.9) & (wb >= 0.9)
+    assert m.sum() >= 0.5 * len(m)
+    return float(np.abs(qa[m] - qb[m]).max())
+
+
 @pytest.mark.parametrize("o,v,A,N,seed,scr", [
     (3, 9, 20, 3, 1, "tda"),
     (4, 16, 42, 5, 2, "tda"),
@@ -65,8 +76,8 @@ def test_fsgw_warm_start_from_its_fixed_point(handle):
     e, l = dev(eps), dev(L)
     r = handle.fsgw(e, l, o, N)
     w = handle.fsgw(e, l, o, N, F0=r["F"])
-    assert w["iterations"] == 2
-    assert np.abs(np.sort(host(w["qp"])) - np.sort(host(r["qp"]))).max() < QP_TOL
+    assert w["iterations"] == 1
+    assert physical_qp_diff(w, r) < QP_TOL
 
 
 @pytest.fixture(scope="module")
@@ -83,7 +94,8 @@ def c5_run(handle):
 def test_fsgw_converges_at_warm_start_test_size(c5_run):
     o, N, e, l, r = c5_run
     assert r["converged"] and r["iterations"] <= 30
-    assert 0 <= r["last_dqp"] < QP_TOL
+    assert 0 <= r["last_dF"] < QP_TOL
+    print(f"last F change {r['last_dF']:.2e}, last sorted-QP change {r['last_dqp']:.2e}", flush=True)
     qp = host(r["qp"])
     assert np.all(np.isfinite(qp))
     F = host(r["F"])
@@ -93,8 +105,8 @@ def test_fsgw_converges_at_warm_start_test_size(c5_run):
 def test_fsgw_fixed_point_at_warm_start_test_size(handle, c5_run):
     o, N, e, l, r = c5_run
     w = handle.fsgw(e, l, o, N, F0=r["F"])
-    assert w["iterations"] == 2
-    assert np.abs(np.sort(host(w["qp"])) - np.sort(host(r["qp"]))).max() < QP_TOL
+    assert w["iterations"] == 1
+    assert physical_qp_diff(w, r) < QP_TOL
 
 
 def test_fsgw_mixed_self_energy_same_frontier_qps(handle):

@@ -127,10 +127,14 @@ def test_warm_started_fsgw_reaches_the_cold_quasiparticles(handle):
     cold = handle.fsgw(e, l, o, 3)
     warm = handle.fsgw(e, l, o, 3, F0=F0)
     assert cold["converged"] and warm["converged"]
-    assert np.abs(np.sort(host(warm["qp"])) - np.sort(host(cold["qp"]))).max() < 1e-6
+    # QP energies of the orbitals with QP weight >= 0.9 in both loops
+    wq, ww, cq, cw = host(warm["qp"]), host(warm["qp_weight"]), host(cold["qp"]), host(cold["qp_weight"])
+    m = (ww >= 0.9) & (cw >= 0.9)
+    assert np.abs(wq[m] - cq[m]).max() < 1e-6
     # the oracle loop from the same warm start agrees as well
     ref = ofs.fsgw(eps, L, o, 3, F0=host(F0))
-    assert np.abs(np.sort(host(warm["qp"])) - ref["qp"]).max() < 1e-6
+    m = (ww >= 0.9) & (ref["qp_weight"] >= 0.9)
+    assert np.abs(wq[m] - ref["qp_orb"][m]).max() < 1e-6
 
 
 def test_norm_target_and_warm_start_entry_points(handle):

@@ -143,19 +143,24 @@ def evaluate(handle, model, seeds, M, nmom_max=5, log=None):
         t2 = time.time()
         shift_err = float((torch.diagonal(F0) - torch.diagonal(cold["F"])).abs().max())
         # QP agreement over the orbitals with QP weight >= 0.9 in both loops
-        # (satellite-embedded orbitals have no stable assignment)
+        # (satellite-embedded orbitals have no stable assignment), all of them
+        # and the frontier ones (HOMO-4 .. LUMO+4, the 1e-6 Ha bar)
         phys = (warm["qp_weight"] >= 0.9) & (cold["qp_weight"] >= 0.9)
-        dqp = float((warm["qp"] - cold["qp"])[phys].abs().max())
+        diff = (warm["qp"] - cold["qp"]).abs()
+        dqp = float(diff[phys].max())
+        front = torch.zeros_like(phys)
+        front[max(0, o - 5):o + 5] = True
+        dqp_front = float(diff[phys & front].max()) if bool((phys & front).any()) else 0.0
         rec = dict(seed=seed, M=M, cold_iterations=cold["iterations"], warm_iterations=warm["iterations"],
                    cold_fock_steps=cold["fock_steps"], warm_fock_steps=warm["fock_steps"],
                    cold_eigensolves=cold["eig_calls"], warm_eigensolves=warm["eig_calls"],
                    cold_s=t1 - t0, warm_s=t2 - t1, max_diag_error=shift_err, max_qp_difference=dqp,
-                   converged=bool(cold["converged"] and warm["converged"]))
+                   max_frontier_qp_difference=dqp_front, converged=bool(cold["converged"] and warm["converged"]))
         out.append(rec)
         if log:
             log(f"test system seed {seed}: cold {rec['cold_iterations']} it / {rec['cold_fock_steps']} Fock, "
                 f"warm {rec['warm_iterations']} it / {rec['warm_fock_steps']} Fock, diag error "
-                f"{shift_err:.2e}, QP difference {dqp:.1e}")
+                f"{shift_err:.2e}, QP difference {dqp:.1e} (frontier {dqp_front:.1e})")
         del e, l
     return out
 
@@ -219,6 +224,7 @@ def main(argv=None):
         fock_step_ratio=float(cf.mean() / wf.mean()),
         max_diag_error=float(max(r["max_diag_error"] for r in res)),
         max_qp_difference=float(max(r["max_qp_difference"] for r in res)),
+        max_frontier_qp_difference=float(max(r["max_frontier_qp_difference"] for r in res)),
         all_converged=all(r["converged"] for r in res),
         per_system=[(r["seed"], r["cold_iterations"], r["warm_iterations"], r["cold_fock_steps"],
                      r["warm_fock_steps"]) for r in res])

@@ -435,7 +435,9 @@ gw_status gw_evgw(gw_handle h, gw_screening screening, int nocc, int nvir, int n
  * is one grouped, persistent launch per contraction stage over a work queue of
  * (job, tile) items; contraction splits follow a work-item target
  * (split_target, or with autotune the fastest of 256, 512, 1024, 2048 by
- * timing the whole sequence).  For TDA the per-molecule work (recursion,
+ * timing the whole sequence), and the contraction tile is 128 x 64, or 64 x
+ * 64 for molecules with nmo <= small_tile_nmo (autotune: then the fastest
+ * of 0, 100, 150, 200).  For TDA the per-molecule work (recursion,
  * digit preparation) of different molecules runs on `branches` streams with
  * their own workspaces, molecules assigned largest first by nmo^4.  The
  * sequence is run once eagerly (the outputs
@@ -462,6 +464,8 @@ typedef struct {
     int autotune;        /* 1: choose split_target by timing */
     int no_graph;        /* 1: replay by re-enqueueing */
     int branches;        /* TDA: concurrent streams for the per-molecule work [4]; 1 = serial */
+    int small_tile_nmo;  /* mixed: molecules with nmo <= this use 64-row contraction tiles [0];
+                            autotune also chooses it among 0, 100, 150, 200 */
 } gw_batch_opts;
 
 typedef struct gw_batch_s* gw_batch;
@@ -470,8 +474,10 @@ gw_status gw_batch_create(gw_handle h, int nsys, const gw_system* sys, gw_screen
                           int nmom_max, gw_precision prec, const gw_opts* opts,
                           const gw_batch_opts* bopts, gw_batch* batch);
 gw_status gw_batch_run(gw_batch batch);
-/* Plan facts (host ints, each nullable): jobs, waves, graph captured (0/1), split target. */
-gw_status gw_batch_info(gw_batch batch, int* njobs, int* nwaves, int* graph, int* split_target);
+/* Plan facts (host ints, each nullable): jobs, waves, graph captured (0/1), split target,
+ * the largest nmo that uses 64-row contraction tiles (0: none). */
+gw_status gw_batch_info(gw_batch batch, int* njobs, int* nwaves, int* graph, int* split_target,
+                        int* small_tile_nmo);
 gw_status gw_batch_destroy(gw_batch batch);
 
 /*

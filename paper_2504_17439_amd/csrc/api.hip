@@ -445,7 +445,8 @@ gw_status gw_batch_create(gw_handle h, int nsys, const gw_system* sys, gw_screen
         return gwm::set_err(h, GW_EINVAL, "mixed precision: nmom_max must be <= 11");
     if (prec == GW_MIXED && nmom_max % 2 == 0)
         return gwm::set_err(h, GW_EINVAL, "mixed precision: nmom_max must be odd");
-    if (bopts && bopts->split_target < 0) return gwm::set_err(h, GW_EINVAL, "gw_batch_create: negative option");
+    if (bopts && (bopts->split_target < 0 || bopts->small_tile_nmo < 0))
+        return gwm::set_err(h, GW_EINVAL, "gw_batch_create: negative option");
     for (int i = 0; i < nsys; ++i) {
         GW_TRY(validate_common(h, sys[i].nocc, sys[i].nvir, sys[i].naux, nmom_max, sys[i].eps, sys[i].L));
         if (!sys[i].sigma_occ || !sys[i].sigma_vir)
@@ -459,9 +460,10 @@ gw_status gw_batch_run(gw_batch batch) {
     return gwm::batch_run(batch);
 }
 
-gw_status gw_batch_info(gw_batch batch, int* njobs, int* nwaves, int* graph, int* split_target) {
+gw_status gw_batch_info(gw_batch batch, int* njobs, int* nwaves, int* graph, int* split_target,
+                        int* small_tile_nmo) {
     if (!batch) return GW_EINVAL;
-    return gwm::batch_info(batch, njobs, nwaves, graph, split_target);
+    return gwm::batch_info(batch, njobs, nwaves, graph, split_target, small_tile_nmo);
 }
 
 gw_status gw_batch_destroy(gw_batch batch) {

@@ -80,6 +80,7 @@ struct gw_batch_s {
 
     int ncu = 256;
     int split_target = 512;
+    int small_tile_nmo = 0;  // jobs with nmo <= this use the 64-row contraction tile
     bool graph_ok = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -89,22 +90,27 @@ namespace gwm {
 
 namespace {
 
-int contract_tiles(int nmo) { return mixed_upper_tiles(nmo); }
+int tile_height(const gw_batch_s* b, int nmo) { return nmo <= b->small_tile_nmo ? 64 : 128; }
+int contract_tiles(int nmo, int tm) { return mixed_upper_tiles(nmo, tm); }
 
 // S for a job of nx orbitals x: enough contraction work items for the target
-int job_split(const gw_batch_s* b, int nmo, int nx, int target) {
-    const int per = contract_tiles(nmo) * 2 * b->nt;
+int job_split(const gw_batch_s* b, int nmo, int nx, int target, int tm) {
+    const int per = contract_tiles(nmo, tm) * 2 * b->nt;
     return std::max(1, std::min({64, nx, (target + per - 1) / per}));
 }
 
-// Build (or rebuild) the contraction split plan and the device job tables.
-gw_status build_tables(gw_batch_s* b, int target) {
+// Build (or rebuild) the contraction plan and the device job tables: the
+// contraction tile of each job (64 rows for nmo <= small_nmo, else 128) and
+// its splits for the work-item target.
+gw_status build_tables(gw_batch_s* b, int target, int small_nmo) {
     Handle* h = b->h;
     const int nt = b->nt;
+    b->small_tile_nmo = small_nmo;
     for (auto& m : b->mol) m.slots = 0;
     // every job's slots are assigned before any table is built: nsplit_total is final
     for (auto& j : b->jobs) {
-        j.S = job_split(b, b->mol[j.m].nmo, j.x1 - j.x0, target);
+        const int nmo = b->mol[j.m].nmo;
+        j.S = job_split(b, nmo, j.x1 - j.x0, target, tile_height(b, nmo));
         j.slot0 = b->mol[j.m].slots;
         b->mol[j.m].slots += j.S;
     }
@@ -143,7 +149,9 @@ gw_status build_tables(gw_batch_s* b, int target) {
                 a.xs0[sec] = xs0;
                 a.nxs[sec] = std::max(0, xs1 - xs0);
             }
-            a.nt = nt; a.nsplit = j.S; a.tilesN = (m.nmo + 63) / 64; a.tiles = contract_tiles(m.nmo); a.ncol = ncol;
+            a.tm = tile_height(b, m.nmo);
+            a.nt = nt; a.nsplit = j.S; a.tilesN = (m.nmo + 63) / 64; a.tiles = contract_tiles(m.nmo, a.tm);
+            a.ncol = ncol;
             a.part = m.part; a.nsplit_total = m.slots; a.split_off = j.slot0;
             a.item0 = ci;
             ci += contract_groups(a);
@@ -351,7 +359,8 @@ gw_status batch_create(Handle* h, int nsys, const gw_system* sys, gw_screening s
             j.x1 = m.nmo;
             j.zrows = (long)nt * m.M2;
             b->jobs.push_back(j);
-            const int slots_max = job_split(b, m.nmo, m.nmo, max_target);
+            // the 128-row tile has the fewest tiles, so the most splits
+            const int slots_max = job_split(b, m.nmo, m.nmo, max_target, 128);
             bytes += align(sizeof(double) * 2 * nt * (size_t)slots_max * m.M2);
             m.slots = slots_max;
         }
@@ -489,18 +498,21 @@ gw_status batch_create(Handle* h, int nsys, const gw_system* sys, gw_screening s
     // ---- contraction split plan (optionally autotuned), eager warm-up
     const bool timing = h->timing;
     gw_status st = GW_OK;
-    if (prec == GW_MIXED) st = build_tables(b, (bo && bo->split_target > 0) ? bo->split_target : 512);
+    const int small0 = (bo && bo->small_tile_nmo > 0) ? bo->small_tile_nmo : 0;
+    if (prec == GW_MIXED) st = build_tables(b, (bo && bo->split_target > 0) ? bo->split_target : 512, small0);
     if (st == GW_OK) st = enqueue(b);  // grows the shared workspace to its final size
     if (st == GW_OK) {
         hipError_t e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) st = set_err(h, GW_EHIP, std::string("batch warm-up: ") + hipGetErrorString(e));
     }
     if (st == GW_OK && autotune) {
+        // coordinate search: the split target with 128-row tiles only, then
+        // the largest nmo that takes the 64-row contraction tile
         h->timing = false;
-        int best = b->split_target;
+        int best = b->split_target, best_small = 0;
         float best_ms = 1e30f;
         for (int target : {256, 512, 1024, 2048}) {
-            st = build_tables(b, target);
+            st = build_tables(b, target, 0);
             float ms = 0.f;
             if (st == GW_OK) st = time_sequence(b, &ms);
             if (st != GW_OK) break;
@@ -509,7 +521,18 @@ gw_status batch_create(Handle* h, int nsys, const gw_system* sys, gw_screening s
                 best = target;
             }
         }
-        if (st == GW_OK) st = build_tables(b, best);
+        for (int small : {100, 150, 200}) {
+            if (st != GW_OK) break;
+            st = build_tables(b, best, small);
+            float ms = 0.f;
+            if (st == GW_OK) st = time_sequence(b, &ms);
+            if (st != GW_OK) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_small = small;
+            }
+        }
+        if (st == GW_OK) st = build_tables(b, best, best_small);
         h->timing = timing;
     }
     // ---- capture
@@ -556,7 +579,8 @@ gw_status batch_run(gw_batch b) {
     return enqueue(b);
 }
 
-gw_status batch_info(gw_batch b, int* njobs, int* nwaves, int* graph, int* split_target) {
+gw_status batch_info(gw_batch b, int* njobs, int* nwaves, int* graph, int* split_target, int* small_tile_nmo) {
+    if (small_tile_nmo) *small_tile_nmo = b->small_tile_nmo;
     if (njobs) *njobs = (int)b->jobs.size();
     if (nwaves) *nwaves = (int)b->waves.size();
     if (graph) *graph = b->graph_ok ? 1 : 0;

@@ -389,7 +389,7 @@ gw_status sigma_moments_noalloc(Handle* h, int nocc, int nvir, int naux, int nmo
 gw_status batch_create(Handle* h, int nsys, const gw_system* sys, gw_screening screening, int nmom_max,
                        gw_precision prec, const gw_opts* opts, const gw_batch_opts* bo, gw_batch* out);
 gw_status batch_run(gw_batch b);
-gw_status batch_info(gw_batch b, int* njobs, int* nwaves, int* graph, int* split_target);
+gw_status batch_info(gw_batch b, int* njobs, int* nwaves, int* graph, int* split_target, int* small_tile_nmo);
 void batch_destroy(gw_batch b);
 
 long mlp_param_count();

@@ -50,7 +50,8 @@ struct ContractArgs {
     int nmo, Ap, naux;
     int x0;                                      // first x of the chunk
     int xs0[2], nxs[2];                          // per sector: first x, count (within the chunk)
-    int nt, nsplit, tilesN, tiles;               // column blocks of 64, upper 128 x 64 tiles
+    int nt, nsplit, tilesN, tiles;               // column blocks of 64, upper tm x 64 tiles
+    int tm;                                      // tile height: 128, or 64 (grouped launches only)
     long ncol;
     double* part;                                // [2][nt][nsplit_total][nmo][nmo] FP64, accumulated
     int nsplit_total, split_off;                 // this job's splits are slots split_off .. + nsplit
@@ -75,12 +76,12 @@ __host__ __device__ constexpr int fold_tg(int nt) { return (nt + fold_tpw(nt) - 
 __host__ __device__ constexpr int fold_cg(int nt) { return 4 / fold_tg(nt); }
 __host__ __device__ constexpr int fold_cols(int nt) { return 64 * fold_cg(nt); }
 
-// Upper 128-row x 64-column tiles of a symmetric M x M result: row block bi
-// keeps column blocks bj >= 2 bi.
-inline int mixed_upper_tiles(int M) {
-    const int TM = (M + 127) / 128, TN = (M + 63) / 64;
+// Upper tm-row x 64-column tiles (tm = 128 or 64) of a symmetric M x M
+// result: row block bi keeps column blocks bj >= (tm / 64) bi.
+inline int mixed_upper_tiles(int M, int tm = 128) {
+    const int R = tm / 64, TM = (M + tm - 1) / tm, TN = (M + 63) / 64;
     int n = 0;
-    for (int bi = 0; bi < TM; ++bi) n += std::max(0, TN - 2 * bi);
+    for (int bi = 0; bi < TM; ++bi) n += std::max(0, TN - R * bi);
     return n;
 }
 

@@ -656,25 +656,32 @@ __global__ __launch_bounds__(256) void zdig_grouped_kernel(const ZdigJob* __rest
 // 128 x 64 upper tiles, 4 waves of 64 x 32, promotion to FP64 once per x.
 // ---------------------------------------------------------------------------
 
-// Upper tiles of a symmetric M x M result in 128-row x 64-column tiles: row
-// block bi keeps the column blocks bj >= 2 bi (those that reach the diagonal
-// or lie right of it); TN = ceil(M / 64) column blocks.
-__device__ inline void upper_tile_rect(int t, int TN, int& bi, int& bj) {
+// Upper tiles of a symmetric M x M result in (64 R)-row x 64-column tiles:
+// row block bi keeps the column blocks bj >= R bi (those that reach the
+// diagonal or lie right of it); TN = ceil(M / 64) column blocks.
+__device__ inline void upper_tile_rect(int t, int TN, int& bi, int& bj, int R = 2) {
     int r = 0;
-    while (t >= TN - 2 * r) { t -= TN - 2 * r; ++r; }
+    while (t >= TN - R * r) { t -= TN - R * r; ++r; }
     bi = r;
-    bj = 2 * r + t;
+    bj = R * r + t;
 }
 
-// One work group: a 128 x 64 upper tile of Sigma^{(n)} for one sector and
-// one split of that sector's x range.  The (x, k-block) steps form one
-// double-buffered LDS-DMA pipeline; the int32 digit-weight accumulators are
-// promoted to FP64 with the row and column scales at the end of every x.
+// One work group: a TM x 64 upper tile of Sigma^{(n)} (TM = 128, or 64 for
+// small molecules: twice the work groups per result) for one sector and one
+// split of that sector's x range; 4 waves of TM/2 x 32.  The (x, k-block)
+// steps form one double-buffered LDS-DMA pipeline; the int32 digit-weight
+// accumulators are promoted to FP64 with the row and column scales at the
+// end of every x.
 constexpr int C_OPA = ND * 128 * 64;  // bytes of the A (128-row) slab (32 KB)
 constexpr int C_OPB = ND * 64 * 64;   // bytes of the B (64-row) slab (16 KB)
 constexpr int C_BUF = C_OPA + C_OPB;
 
+template <int TM>
 __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, int split, int zi, lds_t* lds) {
+    static_assert(TM == 128 || TM == 64, "contraction tile height");
+    constexpr int NI = TM / 32;          // 16-row blocks per wave
+    constexpr int HA = TM / 64;          // 64-row halves of the A slab
+    constexpr int OPA = ND * TM * 64;    // bytes of the A slab
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -686,8 +693,8 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
     const int xs0 = sector ? g.xs0[1] : g.xs0[0];
     if (nxs <= 0) return;
     int bi, bj;
-    upper_tile_rect(tile, g.tilesN, bi, bj);
-    const int m0 = bi * 128, n0 = bj * 64;
+    upper_tile_rect(tile, g.tilesN, bi, bj, HA);
+    const int m0 = bi * TM, n0 = bj * 64;
     const int per = (nxs + g.nsplit - 1) / g.nsplit;
     const int xa = xs0 + split * per;
     const int xb = min(xs0 + nxs, xa + per);
@@ -695,30 +702,30 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
     const int M = g.nmo;
     const long M2 = (long)M * M;
     const long zrows = (long)g.nt * g.ncol;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 32;
+    const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * 32;
 
     // LDS-DMA staging as in stage 1: vector s of wave w fills slab rows
-    // s * 64 + 16 w + (lane >> 2).  A slab (d, i): d = s >> 1, i = 64 (s & 1)
+    // s * 64 + 16 w + (lane >> 2).  A slab (d, i): d = s / HA, i = 64 (s % HA)
     // + 16 w + (lane >> 2); B slab (d, i): d = s, i = 16 w + (lane >> 2).
     // Rows past nmo read clamped rows.
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const int lrow = lane >> 2;
     const int gch = swz(lrow, lane & 3);
-    unsigned offA[2];
+    unsigned offA[HA];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) offA[h] = (unsigned)(min(m0 + h * 64 + wv * 16 + lrow, M - 1) * 64 + gch * 16);
+    for (int h = 0; h < HA; ++h) offA[h] = (unsigned)(min(m0 + h * 64 + wv * 16 + lrow, M - 1) * 64 + gch * 16);
     const unsigned offB = (unsigned)(min(n0 + wv * 16 + lrow, M - 1) * 64 + gch * 16);
     auto load = [&](int x, int kt, int buf) {
         lds_t* A = lds + buf * C_BUF + wv * 16 * 64;
-        lds_t* B = A + C_OPA;
+        lds_t* B = A + OPA;
         const unsigned soA = (unsigned)x * M * 64u;
         const unsigned soB = (unsigned)((long)n * g.ncol + (long)(x - g.x0) * M) * 64u;
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
+        for (int s = 0; s < ND * HA; ++s) {
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void*)(g.Ld + (s >> 1) * g.lplane + (long)kt * M2 * 64), (short)0, (int)(M2 * 64), 0x00020000);
+                (void*)(g.Ld + (s / HA) * g.lplane + (long)kt * M2 * 64), (short)0, (int)(M2 * 64), 0x00020000);
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(A + s * 64 * 64),
-                                                     16, offA[s & 1], soA, 0, 0);
+                                                     16, offA[s % HA], soA, 0, 0);
         }
 #pragma unroll
         for (int s = 0; s < ND; ++s) {
@@ -729,10 +736,10 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
         }
     };
 
-    double acc64[4][2][4];
-    i32x4 acc[MAXW + 1][4][2];
+    double acc64[NI][2][4];
+    i32x4 acc[MAXW + 1][NI][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
 #pragma unroll
@@ -753,13 +760,13 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
     for (int x = xa; x < xb; ++x) {
         // this x's row (p) and column (q) exponents, fetched before its k
         // loop so that the promotion after it waits on no memory
-        int ep[4][4], eq[2];
+        int ep[NI][4], eq[2];
         {
             const long xl = x - g.x0;
 #pragma unroll
             for (int j = 0; j < 2; ++j) eq[j] = eZn[xl * M + min(n0 + wn + j * 16 + lr, M - 1)];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < NI; ++i)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) ep[i][r] = g.eL[(long)x * M + min(m0 + wm + i * 16 + 4 * lk + r, M - 1)];
         }
@@ -770,17 +777,17 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
             __syncthreads();
             if (!wrap || x + 1 < xb) load(wrap ? x + 1 : x, wrap ? 0 : kt + 1, cur ^ 1);
             const lds_t* A = lds + cur * C_BUF;
-            const lds_t* B = A + C_OPA;
+            const lds_t* B = A + OPA;
             i32x4 b[2][ND];
 #pragma unroll
             for (int j = 0; j < 2; ++j)
 #pragma unroll
                 for (int d = 0; d < ND; ++d) b[j][d] = lds_b128(B + (d * 64 + wn + j * 16 + lr) * 64 + so);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < NI; ++i) {
                 i32x4 a[ND];
 #pragma unroll
-                for (int d = 0; d < ND; ++d) a[d] = lds_b128(A + (d * 128 + wm + i * 16 + lr) * 64 + so);
+                for (int d = 0; d < ND; ++d) a[d] = lds_b128(A + (d * TM + wm + i * 16 + lr) * 64 + so);
 #pragma unroll
                 for (int w = 0; w <= MAXW; ++w)
 #pragma unroll
@@ -796,7 +803,7 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < NI; ++i) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     double z = 0.0;
@@ -812,9 +819,9 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
     double* dst = g.part + (((long)sector * g.nt + n) * g.nsplit_total + g.split_off + split) * M2;
     // read every old value before the first store (the stores could alias
     // the later loads as far as the compiler knows)
-    double old[4][2][4];
+    double old[NI][2][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -824,7 +831,7 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
                 old[i][j][r] = dst[(long)row * M + col];
             }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             int col = n0 + wn + j * 16 + lr;
@@ -858,7 +865,7 @@ __global__ __launch_bounds__(256, 1) void contract_mixed_kernel(ContractArgs g, 
     __shared__ __attribute__((aligned(16))) lds_t lds[2 * C_BUF];
     int tile, grp;
     if (!xcd_group_item(tiles, g.nsplit * 2 * g.nt, tile, grp)) return;
-    contract_tile(g, tile, grp % g.nsplit, grp / g.nsplit, lds);
+    contract_tile<128>(g, tile, grp % g.nsplit, grp / g.nsplit, lds);
 }
 
 // Grouped, persistent, XCD-aware: the work items of a job, ordered (tile,
@@ -886,7 +893,8 @@ __global__ __launch_bounds__(256, 1) void contract_grouped_kernel(const Contract
         r /= g.nt;
         const int split = (int)(r % g.nsplit);
         const int sector = (int)(r / g.nsplit);
-        contract_tile(g, (int)(i % T), split, sector * g.nt + n, lds);
+        if (g.tm == 64) contract_tile<64>(g, (int)(i % T), split, sector * g.nt + n, lds);
+        else contract_tile<128>(g, (int)(i % T), split, sector * g.nt + n, lds);
     }
 }
 
@@ -1167,7 +1175,7 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
         a.x0 = 0;
         a.xs0[0] = 0; a.nxs[0] = nocc;
         a.xs0[1] = nocc; a.nxs[1] = nvir;
-        a.nt = nt; a.nsplit = S; a.tilesN = (nmo + 63) / 64; a.tiles = tiles; a.ncol = M2;
+        a.nt = nt; a.nsplit = S; a.tilesN = (nmo + 63) / 64; a.tiles = tiles; a.ncol = M2; a.tm = 128;
         a.part = acc;
         a.nsplit_total = S; a.split_off = 0; a.item0 = 0;
         KTimer tm(h, "sigma_contract");

@@ -54,7 +54,8 @@ class System(ctypes.Structure):
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("job_bytes", ctypes.c_size_t), ("wave_bytes", ctypes.c_size_t), ("split_target", ctypes.c_int),
-                ("autotune", ctypes.c_int), ("no_graph", ctypes.c_int), ("branches", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("no_graph", ctypes.c_int), ("branches", ctypes.c_int),
+                ("small_tile_nmo", ctypes.c_int)]
 
 
 class FsgwOpts(ctypes.Structure):
@@ -137,7 +138,8 @@ def load_library(path: str = LIB_PATH):
         "gw_zeta_shift": ([H, I, I, I, I, P, P, P, D, P, P, P, P, P, P], I),
         "gw_batch_create": ([H, I, P, I, I, I, P, P, ctypes.POINTER(ctypes.c_void_p)], I),
         "gw_batch_run": ([P], I),
-        "gw_batch_info": ([P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)], I),
+        "gw_batch_info": ([P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
+                          ctypes.POINTER(I)], I),
         "gw_batch_destroy": ([P], I),
         "gw_mlp_param_count": ([], ctypes.c_long),
         "gw_mlp_features": ([H, I, I, I, P, P, P], I),
@@ -551,9 +553,10 @@ class Batch:
             raise GWError(st, self.handle.lib.gw_last_error(self.handle.h).decode())
 
     def info(self):
-        v = [ctypes.c_int(0) for _ in range(4)]
+        v = [ctypes.c_int(0) for _ in range(5)]
         self.handle.lib.gw_batch_info(self.b, *[ctypes.byref(x) for x in v])
-        return dict(jobs=v[0].value, waves=v[1].value, graph=bool(v[2].value), split_target=v[3].value)
+        return dict(jobs=v[0].value, waves=v[1].value, graph=bool(v[2].value), split_target=v[3].value,
+                    small_tile_nmo=v[4].value)
 
     def close(self):
         if getattr(self, "b", None) and self.b.value:

@@ -60,6 +60,7 @@ SIZES = [20, 25, 60, 30, 45, 40]
 @pytest.mark.parametrize("prec,scr,bopts", [
     ("mixed", "tda", None),
     ("mixed", "tda", {"job_bytes": 1 << 20, "wave_bytes": 3 << 20}),
+    ("mixed", "tda", {"small_tile_nmo": 45}),      # 64 x 64 contraction tiles for nmo <= 45
     ("fp64", "tda", None),
     ("mixed", "rpa", None),
 ])
@@ -71,8 +72,10 @@ def test_batch_matches_single_calls(handle, prec, scr, bopts):
     b = handle.batch([(e, l, o) for e, l, o in tensors], N, screening=scr, precision=prec, bopts=bopts)
     info = b.info()
     print(info, flush=True)
-    if bopts:
+    if bopts and "wave_bytes" in bopts:
         assert info["waves"] > 1 and info["jobs"] == len(SIZES)
+    if bopts and "small_tile_nmo" in bopts:
+        assert info["small_tile_nmo"] == bopts["small_tile_nmo"]
     assert info["graph"] == (scr == "tda")
     for (e, l, o), (so, sv) in zip(tensors, b.sigma):
         ro, rv = handle.sigma_moments(e, l, o, N, screening=scr, precision=prec)
@@ -122,7 +125,8 @@ def test_autotuned_plan_gives_the_same_moments(handle):
     sy = systems([40, 25, 30], seed0=11)
     tensors = [(dev(e), dev(L), o) for o, e, L in sy]
     b = handle.batch([(e, l, o) for e, l, o in tensors], 7, bopts={"autotune": 1})
-    assert b.info()["split_target"] in (256, 512, 1024, 2048)
+    info = b.info()
+    assert info["split_target"] in (256, 512, 1024, 2048) and info["small_tile_nmo"] in (0, 100, 150, 200)
     for (e, l, o), (so, sv) in zip(tensors, b.sigma):
         ro, rv = handle.sigma_moments(e, l, o, 7, precision="mixed")
         assert rel(host(so), host(ro)) < 1e-12 and rel(host(sv), host(rv)) < 1e-12

@@ -197,6 +197,23 @@ gw_status gw_poles(gw_handle h, int nmo, int nmom_max, const double* sigma_occ,
                    double* E, double* chi, double* qp_e, double* qp_w);
 
 /*
+ * Symmetric eigensolver behind the pole stage (Sec. 2.3: the square roots and
+ * pseudo-inverses of the Lanczos blocks and the block tridiagonal sector
+ * matrices; Sec. 2.4: the upfolded Hamiltonian H~), and behind the Fock,
+ * qsGW and natural-auxiliary eigensolves.  Householder tridiagonalisation in
+ * the library's own kernels (two launches per column), then divide and
+ * conquer on the tridiagonal matrix and the back-transformation (rocSOLVER
+ * dstedc, dormtr).
+ *   A [n][n] (device, row-major, symmetric; only the upper triangle of the
+ *            row-major view is read) is overwritten: row i = eigenvector i
+ *            (unit norm, sign unspecified);
+ *   w [n]    (device) eigenvalues ascending.
+ * Returns GW_EINVAL for n < 1 or null pointers, GW_ENUMERIC when the
+ * tridiagonal eigensolver does not converge.  Synchronises the stream.
+ */
+gw_status gw_eigh(gw_handle h, int n, double* A, double* w);
+
+/*
  * Fock / chemical-potential self-consistent GW (Sec. 3.6, Alg. 2).
  * The loop state is the Fock matrix F in the reference MO basis (eps, L).
  * Outer iteration: diagonalise F (orbital energies e, orbitals C), rotate

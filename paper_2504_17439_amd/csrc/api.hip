@@ -213,6 +213,7 @@ gw_status gw_destroy(gw_handle h) {
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
     (void)hipStreamSynchronize(h->own_stream);
+    gwm::aux_destroy(h);
     gwm::clear_timed(h);
     for (auto& b : h->ws)
         if (b.ptr) (void)hipFree(b.ptr);
@@ -310,6 +311,19 @@ gw_status gw_poles(gw_handle h, int nmo, int nmom_max, const double* sigma_occ, 
         return gwm::set_err(h, GW_EINVAL, "gw_poles: a required pointer is null");
     return gwm::poles_f64(h, nmo, nmom_max, sigma_occ, sigma_vir, fock, opts, npole_occ, npole_vir, pole_e,
                           pole_v, E, chi, qp_e, qp_w);
+}
+
+gw_status gw_eigh(gw_handle h, int n, double* A, double* w) {
+    if (!h) return GW_EINVAL;
+    GW_HIP(h, hipSetDevice(h->device));
+    if (n < 1) return gwm::set_err(h, GW_EINVAL, "gw_eigh: n must be >= 1");
+    if (!A || !w) return gwm::set_err(h, GW_EINVAL, "gw_eigh: A and w must be non-null");
+    double* work = (double*)gwm::ws_get(h, gwm::WS_MISC, sizeof(double) * ((size_t)n + 16));
+    if (!work) return GW_ENOMEM;
+    int* info = (int*)(work + n + 8);
+    GW_TRY(gwm::eigh_rows(h, n, A, w, work, info));
+    GW_HIP(h, hipStreamSynchronize(h->stream));
+    return GW_OK;
 }
 
 gw_status gw_fsgw(gw_handle h, gw_screening screening, int nocc, int nvir, int naux, int nmom_max,

@@ -42,6 +42,10 @@ struct Handle {
     // named workspaces (see WS_* below)
     std::vector<DevBuf> ws;
     hipEvent_t ev = nullptr;
+    // companion handle for work that runs beside this handle's own (its own
+    // stream, rocBLAS handle and workspaces; the occupied-sector Lanczos),
+    // created on first use and destroyed with this handle
+    Handle* aux = nullptr;
 };
 
 enum WsSlot {
@@ -51,12 +55,22 @@ enum WsSlot {
     WS_MIX0, WS_MIX1, WS_MIX2, WS_MIX3, WS_MIX4, WS_MIX5, WS_MIX6,
     WS_FS0, WS_FS1, WS_FS2, WS_FS3, WS_FS4, WS_FS5, WS_FS6, WS_FS7,
     WS_RC0, WS_RC1, WS_RC2, WS_RC3, WS_RC4, WS_RC5,
-    WS_KPART, WS_RPA_PART,
+    WS_KPART, WS_RPA_PART, WS_POLE_TMP, WS_EIG,
     WS_COUNT
 };
 
 // Returns nullptr on failure (and records the message).
 void* ws_get(Handle* h, int slot, size_t bytes);
+// Frees the companion handle of h (if any); gw_destroy calls it.
+void aux_destroy(Handle* h);
+
+// Symmetric eigensolver (own Householder tridiagonalisation, rocSOLVER
+// dstedc + dormtr): A [n][n] symmetric (lower triangle of the column-major
+// view read) is overwritten with the eigenvectors (row i = eigenvector i of
+// the row-major view), w receives the eigenvalues ascending; work holds n
+// doubles, info one int, ws syev_tridiag_bytes(n) bytes.
+size_t syev_tridiag_bytes(int n);
+gw_status syev_tridiag(Handle* h, int n, double* A, double* w, double* work, int* info, void* ws);
 
 // Device scratch of doubles: a handle workspace slot (grown on demand), or a
 // fixed region supplied by the caller (slot < 0), which never grows.

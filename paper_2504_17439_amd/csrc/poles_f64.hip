@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <thread>
 #include <vector>
 
 namespace gwm {
@@ -214,6 +215,11 @@ struct Eig {
 };
 
 gw_status syevd(Handle* h, int n, Eig& e, bool vectors) {
+    if (vectors) {
+        void* ws = ws_get(h, WS_EIG, syev_tridiag_bytes(n));
+        if (!ws) return GW_ENOMEM;
+        return syev_tridiag(h, n, e.A, e.w, e.work, e.info, ws);
+    }
     GW_TRY(blas_ok(h,
                    rocsolver_dsyevd(h->blas, vectors ? rocblas_evect_original : rocblas_evect_none,
                                     rocblas_fill_upper, n, e.A, n, e.w, e.work, e.info),
@@ -466,7 +472,106 @@ gw_status lanczos_sector(Handle* h, int M, int N, const double* T_in, double pin
     return GW_OK;
 }
 
+Handle* aux_handle(Handle* h) {
+    if (h->aux) return h->aux;
+    Handle* a = new (std::nothrow) Handle();
+    if (!a) {
+        set_err(h, GW_ENOMEM, "companion handle: out of host memory");
+        return nullptr;
+    }
+    a->device = h->device;
+    a->cus = h->cus;
+    a->ws.resize(WS_COUNT);
+    if (hipStreamCreateWithFlags(&a->own_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        delete a;
+        set_err(h, GW_EHIP, "companion handle: stream creation failed");
+        return nullptr;
+    }
+    a->stream = a->own_stream;
+    if (rocblas_create_handle(&a->blas) != rocblas_status_success) {
+        (void)hipStreamDestroy(a->own_stream);
+        delete a;
+        set_err(h, GW_ELIB, "companion handle: rocblas_create_handle failed");
+        return nullptr;
+    }
+    rocblas_set_stream(a->blas, a->stream);
+    h->aux = a;
+    return a;
+}
+
+// Both sectors' block Lanczos at once: the occupied one on the companion
+// handle in a second host thread (its own stream, rocBLAS handle and
+// workspaces), the virtual one on h; each is a long chain of small
+// launch-latency-bound steps and host decisions, so the two overlap on the
+// device.  The occupied poles land at columns [0, no) of pole_e / pole_v, the
+// virtual ones are computed into a scratch and moved to [no, no + nv).  The
+// companion stream starts after the work queued on h's stream and h's stream
+// continues after it.
+gw_status lanczos_two_sectors(Handle* h, int M, int N, const double* so, const double* sv, double pinv_tol,
+                              double neg_tol, double kappa, double* pole_e, double* pole_v, long ldv, int* no,
+                              int* nv) {
+    Handle* a = aux_handle(h);
+    if (!a) return GW_EHIP;
+    const long cap = (long)M * (N + 1) / 2;
+    double* tmp = (double*)ws_get(h, WS_POLE_TMP, sizeof(double) * (size_t)(cap + (long)M * cap));
+    if (!tmp) return GW_ENOMEM;
+    hipEvent_t fork = nullptr, join = nullptr;
+    GW_HIP(h, hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipEventDestroy(fork);
+        return set_err(h, GW_EHIP, "lanczos: event creation failed");
+    }
+    struct Events {
+        hipEvent_t a, b;
+        ~Events() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } guard{fork, join};
+    GW_HIP(h, hipEventRecord(fork, h->stream));
+    GW_HIP(h, hipStreamWaitEvent(a->stream, fork, 0));
+    gw_status st_occ = GW_OK;
+    int n_occ = 0, n_vir = 0;
+    std::thread worker([&] {
+        if (hipSetDevice(a->device) != hipSuccess) {
+            (void)hipGetLastError();
+            st_occ = set_err(a, GW_EHIP, "lanczos: hipSetDevice failed in the worker thread");
+            return;
+        }
+        st_occ = lanczos_sector(a, M, N, so, pinv_tol, neg_tol, kappa, pole_e, pole_v, ldv, 0, &n_occ);
+    });
+    const gw_status st_vir = lanczos_sector(h, M, N, sv, pinv_tol, neg_tol, kappa, tmp, tmp + cap, cap, 0, &n_vir);
+    worker.join();
+    // h's stream waits for the occupied sector whatever happened
+    GW_HIP(h, hipEventRecord(join, a->stream));
+    GW_HIP(h, hipStreamWaitEvent(h->stream, join, 0));
+    if (st_occ != GW_OK) return set_err(h, st_occ, a->last_error);
+    if (st_vir != GW_OK) return st_vir;
+    if (n_vir > 0) {
+        GW_HIP(h, hipMemcpyAsync(pole_e + n_occ, tmp, sizeof(double) * n_vir, hipMemcpyDeviceToDevice, h->stream));
+        GW_HIP(h, hipMemcpy2DAsync(pole_v + n_occ, sizeof(double) * ldv, tmp + cap, sizeof(double) * cap,
+                                   sizeof(double) * n_vir, M, hipMemcpyDeviceToDevice, h->stream));
+    }
+    *no = n_occ;
+    *nv = n_vir;
+    return GW_OK;
+}
+
 }  // namespace
+
+void aux_destroy(Handle* h) {
+    Handle* a = h->aux;
+    if (!a) return;
+    (void)hipStreamSynchronize(a->stream);
+    for (auto& b : a->ws)
+        if (b.ptr) (void)hipFree(b.ptr);
+    if (a->blas) rocblas_destroy_handle(a->blas);
+    if (a->own_stream) (void)hipStreamDestroy(a->own_stream);
+    delete a;
+    h->aux = nullptr;
+}
 
 gw_status poles_f64(Handle* h, int nmo, int nmom_max, const double* sigma_occ, const double* sigma_vir,
                     const double* fock, const gw_opts* opts, int* npole_occ, int* npole_vir, double* pole_e,
@@ -480,8 +585,8 @@ gw_status poles_f64(Handle* h, int nmo, int nmom_max, const double* sigma_occ, c
     const long ldv = 2L * cap;
     GW_TRY(blas_ok(h, rocblas_set_stream(h->blas, h->stream), "rocblas_set_stream"));
     int no = 0, nv = 0;
-    GW_TRY(lanczos_sector(h, M, nmom_max, sigma_occ, pinv_tol, neg_tol, kappa, pole_e, pole_v, ldv, 0, &no));
-    GW_TRY(lanczos_sector(h, M, nmom_max, sigma_vir, pinv_tol, neg_tol, kappa, pole_e, pole_v, ldv, no, &nv));
+    GW_TRY(lanczos_two_sectors(h, M, nmom_max, sigma_occ, sigma_vir, pinv_tol, neg_tol, kappa, pole_e, pole_v, ldv,
+                               &no, &nv));
     *npole_occ = no;
     *npole_vir = nv;
     const int np = no + nv;
@@ -532,8 +637,8 @@ gw_status poles_lanczos(Handle* h, int nmo, int nmom_max, const double* sigma_oc
     const double kappa = (opts && opts->moment_eps > 0) ? opts->moment_eps / 2.220446049250313e-16 : 1.0;
     GW_TRY(blas_ok(h, rocblas_set_stream(h->blas, h->stream), "rocblas_set_stream"));
     int no = 0, nv = 0;
-    GW_TRY(lanczos_sector(h, nmo, nmom_max, sigma_occ, pinv_tol, neg_tol, kappa, pole_e, pole_v, ldv, 0, &no));
-    GW_TRY(lanczos_sector(h, nmo, nmom_max, sigma_vir, pinv_tol, neg_tol, kappa, pole_e, pole_v, ldv, no, &nv));
+    GW_TRY(lanczos_two_sectors(h, nmo, nmom_max, sigma_occ, sigma_vir, pinv_tol, neg_tol, kappa, pole_e, pole_v,
+                               ldv, &no, &nv));
     *npole_occ = no;
     *npole_vir = nv;
     return GW_OK;

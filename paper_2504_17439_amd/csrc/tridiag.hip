@@ -1,0 +1,325 @@
+// Symmetric eigensolver of the pole stage: the eigenpairs of the block
+// tridiagonal Lanczos matrices (Sec. 2.3), of the Gram matrices of the
+// Lanczos blocks (their square roots and pseudo-inverses) and of the upfolded
+// Hamiltonian H~ (Sec. 2.4) all come from here.
+//
+// A = Q T Q^T is reached by Householder reflectors, one column at a time, in
+// the classical unblocked order (reflector k annihilates column k below the
+// subdiagonal; the trailing matrix takes the symmetric rank-2 update
+// A <- A - v w^T - w v^T with w = tau A v + alpha2 v, alpha2 = -tau^2 v^T A v / 2).
+// T's eigenpairs then come from rocSOLVER's divide and conquer (dstedc) and
+// the eigenvectors of A from applying Q (dormtr); the reflectors are left in
+// the layout those routines read (lower triangle, column-major, v_k below the
+// subdiagonal of column k with its leading 1 implicit, e_k on the
+// subdiagonal).
+//
+// The reduction is bound by launches and memory, not by arithmetic: a
+// library tridiagonalisation issues several kernels per column (norm,
+// symmetric matrix-vector product, dot products, rank-2 update, ...).  Here
+// column k takes two launches:
+//   * trd_step: every work group owns one 64 x 64 tile of the trailing lower
+//     triangle and applies the still-pending rank-2 update of reflector k-1
+//     to it (written back), so the update of one step and the matrix-vector
+//     product of the next share one pass over the matrix; column k after
+//     that update is x, and the tile writes its share of y = A22 x (both
+//     halves of the symmetric product) as a partial vector, and its shares of
+//     x^T y and |x|^2 as partial scalars;
+//   * trd_reduce: one work group per row block sums that block's partial
+//     vectors into y (a fixed order), and one more sums the partial scalars
+//     and forms beta, tau and alpha2.
+// The reflector is never formed before the product: with v = (x - beta e0) s,
+// s = 1/(alpha - beta), one has A22 v = (y - beta a0) s (a0 the first column
+// of A22) and v^T A22 v = (x^T y - 2 beta y_0 + beta^2 a_00) s^2, so the next
+// trd_step rebuilds v and w row by row from x, y and a0 (column k+1, which
+// trd_step k leaves untouched).  No work group waits for or signals another
+// inside a launch: the launch boundaries are the only synchronisation.
+// Column k itself is rewritten into reflector form by trd_step k+1, which
+// never reads it.
+#include "internal.h"
+
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+namespace gwm {
+
+namespace {
+
+constexpr int TB = 64;  // tile edge
+constexpr int NT = 256;  // threads per work group: 64 rows x 4 column quarters
+
+struct TrdWork {
+    double* X;       // [2][n]          column k after its pending update (rows > k), by parity of k
+    double* Y;       // [n]             y = A22 x of the last reduced step (rows > k)
+    double* part;    // [nbt][nbt][64]  per-tile partial vectors of y
+    double* tsc;     // [nbt][nbt]      per-tile partial x^T y
+    double* s2p;     // [nbt]           per-row-block partial |x|^2 (rows > k+1)
+    double* scal;    // [2][8]          beta, tau, s, alpha2, w_k[k+1] of step k, by parity
+};
+
+// y[i] for row i from the partial vectors in one fixed order: four
+// interleaved partial sums (partner blocks kb + g, kb + g + 4, ...), combined
+// as (g0 + g1) + (g2 + g3).  The row blocks and the scalar work group both
+// use it, so y_0 agrees bit for bit.
+__device__ inline double row_partial(const double* part, int nbt, int kb, int i, int g) {
+    const int B = i / TB;
+    const double* pp = part + (long)B * nbt * TB + (i - B * TB);
+    double y = 0.0;
+#pragma unroll 4
+    for (int J = kb + g; J < nbt; J += 4) y += pp[(long)J * TB];
+    return y;
+}
+
+// One Householder step (column k) on the lower triangle of the column-major
+// n x n matrix A (leading dimension lda): applies reflector k-1 (from the
+// scalars trd_reduce left) and writes the partials of y = A22 x.  Grid: one
+// work group per lower tile (R >= C) of block rows/columns kb = k/64 .. nbt-1.
+__global__ __launch_bounds__(NT) void trd_step_kernel(int n, long lda, int k, int nbt, double* A, double* d,
+                                                      TrdWork wk) {
+    __shared__ double sv[2][TB], sw[2][TB], sx[2][TB];
+    __shared__ double syc[TB][TB + 1];
+    __shared__ double sred[4][TB];
+    __shared__ double syr[TB], sycol[TB];
+    __shared__ double sdot[NT];
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int p = k & 1, q = p ^ 1;
+    const int kb = k / TB;
+    // tile (R, C), R >= C, from the linear index over the trailing lower triangle
+    const int t = blockIdx.x;
+    int rr = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((rr + 1) * (rr + 2) / 2 <= t) ++rr;
+    while (rr * (rr + 1) / 2 > t) --rr;
+    const int cc = t - rr * (rr + 1) / 2;
+    const int R = kb + rr, C = kb + cc;
+    const bool diag = R == C;
+    const int r0 = R * TB, c0 = C * TB;
+
+    // the tile's elements: rows r0 + lane, columns c0 + 16 wv + j
+    const int i = r0 + lane;
+    double a[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int col = c0 + wv * 16 + j;
+        a[j] = (i < n && col < n && i >= col && col >= k) ? A[(long)col * lda + i] : 0.0;
+    }
+
+    // reflector k-1, still to be applied to rows/columns >= k
+    const bool pend = k > 0;
+    double bq = 0.0, tq = 0.0, sq = 0.0, aq = 0.0, wkk = 0.0;
+    if (pend) {
+        const double* sc = wk.scal + q * 8;
+        bq = sc[0];
+        tq = sc[1];
+        sq = sc[2];
+        aq = sc[3];
+        wkk = sc[4];
+    }
+    if (tid < 2 * TB) {
+        const int which = tid >> 6;
+        const int ii = (which ? c0 : r0) + lane;
+        double v = 0.0, w = 0.0, x = 0.0;
+        if (ii < n && ii >= k) {
+            const double aik = A[(long)k * lda + ii];  // column k (lower: ii >= k)
+            if (pend) {
+                v = (ii == k) ? 1.0 : wk.X[q * n + ii] * sq;
+                w = tq * sq * (wk.Y[ii] - bq * aik) + aq * v;
+            }
+            if (ii > k) x = aik - v * wkk - w;
+        }
+        sv[which][lane] = v;
+        sw[which][lane] = w;
+        sx[which][lane] = x;
+    }
+    __syncthreads();
+
+    // the tile: pending update (written back), then its share of y = A22 x
+    const double vi = sv[0][lane], wi = sw[0][lane], xi = sx[0][lane];
+    double yr = 0.0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int cl = wv * 16 + j;
+        const int col = c0 + cl;
+        double yc = 0.0;
+        if (i < n && col < n && i >= col && col >= k) {
+            double x = a[j];
+            if (pend) x -= vi * sw[1][cl] + wi * sv[1][cl];
+            if (col > k) {
+                A[(long)col * lda + i] = x;
+                yr += x * sx[1][cl];
+                if (i != col) yc = x * xi;
+            } else if (i == k) {
+                d[k] = x;
+            }
+        }
+        syc[cl][lane] = yc;
+    }
+    sred[wv][lane] = yr;
+    __syncthreads();
+    {
+        // column sums of the transposed half: thread (cl, quarter) sums 16 rows
+        const int cl = tid & 63, qq = tid >> 6;
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc += syc[cl][qq * 16 + u];
+        sdot[tid] = acc;
+    }
+    __syncthreads();
+    if (tid < TB) {
+        syr[tid] = sred[0][tid] + sred[1][tid] + sred[2][tid] + sred[3][tid];
+        sycol[tid] = sdot[tid] + sdot[TB + tid] + sdot[2 * TB + tid] + sdot[3 * TB + tid];
+    }
+    __syncthreads();
+    // partial vectors, the tile's x^T y share and (diagonal tiles) x, |x|^2
+    double dot = 0.0, sq2 = 0.0;
+    if (tid < TB) {
+        const double y = diag ? syr[tid] + sycol[tid] : syr[tid];
+        wk.part[((long)R * nbt + C) * TB + tid] = y;
+        dot = sx[0][tid] * y;
+        if (!diag) dot += sx[1][tid] * sycol[tid];
+        if (diag) {
+            const int ii = r0 + tid;
+            if (ii < n) {
+                const double xv = sx[0][tid];
+                wk.X[p * n + ii] = xv;
+                if (ii > k + 1) sq2 = xv * xv;
+                // column k-1 in reflector form: e_{k-1} on the subdiagonal, v below
+                if (pend && ii >= k) A[(long)(k - 1) * lda + ii] = (ii == k) ? bq : wk.X[q * n + ii] * sq;
+            }
+        }
+    } else if (tid < 2 * TB && !diag) {
+        wk.part[((long)C * nbt + R) * TB + lane] = sycol[lane];
+    }
+    // wave 0 holds every nonzero term: reduce it in registers
+    if (wv == 0) {
+        for (int o = 32; o > 0; o >>= 1) {
+            dot += __shfl_xor(dot, o);
+            sq2 += __shfl_xor(sq2, o);
+        }
+        if (lane == 0) {
+            wk.tsc[(long)R * nbt + C] = dot;
+            if (diag) wk.s2p[R] = sq2;
+        }
+    }
+}
+
+// Finishes step k: work group 0 forms the reflector's scalars, work group
+// 1 + b sums the partial vectors of row block kb + b into y.
+__global__ __launch_bounds__(NT) void trd_reduce_kernel(int n, long lda, int k, int nbt, const double* A,
+                                                        double* e, double* tau, TrdWork wk) {
+    __shared__ double red[NT];
+    const int tid = threadIdx.x;
+    const int kb = k / TB, m = nbt - kb;
+    if (blockIdx.x > 0) {
+        // thread (row lane, group g)
+        const int B = kb + (int)blockIdx.x - 1;
+        const int lane = tid & 63, g = tid >> 6;
+        const int i = B * TB + lane;
+        red[tid] = (i < n) ? row_partial(wk.part, nbt, kb, i, g) : 0.0;
+        __syncthreads();
+        if (tid < TB && i < n)
+            wk.Y[i] = (i > k) ? (red[tid] + red[TB + tid]) + (red[2 * TB + tid] + red[3 * TB + tid]) : 0.0;
+        return;
+    }
+    __shared__ double y0p[4];
+    if (tid < 4) y0p[tid] = row_partial(wk.part, nbt, kb, k + 1, tid);
+    double xy = 0.0, s2 = 0.0;
+#pragma unroll 4
+    for (int idx = tid; idx < m * m; idx += NT) {
+        const int r1 = idx / m, c1 = idx - r1 * m;
+        if (c1 <= r1) xy += wk.tsc[(long)(kb + r1) * nbt + kb + c1];
+    }
+    for (int B = kb + tid; B < nbt; B += NT) s2 += wk.s2p[B];
+    red[tid] = xy;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    xy = red[0];
+    __syncthreads();
+    red[tid] = s2;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    s2 = red[0];
+    if (tid != 0) return;
+    const double alpha = wk.X[(k & 1) * n + k + 1];
+    const double a00 = A[(long)(k + 1) * lda + k + 1];
+    const double y0 = (y0p[0] + y0p[1]) + (y0p[2] + y0p[3]);
+    double beta = alpha, tk = 0.0, sk = 0.0, a2 = 0.0;
+    if (s2 > 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + s2), alpha);
+        tk = (beta - alpha) / beta;
+        sk = 1.0 / (alpha - beta);
+        const double vav = (xy - 2.0 * beta * y0 + beta * beta * a00) * sk * sk;
+        a2 = -0.5 * tk * tk * vav;
+    }
+    double* sc = wk.scal + (k & 1) * 8;
+    sc[0] = beta;
+    sc[1] = tk;
+    sc[2] = sk;
+    sc[3] = a2;
+    sc[4] = tk * sk * (y0 - beta * a00) + a2;  // w_k[k+1]  (v_k[k+1] = 1)
+    e[k] = beta;
+    tau[k] = tk;
+}
+
+gw_status check_solver(Handle* h, rocblas_status st, const char* what) {
+    if (st == rocblas_status_success) return GW_OK;
+    return set_err(h, GW_ELIB, std::string(what) + " failed: " + rocblas_status_to_string(st));
+}
+
+
+}  // namespace
+
+size_t syev_tridiag_bytes(int n) {
+    const long nbt = (n + TB - 1) / TB;
+    const long doubles = 3L * n + nbt * nbt * TB + nbt * nbt + nbt + 16 + (long)n + (long)n * n;
+    return sizeof(double) * (size_t)doubles;
+}
+
+gw_status syev_tridiag(Handle* h, int n, double* A, double* w, double* work, int* info, void* ws) {
+    const int nbt = (n + TB - 1) / TB;
+    TrdWork wk;
+    wk.X = (double*)ws;
+    wk.Y = wk.X + 2L * n;
+    wk.part = wk.Y + n;
+    wk.tsc = wk.part + (long)nbt * nbt * TB;
+    wk.s2p = wk.tsc + (long)nbt * nbt;
+    wk.scal = wk.s2p + nbt;
+    double* tau = wk.scal + 16;
+    double* Z = tau + n;
+    // A = Q T Q^T: d -> w, e -> work, reflectors -> lower triangle of A
+    for (int k = 0; k < n; ++k) {
+        const int kb = k / TB, m = nbt - kb;
+        hipLaunchKernelGGL(trd_step_kernel, dim3(m * (m + 1) / 2), dim3(NT), 0, h->stream, n, (long)n, k, nbt, A,
+                           w, wk);
+        GW_CHECK_LAUNCH(h);
+        if (k + 1 < n) {
+            hipLaunchKernelGGL(trd_reduce_kernel, dim3(m + 1), dim3(NT), 0, h->stream, n, (long)n, k, nbt, A, work,
+                               tau, wk);
+            GW_CHECK_LAUNCH(h);
+        }
+    }
+    // T = Z diag(w) Z^T, then the eigenvectors of A are Q Z
+    GW_TRY(check_solver(h, rocsolver_dstedc(h->blas, rocblas_evect_tridiagonal, n, w, work, Z, n, info),
+                        "rocsolver_dstedc"));
+    int hinfo = 0;
+    GW_HIP(h, hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    GW_HIP(h, hipStreamSynchronize(h->stream));
+    if (hinfo != 0) return set_err(h, GW_ENUMERIC, "tridiagonal eigensolver did not converge");
+    if (n > 1)
+        GW_TRY(check_solver(h,
+                            rocsolver_dormtr(h->blas, rocblas_side_left, rocblas_fill_lower,
+                                             rocblas_operation_none, n, n, A, n, tau, Z, n),
+                            "rocsolver_dormtr"));
+    GW_HIP(h, hipMemcpyAsync(A, Z, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, h->stream));
+    return GW_OK;
+}
+
+}  // namespace gwm

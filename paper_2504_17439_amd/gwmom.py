@@ -26,7 +26,7 @@ _STATUS = {GW_EINVAL: "GW_EINVAL", GW_ENOMEM: "GW_ENOMEM", GW_EHIP: "GW_EHIP",
 # every symbol declared in include/gwmom.h
 EXPORTS = ("gw_create", "gw_set_stream", "gw_synchronize", "gw_destroy", "gw_last_error",
            "gw_moments_tda", "gw_moments_rpa", "gw_sigma_moments", "gw_sigma_from_R", "gw_sigma_moments_noalloc",
-           "gw_poles",
+           "gw_poles", "gw_eigh",
            "gw_fsgw", "gw_evgw", "gw_naf", "gw_qsgw", "gw_spectral", "gw_aufbau", "gw_zeta_shift", "gw_batch_create", "gw_batch_run", "gw_batch_info", "gw_batch_destroy",
            "gw_mlp_param_count", "gw_mlp_features", "gw_mlp_forward", "gw_mlp_backward",
            "gw_mlp_adam", "gw_mlp_norm", "gw_mlp_target", "gw_mlp_warm_start", "gw_timing_enable",
@@ -129,6 +129,7 @@ def load_library(path: str = LIB_PATH):
         "gw_sigma_from_R": ([H, I, I, I, I, P, P, P, I, P, P, P], I),
         "gw_sigma_moments_noalloc": ([H, I, I, I, I, P, P, P, P], I),
         "gw_poles": ([H, I, I, P, P, P, P, ctypes.POINTER(I), ctypes.POINTER(I), P, P, P, P, P, P], I),
+        "gw_eigh": ([H, I, P, P], I),
         "gw_fsgw": ([H, I, I, I, I, I, P, P, P, I, P, P, P, P, P, P], I),
         "gw_evgw": ([H, I, I, I, I, I, P, P, I, P, P, P, P, P], I),
         "gw_naf": ([H, I, I, I, P, D, I, P, ctypes.POINTER(I), P], I),
@@ -475,6 +476,16 @@ class Handle:
         return dict(e_occ=pe[:no], v_occ=pv[:, :no], e_vir=pe[no:no + nv], v_vir=pv[:, no:no + nv],
                     E=E[:dim], chi=None if chi is None else chi[:, :dim], qp=qe, qp_weight=qw,
                     packed=(pe, pv, no, nv, nmom_max))
+
+    def eigh(self, A):
+        """(w [n] ascending, V [n][n]) of the symmetric A [n][n] (row i of V is
+        eigenvector i); A itself is left unchanged."""
+        n = A.shape[0]
+        _check_dev(A, "A", (n, n))
+        V = A.clone()
+        w = self._new(n)
+        self._call("gw_eigh", n, _ptr(V), _ptr(w))
+        return w, V
 
     # ------------------------------------------------------------------ Green's function
     def spectral(self, E, chi, omega, delta, per_orbital=False):

@@ -204,7 +204,7 @@ gw_status gw_poles(gw_handle h, int nmo, int nmom_max, const double* sigma_occ,
  * the library's own kernels (two launches per column), then divide and
  * conquer on the tridiagonal matrix and the back-transformation (rocSOLVER
  * dstedc, dormtr).
- *   A [n][n] (device, row-major, symmetric; only the upper triangle of the
+ *   A [n][n] (device, row-major, symmetric; only the lower triangle of the
  *            row-major view is read) is overwritten: row i = eigenvector i
  *            (unit norm, sign unspecified);
  *   w [n]    (device) eigenvalues ascending.

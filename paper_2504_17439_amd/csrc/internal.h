@@ -65,8 +65,8 @@ void* ws_get(Handle* h, int slot, size_t bytes);
 void aux_destroy(Handle* h);
 
 // Symmetric eigensolver (own Householder tridiagonalisation, rocSOLVER
-// dstedc + dormtr): A [n][n] symmetric (lower triangle of the column-major
-// view read) is overwritten with the eigenvectors (row i = eigenvector i of
+// dstedc + dormtr): A [n][n] symmetric (the lower triangle of the row-major
+// view defines it) is overwritten with the eigenvectors (row i = eigenvector i of
 // the row-major view), w receives the eigenvalues ascending; work holds n
 // doubles, info one int, ws syev_tridiag_bytes(n) bytes.
 size_t syev_tridiag_bytes(int n);

@@ -7,11 +7,12 @@
 // the classical unblocked order (reflector k annihilates column k below the
 // subdiagonal; the trailing matrix takes the symmetric rank-2 update
 // A <- A - v w^T - w v^T with w = tau A v + alpha2 v, alpha2 = -tau^2 v^T A v / 2).
-// T's eigenpairs then come from rocSOLVER's divide and conquer (dstedc) and
-// the eigenvectors of A from applying Q (dormtr); the reflectors are left in
-// the layout those routines read (lower triangle, column-major, v_k below the
-// subdiagonal of column k with its leading 1 implicit, e_k on the
-// subdiagonal).
+// T's eigenpairs then come from rocSOLVER's divide and conquer (dstedc), and
+// the eigenvectors of A from applying Q to T's, blocked in compact WY form
+// (apply_q: the triangular factor in one small kernel, the three products on
+// rocBLAS dgemm).  The reflectors are kept in LAPACK's layout (lower
+// triangle, column-major, v_k below the subdiagonal of column k with its
+// leading 1 implicit, e_k on the subdiagonal).
 //
 // The reduction is bound by launches and memory, not by arithmetic: a
 // library tridiagonalisation issues several kernels per column (norm,
@@ -269,6 +270,80 @@ __global__ __launch_bounds__(NT) void trd_reduce_kernel(int n, long lda, int k, 
     tau[k] = tk;
 }
 
+// B = J A J (J the index reversal), lower triangle of the column-major view,
+// from the lower triangle of the row-major view of A (the one the Lanczos
+// matrices and LAPACK's convention define):  B(i, j) = A(n-1-i, n-1-j),
+// i >= j.  Reducing B from its first column is reducing A from its last, as
+// LAPACK's and rocSOLVER's upper-triangle reduction does; the moment matrices
+// are strongly graded (eigenvalues spread over many decades, the small ones
+// at the far end of the orbital order), and the small eigenpairs that the
+// pseudo-inverse square roots keep are reproduced far better in that
+// direction.
+__global__ void reverse_kernel(int n, const double* __restrict__ A, double* __restrict__ B) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * n) return;
+    const long j = idx / n, i = idx - j * n;
+    if (i >= j) B[idx] = A[(long)(n - 1 - j) * n + (n - 1 - i)];
+}
+
+// column a of V (an eigenvector of B) -> the eigenvector of A: components reversed
+__global__ void unreverse_kernel(int n, double* __restrict__ V) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long half = n / 2;
+    if (idx >= (long)n * half) return;
+    const long a = idx / half, p = idx - a * half;
+    double* col = V + a * n;
+    const double t = col[p];
+    col[p] = col[n - 1 - p];
+    col[n - 1 - p] = t;
+}
+
+// Back-transformation C <- Q C, Q = H_0 H_1 ... H_{n-2} (the reflectors of
+// the reduction), in blocks of QB reflectors applied last block first: the
+// block H_k0 ... H_k1-1 is I - V T V^T with V the block's reflectors (unit
+// entry explicit, rows k0+1 .. n-1) and T upper triangular (T_cc = tau_c,
+// T[0:c, c] = -tau_c T[0:c, 0:c] V[:, 0:c]^T v_c), and
+// C[k0+1:, :] -= V (T (V^T C[k0+1:, :])) is three GEMMs.
+constexpr int QB = 64;
+
+// V [nr][bj] column-major (ld nr), rows k0+1 .. n-1: column c is reflector
+// k = k0 + c, zero above row k+1, one at row k+1, the stored v below.
+__global__ void build_v_kernel(int n, int k0, int bj, const double* __restrict__ Zr, double* __restrict__ V) {
+    const int nr = n - k0 - 1;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)nr * bj) return;
+    const int c = (int)(idx / nr), r = (int)(idx - (long)c * nr);
+    const int i = k0 + 1 + r, k = k0 + c;
+    double x = 0.0;
+    if (i == k + 1) x = 1.0;
+    else if (i > k + 1) x = Zr[(long)k * n + i];
+    V[idx] = x;
+}
+
+// T [bj][bj] column-major from G = V^T V and tau (one work group)
+__global__ __launch_bounds__(256) void larft_kernel(int bj, const double* __restrict__ G,
+                                                    const double* __restrict__ tau, double* __restrict__ T) {
+    __shared__ double sT[QB][QB + 1];
+    __shared__ double sg[QB];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < QB * QB; e += 256) sT[e % QB][e / QB] = 0.0;
+    __syncthreads();
+    for (int c = 0; c < bj; ++c) {
+        const double tc = tau[c];
+        if (tid < c) sg[tid] = G[(long)c * bj + tid];  // (V^T v_c)[r], r < c
+        __syncthreads();
+        if (tid < c) {
+            // row r of T[0:c, 0:c] times g: T is upper triangular
+            double acc = 0.0;
+            for (int q = tid; q < c; ++q) acc += sT[tid][q] * sg[q];
+            sT[tid][c] = -tc * acc;
+        }
+        if (tid == 0) sT[c][c] = tc;
+        __syncthreads();
+    }
+    for (int e = tid; e < bj * bj; e += 256) T[e] = sT[e % bj][e / bj];
+}
+
 gw_status check_solver(Handle* h, rocblas_status st, const char* what) {
     if (st == rocblas_status_success) return GW_OK;
     return set_err(h, GW_ELIB, std::string(what) + " failed: " + rocblas_status_to_string(st));
@@ -279,9 +354,49 @@ gw_status check_solver(Handle* h, rocblas_status st, const char* what) {
 
 size_t syev_tridiag_bytes(int n) {
     const long nbt = (n + TB - 1) / TB;
-    const long doubles = 3L * n + nbt * nbt * TB + nbt * nbt + nbt + 16 + (long)n + (long)n * n;
+    const long doubles = 3L * n + nbt * nbt * TB + nbt * nbt + nbt + 16 + (long)n + (long)n * n +
+                         (long)n * QB + 2L * QB * QB + 2L * QB * n;
     return sizeof(double) * (size_t)doubles;
 }
+
+namespace {
+
+gw_status apply_q(Handle* h, int n, const double* Zr, const double* tau, double* C, double* V) {
+    double* G = V + (long)n * QB;
+    double* T = G + QB * QB;
+    double* W1 = T + QB * QB;
+    double* W2 = W1 + (long)QB * n;
+    const double one = 1.0, zero = 0.0, mone = -1.0;
+    const int nref = n - 1;
+    for (int k0 = ((nref - 1) / QB) * QB; k0 >= 0; k0 -= QB) {
+        const int bj = std::min(QB, nref - k0), nr = n - k0 - 1;
+        hipLaunchKernelGGL(build_v_kernel, dim3((unsigned)(((long)nr * bj + 255) / 256)), dim3(256), 0, h->stream, n,
+                           k0, bj, Zr, V);
+        GW_CHECK_LAUNCH(h);
+        GW_TRY(check_solver(h,
+                            rocblas_dgemm(h->blas, rocblas_operation_transpose, rocblas_operation_none, bj, bj, nr,
+                                          &one, V, nr, V, nr, &zero, G, bj),
+                            "rocblas_dgemm"));
+        hipLaunchKernelGGL(larft_kernel, dim3(1), dim3(256), 0, h->stream, bj, G, tau + k0, T);
+        GW_CHECK_LAUNCH(h);
+        double* Cs = C + k0 + 1;  // rows k0+1 .. n-1, ld n
+        GW_TRY(check_solver(h,
+                            rocblas_dgemm(h->blas, rocblas_operation_transpose, rocblas_operation_none, bj, n, nr,
+                                          &one, V, nr, Cs, n, &zero, W1, bj),
+                            "rocblas_dgemm"));
+        GW_TRY(check_solver(h,
+                            rocblas_dgemm(h->blas, rocblas_operation_none, rocblas_operation_none, bj, n, bj, &one, T,
+                                          bj, W1, bj, &zero, W2, bj),
+                            "rocblas_dgemm"));
+        GW_TRY(check_solver(h,
+                            rocblas_dgemm(h->blas, rocblas_operation_none, rocblas_operation_none, nr, n, bj, &mone, V,
+                                          nr, W2, bj, &one, Cs, n),
+                            "rocblas_dgemm"));
+    }
+    return GW_OK;
+}
+
+}  // namespace
 
 gw_status syev_tridiag(Handle* h, int n, double* A, double* w, double* work, int* info, void* ws) {
     const int nbt = (n + TB - 1) / TB;
@@ -294,31 +409,36 @@ gw_status syev_tridiag(Handle* h, int n, double* A, double* w, double* work, int
     wk.scal = wk.s2p + nbt;
     double* tau = wk.scal + 16;
     double* Z = tau + n;
-    // A = Q T Q^T: d -> w, e -> work, reflectors -> lower triangle of A
+    double* Vq = Z + (long)n * n;
+    // B = J A J into Z; A = Q T Q^T of B: d -> w, e -> work, reflectors -> lower triangle of Z
+    hipLaunchKernelGGL(reverse_kernel, dim3((unsigned)(((long)n * n + 255) / 256)), dim3(256), 0, h->stream, n, A,
+                       Z);
+    GW_CHECK_LAUNCH(h);
     for (int k = 0; k < n; ++k) {
         const int kb = k / TB, m = nbt - kb;
-        hipLaunchKernelGGL(trd_step_kernel, dim3(m * (m + 1) / 2), dim3(NT), 0, h->stream, n, (long)n, k, nbt, A,
+        hipLaunchKernelGGL(trd_step_kernel, dim3(m * (m + 1) / 2), dim3(NT), 0, h->stream, n, (long)n, k, nbt, Z,
                            w, wk);
         GW_CHECK_LAUNCH(h);
         if (k + 1 < n) {
-            hipLaunchKernelGGL(trd_reduce_kernel, dim3(m + 1), dim3(NT), 0, h->stream, n, (long)n, k, nbt, A, work,
+            hipLaunchKernelGGL(trd_reduce_kernel, dim3(m + 1), dim3(NT), 0, h->stream, n, (long)n, k, nbt, Z, work,
                                tau, wk);
             GW_CHECK_LAUNCH(h);
         }
     }
-    // T = Z diag(w) Z^T, then the eigenvectors of A are Q Z
-    GW_TRY(check_solver(h, rocsolver_dstedc(h->blas, rocblas_evect_tridiagonal, n, w, work, Z, n, info),
+    // T's eigenvectors into A, then Q applied to them (the eigenvectors of B),
+    // then their components reversed (the eigenvectors of A)
+    GW_TRY(check_solver(h, rocsolver_dstedc(h->blas, rocblas_evect_tridiagonal, n, w, work, A, n, info),
                         "rocsolver_dstedc"));
     int hinfo = 0;
     GW_HIP(h, hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     GW_HIP(h, hipStreamSynchronize(h->stream));
     if (hinfo != 0) return set_err(h, GW_ENUMERIC, "tridiagonal eigensolver did not converge");
-    if (n > 1)
-        GW_TRY(check_solver(h,
-                            rocsolver_dormtr(h->blas, rocblas_side_left, rocblas_fill_lower,
-                                             rocblas_operation_none, n, n, A, n, tau, Z, n),
-                            "rocsolver_dormtr"));
-    GW_HIP(h, hipMemcpyAsync(A, Z, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, h->stream));
+    if (n > 1) {
+        GW_TRY(apply_q(h, n, Z, tau, A, Vq));
+        hipLaunchKernelGGL(unreverse_kernel, dim3((unsigned)(((long)n * (n / 2) + 255) / 256)), dim3(256), 0,
+                           h->stream, n, A);
+        GW_CHECK_LAUNCH(h);
+    }
     return GW_OK;
 }
 

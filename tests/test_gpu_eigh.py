@@ -106,11 +106,12 @@ def test_degenerate_and_decoupled(handle, kind):
     check(handle, A, vec_tol=1e-12 * max(1.0, np.abs(A).max()) * n, gap_check=kind == "block")
 
 
-def test_upper_triangle_only_read(handle):
-    # the row-major upper triangle defines the matrix: garbage below must not matter
+def test_lower_triangle_only_read(handle):
+    # the row-major lower triangle defines the matrix (LAPACK's UPLO='L' on a
+    # row-major array): garbage above it must not matter
     n = 97
     A = random_sym(n, 3)
-    B = np.triu(A) + np.tril(np.full((n, n), 1e3), -1)
+    B = np.tril(A) + np.triu(np.full((n, n), 1e3), 1)
     w, V = handle.eigh(dev(B))
     assert np.abs(host(w) - np.linalg.eigvalsh(A)).max() <= 50 * n * EPS * np.abs(A).max() * 4
 

@@ -9,8 +9,7 @@
 // A <- A - v w^T - w v^T with w = tau A v + alpha2 v, alpha2 = -tau^2 v^T A v / 2).
 // T's eigenpairs then come from rocSOLVER's divide and conquer (dstedc), and
 // the eigenvectors of A from applying Q to T's, blocked in compact WY form
-// (apply_q: the triangular factor in one small kernel, the three products on
-// rocBLAS dgemm).  The reflectors are kept in LAPACK's layout (lower
+// (apply_q: two rocBLAS dgemm and one dtrsm per block of 64 reflectors).  The reflectors are kept in LAPACK's layout (lower
 // triangle, column-major, v_k below the subdiagonal of column k with its
 // leading 1 implicit, e_k on the subdiagonal).
 //
@@ -26,8 +25,9 @@
 //     halves of the symmetric product) as a partial vector, and its shares of
 //     x^T y and |x|^2 as partial scalars;
 //   * trd_reduce: one work group per row block sums that block's partial
-//     vectors into y (a fixed order), and one more sums the partial scalars
-//     and forms beta, tau and alpha2.
+//     vectors into y (a fixed order, 16 interleaved partial sums per row
+//     meeting in a fixed tree), and one more sums the partial scalars and
+//     forms beta, tau and alpha2.
 // The reflector is never formed before the product: with v = (x - beta e0) s,
 // s = 1/(alpha - beta), one has A22 v = (y - beta a0) s (a0 the first column
 // of A22) and v^T A22 v = (x^T y - 2 beta y_0 + beta^2 a_00) s^2, so the next
@@ -60,17 +60,39 @@ struct TrdWork {
     double* scal;    // [2][8]          beta, tau, s, alpha2, w_k[k+1] of step k, by parity
 };
 
-// y[i] for row i from the partial vectors in one fixed order: four
-// interleaved partial sums (partner blocks kb + g, kb + g + 4, ...), combined
-// as (g0 + g1) + (g2 + g3).  The row blocks and the scalar work group both
-// use it, so y_0 agrees bit for bit.
-__device__ inline double row_partial(const double* part, int nbt, int kb, int i, int g) {
-    const int B = i / TB;
-    const double* pp = part + (long)B * nbt * TB + (i - B * TB);
+constexpr int RT = 1024;  // threads of a reduce work group: 64 rows x 16 groups of partner blocks
+constexpr int RG = RT / TB;
+
+// the partial vectors of row block B summed into y in one fixed order:
+// thread (lane, g) sums partner blocks kb + g, kb + g + 16, ..., then the 16
+// group sums meet in a fixed binary tree.  The row blocks and the scalar
+// work group both use it, so y_0 agrees bit for bit.  Returns y for row
+// B*64 + lane in the threads of group 0; red holds RT doubles of LDS.
+__device__ inline double row_block_y(const double* part, int nbt, int kb, int B, double* red) {
+    const int tid = threadIdx.x, lane = tid & 63, g = tid >> 6;
+    const double* pp = part + (long)B * nbt * TB + lane;
     double y = 0.0;
-#pragma unroll 4
-    for (int J = kb + g; J < nbt; J += 4) y += pp[(long)J * TB];
-    return y;
+    for (int J = kb + g; J < nbt; J += RG) y += pp[(long)J * TB];
+    red[tid] = y;
+    __syncthreads();
+    for (int s = RG / 2; s > 0; s >>= 1) {
+        if (g < s) red[tid] += red[tid + s * TB];
+        __syncthreads();
+    }
+    return red[lane];
+}
+
+// sum over the work group of one value per thread, fixed tree order
+__device__ inline double block_sum(double v, double* red) {
+    const int tid = threadIdx.x;
+    __syncthreads();
+    red[tid] = v;
+    __syncthreads();
+    for (int s = RT / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    return red[0];
 }
 
 // One Householder step (column k) on the lower triangle of the column-major
@@ -208,50 +230,32 @@ __global__ __launch_bounds__(NT) void trd_step_kernel(int n, long lda, int k, in
 
 // Finishes step k: work group 0 forms the reflector's scalars, work group
 // 1 + b sums the partial vectors of row block kb + b into y.
-__global__ __launch_bounds__(NT) void trd_reduce_kernel(int n, long lda, int k, int nbt, const double* A,
+__global__ __launch_bounds__(RT) void trd_reduce_kernel(int n, long lda, int k, int nbt, const double* A,
                                                         double* e, double* tau, TrdWork wk) {
-    __shared__ double red[NT];
+    __shared__ double red[RT];
     const int tid = threadIdx.x;
     const int kb = k / TB, m = nbt - kb;
     if (blockIdx.x > 0) {
-        // thread (row lane, group g)
         const int B = kb + (int)blockIdx.x - 1;
-        const int lane = tid & 63, g = tid >> 6;
-        const int i = B * TB + lane;
-        red[tid] = (i < n) ? row_partial(wk.part, nbt, kb, i, g) : 0.0;
-        __syncthreads();
-        if (tid < TB && i < n)
-            wk.Y[i] = (i > k) ? (red[tid] + red[TB + tid]) + (red[2 * TB + tid] + red[3 * TB + tid]) : 0.0;
+        const double y = row_block_y(wk.part, nbt, kb, B, red);
+        const int i = B * TB + tid;
+        if (tid < TB && i < n) wk.Y[i] = (i > k) ? y : 0.0;
         return;
     }
-    __shared__ double y0p[4];
-    if (tid < 4) y0p[tid] = row_partial(wk.part, nbt, kb, k + 1, tid);
+    // y_0 = y[k+1], summed exactly as its row block sums it
+    const int B1 = (k + 1) / TB;
+    const double y0 = __shfl(row_block_y(wk.part, nbt, kb, B1, red), (k + 1) - B1 * TB);
     double xy = 0.0, s2 = 0.0;
-#pragma unroll 4
-    for (int idx = tid; idx < m * m; idx += NT) {
+    for (int idx = tid; idx < m * m; idx += RT) {
         const int r1 = idx / m, c1 = idx - r1 * m;
         if (c1 <= r1) xy += wk.tsc[(long)(kb + r1) * nbt + kb + c1];
     }
-    for (int B = kb + tid; B < nbt; B += NT) s2 += wk.s2p[B];
-    red[tid] = xy;
-    __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
-        __syncthreads();
-    }
-    xy = red[0];
-    __syncthreads();
-    red[tid] = s2;
-    __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
-        __syncthreads();
-    }
-    s2 = red[0];
+    for (int B = kb + tid; B < nbt; B += RT) s2 += wk.s2p[B];
+    xy = block_sum(xy, red);
+    s2 = block_sum(s2, red);
     if (tid != 0) return;
     const double alpha = wk.X[(k & 1) * n + k + 1];
     const double a00 = A[(long)(k + 1) * lda + k + 1];
-    const double y0 = (y0p[0] + y0p[1]) + (y0p[2] + y0p[3]);
     double beta = alpha, tk = 0.0, sk = 0.0, a2 = 0.0;
     if (s2 > 0.0) {
         beta = -copysign(sqrt(alpha * alpha + s2), alpha);
@@ -301,47 +305,41 @@ __global__ void unreverse_kernel(int n, double* __restrict__ V) {
 // Back-transformation C <- Q C, Q = H_0 H_1 ... H_{n-2} (the reflectors of
 // the reduction), in blocks of QB reflectors applied last block first: the
 // block H_k0 ... H_k1-1 is I - V T V^T with V the block's reflectors (unit
-// entry explicit, rows k0+1 .. n-1) and T upper triangular (T_cc = tau_c,
-// T[0:c, c] = -tau_c T[0:c, 0:c] V[:, 0:c]^T v_c), and
-// C[k0+1:, :] -= V (T (V^T C[k0+1:, :])) is three GEMMs.
+// entry explicit, rows k0+1 .. n-1), and T's inverse is the upper triangular
+// S = diag(1/tau) + strictly_upper(V^T V) (the UT transform of Joffrain,
+// Low, Quintana-Orti, van de Geijn and Van Zee), so
+// C[k0+1:, :] -= V (S \ (V^T C[k0+1:, :])) is two GEMMs and one triangular
+// solve.  A reflector with tau = 0 is the identity: its column of V is zero
+// and its diagonal entry of S is 1.
 constexpr int QB = 64;
 
 // V [nr][bj] column-major (ld nr), rows k0+1 .. n-1: column c is reflector
 // k = k0 + c, zero above row k+1, one at row k+1, the stored v below.
-__global__ void build_v_kernel(int n, int k0, int bj, const double* __restrict__ Zr, double* __restrict__ V) {
+__global__ void build_v_kernel(int n, int k0, int bj, const double* __restrict__ Zr, const double* __restrict__ tau,
+                               double* __restrict__ V) {
     const int nr = n - k0 - 1;
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)nr * bj) return;
     const int c = (int)(idx / nr), r = (int)(idx - (long)c * nr);
     const int i = k0 + 1 + r, k = k0 + c;
     double x = 0.0;
-    if (i == k + 1) x = 1.0;
-    else if (i > k + 1) x = Zr[(long)k * n + i];
+    if (tau[k] != 0.0) {
+        if (i == k + 1) x = 1.0;
+        else if (i > k + 1) x = Zr[(long)k * n + i];
+    }
     V[idx] = x;
 }
 
-// T [bj][bj] column-major from G = V^T V and tau (one work group)
-__global__ __launch_bounds__(256) void larft_kernel(int bj, const double* __restrict__ G,
-                                                    const double* __restrict__ tau, double* __restrict__ T) {
-    __shared__ double sT[QB][QB + 1];
-    __shared__ double sg[QB];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < QB * QB; e += 256) sT[e % QB][e / QB] = 0.0;
-    __syncthreads();
-    for (int c = 0; c < bj; ++c) {
-        const double tc = tau[c];
-        if (tid < c) sg[tid] = G[(long)c * bj + tid];  // (V^T v_c)[r], r < c
-        __syncthreads();
-        if (tid < c) {
-            // row r of T[0:c, 0:c] times g: T is upper triangular
-            double acc = 0.0;
-            for (int q = tid; q < c; ++q) acc += sT[tid][q] * sg[q];
-            sT[tid][c] = -tc * acc;
-        }
-        if (tid == 0) sT[c][c] = tc;
-        __syncthreads();
-    }
-    for (int e = tid; e < bj * bj; e += 256) T[e] = sT[e % bj][e / bj];
+// S [bj][bj] column-major from G = V^T V and tau
+__global__ void ut_factor_kernel(int bj, const double* __restrict__ G, const double* __restrict__ tau,
+                                 double* __restrict__ S) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= bj * bj) return;
+    const int c = idx / bj, r = idx - c * bj;
+    double x = 0.0;
+    if (r < c) x = G[idx];
+    else if (r == c) x = tau[c] != 0.0 ? 1.0 / tau[c] : 1.0;
+    S[idx] = x;
 }
 
 gw_status check_solver(Handle* h, rocblas_status st, const char* what) {
@@ -355,7 +353,7 @@ gw_status check_solver(Handle* h, rocblas_status st, const char* what) {
 size_t syev_tridiag_bytes(int n) {
     const long nbt = (n + TB - 1) / TB;
     const long doubles = 3L * n + nbt * nbt * TB + nbt * nbt + nbt + 16 + (long)n + (long)n * n +
-                         (long)n * QB + 2L * QB * QB + 2L * QB * n;
+                         (long)n * QB + 2L * QB * QB + (long)QB * n;
     return sizeof(double) * (size_t)doubles;
 }
 
@@ -363,21 +361,21 @@ namespace {
 
 gw_status apply_q(Handle* h, int n, const double* Zr, const double* tau, double* C, double* V) {
     double* G = V + (long)n * QB;
-    double* T = G + QB * QB;
-    double* W1 = T + QB * QB;
-    double* W2 = W1 + (long)QB * n;
+    double* S = G + QB * QB;
+    double* W1 = S + QB * QB;
     const double one = 1.0, zero = 0.0, mone = -1.0;
     const int nref = n - 1;
     for (int k0 = ((nref - 1) / QB) * QB; k0 >= 0; k0 -= QB) {
         const int bj = std::min(QB, nref - k0), nr = n - k0 - 1;
         hipLaunchKernelGGL(build_v_kernel, dim3((unsigned)(((long)nr * bj + 255) / 256)), dim3(256), 0, h->stream, n,
-                           k0, bj, Zr, V);
+                           k0, bj, Zr, tau, V);
         GW_CHECK_LAUNCH(h);
         GW_TRY(check_solver(h,
                             rocblas_dgemm(h->blas, rocblas_operation_transpose, rocblas_operation_none, bj, bj, nr,
                                           &one, V, nr, V, nr, &zero, G, bj),
                             "rocblas_dgemm"));
-        hipLaunchKernelGGL(larft_kernel, dim3(1), dim3(256), 0, h->stream, bj, G, tau + k0, T);
+        hipLaunchKernelGGL(ut_factor_kernel, dim3((unsigned)((bj * bj + 255) / 256)), dim3(256), 0, h->stream, bj, G,
+                           tau + k0, S);
         GW_CHECK_LAUNCH(h);
         double* Cs = C + k0 + 1;  // rows k0+1 .. n-1, ld n
         GW_TRY(check_solver(h,
@@ -385,12 +383,12 @@ gw_status apply_q(Handle* h, int n, const double* Zr, const double* tau, double*
                                           &one, V, nr, Cs, n, &zero, W1, bj),
                             "rocblas_dgemm"));
         GW_TRY(check_solver(h,
-                            rocblas_dgemm(h->blas, rocblas_operation_none, rocblas_operation_none, bj, n, bj, &one, T,
-                                          bj, W1, bj, &zero, W2, bj),
-                            "rocblas_dgemm"));
+                            rocblas_dtrsm(h->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                                          rocblas_diagonal_non_unit, bj, n, &one, S, bj, W1, bj),
+                            "rocblas_dtrsm"));
         GW_TRY(check_solver(h,
                             rocblas_dgemm(h->blas, rocblas_operation_none, rocblas_operation_none, nr, n, bj, &mone, V,
-                                          nr, W2, bj, &one, Cs, n),
+                                          nr, W1, bj, &one, Cs, n),
                             "rocblas_dgemm"));
     }
     return GW_OK;
@@ -420,7 +418,7 @@ gw_status syev_tridiag(Handle* h, int n, double* A, double* w, double* work, int
                            w, wk);
         GW_CHECK_LAUNCH(h);
         if (k + 1 < n) {
-            hipLaunchKernelGGL(trd_reduce_kernel, dim3(m + 1), dim3(NT), 0, h->stream, n, (long)n, k, nbt, Z, work,
+            hipLaunchKernelGGL(trd_reduce_kernel, dim3(m + 1), dim3(RT), 0, h->stream, n, (long)n, k, nbt, Z, work,
                                tau, wk);
             GW_CHECK_LAUNCH(h);
         }

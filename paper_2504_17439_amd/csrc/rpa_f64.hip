@@ -142,7 +142,8 @@ gw_status batched_sym(Handle* h, int naux, long ov, int batch, const double* V, 
 }  // namespace
 
 static gw_status rpa_eta0_f64(Handle* h, int nocc, int nvir, int naux, const double* eps,
-                              const double* V, const double* D, const gw_opts* opts, double* eta0) {
+                              const double* V, const double* D, const gw_opts* opts, double* eta0,
+                              bool digit_nodes) {
     const long ov = (long)nocc * nvir;
     const int nmo = nocc + nvir;
     const long n2 = (long)naux * naux;
@@ -227,7 +228,8 @@ static gw_status rpa_eta0_f64(Handle* h, int nocc, int nvir, int naux, const dou
     }
     // G = V o D + sum_b S_b (V o g_b): one launch over all nodes, the node
     // index innermost in K so that each V slab is loaded once for all nodes
-    GW_TRY(node_sum_f64(h, naux, ov, 2 * nq, QT, V, bs, V, D, G, Scratch{WS_RPA_PART}));
+    if (digit_nodes) GW_TRY(node_sum_mixed(h, naux, ov, 2 * nq, QT, V, bs, D, G));
+    else GW_TRY(node_sum_f64(h, naux, ov, 2 * nq, QT, V, bs, V, D, G, Scratch{WS_RPA_PART}));
     // Woodbury: Hm = (G o D^-1) V^T, Pm = I + 4 (V o D^-1) V^T, Y = Hm Pm^-1,
     // eta~0 = D^-1 o (G - 4 Y V)
     double* Dinv = as;  // the quadrature scale tables are no longer needed
@@ -277,8 +279,8 @@ static gw_status rpa_eta0_f64(Handle* h, int nocc, int nvir, int naux, const dou
 }
 
 gw_status rpa_eta0(Handle* h, int nocc, int nvir, int naux, const double* eps, const double* V, const double* D,
-                   const gw_opts* opts, double* eta0) {
-    return rpa_eta0_f64(h, nocc, nvir, naux, eps, V, D, opts, eta0);
+                   const gw_opts* opts, double* eta0, bool digit_nodes) {
+    return rpa_eta0_f64(h, nocc, nvir, naux, eps, V, D, opts, eta0, digit_nodes);
 }
 
 gw_status rpa_moments_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
@@ -300,7 +302,7 @@ gw_status rpa_moments_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max,
         chain[1] = (double*)ws_get(h, WS_X1, sizeof(double) * xsz);
         if (!chain[0] || !chain[1]) return GW_ENOMEM;
     }
-    GW_TRY(rpa_eta0_f64(h, nocc, nvir, naux, eps, V, D, opts, chain[0]));
+    GW_TRY(rpa_eta0_f64(h, nocc, nvir, naux, eps, V, D, opts, chain[0], false));
     hipLaunchKernelGGL(scale_cols_kernel, dim3((unsigned)((xsz + 255) / 256)), dim3(256), 0, h->stream,
                        (long)naux, ov, V, D, chain[1]);
     GW_CHECK_LAUNCH(h);

@@ -924,6 +924,7 @@ struct DgemmArgs {
     const double* Xin;
     const double* Dv;
     double alpha;
+    const double* Cs;  // per-column scale of the product in the Xout epilogue (nullptr: 1)
 };
 
 // W4: also keep the weight-4 products d2 x d2, d1 x d3 and d3 x d1 (a fifth
@@ -1026,12 +1027,13 @@ __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int spl
     // store: the stores could alias those arrays as far as the compiler
     // knows, so interleaved loads would each wait for a memory round trip.
     int ec[2], er[4][4];
-    double dv[2], xin[2][4][4];
+    double dv[2], cs[2], xin[2][4][4];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int col = min(n0 + wn + j * 16 + lr, g.N - 1);
         ec[j] = g.eB[col];
         dv[j] = g.Xout ? g.Dv[col] : 0.0;
+        cs[j] = g.Cs ? g.Cs[col] : 1.0;
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -1064,7 +1066,7 @@ __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int spl
                 for (int w = NW - 1; w >= 0; --w) z += (double)acc[w][i][j][r] * wscale(w);
                 const double c = ldexp(z, er[i][r] + ec[j] + g.eshift);
                 const long o = (long)row * g.N + col;
-                if (g.Xout) g.Xout[o] = dv[j] * xin[j][i][r] + g.alpha * c;
+                if (g.Xout) g.Xout[o] = dv[j] * xin[j][i][r] + g.alpha * (cs[j] * c);
                 else g.part[(long)split * g.M * g.N + o] = c;
             }
     }
@@ -1409,6 +1411,42 @@ gw_status tda_moments_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_ma
 // both products as int8 digit GEMMs: R_n on the upper tiles (thirteen digit
 // products, mirrored, as the FP64 form), the update with the row digits of R_n
 // against the digits of V o D transposed (k = P) and the D^2 / 4 epilogue.
+gw_status node_sum_mixed(Handle* h, int naux, long ov, int nb, const double* S, const double* V,
+                         const double* gtab, const double* d0, double* G) {
+    if (naux <= 0 || ov <= 0 || nb <= 0) return GW_OK;
+    const int Ap = mixed_Ap(naux);
+    if (ov * 64 >= (1L << 31) || Ap > KEXACT)
+        return set_err(h, GW_EINVAL, "mixed precision: RPA quadrature too large for the digit node sum");
+    const long n2 = (long)naux * naux;
+    i8* Vlt = (i8*)ws_get(h, WS_RPA_VLT, sizeof(i8) * ND * ov * Ap);
+    i8* Sd = (i8*)ws_get(h, WS_RPA_SD, sizeof(i8) * ND * (long)naux * Ap + sizeof(double) * (ov + 1));
+    int* ex = (int*)ws_get(h, WS_RPA_EX, sizeof(int) * (ov + naux));
+    if (!Vlt || !Sd || !ex) return GW_ENOMEM;
+    double* ones = (double*)(Sd + ND * (long)naux * Ap);
+    int* eV = ex;
+    int* eS = ex + ov;
+    KTimer tm(h, "rpa_quad");
+    // B operand: V's digit planes transposed (k = Q, one scale per column ia)
+    hipLaunchKernelGGL(col_exp_kernel, dim3(nb256(ov)), dim3(256), 0, h->stream, naux, ov, V, eV);
+    hipLaunchKernelGGL(digits_lt_kernel, dim3((unsigned)((ov + 31) / 32), (unsigned)((Ap + 31) / 32)), dim3(256), 0,
+                       h->stream, naux, ov, Ap, V, eV, Vlt);
+    GW_CHECK_LAUNCH(h);
+    GW_TRY(fill_f64(h, ones, (size_t)ov, 1.0));
+    for (int b = 0; b < nb; ++b) {
+        GW_TRY(digitise_rows(h, naux, naux, Ap, S + b * n2, eS, Sd));
+        DgemmArgs u{};
+        u.A = Sd; u.aplane = (long)naux * Ap; u.arows = naux; u.eA = eS;
+        u.B = Vlt; u.bplane = ov * Ap; u.brows = (int)ov; u.eB = eV;
+        u.M = naux; u.N = (int)ov; u.nkb = Ap / MK; u.nsplit = 1; u.sym = 0;
+        // G = V o d0 + g_0 o (S_0 V), then G += g_b o (S_b V)
+        u.Xout = G; u.Xin = b == 0 ? V : G; u.Dv = b == 0 ? d0 : ones;
+        u.alpha = 1.0; u.Cs = gtab + (long)b * ov;
+        GW_TRY(launch_dgemm(h, u, nullptr));
+    }
+    tm.stop();
+    return GW_OK;
+}
+
 gw_status rpa_moments_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
                             const double* L, const gw_opts* opts, double* R) {
     const long ov = (long)nocc * nvir;
@@ -1438,7 +1476,7 @@ gw_status rpa_moments_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_ma
     if (!V || !D || !X[0] || !X[1] || !VDt || !Xd || !Vd || !Rk || !ex || !D2 || !part) return GW_ENOMEM;
     int *eVDt = ex, *eX = ex + ov, *eV = eX + naux, *eR = eV + naux;
     GW_TRY(gather_ov(h, nocc, nvir, naux, eps, L, V, D));
-    GW_TRY(rpa_eta0(h, nocc, nvir, naux, eps, V, D, opts, X[0]));
+    GW_TRY(rpa_eta0(h, nocc, nvir, naux, eps, V, D, opts, X[0], true));
     hipLaunchKernelGGL(rpa_prep_kernel, dim3(nb256(xsz)), dim3(256), 0, h->stream, (long)naux, ov, V, D, X[1], D2);
     GW_CHECK_LAUNCH(h);
     {

@@ -55,7 +55,7 @@ enum WsSlot {
     WS_MIX0, WS_MIX1, WS_MIX2, WS_MIX3, WS_MIX4, WS_MIX5, WS_MIX6,
     WS_FS0, WS_FS1, WS_FS2, WS_FS3, WS_FS4, WS_FS5, WS_FS6, WS_FS7,
     WS_RC0, WS_RC1, WS_RC2, WS_RC3, WS_RC4, WS_RC5,
-    WS_KPART, WS_RPA_PART, WS_POLE_TMP, WS_EIG, WS_RPA_VLT, WS_RPA_SD, WS_RPA_EX,
+    WS_KPART, WS_RPA_PART, WS_POLE_TMP, WS_EIG, WS_RPA_VLT, WS_RPA_SD, WS_RPA_EX, WS_RPA_AD, WS_RPA_QP,
     WS_COUNT
 };
 
@@ -228,10 +228,17 @@ gw_status rpa_moments_f64(Handle* h, int nocc, int nvir, int naux, int nmom_max,
                           double* R, double* eta);
 
 // eta~^{(0)} [naux][nocc*nvir] of RPA screening by the quadrature (Sec. 2.2),
-// from the gathered V [naux][ov] and D [ov].  With digit_nodes the node sum
-// runs as int8 digit products (node_sum_mixed); everything else is FP64.
+// from the gathered V [naux][ov] and D [ov].  With digit_nodes the node
+// products and the node sum run as int8 digit products
+// (node_products_mixed, node_sum_mixed); everything else is FP64.
 gw_status rpa_eta0(Handle* h, int nocc, int nvir, int naux, const double* eps, const double* V, const double* D,
                    const gw_opts* opts, double* eta0, bool digit_nodes = false);
+
+// Q[b] = V diag(as[b]) V^T for b < nb (V [naux][ov], as [nb][ov], Q [nb][naux][naux],
+// both triangles) as symmetric int8 digit products: V's row digits once,
+// V o as[b] digitised per node, split-k partials reduced in a fixed order.
+gw_status node_products_mixed(Handle* h, int naux, long ov, int nb, const double* V, const double* as,
+                              double* Q);
 
 // As node_sum_f64 with X0 = V, in int8 digit products: V digitised once
 // (per-column scales), each S[b] by rows, one digit GEMM per node whose

@@ -197,7 +197,8 @@ static gw_status rpa_eta0_f64(Handle* h, int nocc, int nvir, int naux, const dou
         GW_CHECK_LAUNCH(h);
     }
     // Q_j (b < nq) and T_j (b >= nq) in one batched symmetric product
-    GW_TRY(batched_sym(h, naux, ov, 2 * nq, V, as, 1.0, 0.0, QT));
+    if (digit_nodes) GW_TRY(node_products_mixed(h, naux, ov, 2 * nq, V, as, QT));
+    else GW_TRY(batched_sym(h, naux, ov, 2 * nq, V, as, 1.0, 0.0, QT));
     // (I + Q_j)^-1 by batched Cholesky
     GW_TRY(copy_f64(h, Minv, QT, (size_t)nq * n2));
     {

@@ -1411,6 +1411,49 @@ gw_status tda_moments_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_ma
 // both products as int8 digit GEMMs: R_n on the upper tiles (thirteen digit
 // products, mirrored, as the FP64 form), the update with the row digits of R_n
 // against the digits of V o D transposed (k = P) and the D^2 / 4 epilogue.
+gw_status node_products_mixed(Handle* h, int naux, long ov, int nb, const double* V, const double* as,
+                              double* Q) {
+    if (naux <= 0 || nb <= 0) return GW_OK;
+    const int Kp = (int)((ov + MK - 1) / MK * MK);
+    if (ov * 64 >= (1L << 31) || (long)naux * 64 >= (1L << 31))
+        return set_err(h, GW_EINVAL, "mixed precision: RPA quadrature too large for the digit node products");
+    const long n2 = (long)naux * naux;
+    i8* Vd = (i8*)ws_get(h, WS_RPA_AD, sizeof(i8) * 2 * ND * (long)naux * Kp);
+    int* ex = (int*)ws_get(h, WS_RPA_EX, sizeof(int) * (ov + 2L * naux));
+    if (!Vd || !ex) return GW_ENOMEM;
+    i8* Ad = Vd + ND * (long)naux * Kp;
+    int* eV = ex;
+    int* eA = ex + naux;
+    int ncu = 256;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device);
+    const int tiles = mixed_upper_tiles(naux);
+    const int nkb = Kp / MK;
+    const int S = std::max((nkb + KEXACT / MK - 1) / (KEXACT / MK),
+                           std::max(1, std::min(nkb, (3 * ncu + tiles - 1) / tiles)));
+    double* part = (double*)ws_get(h, WS_RPA_QP, sizeof(double) * S * n2);
+    if (!part) return GW_ENOMEM;
+    KTimer tm(h, "rpa_quad");
+    GW_TRY(digitise_rows(h, naux, ov, Kp, V, eV, Vd));
+    for (int b = 0; b < nb; ++b) {
+        // digits of V o as[b] by rows (k = ia)
+        hipLaunchKernelGGL(digitise_rows_kernel, dim3((unsigned)naux), dim3(256), 0, h->stream, (long)naux, (int)ov,
+                           Kp, V, as + (long)b * ov, eA, Ad, (const double*)nullptr, (int*)nullptr, (i8*)nullptr);
+        GW_CHECK_LAUNCH(h);
+        DgemmArgs g{};
+        g.M = g.N = naux;
+        g.nkb = nkb;
+        g.nsplit = S;
+        g.sym = 1;
+        g.part = part;
+        g.A = Ad; g.aplane = (long)naux * Kp; g.arows = naux; g.eA = eA;
+        g.B = Vd; g.bplane = (long)naux * Kp; g.brows = naux; g.eB = eV;
+        GW_TRY(launch_dgemm(h, g, nullptr));
+        GW_TRY(reduce_splits(h, part, S, n2, 1, naux, naux, naux, true, 1.0, 0.0, Q + b * n2, n2, naux));
+    }
+    tm.stop();
+    return GW_OK;
+}
+
 gw_status node_sum_mixed(Handle* h, int naux, long ov, int nb, const double* S, const double* V,
                          const double* gtab, const double* d0, double* G) {
     if (naux <= 0 || ov <= 0 || nb <= 0) return GW_OK;

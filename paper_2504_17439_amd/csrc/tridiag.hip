@@ -3,13 +3,17 @@
 // Lanczos blocks (their square roots and pseudo-inverses) and of the upfolded
 // Hamiltonian H~ (Sec. 2.4) all come from here.
 //
-// A = Q T Q^T is reached by Householder reflectors, one column at a time, in
-// the classical unblocked order (reflector k annihilates column k below the
-// subdiagonal; the trailing matrix takes the symmetric rank-2 update
-// A <- A - v w^T - w v^T with w = tau A v + alpha2 v, alpha2 = -tau^2 v^T A v / 2).
-// T's eigenpairs then come from rocSOLVER's divide and conquer (dstedc), and
-// the eigenvectors of A from applying Q to T's, blocked in compact WY form
-// (apply_q: two rocBLAS dgemm and one dtrsm per block of 64 reflectors).  The reflectors are kept in LAPACK's layout (lower
+// The input is defined by the lower triangle of its row-major view, and the
+// reduction works on B = J A J (J the index reversal; reverse_kernel), i.e.
+// from the far end of the orbital order.  B = Q T Q^T is reached by
+// Householder reflectors, one column at a time, in the classical unblocked
+// order (reflector k annihilates column k below the subdiagonal; the
+// trailing matrix takes the symmetric rank-2 update A <- A - v w^T - w v^T
+// with w = tau A v + alpha2 v, alpha2 = -tau^2 v^T A v / 2).  T's eigenpairs
+// then come from rocSOLVER's divide and conquer (dstedc), B's eigenvectors
+// from applying Q to T's, blocked in compact WY form (apply_q: two rocBLAS
+// dgemm and one dtrsm per block of 64 reflectors), and A's from reversing
+// their components.  The reflectors are kept in LAPACK's layout (lower
 // triangle, column-major, v_k below the subdiagonal of column k with its
 // leading 1 implicit, e_k on the subdiagonal).
 //
@@ -66,8 +70,8 @@ constexpr int RG = RT / TB;
 // the partial vectors of row block B summed into y in one fixed order:
 // thread (lane, g) sums partner blocks kb + g, kb + g + 16, ..., then the 16
 // group sums meet in a fixed binary tree.  The row blocks and the scalar
-// work group both use it, so y_0 agrees bit for bit.  Returns y for row
-// B*64 + lane in the threads of group 0; red holds RT doubles of LDS.
+// work group both use it, so y_0 agrees bit for bit.  Every thread gets y of
+// row B*64 + (its lane); red holds RT doubles of LDS.
 __device__ inline double row_block_y(const double* part, int nbt, int kb, int B, double* red) {
     const int tid = threadIdx.x, lane = tid & 63, g = tid >> 6;
     const double* pp = part + (long)B * nbt * TB + lane;
@@ -408,7 +412,7 @@ gw_status syev_tridiag(Handle* h, int n, double* A, double* w, double* work, int
     double* tau = wk.scal + 16;
     double* Z = tau + n;
     double* Vq = Z + (long)n * n;
-    // B = J A J into Z; A = Q T Q^T of B: d -> w, e -> work, reflectors -> lower triangle of Z
+    // B = J A J into Z; B = Q T Q^T: d -> w, e -> work, reflectors -> lower triangle of Z
     hipLaunchKernelGGL(reverse_kernel, dim3((unsigned)(((long)n * n + 255) / 256)), dim3(256), 0, h->stream, n, A,
                        Z);
     GW_CHECK_LAUNCH(h);

@@ -178,6 +178,163 @@ __global__ void digits_lt_kernel(int naux, long ncol, int Ap, const double* __re
     }
 }
 
+// The row digitisation above with one read of X: the row (at most 8192 * NPR
+// columns) stays in registers between the maxima and the digits, 1024 threads
+// per row, 8 consecutive columns per thread and 8192-column pass.  X is scaled
+// by cs when it is set; with HASY the same read also gives the planes of
+// X o D (D = d2[c], exponents e2; cs is then unset), d2 reloaded per pass;
+// with HASY the passes are kept apart by compiler barriers, so that the loads
+// of later passes do not compete with the row for registers.
+template <int NPR, bool HASY>
+__global__ __launch_bounds__(1024) void digitise_rows_reg_kernel(long rows, int cols, int kpad,
+                                                                 const double* __restrict__ X,
+                                                                 const double* __restrict__ cs, int* __restrict__ e,
+                                                                 i8* __restrict__ Xd, const double* __restrict__ d2,
+                                                                 int* __restrict__ e2, i8* __restrict__ Yd) {
+    const long row = blockIdx.x;
+    const int t = threadIdx.x;
+    const double* __restrict__ x = X + row * cols;
+    // passes past NR live in LDS (64 KB each): with HASY and five or more
+    // passes the row, d2 and the digits together would not fit in registers
+    constexpr int NR = (HASY && NPR >= 5) ? 4 : NPR;
+    __shared__ double red[2][16];
+    __shared__ double vl[NPR > NR ? (NPR - NR) * 8192 : 1];
+    double v[NPR][8];
+    double m = 0.0, m2 = 0.0;
+#pragma unroll
+    for (int p = 0; p < NPR; ++p) {
+        // with HASY one pass at a time (loads not hoisted across passes)
+        if (HASY) asm volatile("" ::: "memory");
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int c = p * 8192 + t * 8 + u;
+            const double a = c < cols ? x[c] * (cs ? cs[c] : 1.0) : 0.0;
+            if (p < NR) v[p][u] = a;
+            else vl[(p - NR) * 8192 + t * 8 + u] = a;
+            m = fmax(m, fabs(a));
+            if (HASY && c < cols) m2 = fmax(m2, fabs(a * d2[c]));
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        m = fmax(m, __shfl_xor(m, o));
+        if (HASY) m2 = fmax(m2, __shfl_xor(m2, o));
+    }
+    if ((t & 63) == 0) {
+        red[0][t >> 6] = m;
+        red[1][t >> 6] = m2;
+    }
+    __syncthreads();
+    m = red[0][0];
+    m2 = red[1][0];
+#pragma unroll
+    for (int w = 1; w < 16; ++w) {
+        m = fmax(m, red[0][w]);
+        m2 = fmax(m2, red[1][w]);
+    }
+    const int ex = scale_exp(m);
+    const int ex2 = scale_exp(m2);
+    if (t == 0) {
+        e[row] = ex;
+        if (HASY) e2[row] = ex2;
+    }
+    const long plane = rows * (long)kpad;
+#pragma unroll
+    for (int p = 0; p < NPR; ++p) {
+        const int c0 = p * 8192 + t * 8;
+        if (c0 >= kpad) break;
+        if (HASY) asm volatile("" ::: "memory");
+        if (p >= NR)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[p][u] = vl[(p - NR) * 8192 + t * 8 + u];
+        const long o = ((long)(c0 >> 6) * rows + row) * 64 + (c0 & 63);
+        i8 dg[ND][8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            i8 q[ND];
+            digitsN(v[p][u], ex, q);
+#pragma unroll
+            for (int d = 0; d < ND; ++d) dg[d][u] = q[d];
+        }
+#pragma unroll
+        for (int d = 0; d < ND; ++d) *(uint2*)(Xd + d * plane + o) = make_uint2(pack4(dg[d]), pack4(dg[d] + 4));
+        if (HASY) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                i8 q[ND];
+                digitsN(c0 + u < cols ? v[p][u] * d2[c0 + u] : 0.0, ex2, q);
+#pragma unroll
+                for (int d = 0; d < ND; ++d) dg[d][u] = q[d];
+            }
+#pragma unroll
+            for (int d = 0; d < ND; ++d) *(uint2*)(Yd + d * plane + o) = make_uint2(pack4(dg[d]), pack4(dg[d] + 4));
+        }
+    }
+}
+
+// col_exp_kernel and digits_lt_kernel in one read of X[naux][ncol]: 16 columns
+// per work group of 512 threads, kept in registers (4 consecutive rows per
+// thread and 128-row pass, NP passes: naux <= Ap <= 128 NP), the column maxima
+// by shuffles and LDS; the digits then go through LDS so that every plane is
+// written in 16-byte stores of whole 64-byte k rows (1 KB of contiguous
+// memory per wave).
+template <int NP>
+__global__ __launch_bounds__(512) void digits_cols_kernel(int naux, long ncol, int Ap,
+                                                             const double* __restrict__ X, int* __restrict__ e,
+                                                             i8* __restrict__ Xd) {
+    constexpr int JS = 128 * NP + 16;  // LDS bytes per column of one plane (the 16 spread the banks)
+    __shared__ double red[8][16];
+    __shared__ __attribute__((aligned(16))) unsigned char dl[ND * 16 * JS];
+    const int t = threadIdx.x;
+    const int jj = t & 15, qr = t >> 4;
+    const long j0 = (long)blockIdx.x * 16;
+    const long j = j0 + jj;
+    const bool jok = j < ncol;
+    double v[NP][4];
+    double m = 0.0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int Q = 128 * i + 4 * qr + r;
+            v[i][r] = (jok && Q < naux) ? X[(long)Q * ncol + j] : 0.0;
+            m = fmax(m, fabs(v[i][r]));
+        }
+    // the four lanes of a wave on one column, then the eight waves
+    m = fmax(m, __shfl_xor(m, 16));
+    m = fmax(m, __shfl_xor(m, 32));
+    if ((t & 63) < 16) red[t >> 6][jj] = m;
+    __syncthreads();
+    m = red[0][jj];
+#pragma unroll
+    for (int w = 1; w < 8; ++w) m = fmax(m, red[w][jj]);
+    const int ex = scale_exp(m);
+    if (qr == 0 && jok) e[j] = ex;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        i8 dg[ND][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            i8 q[ND];
+            digitsN(v[i][r], ex, q);
+#pragma unroll
+            for (int d = 0; d < ND; ++d) dg[d][r] = q[d];
+        }
+#pragma unroll
+        for (int d = 0; d < ND; ++d) *(unsigned*)(dl + (d * 16 + jj) * JS + 128 * i + 4 * qr) = pack4(dg[d]);
+    }
+    __syncthreads();
+    const int nkb = Ap / 64;
+    const long plane = ncol * (long)Ap;
+    // 16-byte chunk c of k block kb of column cj, plane d
+    for (int idx = t; idx < ND * nkb * 64; idx += 512) {
+        const int c = idx & 3, cj = (idx >> 2) & 15, rest = idx >> 6;
+        const int kb = rest % nkb, d = rest / nkb;
+        if (j0 + cj >= ncol) continue;
+        const uint4 val = *(const uint4*)(dl + (d * 16 + cj) * JS + kb * 64 + c * 16);
+        *(uint4*)(Xd + d * plane + ((long)kb * ncol + j0 + cj) * 64 + c * 16) = val;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Stage 1: R_t . L for all t of a 16(P) x 128(j) tile, fold, FP32 + BF16-residual output
 // ---------------------------------------------------------------------------
@@ -1102,6 +1259,68 @@ void launch_fold_mixed(Handle* h, const FoldJob& g) {
 
 unsigned nb256(long n) { return (unsigned)((n + 255) / 256); }
 
+// Row exponents and k-blocked digit planes of X[rows][cols] (times cs), and
+// with Yd set also those of X o D (D = d2[c], exponents e2): rows of up to
+// 49152 columns in one read (up to 40960 with Yd, else a second read with d2
+// as the column scale), shorter and longer rows by the two-pass kernel.
+void launch_digitise_rows(Handle* h, long rows, int cols, int kpad, const double* X, const double* cs, int* e,
+                          i8* Xd, const double* d2 = nullptr, int* e2 = nullptr, i8* Yd = nullptr) {
+    const int npr = (kpad + 8191) / 8192;
+    if (cols < 4096 || npr > 6) {
+        hipLaunchKernelGGL(digitise_rows_kernel, dim3((unsigned)rows), dim3(256), 0, h->stream, rows, cols, kpad, X,
+                           cs, e, Xd, d2, e2, Yd);
+        return;
+    }
+    const dim3 g((unsigned)rows), b(1024);
+#define GW_ROWREG(N, Y, S, E, D, D2, E2, YD)                                                                    \
+    case N:                                                                                                     \
+        hipLaunchKernelGGL((digitise_rows_reg_kernel<N, Y>), g, b, 0, h->stream, rows, cols, kpad, X, S, E, D, \
+                           D2, E2, YD);                                                                         \
+        break;
+    if (Yd && npr <= 5) {
+        switch (npr) {
+            GW_ROWREG(1, true, nullptr, e, Xd, d2, e2, Yd)
+            GW_ROWREG(2, true, nullptr, e, Xd, d2, e2, Yd)
+            GW_ROWREG(3, true, nullptr, e, Xd, d2, e2, Yd)
+            GW_ROWREG(4, true, nullptr, e, Xd, d2, e2, Yd)
+            default: GW_ROWREG(5, true, nullptr, e, Xd, d2, e2, Yd)
+        }
+        return;
+    }
+    // X (times cs), then for six passes with Yd the planes of X o D as a
+    // second read with d2 as the column scale
+    for (int pass = 0; pass < (Yd ? 2 : 1); ++pass) {
+        const double* sc = pass ? d2 : cs;
+        int* ee = pass ? e2 : e;
+        i8* dd = pass ? Yd : Xd;
+        switch (npr) {
+            GW_ROWREG(1, false, sc, ee, dd, nullptr, nullptr, nullptr)
+            GW_ROWREG(2, false, sc, ee, dd, nullptr, nullptr, nullptr)
+            GW_ROWREG(3, false, sc, ee, dd, nullptr, nullptr, nullptr)
+            GW_ROWREG(4, false, sc, ee, dd, nullptr, nullptr, nullptr)
+            GW_ROWREG(5, false, sc, ee, dd, nullptr, nullptr, nullptr)
+            default: GW_ROWREG(6, false, sc, ee, dd, nullptr, nullptr, nullptr)
+        }
+    }
+#undef GW_ROWREG
+}
+
+// Column exponents and transposed k-blocked digit planes of X[naux][ncol]
+// (k = the row index, zero-padded to Ap): one read for Ap <= 2048, else the
+// exponent pass followed by the LDS-transposing digit pass.
+void launch_digitise_cols(Handle* h, int naux, long ncol, int Ap, const double* X, int* e, i8* Xd) {
+    const dim3 g((unsigned)((ncol + 15) / 16)), b(512);
+    if (Ap <= 512) hipLaunchKernelGGL(digits_cols_kernel<4>, g, b, 0, h->stream, naux, ncol, Ap, X, e, Xd);
+    else if (Ap <= 1024) hipLaunchKernelGGL(digits_cols_kernel<8>, g, b, 0, h->stream, naux, ncol, Ap, X, e, Xd);
+    else if (Ap <= 1536) hipLaunchKernelGGL(digits_cols_kernel<12>, g, b, 0, h->stream, naux, ncol, Ap, X, e, Xd);
+    else if (Ap <= 2048) hipLaunchKernelGGL(digits_cols_kernel<16>, g, b, 0, h->stream, naux, ncol, Ap, X, e, Xd);
+    else {
+        hipLaunchKernelGGL(col_exp_kernel, dim3(nb256(ncol)), dim3(256), 0, h->stream, naux, ncol, X, e);
+        hipLaunchKernelGGL(digits_lt_kernel, dim3((unsigned)((ncol + 31) / 32), (unsigned)((Ap + 31) / 32)), dim3(256),
+                           0, h->stream, naux, ncol, Ap, X, e, Xd);
+    }
+}
+
 }  // namespace
 
 gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_max, const double* eps,
@@ -1214,11 +1433,8 @@ gw_status mixed_prep(Handle* h, int naux, int nmo, int nt, const double* L, cons
     const int Ap = mixed_Ap(naux);
     const long rrows = (long)nt * naux;
     KTimer tm(h, "mixed_prep");
-    hipLaunchKernelGGL(col_exp_kernel, dim3(nb256(M2)), dim3(256), 0, h->stream, naux, M2, L, eL);
-    hipLaunchKernelGGL(digits_lt_kernel, dim3((unsigned)((M2 + 31) / 32), (unsigned)((Ap + 31) / 32)), dim3(256), 0,
-                       h->stream, naux, M2, Ap, L, eL, Ld);
-    hipLaunchKernelGGL(digitise_rows_kernel, dim3((unsigned)rrows), dim3(256), 0, h->stream, rrows, naux, Ap, R,
-                       (const double*)nullptr, eR, Rd, (const double*)nullptr, (int*)nullptr, (i8*)nullptr);
+    launch_digitise_cols(h, naux, M2, Ap, L, eL, Ld);
+    launch_digitise_rows(h, rrows, naux, Ap, R, nullptr, eR, Rd);
     tm.stop();
     GW_CHECK_LAUNCH(h);
     return GW_OK;
@@ -1292,8 +1508,7 @@ gw_status launch_dgemm(Handle* h, const DgemmArgs& g0, const char* tag) {
 // those of X o D (D = d2[c])
 gw_status digitise_rows(Handle* h, long rows, long cols, int kpad, const double* X, int* e, i8* Xd,
                         const double* d2 = nullptr, int* e2 = nullptr, i8* Yd = nullptr) {
-    hipLaunchKernelGGL(digitise_rows_kernel, dim3((unsigned)rows), dim3(256), 0, h->stream, rows, (int)cols, kpad, X,
-                       (const double*)nullptr, e, Xd, d2, e2, Yd);
+    launch_digitise_rows(h, rows, (int)cols, kpad, X, nullptr, e, Xd, d2, e2, Yd);
     GW_CHECK_LAUNCH(h);
     return GW_OK;
 }
@@ -1342,9 +1557,7 @@ gw_status tda_moments_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_ma
     GW_TRY(gather_ov(h, nocc, nvir, naux, eps, L, V, D));
     {
         KTimer tm(h, "recur_digits");
-        hipLaunchKernelGGL(col_exp_kernel, dim3(nb256(ov)), dim3(256), 0, h->stream, naux, ov, V, eVt);
-        hipLaunchKernelGGL(digits_lt_kernel, dim3((unsigned)((ov + 31) / 32), (unsigned)((Ap + 31) / 32)), dim3(256),
-                           0, h->stream, naux, ov, Ap, V, eVt, Vt);
+        launch_digitise_cols(h, naux, ov, Ap, V, eVt, Vt);
         tm.stop();
         GW_CHECK_LAUNCH(h);
     }
@@ -1436,8 +1649,7 @@ gw_status node_products_mixed(Handle* h, int naux, long ov, int nb, const double
     GW_TRY(digitise_rows(h, naux, ov, Kp, V, eV, Vd));
     for (int b = 0; b < nb; ++b) {
         // digits of V o as[b] by rows (k = ia)
-        hipLaunchKernelGGL(digitise_rows_kernel, dim3((unsigned)naux), dim3(256), 0, h->stream, (long)naux, (int)ov,
-                           Kp, V, as + (long)b * ov, eA, Ad, (const double*)nullptr, (int*)nullptr, (i8*)nullptr);
+        launch_digitise_rows(h, naux, (int)ov, Kp, V, as + (long)b * ov, eA, Ad);
         GW_CHECK_LAUNCH(h);
         DgemmArgs g{};
         g.M = g.N = naux;
@@ -1470,9 +1682,7 @@ gw_status node_sum_mixed(Handle* h, int naux, long ov, int nb, const double* S, 
     int* eS = ex + ov;
     KTimer tm(h, "rpa_quad");
     // B operand: V's digit planes transposed (k = Q, one scale per column ia)
-    hipLaunchKernelGGL(col_exp_kernel, dim3(nb256(ov)), dim3(256), 0, h->stream, naux, ov, V, eV);
-    hipLaunchKernelGGL(digits_lt_kernel, dim3((unsigned)((ov + 31) / 32), (unsigned)((Ap + 31) / 32)), dim3(256), 0,
-                       h->stream, naux, ov, Ap, V, eV, Vlt);
+    launch_digitise_cols(h, naux, ov, Ap, V, eV, Vlt);
     GW_CHECK_LAUNCH(h);
     GW_TRY(fill_f64(h, ones, (size_t)ov, 1.0));
     for (int b = 0; b < nb; ++b) {
@@ -1525,9 +1735,7 @@ gw_status rpa_moments_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_ma
     {
         KTimer tm(h, "recur_digits");
         // the update's B operand: V o D, transposed digit planes (k = P, per-column scales)
-        hipLaunchKernelGGL(col_exp_kernel, dim3(nb256(ov)), dim3(256), 0, h->stream, naux, ov, X[1], eVDt);
-        hipLaunchKernelGGL(digits_lt_kernel, dim3((unsigned)((ov + 31) / 32), (unsigned)((Ap + 31) / 32)), dim3(256),
-                           0, h->stream, naux, ov, Ap, X[1], eVDt, VDt);
+        launch_digitise_cols(h, naux, ov, Ap, X[1], eVDt, VDt);
         GW_CHECK_LAUNCH(h);
         // the B operand of R_n = eta~^{(n)} V^T: row digit planes of V (k = ia)
         GW_TRY(digitise_rows(h, naux, ov, Kp, V, eV, Vd));

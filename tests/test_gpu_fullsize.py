@@ -87,12 +87,19 @@ def test_fullsize_poles_and_qp_match_oracle_lanczos(c3):
     front = slice(O - 5, O + 5)
     assert np.abs(qp[front] - qp_ref[front]).max() < 1e-8
     assert np.abs(wt[front] - wt_ref[front]).max() < 1e-7
-    # every conserved moment is reproduced by the device poles
+    # every conserved moment is reproduced by the device poles.  At this size
+    # the reconstruction error grows with n (the high moments are dominated by
+    # the extreme poles, and the pseudo-inverse drops T0 directions below
+    # 1e-12 of its largest eigenvalue); the FP64 poles reach ~1e-8 relative,
+    # held here to 1e-7
+    errs = []
     for key, T in (("occ", c3["so"]), ("vir", c3["sv"])):
         e = res["e_" + key].cpu().numpy()
         v = res["v_" + key].cpu().numpy()
         for n in range(N + 1):
-            assert rel((v * e[None, :] ** n) @ v.T, T[n]) < 1e-6, (key, n)
+            errs.append(rel((v * e[None, :] ** n) @ v.T, T[n]))
+    print("pole moment errors " + " ".join(f"{x:.1e}" for x in errs), flush=True)
+    assert max(errs) < 1e-7, errs
 
 
 # Mixed precision at full size.  The digit products carry ~2^-32 relative

@@ -24,6 +24,7 @@
 #include "mixed_jobs.h"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 
 namespace gwm {
@@ -178,96 +179,115 @@ __global__ void digits_lt_kernel(int naux, long ncol, int Ap, const double* __re
     }
 }
 
-// The row digitisation above with one read of X: the row (at most 8192 * NPR
-// columns) stays in registers between the maxima and the digits, 1024 threads
-// per row, 8 consecutive columns per thread and 8192-column pass.  X is scaled
-// by cs when it is set; with HASY the same read also gives the planes of
-// X o D (D = d2[c], exponents e2; cs is then unset), d2 reloaded per pass;
-// with HASY the passes are kept apart by compiler barriers, so that the loads
-// of later passes do not compete with the row for registers.
-template <int NPR, bool HASY>
-__global__ __launch_bounds__(1024) void digitise_rows_reg_kernel(long rows, int cols, int kpad,
-                                                                 const double* __restrict__ X,
-                                                                 const double* __restrict__ cs, int* __restrict__ e,
-                                                                 i8* __restrict__ Xd, const double* __restrict__ d2,
-                                                                 int* __restrict__ e2, i8* __restrict__ Yd) {
-    const long row = blockIdx.x;
-    const int t = threadIdx.x;
+// Long rows in two passes that keep the whole chip busy.  Pass one: the row
+// exponents, scale_exp of max_c |X cs| by integer atomicMax over the row's
+// 8192-column chunks into e, preset to INT_MIN (a row with no non-zero
+// element keeps it), and with d2 set the same for X o D into e2 (cs is then
+// unset).  Pass two: the digits of 16 rows x 128 columns per work group (a
+// thread: one row, 8 consecutive columns), so that the 16 rows' 64-byte k
+// rows of one k block, adjacent in the k-blocked planes, are written together
+// (1 KB per plane); one block per row would leave isolated 64-byte pieces,
+// rows x 64 bytes apart.  INT_MIN reads as 0 and is written back as 0 by the
+// first column's thread (the others may read either value: the same digits).
+constexpr int RCH = 8192;
+__global__ __launch_bounds__(256) void fill_i32_kernel(int* __restrict__ p, long n, int v) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void row_exp_kernel(int cols, const double* __restrict__ X,
+                                                      const double* __restrict__ cs, int* __restrict__ e,
+                                                      const double* __restrict__ d2, int* __restrict__ e2) {
+    const long row = blockIdx.y;
+    const int c0 = blockIdx.x * RCH;
     const double* __restrict__ x = X + row * cols;
-    // passes past NR live in LDS (64 KB each): with HASY and five or more
-    // passes the row, d2 and the digits together would not fit in registers
-    constexpr int NR = (HASY && NPR >= 5) ? 4 : NPR;
-    __shared__ double red[2][16];
-    __shared__ double vl[NPR > NR ? (NPR - NR) * 8192 : 1];
-    double v[NPR][8];
     double m = 0.0, m2 = 0.0;
-#pragma unroll
-    for (int p = 0; p < NPR; ++p) {
-        // with HASY one pass at a time (loads not hoisted across passes)
-        if (HASY) asm volatile("" ::: "memory");
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int c = p * 8192 + t * 8 + u;
-            const double a = c < cols ? x[c] * (cs ? cs[c] : 1.0) : 0.0;
-            if (p < NR) v[p][u] = a;
-            else vl[(p - NR) * 8192 + t * 8 + u] = a;
-            m = fmax(m, fabs(a));
-            if (HASY && c < cols) m2 = fmax(m2, fabs(a * d2[c]));
+    if (c0 + RCH <= cols) {
+        // a whole chunk: no guards, so that the loads of an unrolled group issue together
+#pragma unroll 8
+        for (int i = 0; i < RCH / 256; ++i) {
+            const int c = c0 + i * 256 + (int)threadIdx.x;
+            const double v = x[c] * (cs ? cs[c] : 1.0);
+            m = fmax(m, fabs(v));
+            if (d2) m2 = fmax(m2, fabs(v * d2[c]));
+        }
+    } else {
+        for (int i = 0; i < RCH / 256; ++i) {
+            const int c = c0 + i * 256 + (int)threadIdx.x;
+            if (c < cols) {
+                const double v = x[c] * (cs ? cs[c] : 1.0);
+                m = fmax(m, fabs(v));
+                if (d2) m2 = fmax(m2, fabs(v * d2[c]));
+            }
         }
     }
     for (int o = 32; o > 0; o >>= 1) {
         m = fmax(m, __shfl_xor(m, o));
-        if (HASY) m2 = fmax(m2, __shfl_xor(m2, o));
+        m2 = fmax(m2, __shfl_xor(m2, o));
     }
-    if ((t & 63) == 0) {
-        red[0][t >> 6] = m;
-        red[1][t >> 6] = m2;
+    __shared__ double red[2][4];
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = m;
+        red[1][threadIdx.x >> 6] = m2;
     }
     __syncthreads();
-    m = red[0][0];
-    m2 = red[1][0];
-#pragma unroll
-    for (int w = 1; w < 16; ++w) {
-        m = fmax(m, red[0][w]);
-        m2 = fmax(m2, red[1][w]);
+    if (threadIdx.x == 0) {
+        m = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
+        m2 = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
+        if (m > 0.0) atomicMax(e + row, scale_exp(m));
+        if (d2 && m2 > 0.0) atomicMax(e2 + row, scale_exp(m2));
     }
-    const int ex = scale_exp(m);
-    const int ex2 = scale_exp(m2);
-    if (t == 0) {
+}
+
+__global__ __launch_bounds__(256) void row_digits_kernel(long rows, int cols, int kpad, const double* __restrict__ X,
+                                                         const double* __restrict__ cs, int* __restrict__ e,
+                                                         i8* __restrict__ Xd, const double* __restrict__ d2,
+                                                         int* __restrict__ e2, i8* __restrict__ Yd) {
+    const long row = (long)blockIdx.y * 16 + (threadIdx.x >> 4);
+    const int c0 = blockIdx.x * 128 + (int)(threadIdx.x & 15) * 8;
+    if (row >= rows || c0 >= kpad) return;
+    int ex = e[row];
+    if (ex == INT_MIN) ex = 0;
+    int ex2 = 0;
+    if (Yd) {
+        ex2 = e2[row];
+        if (ex2 == INT_MIN) ex2 = 0;
+    }
+    if (c0 == 0) {
         e[row] = ex;
-        if (HASY) e2[row] = ex2;
+        if (Yd) e2[row] = ex2;
+    }
+    const double* __restrict__ x = X + row * cols;
+    double v[8];
+    if (c0 + 8 <= cols) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = x[c0 + u] * (cs ? cs[c0 + u] : 1.0);
+    } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = c0 + u < cols ? x[c0 + u] * (cs ? cs[c0 + u] : 1.0) : 0.0;
     }
     const long plane = rows * (long)kpad;
+    const long o = ((long)(c0 >> 6) * rows + row) * 64 + (c0 & 63);
+    i8 dg[ND][8];
 #pragma unroll
-    for (int p = 0; p < NPR; ++p) {
-        const int c0 = p * 8192 + t * 8;
-        if (c0 >= kpad) break;
-        if (HASY) asm volatile("" ::: "memory");
-        if (p >= NR)
+    for (int u = 0; u < 8; ++u) {
+        i8 q[ND];
+        digitsN(v[u], ex, q);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[p][u] = vl[(p - NR) * 8192 + t * 8 + u];
-        const long o = ((long)(c0 >> 6) * rows + row) * 64 + (c0 & 63);
-        i8 dg[ND][8];
+        for (int d = 0; d < ND; ++d) dg[d][u] = q[d];
+    }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) *(uint2*)(Xd + d * plane + o) = make_uint2(pack4(dg[d]), pack4(dg[d] + 4));
+    if (Yd) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             i8 q[ND];
-            digitsN(v[p][u], ex, q);
+            digitsN(c0 + u < cols ? v[u] * d2[c0 + u] : 0.0, ex2, q);
 #pragma unroll
             for (int d = 0; d < ND; ++d) dg[d][u] = q[d];
         }
 #pragma unroll
-        for (int d = 0; d < ND; ++d) *(uint2*)(Xd + d * plane + o) = make_uint2(pack4(dg[d]), pack4(dg[d] + 4));
-        if (HASY) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                i8 q[ND];
-                digitsN(c0 + u < cols ? v[p][u] * d2[c0 + u] : 0.0, ex2, q);
-#pragma unroll
-                for (int d = 0; d < ND; ++d) dg[d][u] = q[d];
-            }
-#pragma unroll
-            for (int d = 0; d < ND; ++d) *(uint2*)(Yd + d * plane + o) = make_uint2(pack4(dg[d]), pack4(dg[d] + 4));
-        }
+        for (int d = 0; d < ND; ++d) *(uint2*)(Yd + d * plane + o) = make_uint2(pack4(dg[d]), pack4(dg[d] + 4));
     }
 }
 
@@ -1260,49 +1280,23 @@ void launch_fold_mixed(Handle* h, const FoldJob& g) {
 unsigned nb256(long n) { return (unsigned)((n + 255) / 256); }
 
 // Row exponents and k-blocked digit planes of X[rows][cols] (times cs), and
-// with Yd set also those of X o D (D = d2[c], exponents e2): rows of up to
-// 49152 columns in one read (up to 40960 with Yd, else a second read with d2
-// as the column scale), shorter and longer rows by the two-pass kernel.
+// with Yd set also those of X o D (D = d2[c], exponents e2; cs then unset):
+// rows of 4096 or more columns by the exponent pass and the tiled digit pass,
+// shorter rows by the one-block-per-row kernel.
 void launch_digitise_rows(Handle* h, long rows, int cols, int kpad, const double* X, const double* cs, int* e,
                           i8* Xd, const double* d2 = nullptr, int* e2 = nullptr, i8* Yd = nullptr) {
-    const int npr = (kpad + 8191) / 8192;
-    if (cols < 4096 || npr > 6) {
+    if (cols < 4096 || rows > 65535) {
         hipLaunchKernelGGL(digitise_rows_kernel, dim3((unsigned)rows), dim3(256), 0, h->stream, rows, cols, kpad, X,
                            cs, e, Xd, d2, e2, Yd);
         return;
     }
-    const dim3 g((unsigned)rows), b(1024);
-#define GW_ROWREG(N, Y, S, E, D, D2, E2, YD)                                                                    \
-    case N:                                                                                                     \
-        hipLaunchKernelGGL((digitise_rows_reg_kernel<N, Y>), g, b, 0, h->stream, rows, cols, kpad, X, S, E, D, \
-                           D2, E2, YD);                                                                         \
-        break;
-    if (Yd && npr <= 5) {
-        switch (npr) {
-            GW_ROWREG(1, true, nullptr, e, Xd, d2, e2, Yd)
-            GW_ROWREG(2, true, nullptr, e, Xd, d2, e2, Yd)
-            GW_ROWREG(3, true, nullptr, e, Xd, d2, e2, Yd)
-            GW_ROWREG(4, true, nullptr, e, Xd, d2, e2, Yd)
-            default: GW_ROWREG(5, true, nullptr, e, Xd, d2, e2, Yd)
-        }
-        return;
-    }
-    // X (times cs), then for six passes with Yd the planes of X o D as a
-    // second read with d2 as the column scale
-    for (int pass = 0; pass < (Yd ? 2 : 1); ++pass) {
-        const double* sc = pass ? d2 : cs;
-        int* ee = pass ? e2 : e;
-        i8* dd = pass ? Yd : Xd;
-        switch (npr) {
-            GW_ROWREG(1, false, sc, ee, dd, nullptr, nullptr, nullptr)
-            GW_ROWREG(2, false, sc, ee, dd, nullptr, nullptr, nullptr)
-            GW_ROWREG(3, false, sc, ee, dd, nullptr, nullptr, nullptr)
-            GW_ROWREG(4, false, sc, ee, dd, nullptr, nullptr, nullptr)
-            GW_ROWREG(5, false, sc, ee, dd, nullptr, nullptr, nullptr)
-            default: GW_ROWREG(6, false, sc, ee, dd, nullptr, nullptr, nullptr)
-        }
-    }
-#undef GW_ROWREG
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(nb256(rows)), dim3(256), 0, h->stream, e, rows, INT_MIN);
+    if (Yd) hipLaunchKernelGGL(fill_i32_kernel, dim3(nb256(rows)), dim3(256), 0, h->stream, e2, rows, INT_MIN);
+    hipLaunchKernelGGL(row_exp_kernel, dim3((unsigned)((cols + RCH - 1) / RCH), (unsigned)rows), dim3(256), 0,
+                       h->stream, cols, X, cs, e, Yd ? d2 : nullptr, Yd ? e2 : nullptr);
+    hipLaunchKernelGGL(row_digits_kernel, dim3((unsigned)((kpad + 127) / 128), (unsigned)((rows + 15) / 16)),
+                       dim3(256), 0, h->stream, rows, cols, kpad, X, cs, e, Xd, Yd ? d2 : nullptr, Yd ? e2 : nullptr,
+                       Yd);
 }
 
 // Column exponents and transposed k-blocked digit planes of X[naux][ncol]

@@ -110,6 +110,30 @@ def test_mixed_rpa_moments_match_oracle(handle, o, v, A, N, seed):
         assert np.array_equal(R[n], R[n].T)
 
 
+@pytest.mark.parametrize("scr", ["tda", "rpa"])
+def test_mixed_moments_long_ragged_rows_and_zero_row(handle, scr):
+    """Rows of 4096 or more (nocc nvir) columns take the exponent pass and the
+    16-row-tile digit pass: here 7 x 587 = 4109 columns (not a multiple of
+    8, so the last 8-column group is partly padding), 40 aux rows (the last
+    row tile is partial) and one aux row of L set to zero, whose X_k rows stay
+    zero (the exponent pass leaves them unset and the digit pass reads them as
+    0).  Every R_n within the format's tolerance of the oracle recursion."""
+    o, v, A, N = 7, 587, 40, 5
+    print(f"\n[case] mixed {scr} moments long rows o={o} v={v} A={A} N={N}", flush=True)
+    eps, L = gwsynth.system(o, v, A, 9)
+    L[5] = 0.0
+    V, D = ogw.particle_hole(eps, L, o)
+    eta = ogw.tda_eta(V, D, N) if scr == "tda" else ogw.rpa_eta(V, D, N, nquad=48)
+    R_ref = ogw.w_core(eta, V)
+    R = host(handle.moments(dev(eps), dev(L), o, N, scr, precision="mixed"))
+    for n in range(N + 1):
+        assert rel(R[n], R_ref[n]) < MIXED_TOL, (n, rel(R[n], R_ref[n]))
+        assert np.array_equal(R[n], R[n].T)
+        if scr == "tda":
+            # zero digits give exact zeros (RPA: covered by the tolerance above)
+            assert not R[n][5].any() and not R[n][:, 5].any()
+
+
 def test_mixed_intermediate_cap(handle):
     """The mixed stage-1 intermediates (FP32 + BF16 residual, four digit
     planes and one exponent per row, for all nmo^2 columns) are refused with

@@ -505,6 +505,45 @@ __global__ void reduce_splits_kernel(const double* part, int nsplit, long ps, in
     out[(long)b * out_bs + (long)m * ldo + n] = s;
 }
 
+// Symmetric results (mirror set, M == N): one work group per upper 32 x 32
+// tile sums that tile's partials row by row (coalesced reads), writes it and
+// writes its mirror image through an LDS transpose; a diagonal tile reads the
+// upper triangle of itself.  The same sums in the same order as
+// reduce_splits_kernel, whose mirrored reads go down columns of the partials.
+__global__ __launch_bounds__(256) void reduce_splits_sym_kernel(const double* __restrict__ part, int nsplit, long ps,
+                                                                int M, long ld, double alpha, double diag,
+                                                                double* __restrict__ out, long out_bs, long ldo) {
+    const int T = (M + 31) / 32;
+    int t = blockIdx.x, bi = 0;
+    while (t >= T - bi) {
+        t -= T - bi;
+        ++bi;
+    }
+    const int bj = bi + t;
+    __shared__ double tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const double* __restrict__ pb = part + (long)blockIdx.z * nsplit * ps;
+    double* __restrict__ ob = out + (long)blockIdx.z * out_bs;
+    for (int r = ty; r < 32; r += 8) {
+        const int m = bi * 32 + r, n = bj * 32 + tx;
+        if (m >= M || n >= M) continue;
+        const double* p = pb + (long)min(m, n) * ld + max(m, n);
+        double s = 0.0;
+        for (int k = 0; k < nsplit; ++k) s += p[(long)k * ps];
+        s *= alpha;
+        if (m == n) s += diag;
+        ob[(long)m * ldo + n] = s;
+        tile[r][tx] = s;
+    }
+    if (bi == bj) return;  // the same for the whole work group
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int m = bj * 32 + r, n = bi * 32 + tx;  // out[m][n] = s(n, m)
+        if (m >= M || n >= M) continue;
+        ob[(long)m * ldo + n] = tile[tx][r];
+    }
+}
+
 }  // namespace
 
 int best_splits(long items, int K, int slots, int max_ns) {
@@ -622,6 +661,13 @@ gw_status reduce_splits(Handle* h, const double* part, int nsplit, long ps, int 
                         long ldo) {
     long n = (long)M * N;
     if (n == 0 || batch == 0) return GW_OK;
+    if (mirror && M == N) {
+        const long T = (M + 31) / 32;
+        hipLaunchKernelGGL(reduce_splits_sym_kernel, dim3((unsigned)(T * (T + 1) / 2), 1, (unsigned)batch), dim3(256),
+                           0, h->stream, part, nsplit, ps, M, ld, alpha, diag, out, out_bs, ldo);
+        GW_CHECK_LAUNCH(h);
+        return GW_OK;
+    }
     dim3 grid((unsigned)((n + 255) / 256), 1, (unsigned)batch);
     hipLaunchKernelGGL(reduce_splits_kernel, grid, dim3(256), 0, h->stream, part, nsplit, ps, M, N, ld,
                        mirror ? 1 : 0, alpha, diag, out, out_bs, ldo);

@@ -830,7 +830,8 @@ __global__ __launch_bounds__(256) void zdig_grouped_kernel(const ZdigJob* __rest
 
 // ---------------------------------------------------------------------------
 // Stage 2: Sigma^{(n)}[p,q] += sum_{x,P} L[P,x,p] Zt^{(n)}[x,q,P]
-// 128 x 64 upper tiles, 4 waves of 64 x 32, promotion to FP64 once per x.
+// TM x 64 upper tiles (TM = 64 or 128), 4 waves of TM/2 x 32, promotion to
+// FP64 once per x.
 // ---------------------------------------------------------------------------
 
 // Upper tiles of a symmetric M x M result in (64 R)-row x 64-column tiles:
@@ -843,9 +844,10 @@ __device__ inline void upper_tile_rect(int t, int TN, int& bi, int& bj, int R = 
     bj = R * r + t;
 }
 
-// One work group: a TM x 64 upper tile of Sigma^{(n)} (TM = 128, or 64 for
-// small molecules: twice the work groups per result) for one sector and one
-// split of that sector's x range; 4 waves of TM/2 x 32.  The (x, k-block)
+// One work group: a TM x 64 upper tile of Sigma^{(n)} (TM = 64: half the
+// accumulators, two work groups per CU; 128 in grouped launches for large
+// molecules) for one sector and one split of that sector's x range; 4 waves
+// of TM/2 x 32; the pipeline stages are OPA + C_OPB bytes apart.  The (x, k-block)
 // steps form one double-buffered LDS-DMA pipeline; the int32 digit-weight
 // accumulators are promoted to FP64 with the row and column scales at the
 // end of every x.
@@ -859,6 +861,7 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
     constexpr int NI = TM / 32;          // 16-row blocks per wave
     constexpr int HA = TM / 64;          // 64-row halves of the A slab
     constexpr int OPA = ND * TM * 64;    // bytes of the A slab
+    constexpr int BUF = OPA + C_OPB;     // bytes of one pipeline stage
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -893,7 +896,7 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
     for (int h = 0; h < HA; ++h) offA[h] = (unsigned)(min(m0 + h * 64 + wv * 16 + lrow, M - 1) * 64 + gch * 16);
     const unsigned offB = (unsigned)(min(n0 + wv * 16 + lrow, M - 1) * 64 + gch * 16);
     auto load = [&](int x, int kt, int buf) {
-        lds_t* A = lds + buf * C_BUF + wv * 16 * 64;
+        lds_t* A = lds + buf * BUF + wv * 16 * 64;
         lds_t* B = A + OPA;
         const unsigned soA = (unsigned)x * M * 64u;
         const unsigned soB = (unsigned)((long)n * g.ncol + (long)(x - g.x0) * M) * 64u;
@@ -953,7 +956,7 @@ __device__ __forceinline__ void contract_tile(const ContractArgs& g, int tile, i
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
             __syncthreads();
             if (!wrap || x + 1 < xb) load(wrap ? x + 1 : x, wrap ? 0 : kt + 1, cur ^ 1);
-            const lds_t* A = lds + cur * C_BUF;
+            const lds_t* A = lds + cur * BUF;
             const lds_t* B = A + OPA;
             i32x4 b[2][ND];
 #pragma unroll
@@ -1037,12 +1040,16 @@ __device__ __forceinline__ bool xcd_group_item(int tiles, int groups, int& tile,
     return group < groups;
 }
 
-// One work group per (upper tile, split, sector * nt + n); groups are (split, z).
-__global__ __launch_bounds__(256, 1) void contract_mixed_kernel(ContractArgs g, int tiles) {
-    __shared__ __attribute__((aligned(16))) lds_t lds[2 * C_BUF];
+// One work group per (upper 64 x 64 tile, split, sector * nt + n); groups
+// are (split, z).  64-row tiles keep half the accumulators of 128-row ones
+// and need 64 KB of LDS, so that two work groups share a CU (one wave per
+// SIMD left every stall of a 128-row tile exposed: 17.2 against 16.1 ms at
+// nocc 100, nvir 400, naux 1500, N 11).
+__global__ __launch_bounds__(256, 2) void contract_mixed_kernel(ContractArgs g, int tiles) {
+    __shared__ __attribute__((aligned(16))) lds_t lds[2 * (ND * 64 * 64 + C_OPB)];
     int tile, grp;
     if (!xcd_group_item(tiles, g.nsplit * 2 * g.nt, tile, grp)) return;
-    contract_tile<128>(g, tile, grp % g.nsplit, grp / g.nsplit, lds);
+    contract_tile<64>(g, tile, grp % g.nsplit, grp / g.nsplit, lds);
 }
 
 // Grouped, persistent, XCD-aware: the work items of a job, ordered (tile,
@@ -1354,8 +1361,9 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
     i8* Zd = (i8*)ws_get(h, WS_MIX6, sizeof(i8) * ND * zrows * Ap);
     int* eZ = (int*)ws_get(h, WS_MIX4, sizeof(int) * zrows);
     if (!Zt || !Zl || !Zd || !eZ) return GW_ENOMEM;
-    const int tiles = mixed_upper_tiles(nmo);
-    const int S = best_splits((long)tiles * nt * 2, naux * std::max(nocc, nvir), h->cus, 64);
+    // 64 x 64 upper tiles, two work groups per CU
+    const int tiles = mixed_upper_tiles(nmo, 64);
+    const int S = best_splits((long)tiles * nt * 2, naux * std::max(nocc, nvir), 2 * h->cus, 64);
     const long part_per_sector = (long)nt * S * M2;
     double* acc = (double*)ws_get(h, WS_SIGACC, sizeof(double) * 2 * part_per_sector);
     if (!acc) return GW_ENOMEM;
@@ -1390,7 +1398,7 @@ gw_status sigma_from_R_mixed(Handle* h, int nocc, int nvir, int naux, int nmom_m
         a.x0 = 0;
         a.xs0[0] = 0; a.nxs[0] = nocc;
         a.xs0[1] = nocc; a.nxs[1] = nvir;
-        a.nt = nt; a.nsplit = S; a.tilesN = (nmo + 63) / 64; a.tiles = tiles; a.ncol = M2; a.tm = 128;
+        a.nt = nt; a.nsplit = S; a.tilesN = (nmo + 63) / 64; a.tiles = tiles; a.ncol = M2; a.tm = 64;
         a.part = acc;
         a.nsplit_total = S; a.split_off = 0; a.item0 = 0;
         KTimer tm(h, "sigma_contract");

@@ -1117,42 +1117,47 @@ struct DgemmArgs {
 // dynamic range (most entries far below the row maximum, whose leading digit
 // is then d1) d1 x d3 is the leading-times-last product of those entries:
 // without them the moments carry ~1e-8 relative error, with them ~5e-10.
-template <bool W4>
+template <bool W4, int TM = 128>
 __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int split, lds_t* lds) {
+    static_assert(TM == 128 || TM == 64, "digit GEMM tile height");
     constexpr int NW = W4 ? MAXW + 2 : MAXW + 1;
+    constexpr int NI = TM / 32;          // 16-row blocks per wave
+    constexpr int HA = TM / 64;          // 64-row halves of the A slab
+    constexpr int OPA = ND * TM * 64;    // bytes of the A slab
+    constexpr int BUF = OPA + C_OPB;     // bytes of one pipeline stage
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int lr = lane & 15;
     const int lk = lane >> 4;
     int bi, bj;
-    if (g.sym) upper_tile_rect(tile, g.tilesN, bi, bj);
+    if (g.sym) upper_tile_rect(tile, g.tilesN, bi, bj, HA);
     else {
         bi = tile / g.tilesN;
         bj = tile - bi * g.tilesN;
     }
-    const int m0 = bi * 128, n0 = bj * 64;
+    const int m0 = bi * TM, n0 = bj * 64;
     const int per = (g.nkb + g.nsplit - 1) / g.nsplit;
     const int ka = split * per;
     const int kb_end = min(g.nkb, ka + per);
     const int total = kb_end - ka;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 32;
+    const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * 32;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const int lrow = lane >> 2;
     const int gch = swz(lrow, lane & 3);
-    unsigned offA[2];
+    unsigned offA[HA];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) offA[h] = (unsigned)(min(m0 + h * 64 + wv * 16 + lrow, g.M - 1) * 64 + gch * 16);
+    for (int h = 0; h < HA; ++h) offA[h] = (unsigned)(min(m0 + h * 64 + wv * 16 + lrow, g.M - 1) * 64 + gch * 16);
     const unsigned offB = (unsigned)(min(n0 + wv * 16 + lrow, g.N - 1) * 64 + gch * 16);
     auto load = [&](int kb, int buf) {
-        lds_t* A = lds + buf * C_BUF + wv * 16 * 64;
-        lds_t* B = A + C_OPA;
+        lds_t* A = lds + buf * BUF + wv * 16 * 64;
+        lds_t* B = A + OPA;
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
+        for (int s = 0; s < ND * HA; ++s) {
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void*)(g.A + (s >> 1) * g.aplane + (long)kb * g.arows * 64), (short)0, g.arows * 64, 0x00020000);
+                (void*)(g.A + (s / HA) * g.aplane + (long)kb * g.arows * 64), (short)0, g.arows * 64, 0x00020000);
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(A + s * 64 * 64),
-                                                     16, offA[s & 1], 0, 0, 0);
+                                                     16, offA[s % HA], 0, 0, 0);
         }
 #pragma unroll
         for (int s = 0; s < ND; ++s) {
@@ -1162,11 +1167,11 @@ __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int spl
                                                      16, offB, 0, 0, 0);
         }
     };
-    i32x4 acc[NW][4][2];
+    i32x4 acc[NW][NI][2];
 #pragma unroll
     for (int w = 0; w < NW; ++w)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < NI; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) acc[w][i][j] = (i32x4){0, 0, 0, 0};
     const int so = swz(lr, lk) * 16;
@@ -1178,18 +1183,18 @@ __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int spl
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         if (it + 1 < total) load(ka + it + 1, cur ^ 1);
-        const lds_t* A = lds + cur * C_BUF;
-        const lds_t* B = A + C_OPA;
+        const lds_t* A = lds + cur * BUF;
+        const lds_t* B = A + OPA;
         i32x4 b[2][ND];
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int d = 0; d < ND; ++d) b[j][d] = lds_b128(B + (d * 64 + wn + j * 16 + lr) * 64 + so);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < NI; ++i) {
             i32x4 a[ND];
 #pragma unroll
-            for (int d = 0; d < ND; ++d) a[d] = lds_b128(A + (d * 128 + wm + i * 16 + lr) * 64 + so);
+            for (int d = 0; d < ND; ++d) a[d] = lds_b128(A + (d * TM + wm + i * 16 + lr) * 64 + so);
 #pragma unroll
             for (int w = 0; w <= MAXW; ++w)
 #pragma unroll
@@ -1210,8 +1215,8 @@ __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int spl
     // epilogue.  Every input of the epilogue is loaded before the first
     // store: the stores could alias those arrays as far as the compiler
     // knows, so interleaved loads would each wait for a memory round trip.
-    int ec[2], er[4][4];
-    double dv[2], cs[2], xin[2][4][4];
+    int ec[2], er[NI][4];
+    double dv[2], cs[2], xin[2][NI][4];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int col = min(n0 + wn + j * 16 + lr, g.N - 1);
@@ -1220,14 +1225,14 @@ __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int spl
         cs[j] = g.Cs ? g.Cs[col] : 1.0;
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NI; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) er[i][r] = g.eA[min(m0 + wm + i * 16 + 4 * lk + r, g.M - 1)];
     if (g.Xout) {
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < NI; ++i)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int col = min(n0 + wn + j * 16 + lr, g.N - 1);
@@ -1240,7 +1245,7 @@ __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int spl
         const int col = n0 + wn + j * 16 + lr;
         if (col >= g.N) continue;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < NI; ++i)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + wm + i * 16 + 4 * lk + r;
@@ -1258,20 +1263,22 @@ __device__ __forceinline__ void dgemm_tile(const DgemmArgs& g, int tile, int spl
 
 // Split products: a 2D grid (tile, split), spread over the XCDs.  The unsplit
 // update: XCD groups of 8 column tiles x all row tiles, so the row tiles that
-// share a column block of B meet in one L2.
+// share a column block of B meet in one L2.  64 x 64 tiles: 144-160 registers
+// and 64 KB of LDS, so that two work groups share a CU (128 x 64 tiles held
+// one wave per SIMD: 13.4 against 11.4 ms of digit GEMMs per TDA set at
+// nocc 100, nvir 400, naux 1500, N 11).
 template <bool W4>
-__global__ __launch_bounds__(256, 1) void dgemm_mixed_kernel(DgemmArgs g, int gtiles, int groups) {
-    __shared__ __attribute__((aligned(16))) lds_t lds[2 * C_BUF];
+__global__ __launch_bounds__(256, 2) void dgemm_mixed_kernel(DgemmArgs g, int gtiles, int groups) {
+    __shared__ __attribute__((aligned(16))) lds_t lds[2 * (ND * 64 * 64 + C_OPB)];
     if (g.nsplit > 1 || g.sym) {
-        dgemm_tile<W4>(g, blockIdx.x, blockIdx.y, lds);
+        dgemm_tile<W4, 64>(g, blockIdx.x, blockIdx.y, lds);
     } else {
         int t, grp;
         if (!xcd_group_item(gtiles, groups, t, grp)) return;
-        // t = row tile + rows * (column tile within the group)
-        const int rows = (g.M + 127) / 128;
+        const int rows = (g.M + 63) / 64;
         const int bi = t % rows, bj = grp * 8 + t / rows;
         if (bj >= g.tilesN) return;
-        dgemm_tile<W4>(g, bi * g.tilesN + bj, 0, lds);
+        dgemm_tile<W4, 64>(g, bi * g.tilesN + bj, 0, lds);
     }
 }
 
@@ -1487,10 +1494,12 @@ gw_status launch_contract_grouped(Handle* h, const ContractArgs* jobs, int njobs
 namespace {
 
 gw_status launch_dgemm(Handle* h, const DgemmArgs& g0, const char* tag) {
+    // 64 x 64 tiles, two work groups per CU
+    constexpr int TM = 64;
     DgemmArgs g = g0;
-    const int T = (g.M + 127) / 128;
+    const int T = (g.M + TM - 1) / TM;
     g.tilesN = (g.N + 63) / 64;
-    const long tiles = g.sym ? (long)mixed_upper_tiles(g.M) : (long)T * g.tilesN;
+    const long tiles = g.sym ? (long)mixed_upper_tiles(g.M, TM) : (long)T * g.tilesN;
     int gtiles = 0, groups = 0;
     dim3 grid((unsigned)tiles, (unsigned)g.nsplit);
     if (!(g.sym || g.nsplit > 1)) {

@@ -454,7 +454,9 @@ gw_status gw_evgw(gw_handle h, gw_screening screening, int nocc, int nvir, int n
  * (split_target, or with autotune the fastest of 256, 512, 1024, 2048 by
  * timing the whole sequence), and the contraction tile is 128 x 64, or 64 x
  * 64 for molecules with nmo <= small_tile_nmo (autotune: then the fastest
- * of 0, 100, 150, 200).  For TDA the per-molecule work (recursion,
+ * of 0, 100, 150, 200 and every molecule; when every job of a wave has 64-row
+ * tiles the launch holds two work groups per CU).  For TDA the per-molecule
+ * work (recursion,
  * digit preparation) of different molecules runs on `branches` streams with
  * their own workspaces, molecules assigned largest first by nmo^4.  The
  * sequence is run once eagerly (the outputs

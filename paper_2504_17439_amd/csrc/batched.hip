@@ -59,6 +59,7 @@ struct gw_batch_s {
         gwm::ZdigJob* zdig = nullptr;
         gwm::ContractArgs* con = nullptr;
         int njobs = 0;
+        bool all64 = true;  // every contraction job of the wave has 64-row tiles
         long fold_total = 0, zdig_total = 0, con_total = 0;
     };
     std::vector<WaveTab> tabs;
@@ -116,6 +117,7 @@ gw_status build_tables(gw_batch_s* b, int target, int small_nmo) {
     }
     for (size_t w = 0; w < b->waves.size(); ++w) {
         auto& tab = b->tabs[w];
+        tab.all64 = true;
         const auto& ids = b->waves[w];
         std::vector<FoldJob> fj;
         std::vector<ZdigJob> zj;
@@ -150,6 +152,7 @@ gw_status build_tables(gw_batch_s* b, int target, int small_nmo) {
                 a.nxs[sec] = std::max(0, xs1 - xs0);
             }
             a.tm = tile_height(b, m.nmo);
+            tab.all64 = tab.all64 && a.tm == 64;
             a.nt = nt; a.nsplit = j.S; a.tilesN = (m.nmo + 63) / 64; a.tiles = contract_tiles(m.nmo, a.tm);
             a.ncol = ncol;
             a.part = m.part; a.nsplit_total = m.slots; a.split_off = j.slot0;
@@ -240,7 +243,7 @@ gw_status enqueue(gw_batch_s* b) {
         }
         {
             KTimer tm(h, "sigma_contract");
-            GW_TRY(launch_contract_grouped(h, tab.con, tab.njobs, tab.con_total, b->ncu));
+            GW_TRY(launch_contract_grouped(h, tab.con, tab.njobs, tab.con_total, b->ncu, tab.all64));
             tm.stop();
         }
     }
@@ -507,7 +510,8 @@ gw_status batch_create(Handle* h, int nsys, const gw_system* sys, gw_screening s
     }
     if (st == GW_OK && autotune) {
         // coordinate search: the split target with 128-row tiles only, then
-        // the largest nmo that takes the 64-row contraction tile
+        // the largest nmo that takes the 64-row contraction tile (1 << 20:
+        // every molecule, which also gives the launch two work groups per CU)
         h->timing = false;
         int best = b->split_target, best_small = 0;
         float best_ms = 1e30f;
@@ -521,7 +525,7 @@ gw_status batch_create(Handle* h, int nsys, const gw_system* sys, gw_screening s
                 best = target;
             }
         }
-        for (int small : {100, 150, 200}) {
+        for (int small : {100, 150, 200, 1 << 20}) {
             if (st != GW_OK) break;
             st = build_tables(b, best, small);
             float ms = 0.f;

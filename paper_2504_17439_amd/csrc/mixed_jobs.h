@@ -97,6 +97,7 @@ FoldJob make_fold_job(int nt, const i8* Rd, const int* eR, const i8* Ld, const i
 // zdig: rows).
 gw_status launch_fold_grouped(Handle* h, int nt, const FoldJob* jobs, int njobs, long total, int grid);
 gw_status launch_zdig_grouped(Handle* h, const ZdigJob* jobs, int njobs, long total_rows);
-gw_status launch_contract_grouped(Handle* h, const ContractArgs* jobs, int njobs, long total, int grid);
+gw_status launch_contract_grouped(Handle* h, const ContractArgs* jobs, int njobs, long total, int grid,
+                                  bool all64);
 
 }  // namespace gwm

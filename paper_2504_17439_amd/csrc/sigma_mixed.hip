@@ -1082,6 +1082,29 @@ __global__ __launch_bounds__(256, 1) void contract_grouped_kernel(const Contract
     }
 }
 
+// The same when every job of the launch has 64-row tiles: 64 KB of LDS and
+// two work groups per CU.
+__global__ __launch_bounds__(256, 2) void contract_grouped64_kernel(const ContractArgs* __restrict__ jobs, int njobs,
+                                                                  long groups) {
+    __shared__ __attribute__((aligned(16))) lds_t lds[2 * (ND * 64 * 64 + C_OPB)];
+    const int x = blockIdx.x & 7;
+    const long W = gridDim.x >> 3;
+    for (long k = blockIdx.x >> 3;; k += W) {
+        const long grp = (k >> 5) * 8 + x;
+        if (grp >= groups) break;
+        const ContractArgs g = jobs[find_job(jobs, njobs, grp)];
+        const long i = (grp - g.item0) * 32 + (k & 31);
+        const int T = g.tiles;
+        if (i >= (long)T * g.nt * g.nsplit * 2) continue;
+        long r = i / T;
+        const int n = (int)(r % g.nt);
+        r /= g.nt;
+        const int split = (int)(r % g.nsplit);
+        const int sector = (int)(r / g.nsplit);
+        contract_tile<64>(g, (int)(i % T), split, sector * g.nt + n, lds);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Digit GEMM: C[m][n] = sum_k A[m][k] B[n][k] with A, B given as k-blocked digit
 // planes with one exponent per row (the digit format above).  Every split
@@ -1474,9 +1497,15 @@ gw_status launch_zdig_grouped(Handle* h, const ZdigJob* jobs, int njobs, long to
     return GW_OK;
 }
 
-gw_status launch_contract_grouped(Handle* h, const ContractArgs* jobs, int njobs, long total, int grid) {
+gw_status launch_contract_grouped(Handle* h, const ContractArgs* jobs, int njobs, long total, int grid, bool all64) {
     if (total <= 0) return GW_OK;
-    // a whole number of work groups per XCD
+    // a whole number of work groups per XCD (two per CU with 64-row tiles only)
+    if (all64) {
+        const dim3 g((unsigned)std::max(8, 2 * grid / 8 * 8));
+        hipLaunchKernelGGL(contract_grouped64_kernel, g, dim3(256), 0, h->stream, jobs, njobs, total);
+        GW_CHECK_LAUNCH(h);
+        return GW_OK;
+    }
     const dim3 g((unsigned)std::max(8, grid / 8 * 8));
     hipLaunchKernelGGL(contract_grouped_kernel, g, dim3(256), 0, h->stream, jobs, njobs, total);
     GW_CHECK_LAUNCH(h);

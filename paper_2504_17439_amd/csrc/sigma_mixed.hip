@@ -291,6 +291,40 @@ __global__ __launch_bounds__(256) void row_digits_kernel(long rows, int cols, in
     }
 }
 
+// Row exponents of X o as_b for all nb column scales as_b (the RPA quadrature
+// nodes) in one read of X: e[b][row] = scale_exp(max_c |X[row][c] as_b[c]|),
+// by integer atomicMax into e preset to INT_MIN, as row_exp_kernel does for
+// one scale.  A work group takes 16 rows x 512 columns (a thread: one row, the
+// columns cg + 16 u), so that each as_b chunk is read once per 16 rows; the
+// 16 threads of a row reduce each node's maximum by shuffles.
+__global__ __launch_bounds__(256) void node_row_exp_kernel(int rows, int cols, const double* __restrict__ X,
+                                                           const double* __restrict__ as, int nb,
+                                                           int* __restrict__ e) {
+    const int r = threadIdx.x >> 4, cg = threadIdx.x & 15;
+    const int row = blockIdx.y * 16 + r;
+    const int c0 = blockIdx.x * 512 + cg;
+    double x[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+        const int c = c0 + u * 16;
+        x[u] = (row < rows && c < cols) ? X[(long)row * cols + c] : 0.0;
+    }
+    for (int b = 0; b < nb; ++b) {
+        const double* __restrict__ a = as + (long)b * cols;
+        double m = 0.0;
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            const int c = c0 + u * 16;
+            if (c < cols) m = fmax(m, fabs(x[u] * a[c]));
+        }
+        m = fmax(m, __shfl_xor(m, 1));
+        m = fmax(m, __shfl_xor(m, 2));
+        m = fmax(m, __shfl_xor(m, 4));
+        m = fmax(m, __shfl_xor(m, 8));
+        if (cg == 0 && row < rows && m > 0.0) atomicMax(e + (long)b * rows + row, scale_exp(m));
+    }
+}
+
 // col_exp_kernel and digits_lt_kernel in one read of X[naux][ncol]: 16 columns
 // per work group of 512 threads, kept in registers (4 consecutive rows per
 // thread and 128-row pass, NP passes: naux <= Ap <= 128 NP), the column maxima
@@ -1336,6 +1370,15 @@ void launch_digitise_rows(Handle* h, long rows, int cols, int kpad, const double
                        Yd);
 }
 
+// The digit pass of launch_digitise_rows alone, for rows of 4096 or more
+// columns whose exponents (times cs) are already in e (preset INT_MIN, set by
+// atomicMax).
+void launch_row_digits(Handle* h, long rows, int cols, int kpad, const double* X, const double* cs, int* e, i8* Xd) {
+    hipLaunchKernelGGL(row_digits_kernel, dim3((unsigned)((kpad + 127) / 128), (unsigned)((rows + 15) / 16)),
+                       dim3(256), 0, h->stream, rows, cols, kpad, X, cs, e, Xd, (const double*)nullptr, (int*)nullptr,
+                       (i8*)nullptr);
+}
+
 // Column exponents and transposed k-blocked digit planes of X[naux][ncol]
 // (k = the row index, zero-padded to Ap): one read for Ap <= 2048, else the
 // exponent pass followed by the LDS-transposing digit pass.
@@ -1672,11 +1715,15 @@ gw_status node_products_mixed(Handle* h, int naux, long ov, int nb, const double
         return set_err(h, GW_EINVAL, "mixed precision: RPA quadrature too large for the digit node products");
     const long n2 = (long)naux * naux;
     i8* Vd = (i8*)ws_get(h, WS_RPA_AD, sizeof(i8) * 2 * ND * (long)naux * Kp);
-    int* ex = (int*)ws_get(h, WS_RPA_EX, sizeof(int) * (ov + 2L * naux));
+    int* ex = (int*)ws_get(h, WS_RPA_EX, sizeof(int) * (ov + 2L * naux + (long)nb * naux));
     if (!Vd || !ex) return GW_ENOMEM;
     i8* Ad = Vd + ND * (long)naux * Kp;
     int* eV = ex;
     int* eA = ex + naux;
+    int* eN = ex + 2L * naux;  // [nb][naux] exponents of V o as_b
+    // long rows: every node's row exponents in one pass over V, then only the
+    // digit pass per node
+    const bool all_exps = ov >= 4096 && naux <= 65535 * 16;
     int ncu = 256;
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device);
     const int tiles = mixed_upper_tiles(naux);
@@ -1687,9 +1734,21 @@ gw_status node_products_mixed(Handle* h, int naux, long ov, int nb, const double
     if (!part) return GW_ENOMEM;
     KTimer tm(h, "rpa_quad");
     GW_TRY(digitise_rows(h, naux, ov, Kp, V, eV, Vd));
+    if (all_exps) {
+        hipLaunchKernelGGL(fill_i32_kernel, dim3(nb256((long)nb * naux)), dim3(256), 0, h->stream, eN,
+                           (long)nb * naux, INT_MIN);
+        hipLaunchKernelGGL(node_row_exp_kernel, dim3((unsigned)((ov + 511) / 512), (unsigned)((naux + 15) / 16)),
+                           dim3(256), 0, h->stream, naux, (int)ov, V, as, nb, eN);
+        GW_CHECK_LAUNCH(h);
+    }
     for (int b = 0; b < nb; ++b) {
         // digits of V o as[b] by rows (k = ia)
-        launch_digitise_rows(h, naux, (int)ov, Kp, V, as + (long)b * ov, eA, Ad);
+        if (all_exps) {
+            eA = eN + (long)b * naux;
+            launch_row_digits(h, naux, (int)ov, Kp, V, as + (long)b * ov, eA, Ad);
+        } else {
+            launch_digitise_rows(h, naux, (int)ov, Kp, V, as + (long)b * ov, eA, Ad);
+        }
         GW_CHECK_LAUNCH(h);
         DgemmArgs g{};
         g.M = g.N = naux;
